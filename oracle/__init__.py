@@ -1,0 +1,46 @@
+"""CPU float64 oracle for spatially adaptive (extended) correlation and convolution.
+
+TEST INFRASTRUCTURE ONLY. This package is the slow, obviously correct reference
+that the HIP path is checked against. Only the tests, the smoke check and the
+bench's CPU-baseline leg may import it; the product path never does, and it shares
+no code, tables or helpers with the HIP library.
+
+Everything here follows "Efficient Spatially Adaptive Convolution and Correlation"
+(arXiv 2006.13188):
+  * definitions of extended correlation / convolution: Sec. 2.1 eq. (Def-ECorr),
+    Sec. 2.2 eq. (Def-EConv);
+  * the rotation algorithm: Sec. 4.1 (filter decomposition, standard correlations,
+    linear combination, and the pre-multiplied convolution);
+  * band-limiting: Sec. 4.3;
+  * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal.
+
+Readings where the paper is silent are listed per function (boundary = zero outside
+the image, bilinear polar resampling at the exact grid radii, k = -K..K, etc.).
+
+Parity status: every function below is pinned by tests in tests/test_oracle_*.py
+except the scale-group coefficients c_k, whose values are fixed only by the reading
+of the scale decomposition (parity unpinned; see scale.py).
+"""
+from .decompose import (
+    default_angular_samples, bilinear, grid_radii, angular_components,
+    rotated_filter, half_components,
+)
+from .extended import (
+    ext_corr_brute, ext_conv_brute, ext_corr_fft, ext_conv_fft,
+    ext_conv_half, ext_corr_half, match_rotations, min_fft_size,
+)
+from .adjoint import conv_backward, corr_backward
+from .scale import (
+    ScaleParams, scale_components, scale_filter_at, scale_smooth_brute,
+    scale_smooth_fft,
+)
+
+__all__ = [
+    "default_angular_samples", "bilinear", "grid_radii", "angular_components",
+    "rotated_filter", "half_components",
+    "ext_corr_brute", "ext_conv_brute", "ext_corr_fft", "ext_conv_fft",
+    "ext_conv_half", "ext_corr_half", "match_rotations", "min_fft_size",
+    "conv_backward", "corr_backward",
+    "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
+    "scale_smooth_fft",
+]
