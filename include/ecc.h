@@ -1,0 +1,186 @@
+/*
+ * libecc — spatially adaptive ("extended") correlation and convolution on one MI355X
+ * (gfx950) GPU, after "Efficient Spatially Adaptive Convolution and Correlation"
+ * (arXiv 2006.13188).
+ *
+ * Problem statement (Sec. 2): a signal H, a filter F and a transformation field T that
+ * says how F is transformed at every pixel. Extended correlation (Sec. 2.1, eq.
+ * Def-ECorr) gathers: y(p) = sum_q H(q) conj((T(p)F)(q - p)). Extended convolution
+ * (Sec. 2.2, eq. Def-EConv) scatters: y(p) = sum_q H(q) (T(q)F)(p - q).
+ * For 2D rotation the filter is split into angular components F_k(r, phi) =
+ * f_k(r) e^{i k phi}, k = -K..K (Sec. 4.1, band-limited as in Sec. 4.3); rotating by
+ * theta multiplies F_k by e^{-i k theta}, so the correlation is
+ * sum_k e^{i k theta(p)} (H star F_k)(p) and the convolution is
+ * sum_k (H e^{-i k theta}) * F_k. For the scale group (Sec. 8) the components are
+ * Fourier modes in log r.
+ *
+ * Conventions shared by every call:
+ *  - Images are row-major float32, ny rows by nx columns, row stride `ld` elements
+ *    (ld >= nx); x = column (right), y = row (down); angles are atan2(dy, dx) radians.
+ *  - Components are complex64 stored as interleaved (re, im) float pairs, layout
+ *    [k][row][col] with k = 0..K and an S x S window centred at (R, R), R = (S-1)/2.
+ *  - Filters are real, so F_{-k} = conj(F_k) and only k = 0..K are stored.
+ *  - Zero boundary: H is zero outside the image; outputs have the image's size.
+ *  - Every pointer marked "device" is a HIP device pointer owned by the caller; it must
+ *    stay valid until the work enqueued on `stream` has completed. `stream` is a
+ *    hipStream_t (NULL = the null stream). Calls enqueue work and return without
+ *    waiting, except plan creation, which may wait for its own set-up.
+ *  - Every call returns an ecc_status. Arguments are validated before anything is
+ *    enqueued, so a failed call leaves outputs untouched; ecc_last_error() gives the
+ *    message (thread-local). No call aborts, throws or prints.
+ */
+#ifndef ECC_H
+#define ECC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ECC_OK = 0,
+  ECC_ERR_INVALID_ARGUMENT = 1,
+  ECC_ERR_UNSUPPORTED = 2,
+  ECC_ERR_OUT_OF_MEMORY = 3,
+  ECC_ERR_HIP = 4,
+  ECC_ERR_PLAN_MISMATCH = 5,
+  ECC_ERR_INTERNAL = 6
+} ecc_status;
+
+typedef enum { ECC_GROUP_ROTATION = 0, ECC_GROUP_SCALE = 1 } ecc_group;
+typedef enum { ECC_CORRELATION = 0, ECC_CONVOLUTION = 1 } ecc_op;
+typedef enum {
+  ECC_PREC_FP32 = 0,
+  ECC_PREC_MFMA_FP16_HILO = 1,
+  ECC_PREC_MFMA_BF16_HILO = 2
+} ecc_precision;
+
+typedef struct ecc_context_s* ecc_context;
+typedef struct ecc_filter_plan_s* ecc_filter_plan;
+
+/* Parameters of the transformation group. Zero fields take the defaults shown. */
+typedef struct {
+  int angular_samples;        /* rotation: angular samples M per radius; 0 = smallest power
+                                 of two >= max(8(2K+1), 4 ceil(2 pi R))                   */
+  double sigma0;              /* scale: base Gaussian width in pixels at s = 1 (1.0)       */
+  double scale_min;           /* scale: smallest per-pixel scale (1.0)                     */
+  double scale_max;           /* scale: largest per-pixel scale (8.0)                      */
+  int scale_components;       /* scale: number of log-radial Fourier modes n (24)          */
+  double scale_period_factor; /* scale: period of the log-radial expansion relative to the
+                                 range of ln|x| - ln s met on the grid (1.5)              */
+} ecc_group_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context bound to HIP device `hip_device` (made current for the call).
+ * The context owns twiddle tables, scratch workspace and size choices. One context
+ * must not be used by two host threads at once. Errors: INVALID_ARGUMENT (bad device
+ * or NULL out), HIP. */
+ecc_status ecc_create(int hip_device, ecc_context* out);
+/* Waits for the device, then frees everything the context owns (plans made from it
+ * must be destroyed first). NULL is accepted. */
+ecc_status ecc_destroy(ecc_context ctx);
+const char* ecc_status_string(ecc_status s);
+/* Message of the last failed call on this host thread ("" if none). */
+const char* ecc_last_error(void);
+
+/* FFT size used for an image side n and filter radius R: the smallest 7-smooth integer
+ * >= n + R (zero-boundary linear correlation needs >= n + R), unless the autotuner
+ * has chosen a larger one for this shape. */
+ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
+/* Enables (1) or disables (0) timing-based choice of FFT sizes on first use of a shape. */
+ecc_status ecc_set_autotune(ecc_context ctx, int enable);
+
+/* ---------------------------------------------------------------- filter plans */
+
+/* Rotation (Sec. 4.1, "Filter Decomposition"): `filter` is a device S x S float32 array
+ * (S odd, 3 <= S <= 255), centre at (R, R). The plan samples it bilinearly (zero outside
+ * the array) on every distinct grid radius 0 < rho <= R at M equispaced angles, takes
+ * the angular DFT f_k(rho) = (1/M) sum_m F(rho, phi_m) e^{-i k phi_m} for k = 0..K
+ * (0 <= K <= M/2 - 1), and stores F_k(x) = f_k(|x|) e^{i k phi(x)} on the disk |x| <= R
+ * (F_0(0) = F(0), F_k(0) = 0 otherwise, zero outside the disk). All of this runs in
+ * float64 on the GPU; components are kept in float64 and float32.
+ * Scale (Sec. 8): `filter` must be NULL and S, K are ignored (pass 0); the plan builds
+ * the log-radial components of a Gaussian from `gp` (see ecc_group_params): F_k(x) =
+ * c_k e^{i omega_k (ln|x| - u_lo)}, k = 0..n/2, on the disk of radius
+ * R = ceil(4 sigma0 scale_max).
+ * `gp` may be NULL (defaults). Waits for `stream`. Errors: INVALID_ARGUMENT, UNSUPPORTED
+ * (complex filters are not accepted by this signature), OUT_OF_MEMORY, HIP. */
+ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float* filter,
+                                  int S, int K, const ecc_group_params* gp, void* stream,
+                                  ecc_filter_plan* out);
+/* Plan from explicit components: `comps` is device complex64 (interleaved), (K+1) x S x S,
+ * k = 0..K, as described above. For ECC_GROUP_SCALE the field angle and weights come
+ * from `gp` as for ecc_filter_plan_create. Waits for `stream`. */
+ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, const float* comps,
+                                           int S, int K, const ecc_group_params* gp,
+                                           void* stream, ecc_filter_plan* out);
+/* Copies the plan's complex64 components ((K+1) x S x S, interleaved) to device `out`. */
+ecc_status ecc_filter_plan_get_components(ecc_filter_plan plan, float* out, void* stream);
+/* Window size S, band limit K (components k = 0..K) and angular samples M of a plan. */
+ecc_status ecc_filter_plan_info(ecc_filter_plan plan, int* S, int* K, int* M);
+ecc_status ecc_filter_plan_destroy(ecc_filter_plan plan);
+
+/* ---------------------------------------------------------------- forward operators */
+
+/* Extended correlation (Sec. 2.1) or convolution (Sec. 2.2) of `batch` images.
+ * signal, field, out: device float32, batch x ny x nx with row strides ld_* and image
+ * stride ny * ld_*. field = theta(p) in radians (rotation plans) or s(p) > 0 (scale
+ * plans; the phase is e^{-i omega_k ln s}). out must not alias an input.
+ * Rotation: correlation y = Re sum_k w_k e^{i k theta} (H star F_k), convolution
+ * y = Re sum_k w_k (H e^{-i k theta}) * F_k, with w_0 = 1, w_k = 2 (k and -k together).
+ * Only ECC_PREC_FP32 is implemented. Errors: INVALID_ARGUMENT (sizes, strides, NULL,
+ * aliasing, filter larger than the image), UNSUPPORTED (precision), HIP. */
+ecc_status ecc_extended(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny,
+                        int nx, const float* signal, int ld_signal, const float* field,
+                        int ld_field, float* out, int ld_out, ecc_precision prec, void* stream);
+
+/* Scale-adaptive smoothing (Sec. 8, eq. normalization with the normalised signal):
+ * out = {H / s^2, s} * F divided by {1 / s^2, s} * F, for a scale plan.
+ * signal, scale, out: device float32 ny x nx with the given row strides. */
+ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
+                            const float* signal, int ld_signal, const float* scale,
+                            int ld_scale, float* out, int ld_out, ecc_precision prec,
+                            void* stream);
+
+/* Rotation-independent matching (Sec. 5.2 in band-limited form): the correlation
+ * response at n_angles equispaced angles 2 pi m / n_angles,
+ * C(p, m) = sum_k w_k Re(e^{2 pi i k m / n_angles} (H star F_k)(p)); best_score = max_m C,
+ * best_index = the smallest maximising m. 2K+1 <= n_angles <= 64.
+ * signal: device float32 ny x nx (stride ld); best_score (float32) and best_index
+ * (int32): device ny x nx with stride ld_out. */
+ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
+                               const float* signal, int ld, int n_angles, float* best_score,
+                               int* best_index, int ld_out, ecc_precision prec, void* stream);
+
+/* ---------------------------------------------------------------- adjoint */
+
+/* Gradients of the rotation-plan extended convolution y = Re sum_k w_k (H e^{-ik theta}) * F_k
+ * with respect to H, theta and the components, given grad_out = dL/dy (all images
+ * batch x ny x nx, contiguous rows, ld = nx):
+ *   grad_signal(q) = Re sum_k w_k e^{-ik theta(q)} A_k(q), A_k(q) = sum_x gbar(q+x) F_k(x)
+ *   grad_field(q)  = H(q) sum_k w_k k Im(e^{-ik theta(q)} A_k(q))
+ *   grad_comps_k(x) = w_k sum_b sum_p gbar_b(p) conj(H_b(p-x) e^{-ik theta_b(p-x)})
+ *                     (summed over the batch in a fixed order; complex64 (K+1) x S x S)
+ * Any of grad_signal, grad_field, grad_comps may be NULL (not computed). `saved` is NULL
+ * (recompute the modulated-signal stack) or device memory of
+ * ecc_backward_saved_size() bytes filled by ecc_extended_save(). Only ECC_CONVOLUTION
+ * is implemented (ECC_CORRELATION returns UNSUPPORTED). */
+ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch,
+                                 int ny, int nx, const float* signal, const float* field,
+                                 const float* grad_out, float* grad_signal, float* grad_comps,
+                                 float* grad_field, void* saved, void* stream);
+/* Bytes of the stack saved by the forward pass for ecc_extended_backward. */
+ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int batch, int ny,
+                                   int nx, size_t* bytes);
+/* Forward extended convolution that also writes the per-component row spectra of the
+ * modulated signal into `saved` (ecc_backward_saved_size bytes, device). */
+ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                             const float* signal, const float* field, float* out, void* saved,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECC_H */

@@ -1,0 +1,279 @@
+"""Python binding of libecc: spatially adaptive correlation/convolution on MI355X.
+
+Thin wrappers with the C ABI's names (include/ecc.h). Tensors are torch tensors on a
+HIP device (float32, contiguous rows); every call passes raw device pointers and the
+current HIP stream. No computation happens here: if the library is missing the import
+of `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+from . import _lib
+from ._lib import (CONVOLUTION, CORRELATION, GROUP_ROTATION, GROUP_SCALE, PREC_FP32,
+                   EccError, GroupParams)
+
+__all__ = [
+    "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
+    "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv",
+    "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
+    "GroupParams",
+]
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _lib.load()
+    return _LIB
+
+
+def _check(status):
+    if status != _lib.ECC_OK:
+        raise EccError(status, lib().ecc_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _img(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
+        raise TypeError(f"{name} must be a float32 tensor on a HIP device")
+    if t.stride(-1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return t
+
+
+def _ld(t):
+    return t.stride(-2) if t.dim() >= 2 else t.shape[-1]
+
+
+class Context:
+    """Owns a libecc context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().ecc_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().ecc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fft_size(self, n: int, R: int) -> int:
+        P = C.c_int()
+        _check(lib().ecc_fft_size(self.h, n, R, C.byref(P)))
+        return P.value
+
+
+class FilterPlan:
+    """A filter decomposed into components F_k, k = 0..K (see ecc_filter_plan_create)."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        S, K, M = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().ecc_filter_plan_info(h, C.byref(S), C.byref(K), C.byref(M)))
+        self.S, self.K, self.M = S.value, K.value, M.value
+
+    @classmethod
+    def rotation(cls, ctx: Context, filt, K: int, angular_samples: int = 0, stream=None):
+        filt = _img(filt, "filter").contiguous()
+        gp = GroupParams(angular_samples=angular_samples)
+        h = C.c_void_p()
+        _check(lib().ecc_filter_plan_create(ctx.h, GROUP_ROTATION, _ptr(filt), filt.shape[-1], K,
+                                            C.byref(gp), _stream(stream), C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def scale(cls, ctx: Context, sigma0=1.0, scale_min=1.0, scale_max=8.0, components=24,
+              period_factor=1.5, stream=None):
+        gp = GroupParams(0, sigma0, scale_min, scale_max, components, period_factor)
+        h = C.c_void_p()
+        _check(lib().ecc_filter_plan_create(ctx.h, GROUP_SCALE, None, 0, 0, C.byref(gp),
+                                            _stream(stream), C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def from_components(cls, ctx: Context, comps, group=GROUP_ROTATION, gp: Optional[GroupParams] = None,
+                        stream=None):
+        """comps: complex64 tensor (K+1, S, S) on the device."""
+        import torch
+        if not (comps.is_cuda and comps.dtype == torch.complex64 and comps.dim() == 3):
+            raise TypeError("comps must be a (K+1, S, S) complex64 device tensor")
+        comps = comps.contiguous()
+        h = C.c_void_p()
+        _check(lib().ecc_filter_plan_from_components(ctx.h, group, _ptr(comps), comps.shape[-1],
+                                                     comps.shape[0] - 1,
+                                                     C.byref(gp) if gp is not None else None,
+                                                     _stream(stream), C.byref(h)))
+        return cls(ctx, h)
+
+    def components(self, stream=None):
+        import torch
+        out = torch.empty((self.K + 1, self.S, self.S), dtype=torch.complex64,
+                          device=f"cuda:{self.ctx.device}")
+        _check(lib().ecc_filter_plan_get_components(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if self.h:
+            lib().ecc_filter_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ecc_extended(ctx: Context, op: int, plan: FilterPlan, signal, field, out=None, stream=None):
+    """Extended correlation (op=CORRELATION) or convolution (op=CONVOLUTION).
+    signal, field: (ny, nx) or (batch, ny, nx) float32 device tensors."""
+    import torch
+    _img(signal, "signal")
+    _img(field, "field")
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    _img(out, "out")
+    ny, nx = signal.shape[-2], signal.shape[-1]
+    batch = signal.shape[0] if signal.dim() == 3 else 1
+    for t in (signal, field, out):
+        if t.dim() == 3 and t.stride(0) != t.shape[-2] * t.stride(-2):
+            raise ValueError("batched images must be stacked with image stride ny * ld")
+    _check(lib().ecc_extended(ctx.h, op, plan.h, batch, ny, nx, _ptr(signal), _ld(signal),
+                              _ptr(field), _ld(field), _ptr(out), _ld(out), PREC_FP32,
+                              _stream(stream)))
+    return out
+
+
+def ecc_scale_smooth(ctx: Context, plan: FilterPlan, signal, scale, out=None, stream=None):
+    import torch
+    _img(signal, "signal")
+    _img(scale, "scale")
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    ny, nx = signal.shape
+    _check(lib().ecc_scale_smooth(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), _ptr(scale),
+                                  _ld(scale), _ptr(out), _ld(out), PREC_FP32, _stream(stream)))
+    return out
+
+
+def ecc_match_rotations(ctx: Context, plan: FilterPlan, signal, n_angles=64, stream=None):
+    import torch
+    _img(signal, "signal")
+    ny, nx = signal.shape
+    score = torch.empty((ny, nx), dtype=torch.float32, device=signal.device)
+    index = torch.empty((ny, nx), dtype=torch.int32, device=signal.device)
+    _check(lib().ecc_match_rotations(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), n_angles,
+                                     _ptr(score), _ptr(index), nx, PREC_FP32, _stream(stream)))
+    return score, index
+
+
+def ecc_backward_saved_size(ctx: Context, plan: FilterPlan, batch, ny, nx) -> int:
+    n = C.c_size_t()
+    _check(lib().ecc_backward_saved_size(ctx.h, plan.h, batch, ny, nx, C.byref(n)))
+    return n.value
+
+
+def ecc_extended_save(ctx: Context, plan: FilterPlan, signal, field, saved, out=None, stream=None):
+    import torch
+    signal = signal.contiguous()
+    field = field.contiguous()
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    batch = signal.shape[0] if signal.dim() == 3 else 1
+    ny, nx = signal.shape[-2:]
+    _check(lib().ecc_extended_save(ctx.h, plan.h, batch, ny, nx, _ptr(signal), _ptr(field),
+                                   _ptr(out), _ptr(saved), _stream(stream)))
+    return out
+
+
+def ecc_extended_backward(ctx: Context, plan: FilterPlan, signal, field, grad_out, need_signal=True,
+                          need_comps=True, need_field=True, saved=None, stream=None):
+    """Adjoint of the extended convolution: returns (grad_signal, grad_comps, grad_field)."""
+    import torch
+    signal = signal.contiguous()
+    field = field.contiguous()
+    grad_out = grad_out.contiguous()
+    batch = signal.shape[0] if signal.dim() == 3 else 1
+    ny, nx = signal.shape[-2:]
+    dev = signal.device
+    gs = torch.empty(signal.shape, dtype=torch.float32, device=dev) if need_signal else None
+    gf = torch.empty(signal.shape, dtype=torch.float32, device=dev) if need_field else None
+    gc = torch.empty((plan.K + 1, plan.S, plan.S), dtype=torch.complex64, device=dev) if need_comps else None
+    _check(lib().ecc_extended_backward(ctx.h, CONVOLUTION, plan.h, batch, ny, nx, _ptr(signal),
+                                       _ptr(field), _ptr(grad_out), _ptr(gs), _ptr(gc), _ptr(gf),
+                                       _ptr(saved), _stream(stream)))
+    return gs, gc, gf
+
+
+def _ext_conv_function():
+    import torch
+
+    class ExtConv(torch.autograd.Function):
+        """y = extended convolution of `signal` with components `comps` ((K+1, S, S)
+        complex64) steered by the angle field `theta`; backward uses the hand-written
+        adjoint. checkpoint=True recomputes the modulated-signal stack in backward
+        instead of keeping it."""
+
+        @staticmethod
+        def forward(ctx_, signal, theta, comps, ectx, checkpoint=False):
+            plan = FilterPlan.from_components(ectx, comps.detach())
+            sig = signal.detach().contiguous()
+            th = theta.detach().contiguous()
+            batch = sig.shape[0] if sig.dim() == 3 else 1
+            if checkpoint:
+                y = ecc_extended(ectx, CONVOLUTION, plan, sig, th)
+                saved = None
+            else:
+                nbytes = ecc_backward_saved_size(ectx, plan, batch, sig.shape[-2], sig.shape[-1])
+                saved = torch.empty(nbytes // 4, dtype=torch.float32, device=sig.device)
+                y = ecc_extended_save(ectx, plan, sig, th, saved)
+            ctx_.plan, ctx_.ectx, ctx_.saved_stack = plan, ectx, saved
+            ctx_.save_for_backward(sig, th)
+            return y
+
+        @staticmethod
+        def backward(ctx_, gy):
+            sig, th = ctx_.saved_tensors
+            gs, gc, gf = ecc_extended_backward(
+                ctx_.ectx, ctx_.plan, sig, th, gy, need_signal=ctx_.needs_input_grad[0],
+                need_comps=ctx_.needs_input_grad[2], need_field=ctx_.needs_input_grad[1],
+                saved=ctx_.saved_stack)
+            return gs, gf, gc, None, None
+
+    return ExtConv
+
+
+class _Lazy:
+    def __init__(self):
+        self._f = None
+
+    def apply(self, *args, **kw):
+        if self._f is None:
+            self._f = _ext_conv_function()
+        return self._f.apply(*args, **kw)
+
+
+ExtConv = _Lazy()

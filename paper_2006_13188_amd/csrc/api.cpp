@@ -1,0 +1,704 @@
+// C-ABI of libecc: validation, plan construction, and the launch sequences of the
+// correlation / convolution / matching / smoothing / adjoint paths.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ecc;
+
+namespace {
+
+thread_local std::string g_err;
+
+ecc_status fail(ecc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define ECC_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (e_ == hipErrorOutOfMemory)                                                   \
+        return fail(ECC_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of memory");    \
+      return fail(ECC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    }                                                                                  \
+  } while (0)
+
+#define ECC_REQ(cond, msg)                                             \
+  do {                                                                 \
+    if (!(cond)) return fail(ECC_ERR_INVALID_ARGUMENT, (msg));         \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+int fft_size_for(ecc_context ctx, int n, int R) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  const std::string key = std::to_string(n) + ":" + std::to_string(R);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) return it->second;
+  return next_smooth7(n + R);
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+ecc_status check_cfg_row(const RowCfg& c, const Transform& t, size_t elem, const char* what) {
+  if (c.NB < 0 || c.EPX < 0 || lds_rows(c, t.desc, elem) > kMaxLds)
+    return fail(ECC_ERR_UNSUPPORTED, std::string("transform too long for the ") + what + " kernel");
+  return ECC_OK;
+}
+ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const char* what, bool need_ept) {
+  if (c.NB < 0 || (need_ept && c.EPT < 0) || lds_cols(c, t.desc, elem) > kMaxLds)
+    return fail(ECC_ERR_UNSUPPORTED, std::string("transform too long for the ") + what + " kernel");
+  return ECC_OK;
+}
+#define ECC_TRY(expr)                 \
+  do {                                \
+    ecc_status s_ = (expr);           \
+    if (s_ != ECC_OK) return s_;      \
+  } while (0)
+
+// Filter spectra Fh_k = FFT2(F_k placed with its centre at (0, 0)) on a Py x Px grid,
+// computed in float64 and rounded to float32. Symmetric plans keep columns [0, W).
+ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, const Spectrum** out) {
+  std::lock_guard<std::mutex> g(plan->mu);
+  auto key = std::make_pair(Py, Px);
+  auto it = plan->spectra.find(key);
+  if (it != plan->spectra.end()) {
+    *out = it->second.get();
+    return ECC_OK;
+  }
+  const Transform *Ty = nullptr, *Tx = nullptr;
+  ECC_HIP(get_transform(plan->ctx, Py, &Ty));
+  ECC_HIP(get_transform(plan->ctx, Px, &Tx));
+  auto sp = std::make_unique<Spectrum>();
+  sp->Py = Py;
+  sp->Px = Px;
+  sp->full = plan->symmetric ? 0 : 1;
+  const int W = Px / 2 + 1;
+  const int Wst = sp->full ? Px : W;
+  sp->ld = Wst;
+  const int U = plan->U, Sz = plan->S, R = plan->R;
+  DevBuf tmp, spec64;
+  ECC_HIP(tmp.ensure((size_t)U * Sz * Wst * sizeof(cx<double>)));
+  ECC_HIP(spec64.ensure((size_t)U * Py * Wst * sizeof(cx<double>)));
+  ECC_HIP(sp->buf.ensure((size_t)U * Py * Wst * sizeof(cx<float>)));
+  RowCfg rc = row_config(*Tx, Px, sizeof(cx<double>));
+  ColCfg cc = col_config(*Ty, 2, sizeof(cx<double>), 256);
+  ECC_TRY(check_cfg_row(rc, *Tx, sizeof(cx<double>), "filter row"));
+  ECC_TRY(check_cfg_col(cc, *Ty, sizeof(cx<double>), "filter column", false));
+  ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
+                                   Sz, Sz, -R, tmp.as<cx<double>>(), (long long)Sz * Wst, Wst, Wst, 0,
+                                   Tx->desc, Tx->d())));
+  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * Wst, Wst, Wst,
+                                   Sz, -R, spec64.as<cx<double>>(), (long long)Py * Wst, Wst, Py, 0,
+                                   Ty->desc, Ty->d())));
+  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * Py * Wst));
+  ECC_HIP(hipStreamSynchronize(st));   // temporaries are freed on return
+  *out = sp.get();
+  plan->spectra[key] = std::move(sp);
+  return ECC_OK;
+}
+
+ecc_status finish_plan(ecc_filter_plan p, hipStream_t st) {
+  const size_t n = (size_t)p->U * p->S * p->S;
+  ECC_HIP(p->comps32.ensure(n * sizeof(cx<float>)));
+  ECC_HIP(launch_d2f(st, p->comps64.as<cx<double>>(), p->comps32.as<cx<float>>(), (long long)n));
+  ECC_HIP(p->d_weights.ensure(p->U * sizeof(float)));
+  ECC_HIP(hipMemcpyAsync(p->d_weights.p, p->weights.data(), p->U * sizeof(float), hipMemcpyHostToDevice, st));
+  if (p->symmetric) {
+    ECC_HIP(p->d_parity.ensure(p->U * sizeof(float)));
+    ECC_HIP(hipMemcpyAsync(p->d_parity.p, p->parity.data(), p->U * sizeof(float), hipMemcpyHostToDevice, st));
+  }
+  ECC_HIP(hipStreamSynchronize(st));
+  return ECC_OK;
+}
+
+struct ScaleSetup {
+  double sigma0, smin, smax, pf, u_lo, u_hi, L;
+  int n, R;
+};
+
+ecc_status scale_setup(const ecc_group_params* gp, ScaleSetup& s) {
+  s.sigma0 = (gp && gp->sigma0 > 0) ? gp->sigma0 : 1.0;
+  s.smin = (gp && gp->scale_min > 0) ? gp->scale_min : 1.0;
+  s.smax = (gp && gp->scale_max > 0) ? gp->scale_max : 8.0;
+  s.n = (gp && gp->scale_components > 0) ? gp->scale_components : 24;
+  s.pf = (gp && gp->scale_period_factor > 0) ? gp->scale_period_factor : 1.5;
+  ECC_REQ(s.smax >= s.smin, "scale_max must be >= scale_min");
+  ECC_REQ(s.n >= 2 && s.n <= 512, "scale_components must be in [2, 512]");
+  ECC_REQ(s.pf > 1.0, "scale_period_factor must exceed 1");
+  s.R = (int)std::ceil(4.0 * s.sigma0 * s.smax - 1e-12);
+  ECC_REQ(s.R >= 1 && s.R <= 127, "scaled filter radius ceil(4 sigma0 scale_max) must be in [1, 127]");
+  s.u_lo = -std::log(s.smax);
+  s.u_hi = std::log((double)s.R) - std::log(s.smin);
+  s.L = s.pf * (s.u_hi - s.u_lo);
+  return ECC_OK;
+}
+
+void scale_plan_fields(ecc_filter_plan p, const ScaleSetup& s) {
+  p->U = s.n / 2 + 1;
+  p->K = p->U - 1;
+  p->R = s.R;
+  p->S = 2 * s.R + 1;
+  p->M = 0;
+  p->weights.assign(p->U, 2.f);
+  p->weights[0] = 1.f;
+  if (s.n % 2 == 0) p->weights[p->U - 1] = 1.f;
+  p->field_mul = 2.0 * 3.14159265358979323846 / s.L;
+  p->log_mode = 1;
+  p->sig_norm = 1;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+const char* ecc_status_string(ecc_status s) {
+  switch (s) {
+    case ECC_OK: return "ok";
+    case ECC_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case ECC_ERR_UNSUPPORTED: return "unsupported";
+    case ECC_ERR_OUT_OF_MEMORY: return "out of memory";
+    case ECC_ERR_HIP: return "HIP error";
+    case ECC_ERR_PLAN_MISMATCH: return "plan mismatch";
+    case ECC_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ecc_last_error(void) { return g_err.c_str(); }
+
+ecc_status ecc_create(int hip_device, ecc_context* out) {
+  ECC_REQ(out != nullptr, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  ECC_HIP(hipGetDeviceCount(&n));
+  ECC_REQ(hip_device >= 0 && hip_device < n, "no such HIP device");
+  DeviceGuard dg(hip_device);
+  static std::once_flag once;
+  static hipError_t prep = hipSuccess;
+  std::call_once(once, [] { prep = prepare_kernels(); });
+  ECC_HIP(prep);
+  auto* ctx = new (std::nothrow) ecc_context_s();
+  if (!ctx) return fail(ECC_ERR_OUT_OF_MEMORY, "context allocation failed");
+  ctx->device = hip_device;
+  *out = ctx;
+  return ECC_OK;
+}
+
+ecc_status ecc_destroy(ecc_context ctx) {
+  if (!ctx) return ECC_OK;
+  DeviceGuard dg(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return ECC_OK;
+}
+
+ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P) {
+  ECC_REQ(ctx && P, "NULL argument");
+  ECC_REQ(n >= 1 && R >= 0 && n + R <= 16384, "size out of range");
+  *P = fft_size_for(ctx, n, R);
+  return ECC_OK;
+}
+
+ecc_status ecc_set_autotune(ecc_context ctx, int enable) {
+  ECC_REQ(ctx, "NULL context");
+  ctx->autotune = enable ? 1 : 0;
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float* filter, int Sz,
+                                  int K, const ecc_group_params* gp, void* stream,
+                                  ecc_filter_plan* out) {
+  ECC_REQ(ctx && out, "NULL argument");
+  *out = nullptr;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  auto plan = std::make_unique<ecc_filter_plan_s>();
+  plan->ctx = ctx;
+  plan->group = group;
+  if (group == ECC_GROUP_ROTATION) {
+    ECC_REQ(filter != nullptr, "filter is NULL");
+    ECC_REQ(Sz >= 3 && Sz <= 255 && Sz % 2 == 1, "S must be odd, 3 <= S <= 255");
+    const int R = (Sz - 1) / 2;
+    int M = (gp && gp->angular_samples > 0) ? gp->angular_samples : 0;
+    if (M == 0) {
+      const int need = std::max(8 * (2 * K + 1), 4 * (int)std::ceil(2.0 * 3.14159265358979323846 * R));
+      M = 1;
+      while (M < need) M *= 2;
+    }
+    ECC_REQ(K >= 0 && 2 * K + 2 <= M, "need 0 <= K <= M/2 - 1");
+    ECC_REQ(M <= 2048, "angular_samples must be <= 2048");
+    plan->S = Sz;
+    plan->R = R;
+    plan->K = K;
+    plan->U = K + 1;
+    plan->M = M;
+    // distinct squared radii and the radius index of every window pixel
+    std::vector<int> d2list;
+    for (int d2 = 1; d2 <= R * R; ++d2) {
+      bool hit = false;
+      for (int a = 0; a <= R && !hit; ++a) {
+        const int b2 = d2 - a * a;
+        if (b2 < 0) break;
+        const int b = (int)std::lround(std::sqrt((double)b2));
+        if (b * b == b2) hit = true;
+      }
+      if (hit) d2list.push_back(d2);
+    }
+    std::vector<int> rmap(Sz * Sz, -1);
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int d2 = dx * dx + dy * dy;
+        if (d2 == 0 || d2 > R * R) continue;
+        rmap[(dy + R) * Sz + (dx + R)] =
+            (int)(std::lower_bound(d2list.begin(), d2list.end(), d2) - d2list.begin());
+      }
+    const int nrad = (int)d2list.size();
+    DevBuf dd2, drmap, fk;
+    ECC_HIP(dd2.ensure(std::max(1, nrad) * sizeof(int)));
+    ECC_HIP(drmap.ensure(rmap.size() * sizeof(int)));
+    ECC_HIP(fk.ensure((size_t)std::max(1, nrad) * plan->U * sizeof(cx<double>)));
+    ECC_HIP(plan->comps64.ensure((size_t)plan->U * Sz * Sz * sizeof(cx<double>)));
+    if (nrad) ECC_HIP(hipMemcpyAsync(dd2.p, d2list.data(), nrad * sizeof(int), hipMemcpyHostToDevice, st));
+    ECC_HIP(hipMemcpyAsync(drmap.p, rmap.data(), rmap.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (nrad) ECC_HIP(launch_polar_dft(st, filter, Sz, K, M, dd2.as<int>(), nrad, fk.as<cx<double>>()));
+    ECC_HIP(launch_synth_rotation(st, filter, Sz, K, drmap.as<int>(), fk.as<cx<double>>(),
+                                  plan->comps64.as<cx<double>>()));
+    plan->weights.assign(plan->U, 2.f);
+    plan->weights[0] = 1.f;
+    plan->parity.resize(plan->U);
+    for (int k = 0; k < plan->U; ++k) plan->parity[k] = (k % 2) ? -1.f : 1.f;
+    plan->symmetric = 1;
+    ECC_HIP(hipStreamSynchronize(st));   // temporaries above are freed on return
+  } else if (group == ECC_GROUP_SCALE) {
+    ECC_REQ(filter == nullptr, "scale plans build their Gaussian from gp; filter must be NULL");
+    ScaleSetup s{};
+    ECC_TRY(scale_setup(gp, s));
+    scale_plan_fields(plan.get(), s);
+    ECC_HIP(plan->comps64.ensure((size_t)plan->U * plan->S * plan->S * sizeof(cx<double>)));
+    ECC_HIP(launch_scale_components(st, s.sigma0, s.u_lo, s.u_hi, s.L, s.n, s.R,
+                                    plan->comps64.as<cx<double>>()));
+    plan->parity.assign(plan->U, 1.f);   // radial components: F_k(-x) = F_k(x)
+    plan->symmetric = 1;
+  } else {
+    return fail(ECC_ERR_INVALID_ARGUMENT, "unknown group");
+  }
+  ECC_TRY(finish_plan(plan.get(), st));
+  *out = plan.release();
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, const float* comps,
+                                           int Sz, int K, const ecc_group_params* gp,
+                                           void* stream, ecc_filter_plan* out) {
+  ECC_REQ(ctx && out && comps, "NULL argument");
+  *out = nullptr;
+  ECC_REQ(Sz >= 1 && Sz <= 255 && Sz % 2 == 1, "S must be odd, 1 <= S <= 255");
+  ECC_REQ(K >= 0 && K <= 255, "K out of range");
+  ECC_REQ(((uintptr_t)comps & 7) == 0, "components must be 8-byte aligned");
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  auto plan = std::make_unique<ecc_filter_plan_s>();
+  plan->ctx = ctx;
+  plan->group = group;
+  if (group == ECC_GROUP_SCALE) {
+    ScaleSetup s{};
+    ECC_TRY(scale_setup(gp, s));
+    scale_plan_fields(plan.get(), s);
+    ECC_REQ(K + 1 == plan->U, "scale plans need K + 1 = scale_components / 2 + 1 components");
+  } else if (group == ECC_GROUP_ROTATION) {
+    plan->weights.assign(K + 1, 2.f);
+    plan->weights[0] = 1.f;
+  } else {
+    return fail(ECC_ERR_INVALID_ARGUMENT, "unknown group");
+  }
+  plan->S = Sz;
+  plan->R = (Sz - 1) / 2;
+  plan->K = K;
+  plan->U = K + 1;
+  plan->M = 0;
+  plan->symmetric = 0;   // arbitrary components: keep full-plane spectra
+  const size_t n = (size_t)plan->U * Sz * Sz;
+  ECC_HIP(plan->comps64.ensure(n * sizeof(cx<double>)));
+  ECC_HIP(launch_f2d(st, reinterpret_cast<const cx<float>*>(comps), plan->comps64.as<cx<double>>(), (long long)n));
+  ECC_TRY(finish_plan(plan.get(), st));
+  *out = plan.release();
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_get_components(ecc_filter_plan plan, float* out, void* stream) {
+  ECC_REQ(plan && out, "NULL argument");
+  DeviceGuard dg(plan->ctx->device);
+  ECC_HIP(hipMemcpyAsync(out, plan->comps32.p, (size_t)plan->U * plan->S * plan->S * sizeof(cx<float>),
+                         hipMemcpyDeviceToDevice, S(stream)));
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_info(ecc_filter_plan plan, int* Sz, int* K, int* M) {
+  ECC_REQ(plan, "NULL plan");
+  if (Sz) *Sz = plan->S;
+  if (K) *K = plan->K;
+  if (M) *M = plan->M;
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_destroy(ecc_filter_plan plan) {
+  if (!plan) return ECC_OK;
+  DeviceGuard dg(plan->ctx->device);
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return ECC_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================================
+namespace {
+
+struct Geometry {
+  int ny, nx, Py, Px, W;
+  const Transform *Tx, *Ty;
+  const Spectrum* sp;
+};
+
+ecc_status geometry(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, hipStream_t st, Geometry& g) {
+  g.ny = ny;
+  g.nx = nx;
+  g.Py = fft_size_for(ctx, ny, plan->R);
+  g.Px = fft_size_for(ctx, nx, plan->R);
+  g.W = g.Px / 2 + 1;
+  ECC_HIP(get_transform(ctx, g.Py, &g.Ty));
+  ECC_HIP(get_transform(ctx, g.Px, &g.Tx));
+  ECC_TRY(get_spectrum(plan, g.Py, g.Px, st, &g.sp));
+  return ECC_OK;
+}
+
+ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx) {
+  ECC_REQ(batch >= 1 && batch <= 65535, "batch must be in [1, 65535]");
+  ECC_REQ(ny >= 1 && nx >= 1 && ny <= 4096 && nx <= 4096, "image sides must be in [1, 4096]");
+  ECC_REQ(plan->S <= std::min(ny, nx) || plan->group == ECC_GROUP_SCALE,
+          "filter window larger than the image");
+  return ECC_OK;
+}
+
+// Correlation-type stack: T_k = IFFT_y(Hh . filter product) for k = 0..U-1.
+ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, int batch,
+                      const float* H, long long planeH, int ldH, int conj_mode, hipStream_t st,
+                      cx<float>** T_out, long long* planeTk, long long* planeTimg) {
+  const int ny = g.ny, nx = g.nx, Py = g.Py, Px = g.Px, W = g.W, U = plan->U;
+  const long long pA = (long long)ny * W, pH = (long long)Py * W, pTk = (long long)ny * Px,
+                  pTi = pTk * U;
+  const size_t need = ((size_t)batch * (pA + pH + pTi)) * sizeof(cx<float>);
+  ECC_HIP(ctx->ws.ensure(need));
+  cx<float>* A = ctx->ws.as<cx<float>>();
+  cx<float>* Hh = A + batch * pA;
+  cx<float>* T = Hh + batch * pH;
+  RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
+  ColCfg c2 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
+  ColCfg c3 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
+  ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+  ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", false));
+  ECC_TRY(check_cfg_col(c3, *g.Ty, sizeof(cx<float>), "column", false));
+  ECC_HIP(launch_rows_r2c(st, r1, batch, H, planeH, ldH, A, pA, W, ny, nx, W, g.Tx->desc, g.Tx->f()));
+  ECC_HIP(launch_cols_fwd(st, c2, batch, A, pA, W, ny, W, Hh, pH, W, g.Ty->desc, g.Ty->f()));
+  const int nblk = (W + (1 << c3.lgB) - 1) >> c3.lgB;
+  int kchunk = std::max(1, (U * nblk * batch) / 1024);
+  kchunk = std::min(kchunk, U);
+  const float* par = plan->symmetric ? plan->d_parity.as<float>() : nullptr;
+  ECC_HIP(launch_corr_cols(st, c3, batch, kchunk, Hh, pH, W, g.sp->buf.as<cx<float>>(),
+                           (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi, Px,
+                           ny, Px, W, U, conj_mode, g.Ty->desc, g.Ty->f()));
+  *T_out = T;
+  *planeTk = pTk;
+  *planeTimg = pTi;
+  return ECC_OK;
+}
+
+// Convolution-type output: C = IFFT_y(sum_k w_k FFT_y(B_k) Fh_k) from the row stack B.
+ecc_status conv_stack_rows(ecc_filter_plan plan, const Geometry& g, int batch, const float* H,
+                           long long planeH, int ldH, const Field& fld, int sig_norm, int nsig,
+                           cx<float>* Bk, hipStream_t st) {
+  const int ny = g.ny, nx = g.nx, Px = g.Px, U = plan->U;
+  const long long pBk = (long long)ny * Px, pBs = pBk * U, pBi = pBs * nsig;
+  RowCfg r1 = row_config(*g.Tx, nx, sizeof(cx<float>));
+  ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+  ECC_HIP(launch_conv_rows_fwd(st, r1, batch, H, planeH, ldH, fld, sig_norm, nsig, Bk, pBk, pBs, pBi,
+                               Px, ny, nx, U, g.Tx->desc, g.Tx->f()));
+  return ECC_OK;
+}
+
+ecc_status conv_finish(ecc_filter_plan plan, const Geometry& g, int batch, const cx<float>* Bk, int nsig,
+                       cx<float>* C, float* y, long long planeY, int ldY, hipStream_t st) {
+  const int ny = g.ny, nx = g.nx, Py = g.Py, Px = g.Px, U = plan->U;
+  const long long pBk = (long long)ny * Px, pBs = pBk * U, pBi = pBs * nsig;
+  const long long pCs = (long long)ny * Px, pCi = pCs * nsig;
+  ColCfg c2 = col_config(*g.Ty, 2, sizeof(cx<float>), 512);
+  RowCfg r3 = row_config(*g.Tx, nx, sizeof(cx<float>));
+  ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", true));
+  ECC_TRY(check_cfg_row(r3, *g.Tx, sizeof(cx<float>), "row"));
+  const float* par = plan->symmetric ? plan->d_parity.as<float>() : nullptr;
+  ECC_HIP(launch_conv_cols(st, c2, batch, Bk, pBk, pBs, pBi, Px, g.sp->buf.as<cx<float>>(),
+                           (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par,
+                           plan->d_weights.as<float>(), C, pCs, pCi, Px, ny, Py, Px, g.W, U, nsig,
+                           g.Ty->desc, g.Ty->f()));
+  ECC_HIP(launch_conv_rows_inv(st, r3, batch, C, pCs, pCi, Px, y, planeY, ldY, ny, nx, nsig,
+                               1.0f / ((float)Py * (float)Px), g.Tx->desc, g.Tx->f()));
+  return ECC_OK;
+}
+
+Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, double mul_sign) {
+  Field fl;
+  fl.ptr = f;
+  fl.plane = plane;
+  fl.ld = ld;
+  fl.log_mode = plan->log_mode;
+  fl.mul = plan->field_mul * mul_sign;
+  fl.add = 0.0;
+  return fl;
+}
+
+ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
+                        const float* signal, int ld_signal, const float* field, int ld_field,
+                        float* out, int ld_out, hipStream_t st, void* saved) {
+  Geometry g{};
+  ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+  const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
+  if (op == ECC_CORRELATION) {
+    cx<float>* T;
+    long long pTk, pTi;
+    ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pS, ld_signal, 0, st, &T, &pTk, &pTi));
+    RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>));
+    ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
+    Field fl = make_field(plan, field, pF, ld_field, 1.0);
+    ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, g.Px, fl, out, pO, ld_out, ny, nx, plan->U,
+                             plan->d_weights.as<float>(), 1.0f / ((float)g.Py * (float)g.Px), nullptr,
+                             nullptr, 0, 0, 0.f, g.Tx->desc, g.Tx->f()));
+    return ECC_OK;
+  }
+  const long long pB = (long long)batch * plan->U * ny * g.Px;
+  const long long pC = (long long)batch * ny * g.Px;
+  const size_t need = (size_t)((saved ? 0 : pB) + pC) * sizeof(cx<float>);
+  ECC_HIP(ctx->ws.ensure(need));
+  cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : ctx->ws.as<cx<float>>();
+  cx<float>* C = saved ? ctx->ws.as<cx<float>>() : ctx->ws.as<cx<float>>() + pB;
+  Field fl = make_field(plan, field, pF, ld_field, 1.0);
+  ECC_TRY(conv_stack_rows(plan, g, batch, signal, pS, ld_signal, fl, 0, 1, Bk, st));
+  ECC_TRY(conv_finish(plan, g, batch, Bk, 1, C, out, pO, ld_out, st));
+  return ECC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecc_status ecc_extended(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
+                        const float* signal, int ld_signal, const float* field, int ld_field,
+                        float* out, int ld_out, ecc_precision prec, void* stream) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_REQ(signal && field && out, "NULL image pointer");
+  ECC_REQ(op == ECC_CORRELATION || op == ECC_CONVOLUTION, "unknown op");
+  if (prec != ECC_PREC_FP32)
+    return fail(ECC_ERR_UNSUPPORTED, "only ECC_PREC_FP32 is implemented for ecc_extended");
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  ECC_REQ(ld_signal >= nx && ld_field >= nx && ld_out >= nx, "row strides must be >= nx");
+  const size_t bo = (size_t)batch * ny * ld_out * sizeof(float);
+  ECC_REQ(!overlaps(out, bo, signal, (size_t)batch * ny * ld_signal * sizeof(float)) &&
+              !overlaps(out, bo, field, (size_t)batch * ny * ld_field * sizeof(float)),
+          "out aliases an input");
+  DeviceGuard dg(ctx->device);
+  return forward_impl(ctx, op, plan, batch, ny, nx, signal, ld_signal, field, ld_field, out, ld_out,
+                      S(stream), nullptr);
+}
+
+ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, const float* signal,
+                            int ld_signal, const float* scale_, int ld_scale, float* out, int ld_out,
+                            ecc_precision prec, void* stream) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_REQ(plan->group == ECC_GROUP_SCALE, "ecc_scale_smooth needs a scale plan");
+  ECC_REQ(signal && scale_ && out, "NULL image pointer");
+  if (prec != ECC_PREC_FP32) return fail(ECC_ERR_UNSUPPORTED, "precision not implemented");
+  ECC_TRY(validate_images(plan, 1, ny, nx));
+  ECC_REQ(ld_signal >= nx && ld_scale >= nx && ld_out >= nx, "row strides must be >= nx");
+  const size_t bo = (size_t)ny * ld_out * sizeof(float);
+  ECC_REQ(!overlaps(out, bo, signal, (size_t)ny * ld_signal * sizeof(float)) &&
+              !overlaps(out, bo, scale_, (size_t)ny * ld_scale * sizeof(float)),
+          "out aliases an input");
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  Geometry g{};
+  ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+  const long long pB = 2LL * plan->U * ny * g.Px, pC = 2LL * ny * g.Px;
+  ECC_HIP(ctx->ws.ensure((size_t)(pB + pC) * sizeof(cx<float>)));
+  cx<float>* Bk = ctx->ws.as<cx<float>>();
+  cx<float>* C = Bk + pB;
+  Field fl = make_field(plan, scale_, 0, ld_scale, 1.0);
+  ECC_TRY(conv_stack_rows(plan, g, 1, signal, 0, ld_signal, fl, 1, 2, Bk, st));
+  ECC_TRY(conv_finish(plan, g, 1, Bk, 2, C, out, 0, ld_out, st));
+  return ECC_OK;
+}
+
+ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, const float* signal,
+                               int ld, int n_angles, float* best_score, int* best_index, int ld_out,
+                               ecc_precision prec, void* stream) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_REQ(plan->group == ECC_GROUP_ROTATION, "matching needs a rotation plan");
+  ECC_REQ(signal && best_score && best_index, "NULL pointer");
+  if (prec != ECC_PREC_FP32) return fail(ECC_ERR_UNSUPPORTED, "precision not implemented");
+  ECC_TRY(validate_images(plan, 1, ny, nx));
+  ECC_REQ(ld >= nx && ld_out >= nx, "row strides must be >= nx");
+  ECC_REQ(n_angles >= 2 * plan->K + 1 && n_angles <= 64, "need 2K+1 <= n_angles <= 64");
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  if (ctx->angle_tab_n != n_angles) {
+    std::vector<float> tab(128, 0.f);
+    for (int t = 0; t < n_angles; ++t) {
+      const long double a = 2.0L * 3.14159265358979323846264338327950288L * t / n_angles;
+      tab[t] = (float)cosl(a);
+      tab[64 + t] = (float)sinl(a);
+    }
+    ECC_HIP(ctx->angle_tab.ensure(128 * sizeof(float)));
+    ECC_HIP(hipMemcpy(ctx->angle_tab.p, tab.data(), 128 * sizeof(float), hipMemcpyHostToDevice));
+    ctx->angle_tab_n = n_angles;
+  }
+  Geometry g{};
+  ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+  cx<float>* T;
+  long long pTk, pTi;
+  ECC_TRY(corr_stack(ctx, plan, g, 1, signal, 0, ld, 0, st, &T, &pTk, &pTi));
+  RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>), 512);
+  r4.B = 1;
+  if (r4.EPX > 2) return fail(ECC_ERR_UNSUPPORTED, "image too wide for the matching kernel");
+  if (lds_rows(r4, g.Tx->desc, sizeof(cx<float>)) + 64 * sizeof(cx<float>) > kMaxLds) return fail(ECC_ERR_UNSUPPORTED, "matching row transform too long");
+  ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "matching row"));
+  ECC_HIP(launch_match_rows(st, r4, T, pTk, g.Px, best_score, best_index, ld_out, ny, nx, plan->U,
+                            plan->d_weights.as<float>(), 1.0f / ((float)g.Py * (float)g.Px), n_angles,
+                            ctx->angle_tab.as<float>(), g.Tx->desc, g.Tx->f()));
+  return ECC_OK;
+}
+
+ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                                   size_t* bytes) {
+  ECC_REQ(ctx && plan && bytes, "NULL argument");
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  const int Px = fft_size_for(ctx, nx, plan->R);
+  *bytes = (size_t)batch * plan->U * ny * Px * sizeof(cx<float>);
+  return ECC_OK;
+}
+
+ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                             const float* signal, const float* field, float* out, void* saved,
+                             void* stream) {
+  ECC_REQ(ctx && plan && signal && field && out && saved, "NULL argument");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  DeviceGuard dg(ctx->device);
+  return forward_impl(ctx, ECC_CONVOLUTION, plan, batch, ny, nx, signal, nx, field, nx, out, nx,
+                      S(stream), saved);
+}
+
+ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny,
+                                 int nx, const float* signal, const float* field,
+                                 const float* grad_out, float* grad_signal, float* grad_comps,
+                                 float* grad_field, void* saved, void* stream) {
+  ECC_REQ(ctx && plan && signal && field && grad_out, "NULL argument");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  if (op != ECC_CONVOLUTION) return fail(ECC_ERR_UNSUPPORTED, "only the convolution adjoint is implemented");
+  ECC_REQ(plan->group == ECC_GROUP_ROTATION, "the adjoint needs a rotation plan");
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  Geometry g{};
+  ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+  const int Py = g.Py, Px = g.Px, W = g.W, U = plan->U, Sz = plan->S, R = plan->R;
+  const long long pI = (long long)ny * nx;
+  const float scl = 1.0f / ((float)Py * (float)Px);
+  // grad_signal and grad_field: A_k = IFFT(Gh(w) Fh_k(-w)) combined with e^{-ik theta}
+  if (grad_signal || grad_field) {
+    cx<float>* T;
+    long long pTk, pTi;
+    ECC_TRY(corr_stack(ctx, plan, g, batch, grad_out, pI, nx, 2, st, &T, &pTk, &pTi));
+    RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>));
+    ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
+    Field fl = make_field(plan, field, pI, nx, -1.0);
+    DevBuf tmp;
+    float* gs = grad_signal;
+    if (!gs) {
+      ECC_HIP(tmp.ensure((size_t)batch * pI * sizeof(float)));
+      gs = tmp.as<float>();
+    }
+    ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, Px, fl, gs, pI, nx, ny, nx, U,
+                             plan->d_weights.as<float>(), scl, grad_field, signal, pI, nx, 1.0f,
+                             g.Tx->desc, g.Tx->f()));
+    if (tmp.p) ECC_HIP(hipStreamSynchronize(st));
+  }
+  if (grad_comps) {
+    // stack B_k (saved or recomputed), Gh full spectra of grad_out, D_k, small inverse
+    const long long pBk = (long long)ny * Px, pBi = pBk * U;
+    const long long pA = (long long)ny * W, pG = (long long)Py * W;
+    const long long pD = (long long)Py * Px;
+    size_t need = (size_t)(batch * (pA + pG) + U * pD + (long long)U * Sz * Px + (long long)U * Sz * Sz) * sizeof(cx<float>);
+    if (!saved) need += (size_t)batch * pBi * sizeof(cx<float>);
+    ECC_HIP(ctx->ws.ensure(need));
+    cx<float>* A = ctx->ws.as<cx<float>>();
+    cx<float>* Gh = A + batch * pA;
+    cx<float>* D = Gh + batch * pG;
+    cx<float>* Ts = D + U * pD;
+    cx<float>* win = Ts + (long long)U * Sz * Px;
+    cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : win + (long long)U * Sz * Sz;
+    if (!saved) {
+      Field fl = make_field(plan, field, pI, nx, 1.0);
+      ECC_TRY(conv_stack_rows(plan, g, batch, signal, pI, nx, fl, 0, 1, Bk, st));
+    }
+    RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
+    ColCfg c2 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
+    ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+    ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", false));
+    ECC_HIP(launch_rows_r2c(st, r1, batch, grad_out, pI, nx, A, pA, W, ny, nx, W, g.Tx->desc, g.Tx->f()));
+    ECC_HIP(launch_cols_fwd(st, c2, batch, A, pA, W, ny, W, Gh, pG, W, g.Ty->desc, g.Ty->f()));
+    ColCfg c3 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
+    ECC_TRY(check_cfg_col(c3, *g.Ty, sizeof(cx<float>), "column", false));
+    ECC_HIP(launch_grad_filter_cols(st, c3, batch, Bk, pBk, pBi, Px, Gh, pG, W, D, pD, Px, ny, Py, Px, U,
+                                    g.Ty->desc, g.Ty->f()));
+    ColCfg c4 = col_config(*g.Ty, 3, sizeof(cx<float>), 256);
+    RowCfg r5 = row_config(*g.Tx, Px, sizeof(cx<float>));
+    ECC_TRY(check_cfg_col(c4, *g.Ty, sizeof(cx<float>), "column", false));
+    ECC_TRY(check_cfg_row(r5, *g.Tx, sizeof(cx<float>), "row"));
+    ECC_HIP((launch_fft_cols<float>(st, c4, U, +1, D, pD, Px, Px, Py, 0, Ts, (long long)Sz * Px, Px, Sz,
+                                    -R, g.Ty->desc, g.Ty->f())));
+    ECC_HIP((launch_fft_rows<float>(st, r5, U, +1, Ts, (long long)Sz * Px, Px, Sz, Px, 0, win,
+                                    (long long)Sz * Sz, Sz, Sz, -R, g.Tx->desc, g.Tx->f())));
+    ECC_HIP(launch_grad_filter_finish(st, win, (long long)Sz * Sz, Sz, plan->d_weights.as<float>(), scl,
+                                      reinterpret_cast<cx<float>*>(grad_comps), Sz, U));
+  }
+  return ECC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_device.hpp"
+
+namespace ecc {
+
+// Transform-set geometry chosen on the host for one kernel launch.
+struct RowCfg {   // blocked layout: B transforms (rows) per workgroup, TF threads each
+  int B, TF, NB, EPX;
+};
+struct ColCfg {   // interleaved layout: B = 2^lgB adjacent columns per workgroup
+  int lgB, nthr, NB, EPT;
+};
+
+struct Field {    // per-pixel angle alpha(q) = mul * g(field(q)) + add, g = id or ln
+  const float* ptr;
+  long long plane;
+  int ld;
+  int log_mode;
+  double mul, add;
+};
+
+// ---- correlation path
+hipError_t launch_rows_r2c(hipStream_t s, const RowCfg& c, int batch, const float* H, long long planeH,
+                           int ldH, cx<float>* A, long long planeA, int ldA, int ny, int nx, int W,
+                           const FftDesc& d, const cx<float>* tw);
+hipError_t launch_cols_fwd(hipStream_t s, const ColCfg& c, int batch, const cx<float>* A,
+                           long long planeA, int ldA, int nyValid, int ncols, cx<float>* out,
+                           long long planeOut, int ldOut, const FftDesc& d, const cx<float>* tw);
+hipError_t launch_corr_cols(hipStream_t s, const ColCfg& c, int batch, int kchunk,
+                            const cx<float>* Hh, long long planeHh, int ldHh, const cx<float>* Fh,
+                            long long planeFk, int ldF, int fullplane, const float* parity,
+                            cx<float>* T, long long planeTk, long long planeTimg, int ldT, int ny,
+                            int Px, int W, int U, int conj_mode, const FftDesc& d,
+                            const cx<float>* tw);
+hipError_t launch_corr_rows(hipStream_t s, const RowCfg& c, int batch, const cx<float>* T,
+                            long long planeTk, long long planeTimg, int ldT, const Field& fld,
+                            float* y, long long planeY, int ldY, int ny, int nx, int U,
+                            const float* w, float scale, float* y2, const float* mulsig,
+                            long long planeMul, int ldMul, float y2scale, const FftDesc& d,
+                            const cx<float>* tw);
+hipError_t launch_match_rows(hipStream_t s, const RowCfg& c, const cx<float>* T, long long planeTk,
+                             int ldT, float* score, int* index, int ldOut, int ny, int nx, int U,
+                             const float* w, float scale, int n_angles, const float* angle_tab,
+                             const FftDesc& d, const cx<float>* tw);
+
+// ---- convolution path
+hipError_t launch_conv_rows_fwd(hipStream_t s, const RowCfg& c, int batch, const float* H,
+                                long long planeH, int ldH, const Field& fld, int sig_norm,
+                                int nsig, cx<float>* Bk, long long planeBk, long long planeBsig,
+                                long long planeBimg, int ldB, int ny, int nx, int U,
+                                const FftDesc& d, const cx<float>* tw);
+hipError_t launch_conv_cols(hipStream_t s, const ColCfg& c, int batch, const cx<float>* Bk,
+                            long long planeBk, long long planeBsig, long long planeBimg, int ldB,
+                            const cx<float>* Fh, long long planeFk, int ldF, int fullplane,
+                            const float* parity, const float* w, cx<float>* C, long long planeCsig,
+                            long long planeCimg, int ldC, int ny, int Py, int Px, int W, int U,
+                            int nsig, const FftDesc& d, const cx<float>* tw);
+hipError_t launch_conv_rows_inv(hipStream_t s, const RowCfg& c, int batch, const cx<float>* C,
+                                long long planeCsig, long long planeCimg, int ldC, float* y,
+                                long long planeY, int ldY, int ny, int nx, int nsig, float scale,
+                                const FftDesc& d, const cx<float>* tw);
+
+// ---- generic complex transforms (float or double), used by plans and the adjoint
+template <typename T>
+hipError_t launch_fft_rows(hipStream_t s, const RowCfg& c, int nplanes, int dir, const cx<T>* in,
+                           long long planeIn, int ldIn, int nrows, int nvalid, int shift_in,
+                           cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
+                           const FftDesc& d, const cx<T>* tw);
+template <typename T>
+hipError_t launch_fft_cols(hipStream_t s, const ColCfg& c, int nplanes, int dir, const cx<T>* in,
+                           long long planeIn, int ldIn, int ncols, int nvalid, int shift_in,
+                           cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
+                           const FftDesc& d, const cx<T>* tw);
+
+// ---- filter plans (float64)
+hipError_t launch_polar_dft(hipStream_t s, const float* F, int S, int K, int M, const int* d2list,
+                            int nrad, cx<double>* fk);
+hipError_t launch_synth_rotation(hipStream_t s, const float* F, int S, int K, const int* rmap,
+                                 const cx<double>* fk, cx<double>* comps);
+hipError_t launch_scale_components(hipStream_t s, double sigma0, double u_lo, double u_hi,
+                                   double L, int n, int R, cx<double>* comps);
+hipError_t launch_d2f(hipStream_t s, const cx<double>* in, cx<float>* out, long long n);
+hipError_t launch_f2d(hipStream_t s, const cx<float>* in, cx<double>* out, long long n);
+
+// ---- adjoint helpers
+hipError_t launch_grad_filter_cols(hipStream_t s, const ColCfg& c, int batch,
+                                   const cx<float>* Bk, long long planeBk, long long planeBimg,
+                                   int ldB, const cx<float>* Gh, long long planeGimg, int ldG,
+                                   cx<float>* D, long long planeDk, int ldD, int ny, int Py, int Px,
+                                   int U, const FftDesc& d, const cx<float>* tw);
+hipError_t launch_grad_filter_finish(hipStream_t s, const cx<float>* win, long long planeWin,
+                                     int ldWin, const float* w, float scale, cx<float>* out, int S,
+                                     int U);
+
+// LDS needed for a launch, in bytes (twiddles + transform buffers).
+size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);
+size_t lds_cols(const ColCfg& c, const FftDesc& d, size_t elem);
+hipError_t prepare_kernels();   // raises per-kernel dynamic LDS limits once
+
+}  // namespace ecc
