@@ -92,6 +92,16 @@ ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
 /* Enables (1) or disables (0) timing-based choice of FFT sizes on first use of a shape. */
 ecc_status ecc_set_autotune(ecc_context ctx, int enable);
 
+/* Measurement hook: while set, every forward call (ecc_extended, ecc_scale_smooth,
+ * ecc_match_rotations) records events[0] on its stream before its first kernel and
+ * events[i + 1] after its i-th kernel, for i + 1 < n. `events` holds n hipEvent_t
+ * handles created by the caller and must stay valid while set; n = 0 or NULL clears
+ * the hook. Kernel order: correlation = row FFT, column FFT, component column
+ * transforms, row transforms + combination; convolution = modulated row FFTs, column
+ * transforms + component sum, row transforms; matching as correlation with the angle
+ * search in the last kernel. */
+ecc_status ecc_set_stage_events(ecc_context ctx, void* const* events, int n);
+
 /* ---------------------------------------------------------------- filter plans */
 
 /* Rotation (Sec. 4.1, "Filter Decomposition"): `filter` is a device S x S float32 array

@@ -42,6 +42,7 @@ PROTOS = {
     "ecc_destroy": [_P],
     "ecc_fft_size": [_P, _I, _I, C.POINTER(_I)],
     "ecc_set_autotune": [_P, _I],
+    "ecc_set_stage_events": [_P, C.POINTER(_P), _I],
     "ecc_filter_plan_create": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_from_components": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_get_components": [_P, _P, _P],

@@ -2,6 +2,7 @@
 // correlation / convolution / matching / smoothing / adjoint paths.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -64,6 +65,22 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// complex row pitch rounded up to 16 elements (128 bytes)
+inline int pitch16(int n) { return (n + 15) & ~15; }
+
+// Launch-shape overrides for tuning experiments (environment, read once per process).
+int tune_int(const char* name, int dflt) {
+  static std::mutex mu;
+  static std::map<std::string, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(name);
+  if (it != cache.end()) return it->second;
+  const char* v = std::getenv(name);
+  const int r = (v && *v) ? std::atoi(v) : dflt;
+  cache[name] = r;
+  return r;
+}
+
 ecc_status check_cfg_row(const RowCfg& c, const Transform& t, size_t elem, const char* what) {
   if (c.NB < 0 || c.EPX < 0 || lds_rows(c, t.desc, elem) > kMaxLds)
     return fail(ECC_ERR_UNSUPPORTED, std::string("transform too long for the ") + what + " kernel");
@@ -79,6 +96,13 @@ ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const
     ecc_status s_ = (expr);           \
     if (s_ != ECC_OK) return s_;      \
   } while (0)
+
+// records stage event i of the measurement hook, if set
+inline hipError_t mark_event(ecc_context ctx, int i, hipStream_t st) {
+  if (i < (int)ctx->stage_events.size()) return hipEventRecord(ctx->stage_events[i], st);
+  return hipSuccess;
+}
+#define mark(ctx, i, st) ECC_HIP(mark_event(ctx, i, st))
 
 // Filter spectra Fh_k = FFT2(F_k placed with its centre at (0, 0)) on a Py x Px grid,
 // computed in float64 and rounded to float32. Symmetric plans keep columns [0, W).
@@ -99,23 +123,25 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
   sp->full = plan->symmetric ? 0 : 1;
   const int W = Px / 2 + 1;
   const int Wst = sp->full ? Px : W;
-  sp->ld = Wst;
+  const int ld = pitch16(Wst);   // rows start on 128-byte boundaries
+  sp->ld = ld;
   const int U = plan->U, Sz = plan->S, R = plan->R;
   DevBuf tmp, spec64;
-  ECC_HIP(tmp.ensure((size_t)U * Sz * Wst * sizeof(cx<double>)));
-  ECC_HIP(spec64.ensure((size_t)U * Py * Wst * sizeof(cx<double>)));
-  ECC_HIP(sp->buf.ensure((size_t)U * Py * Wst * sizeof(cx<float>)));
+  ECC_HIP(tmp.ensure((size_t)U * Sz * ld * sizeof(cx<double>)));
+  ECC_HIP(spec64.ensure((size_t)U * Py * ld * sizeof(cx<double>)));
+  ECC_HIP(sp->buf.ensure((size_t)U * Py * ld * sizeof(cx<float>)));
+  ECC_HIP(hipMemsetAsync(spec64.p, 0, (size_t)U * Py * ld * sizeof(cx<double>), st));
   RowCfg rc = row_config(*Tx, Px, sizeof(cx<double>));
   ColCfg cc = col_config(*Ty, 2, sizeof(cx<double>), 256);
   ECC_TRY(check_cfg_row(rc, *Tx, sizeof(cx<double>), "filter row"));
   ECC_TRY(check_cfg_col(cc, *Ty, sizeof(cx<double>), "filter column", false));
   ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
-                                   Sz, Sz, -R, tmp.as<cx<double>>(), (long long)Sz * Wst, Wst, Wst, 0,
+                                   Sz, Sz, -R, tmp.as<cx<double>>(), (long long)Sz * ld, ld, Wst, 0,
                                    Tx->desc, Tx->d())));
-  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * Wst, Wst, Wst,
-                                   Sz, -R, spec64.as<cx<double>>(), (long long)Py * Wst, Wst, Py, 0,
+  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * ld, ld, Wst,
+                                   Sz, -R, spec64.as<cx<double>>(), (long long)Py * ld, ld, Py, 0,
                                    Ty->desc, Ty->d())));
-  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * Py * Wst));
+  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * Py * ld));
   ECC_HIP(hipStreamSynchronize(st));   // temporaries are freed on return
   *out = sp.get();
   plan->spectra[key] = std::move(sp);
@@ -222,6 +248,15 @@ ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P) {
   ECC_REQ(ctx && P, "NULL argument");
   ECC_REQ(n >= 1 && R >= 0 && n + R <= 16384, "size out of range");
   *P = fft_size_for(ctx, n, R);
+  return ECC_OK;
+}
+
+ecc_status ecc_set_stage_events(ecc_context ctx, void* const* events, int n) {
+  ECC_REQ(ctx, "NULL context");
+  ECC_REQ(n >= 0 && n <= 64, "n must be in [0, 64]");
+  ctx->stage_events.clear();
+  if (events && n > 0)
+    for (int i = 0; i < n; ++i) ctx->stage_events.push_back(static_cast<hipEvent_t>(events[i]));
   return ECC_OK;
 }
 
@@ -407,32 +442,65 @@ ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx) {
 }
 
 // Correlation-type stack: T_k = IFFT_y(Hh . filter product) for k = 0..U-1.
+// Forward transform of the signal (once) and the component stack for components
+// [kb, kb + kn): T_k = IFFT_y(Hh . filter product). With fwd = false the signal spectrum
+// of the previous call is reused (same signal, next chunk of components).
 ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, int batch,
                       const float* H, long long planeH, int ldH, int conj_mode, hipStream_t st,
-                      cx<float>** T_out, long long* planeTk, long long* planeTimg) {
-  const int ny = g.ny, nx = g.nx, Py = g.Py, Px = g.Px, W = g.W, U = plan->U;
-  const long long pA = (long long)ny * W, pH = (long long)Py * W, pTk = (long long)ny * Px,
+                      cx<float>** T_out, long long* planeTk, long long* planeTimg, int kb = 0,
+                      int kn = -1, bool fwd = true) {
+  const int ny = g.ny, nx = g.nx, Py = g.Py, Px = g.Px, W = g.W;
+  if (kn < 0) kn = plan->U - kb;
+  const int U = kn;
+  const int ldW = pitch16(W);
+  const long long pA = (long long)ny * ldW, pH = (long long)Py * ldW, pTk = 2LL * ny * ldW,
                   pTi = pTk * U;
   const size_t need = ((size_t)batch * (pA + pH + pTi)) * sizeof(cx<float>);
-  ECC_HIP(ctx->ws.ensure(need));
+  if (fwd) ECC_HIP(ctx->ws.ensure(need));
+  else if (ctx->ws.n < need) return fail(ECC_ERR_INTERNAL, "component chunk larger than the first");
   cx<float>* A = ctx->ws.as<cx<float>>();
   cx<float>* Hh = A + batch * pA;
   cx<float>* T = Hh + batch * pH;
   RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
-  ColCfg c2 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
-  ColCfg c3 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);
+  ColCfg c2 = col_config(*g.Ty, 2, sizeof(cx<float>), 512);
+  ColCfg c3 = col_config(*g.Ty, tune_int("ECC_CORR_LGB", 2), sizeof(cx<float>),
+                         tune_int("ECC_CORR_NTHR", 1024));
+  {
+    // the component kernel supports NB <= 2 and at most 16 rows per thread
+    const int TF = c3.nthr >> c3.lgB;
+    if (c3.NB > 2 || (g.Py + TF - 1) / TF > 16) c3.NB = -1;
+  }
   ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
   ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", false));
-  ECC_TRY(check_cfg_col(c3, *g.Ty, sizeof(cx<float>), "column", false));
-  ECC_HIP(launch_rows_r2c(st, r1, batch, H, planeH, ldH, A, pA, W, ny, nx, W, g.Tx->desc, g.Tx->f()));
-  ECC_HIP(launch_cols_fwd(st, c2, batch, A, pA, W, ny, W, Hh, pH, W, g.Ty->desc, g.Ty->f()));
+  ECC_TRY(check_cfg_col(c3, *g.Ty, sizeof(cx<float>), "column", true));
+  if (fwd) {
+    mark(ctx, 0, st);
+    ECC_HIP(launch_rows_r2c(st, r1, batch, H, planeH, ldH, A, pA, ldW, ny, nx, W, g.Tx->desc, g.Tx->f()));
+    mark(ctx, 1, st);
+    ECC_HIP(launch_cols_fwd(st, c2, batch, A, pA, ldW, ny, W, Hh, pH, ldW, g.Ty->desc, g.Ty->f()));
+    mark(ctx, 2, st);
+  }
+  const cx<float>* Fspec = g.sp->buf.as<cx<float>>() + (long long)kb * Py * g.sp->ld;
   const int nblk = (W + (1 << c3.lgB) - 1) >> c3.lgB;
-  int kchunk = std::max(1, (U * nblk * batch) / 1024);
+  int kchunk = tune_int("ECC_CORR_KCHUNK", 0);
+  if (kchunk <= 0) kchunk = std::max(1, (U * nblk * batch + 2047) / 2048);
   kchunk = std::min(kchunk, U);
-  const float* par = plan->symmetric ? plan->d_parity.as<float>() : nullptr;
-  ECC_HIP(launch_corr_cols(st, c3, batch, kchunk, Hh, pH, W, g.sp->buf.as<cx<float>>(),
-                           (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi, Px,
-                           ny, Px, W, U, conj_mode, g.Ty->desc, g.Ty->f()));
+  const float* par = plan->symmetric ? plan->d_parity.as<float>() + kb : nullptr;
+  if (g.Ty->fR0 > 0 && tune_int("ECC_FIXED_COLS", 0)) {
+    const int Bc = tune_int("ECC_FCOLS_B", 8);
+    const int nxb = (W + Bc - 1) / Bc;
+    int kc = tune_int("ECC_FCOLS_KCHUNK", 0);
+    if (kc <= 0) kc = std::max(1, (U * nxb * batch + 511) / 512);
+    kc = std::min(kc, U);
+    ECC_HIP(launch_corr_cols_fixed(st, Bc, batch, kc, Hh, pH, ldW, Fspec,
+                                   (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi,
+                                   ldW, ny, Px, W, U, conj_mode, Py, g.Ty->fx()));
+  } else {
+    ECC_HIP(launch_corr_cols(st, c3, batch, kchunk, Hh, pH, ldW, Fspec,
+                             (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi, ldW,
+                             ny, Px, W, U, conj_mode, g.Ty->desc, g.Ty->f()));
+  }
+  if (fwd) mark(ctx, 3, st);
   *T_out = T;
   *planeTk = pTk;
   *planeTimg = pTi;
@@ -440,19 +508,21 @@ ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, 
 }
 
 // Convolution-type output: C = IFFT_y(sum_k w_k FFT_y(B_k) Fh_k) from the row stack B.
-ecc_status conv_stack_rows(ecc_filter_plan plan, const Geometry& g, int batch, const float* H,
+ecc_status conv_stack_rows(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, int batch, const float* H,
                            long long planeH, int ldH, const Field& fld, int sig_norm, int nsig,
                            cx<float>* Bk, hipStream_t st) {
   const int ny = g.ny, nx = g.nx, Px = g.Px, U = plan->U;
   const long long pBk = (long long)ny * Px, pBs = pBk * U, pBi = pBs * nsig;
   RowCfg r1 = row_config(*g.Tx, nx, sizeof(cx<float>));
   ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+  mark(ctx, 0, st);
   ECC_HIP(launch_conv_rows_fwd(st, r1, batch, H, planeH, ldH, fld, sig_norm, nsig, Bk, pBk, pBs, pBi,
                                Px, ny, nx, U, g.Tx->desc, g.Tx->f()));
+  mark(ctx, 1, st);
   return ECC_OK;
 }
 
-ecc_status conv_finish(ecc_filter_plan plan, const Geometry& g, int batch, const cx<float>* Bk, int nsig,
+ecc_status conv_finish(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, int batch, const cx<float>* Bk, int nsig,
                        cx<float>* C, float* y, long long planeY, int ldY, hipStream_t st) {
   const int ny = g.ny, nx = g.nx, Py = g.Py, Px = g.Px, U = plan->U;
   const long long pBk = (long long)ny * Px, pBs = pBk * U, pBi = pBs * nsig;
@@ -466,8 +536,34 @@ ecc_status conv_finish(ecc_filter_plan plan, const Geometry& g, int batch, const
                            (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par,
                            plan->d_weights.as<float>(), C, pCs, pCi, Px, ny, Py, Px, g.W, U, nsig,
                            g.Ty->desc, g.Ty->f()));
+  mark(ctx, 2, st);
   ECC_HIP(launch_conv_rows_inv(st, r3, batch, C, pCs, pCi, Px, y, planeY, ldY, ny, nx, nsig,
                                1.0f / ((float)Py * (float)Px), g.Tx->desc, g.Tx->f()));
+  mark(ctx, 3, st);
+  return ECC_OK;
+}
+
+// Row transforms + per-pixel combination of a correlation-type stack.
+ecc_status corr_rows(ecc_filter_plan plan, const Geometry& g, int batch, const cx<float>* T, long long pTk,
+                     long long pTi, const Field& fl, float* y, long long planeY, int ldY, float scl,
+                     float* y2, const float* mulsig, long long planeMul, int ldMul, hipStream_t st,
+                     int kb = 0, int kn = -1, int accum = 0) {
+  if (kn < 0) kn = plan->U - kb;
+  const int U = kn;
+  const float* wts = plan->d_weights.as<float>() + kb;
+  if (g.Tx->fR0 > 0 && tune_int("ECC_FIXED", 1)) {
+    const int NR = tune_int("ECC_FROWS_NR", 4);
+    ECC_HIP(launch_corr_rows_fixed(st, NR, batch, T, pTk, pTi, pitch16(g.W), fl, y, planeY, ldY, g.ny, g.nx, U,
+                                   wts, scl, y2, mulsig, planeMul, ldMul, 1.0f, kb, accum, g.Px,
+                                   g.Tx->fx()));
+    return ECC_OK;
+  }
+  RowCfg r4 = row_config(*g.Tx, g.nx, sizeof(cx<float>));
+  r4.B = 2;   // two component transforms per workgroup
+  ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
+  ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, pitch16(g.W), fl, y, planeY, ldY, g.ny, g.nx, U,
+                           wts, scl, y2, mulsig, planeMul, ldMul, 1.0f, kb, accum, g.Tx->desc,
+                           g.Tx->f()));
   return ECC_OK;
 }
 
@@ -489,15 +585,22 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
   if (op == ECC_CORRELATION) {
-    cx<float>* T;
-    long long pTk, pTi;
-    ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pS, ld_signal, 0, st, &T, &pTk, &pTi));
-    RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>));
-    ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
+    // components in chunks: the stack of one chunk is written and read back while it
+    // is still resident in the last-level cache
+    const int U = plan->U;
+    int nck = tune_int("ECC_KCHUNKS", 1);
+    nck = std::max(1, std::min(nck, U));
+    const int per = (U + nck - 1) / nck;
     Field fl = make_field(plan, field, pF, ld_field, 1.0);
-    ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, g.Px, fl, out, pO, ld_out, ny, nx, plan->U,
-                             plan->d_weights.as<float>(), 1.0f / ((float)g.Py * (float)g.Px), nullptr,
-                             nullptr, 0, 0, 0.f, g.Tx->desc, g.Tx->f()));
+    for (int kb = 0, j = 0; kb < U; kb += per, ++j) {
+      const int kn = std::min(per, U - kb);
+      cx<float>* T;
+      long long pTk, pTi;
+      ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pS, ld_signal, 0, st, &T, &pTk, &pTi, kb, kn, j == 0));
+      ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, out, pO, ld_out,
+                        1.0f / ((float)g.Py * (float)g.Px), nullptr, nullptr, 0, 0, st, kb, kn, j > 0));
+    }
+    mark(ctx, 4, st);
     return ECC_OK;
   }
   const long long pB = (long long)batch * plan->U * ny * g.Px;
@@ -507,8 +610,8 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : ctx->ws.as<cx<float>>();
   cx<float>* C = saved ? ctx->ws.as<cx<float>>() : ctx->ws.as<cx<float>>() + pB;
   Field fl = make_field(plan, field, pF, ld_field, 1.0);
-  ECC_TRY(conv_stack_rows(plan, g, batch, signal, pS, ld_signal, fl, 0, 1, Bk, st));
-  ECC_TRY(conv_finish(plan, g, batch, Bk, 1, C, out, pO, ld_out, st));
+  ECC_TRY(conv_stack_rows(ctx, plan, g, batch, signal, pS, ld_signal, fl, 0, 1, Bk, st));
+  ECC_TRY(conv_finish(ctx, plan, g, batch, Bk, 1, C, out, pO, ld_out, st));
   return ECC_OK;
 }
 
@@ -559,8 +662,8 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + pB;
   Field fl = make_field(plan, scale_, 0, ld_scale, 1.0);
-  ECC_TRY(conv_stack_rows(plan, g, 1, signal, 0, ld_signal, fl, 1, 2, Bk, st));
-  ECC_TRY(conv_finish(plan, g, 1, Bk, 2, C, out, 0, ld_out, st));
+  ECC_TRY(conv_stack_rows(ctx, plan, g, 1, signal, 0, ld_signal, fl, 1, 2, Bk, st));
+  ECC_TRY(conv_finish(ctx, plan, g, 1, Bk, 2, C, out, 0, ld_out, st));
   return ECC_OK;
 }
 
@@ -593,14 +696,24 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
   cx<float>* T;
   long long pTk, pTi;
   ECC_TRY(corr_stack(ctx, plan, g, 1, signal, 0, ld, 0, st, &T, &pTk, &pTi));
+  // one row per workgroup, up to 512 threads, at most 2 pixels per thread (each pixel
+  // keeps n_angles accumulators in registers)
   RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>), 512);
   r4.B = 1;
-  if (r4.EPX > 2) return fail(ECC_ERR_UNSUPPORTED, "image too wide for the matching kernel");
+  if ((nx + r4.TF - 1) / r4.TF > 2) {
+    r4.TF = 512;
+    const int nb = max_butterflies(*g.Tx);
+    r4.NB = nb <= 512 ? 1 : (nb <= 1024 ? 2 : (nb <= 2048 ? 4 : -1));
+    const int need = (nx + 511) / 512;
+    r4.EPX = need <= 1 ? 1 : (need <= 2 ? 2 : -1);
+  }
+  if (r4.EPX < 0 || r4.EPX > 2) return fail(ECC_ERR_UNSUPPORTED, "image too wide for the matching kernel");
   if (lds_rows(r4, g.Tx->desc, sizeof(cx<float>)) + 64 * sizeof(cx<float>) > kMaxLds) return fail(ECC_ERR_UNSUPPORTED, "matching row transform too long");
   ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "matching row"));
-  ECC_HIP(launch_match_rows(st, r4, T, pTk, g.Px, best_score, best_index, ld_out, ny, nx, plan->U,
+  ECC_HIP(launch_match_rows(st, r4, T, pTk, pitch16(g.W), best_score, best_index, ld_out, ny, nx, plan->U,
                             plan->d_weights.as<float>(), 1.0f / ((float)g.Py * (float)g.Px), n_angles,
                             ctx->angle_tab.as<float>(), g.Tx->desc, g.Tx->f()));
+  mark(ctx, 4, st);
   return ECC_OK;
 }
 
@@ -645,8 +758,6 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     cx<float>* T;
     long long pTk, pTi;
     ECC_TRY(corr_stack(ctx, plan, g, batch, grad_out, pI, nx, 2, st, &T, &pTk, &pTi));
-    RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>));
-    ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
     Field fl = make_field(plan, field, pI, nx, -1.0);
     DevBuf tmp;
     float* gs = grad_signal;
@@ -654,9 +765,7 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
       ECC_HIP(tmp.ensure((size_t)batch * pI * sizeof(float)));
       gs = tmp.as<float>();
     }
-    ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, Px, fl, gs, pI, nx, ny, nx, U,
-                             plan->d_weights.as<float>(), scl, grad_field, signal, pI, nx, 1.0f,
-                             g.Tx->desc, g.Tx->f()));
+    ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, gs, pI, nx, scl, grad_field, signal, pI, nx, st));
     if (tmp.p) ECC_HIP(hipStreamSynchronize(st));
   }
   if (grad_comps) {
@@ -675,7 +784,7 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : win + (long long)U * Sz * Sz;
     if (!saved) {
       Field fl = make_field(plan, field, pI, nx, 1.0);
-      ECC_TRY(conv_stack_rows(plan, g, batch, signal, pI, nx, fl, 0, 1, Bk, st));
+      ECC_TRY(conv_stack_rows(ctx, plan, g, batch, signal, pI, nx, fl, 0, 1, Bk, st));
     }
     RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
     ColCfg c2 = col_config(*g.Ty, 3, sizeof(cx<float>), 512);

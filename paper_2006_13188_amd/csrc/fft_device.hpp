@@ -1,4 +1,4 @@
-// Device-side FFT engine for gfx950: mixed-radix (2,3,4,5,6,7,8,9,10)
+// Device-side FFT engine for gfx950: mixed-radix (2,3,4,5,6,7,8)
 // Stockham autosort transforms staged through LDS, with register butterflies.
 //
 // One workgroup runs B transforms of length P at once. Two layouts are supported:
@@ -274,8 +274,6 @@ __device__ void run_fft(cx<T>* buf, const Layout& L, const FftDesc& d, const cx<
       case 6: stockham_pass<6, NB, DIR, ILV, T>(buf, L, d.P, Ls, m, t, c, f, TF, active); break;
       case 7: stockham_pass<7, NB, DIR, ILV, T>(buf, L, d.P, Ls, m, t, c, f, TF, active); break;
       case 8: stockham_pass<8, NB, DIR, ILV, T>(buf, L, d.P, Ls, m, t, c, f, TF, active); break;
-      case 9: stockham_pass<9, NB, DIR, ILV, T>(buf, L, d.P, Ls, m, t, c, f, TF, active); break;
-      case 10: stockham_pass<10, NB, DIR, ILV, T>(buf, L, d.P, Ls, m, t, c, f, TF, active); break;
       default: break;  // the host planner never emits other radices
     }
     Ls *= d.radix[p];

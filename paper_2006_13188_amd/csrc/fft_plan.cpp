@@ -29,8 +29,9 @@ int next_smooth7(int n) {
     if (is_smooth7(m)) return m;
 }
 
-// Fewest passes with radices in [2, 10]; ties go to the schedule with the largest
-// smallest radix (fewer butterflies per thread in the worst pass).
+// Fewest passes with radices in [2, 8] (the butterflies the LDS engine instantiates);
+// ties go to the schedule with the largest smallest radix (fewer butterflies per
+// thread in the worst pass).
 std::vector<int> choose_radices(int P) {
   std::vector<int> primes;
   if (!factor7(P, primes)) return {};
@@ -49,7 +50,7 @@ std::vector<int> choose_radices(int P) {
     }
     const int p = primes[i];
     for (size_t j = 0; j < groups.size(); ++j) {
-      if (groups[j] * p <= 10) {
+      if (groups[j] * p <= 8) {
         groups[j] *= p;
         dfs(i + 1);
         groups[j] /= p;
@@ -103,7 +104,35 @@ static hipError_t make_transform(int P, Transform& t) {
   if (e != hipSuccess) return e;
   e = hipMemcpy(t.tw32, tw32.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  return hipMemcpy(t.tw64, tw64.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+  e = hipMemcpy(t.tw64, tw64.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  int R0 = 0, R1 = 0, R2 = 0;
+  if (fixed_split(P, &R0, &R1, &R2)) {
+    // pass 1: rows j < R0 of w1^{r j}, w1 = exp(-2 pi i / (R0 R1)), 1 <= r < R1;
+    // pass 2: rows b < R0 R1 of w^{r b}, w = exp(-2 pi i / P), 1 <= r < R2
+    std::vector<float> fx;
+    auto put = [&](long long m, long long N) {
+      m %= N;
+      if (2 * m > N) m -= N;
+      const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
+      fx.push_back((float)cosl(a));
+      fx.push_back((float)sinl(a));
+    };
+    for (int j = 0; j < R0; ++j)
+      for (int r = 1; r < R1; ++r) put((long long)r * j, (long long)R0 * R1);
+    if (R2 > 1)
+      for (int b = 0; b < R0 * R1; ++b)
+        for (int r = 1; r < R2; ++r) put((long long)r * b, P);
+    if (fx.empty()) fx.assign(2, 0.f);
+    e = hipMalloc(&t.fx_tw32, fx.size() * sizeof(float));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(t.fx_tw32, fx.data(), fx.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    t.fR0 = R0;
+    t.fR1 = R1;
+    t.fR2 = R2;
+  }
+  return hipSuccess;
 }
 
 hipError_t get_transform(ecc_context_s* ctx, int P, const Transform** out) {
@@ -122,6 +151,7 @@ hipError_t get_transform(ecc_context_s* ctx, int P, const Transform** out) {
 }
 
 Transform::~Transform() {
+  if (fx_tw32) (void)hipFree(fx_tw32);
   if (tw32) (void)hipFree(tw32);
   if (tw64) (void)hipFree(tw64);
 }

@@ -20,9 +20,12 @@ struct Transform {
   std::vector<int> rad;
   void* tw32 = nullptr;   // cx<float>[twsize]
   void* tw64 = nullptr;   // cx<double>[twsize]
+  int fR0 = 0, fR1 = 0, fR2 = 0;   // compiled three-pass schedule (fR0 = 0 if none)
+  void* fx_tw32 = nullptr;         // its pass-1 and pass-2 twiddle tables
   ~Transform();
   const cx<float>* f() const { return static_cast<const cx<float>*>(tw32); }
   const cx<double>* d() const { return static_cast<const cx<double>*>(tw64); }
+  const cx<float>* fx() const { return static_cast<const cx<float>*>(fx_tw32); }
 };
 
 hipError_t get_transform(ecc_context_s* ctx, int P, const Transform** out);
@@ -71,6 +74,7 @@ struct ecc_context_s {
   int angle_tab_n = 0;
   int autotune = 0;
   std::map<std::string, int> tuned;   // shape key -> chosen FFT size
+  std::vector<hipEvent_t> stage_events;   // measurement hook (see ecc_set_stage_events)
 };
 
 struct Spectrum {

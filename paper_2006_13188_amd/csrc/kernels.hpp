@@ -40,8 +40,8 @@ hipError_t launch_corr_rows(hipStream_t s, const RowCfg& c, int batch, const cx<
                             long long planeTk, long long planeTimg, int ldT, const Field& fld,
                             float* y, long long planeY, int ldY, int ny, int nx, int U,
                             const float* w, float scale, float* y2, const float* mulsig,
-                            long long planeMul, int ldMul, float y2scale, const FftDesc& d,
-                            const cx<float>* tw);
+                            long long planeMul, int ldMul, float y2scale, int kofs, int accum,
+                            const FftDesc& d, const cx<float>* tw);
 hipError_t launch_match_rows(hipStream_t s, const RowCfg& c, const cx<float>* T, long long planeTk,
                              int ldT, float* score, int* index, int ldOut, int ny, int nx, int U,
                              const float* w, float scale, int n_angles, const float* angle_tab,
@@ -95,6 +95,20 @@ hipError_t launch_grad_filter_cols(hipStream_t s, const ColCfg& c, int batch,
 hipError_t launch_grad_filter_finish(hipStream_t s, const cx<float>* win, long long planeWin,
                                      int ldWin, const float* w, float scale, cx<float>* out, int S,
                                      int U);
+
+// ---- correlation kernels for transform lengths with a compiled schedule P = R0 R1 R2
+bool fixed_split(int P, int* R0, int* R1, int* R2);
+hipError_t launch_corr_cols_fixed(hipStream_t s, int Bc, int batch, int kchunk, const cx<float>* Hh,
+                                  long long planeHh, int ldHh, const cx<float>* Fh, long long planeFk,
+                                  int ldF, int fullplane, const float* parity, cx<float>* T,
+                                  long long planeTk, long long planeTimg, int ldT, int ny, int Px, int W,
+                                  int U, int conj_mode, int Py, const cx<float>* tw);
+hipError_t launch_corr_rows_fixed(hipStream_t s, int NR, int batch, const cx<float>* T, long long planeTk,
+                                  long long planeTimg, int ldT, const Field& fld, float* y,
+                                  long long planeY, int ldY, int ny, int nx, int U, const float* w,
+                                  float scale_, float* y2, const float* mulsig, long long planeMul,
+                                  int ldMul, float y2scale, int kofs, int accum, int Px,
+                                  const cx<float>* tw);
 
 // LDS needed for a launch, in bytes (twiddles + transform buffers).
 size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);
