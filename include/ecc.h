@@ -56,6 +56,19 @@ typedef enum {
   ECC_PREC_MFMA_BF16_HILO = 2
 } ecc_precision;
 
+/* How extended correlations are evaluated (both reach the same result up to rounding).
+ * TWO_PASS: the paper's form (Sec. 4): one zero-padded FFT correlation per component over
+ * the whole image, P >= n + R, with the per-pixel combination fused into the last
+ * inverse pass. TILED: overlap-save blocks: each T x T block of outputs is computed from
+ * an N x N window (N - 2R >= T) entirely on chip, per component, then combined per
+ * pixel (block shapes exist for R <= 56). AUTO compares the two with a cost model.
+ * Convolution, matching and the adjoint always use TWO_PASS. */
+typedef enum {
+  ECC_STRATEGY_AUTO = 0,
+  ECC_STRATEGY_TWO_PASS = 1,
+  ECC_STRATEGY_TILED = 2
+} ecc_strategy;
+
 typedef struct ecc_context_s* ecc_context;
 typedef struct ecc_filter_plan_s* ecc_filter_plan;
 
@@ -91,6 +104,14 @@ const char* ecc_last_error(void);
 ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
 /* Enables (1) or disables (0) timing-based choice of FFT sizes on first use of a shape. */
 ecc_status ecc_set_autotune(ecc_context ctx, int enable);
+/* Sets the evaluation strategy of later ecc_extended correlations on this context.
+ * TILED with a filter radius that has no block shape fails with UNSUPPORTED at the call. */
+ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy);
+/* Reports how ecc_extended(op, plan, ny x nx) would run on this context: the strategy,
+ * the transform length (TILED: N; TWO_PASS: the column-direction size P_y) and the block
+ * side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is enqueued. */
+ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx,
+                        ecc_strategy* strategy, int* fft_size, int* block);
 
 /* Measurement hook: while set, every forward call (ecc_extended, ecc_scale_smooth,
  * ecc_match_rotations) records events[0] on its stream before its first kernel and

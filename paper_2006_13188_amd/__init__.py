@@ -12,12 +12,13 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (CONVOLUTION, CORRELATION, GROUP_ROTATION, GROUP_SCALE, PREC_FP32,
-                   EccError, GroupParams)
+                   STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_TWO_PASS, EccError, GroupParams)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
+    "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED",
     "GroupParams",
 ]
 
@@ -83,6 +84,15 @@ class Context:
         P = C.c_int()
         _check(lib().ecc_fft_size(self.h, n, R, C.byref(P)))
         return P.value
+
+    def set_strategy(self, strategy: int):
+        _check(lib().ecc_set_strategy(self.h, strategy))
+
+    def describe(self, op: int, plan: "FilterPlan", ny: int, nx: int):
+        """(strategy, transform length, block side) that ecc_extended would use."""
+        s, n, b = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().ecc_describe(self.h, op, plan.h, ny, nx, C.byref(s), C.byref(n), C.byref(b)))
+        return s.value, n.value, b.value
 
 
 class FilterPlan:

@@ -13,6 +13,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory", 
 GROUP_ROTATION, GROUP_SCALE = 0, 1
 CORRELATION, CONVOLUTION = 0, 1
 PREC_FP32, PREC_MFMA_FP16_HILO, PREC_MFMA_BF16_HILO = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED = 0, 1, 2
 
 
 class GroupParams(C.Structure):
@@ -43,6 +44,8 @@ PROTOS = {
     "ecc_fft_size": [_P, _I, _I, C.POINTER(_I)],
     "ecc_set_autotune": [_P, _I],
     "ecc_set_stage_events": [_P, C.POINTER(_P), _I],
+    "ecc_set_strategy": [_P, _I],
+    "ecc_describe": [_P, _I, _P, _I, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
     "ecc_filter_plan_create": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_from_components": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_get_components": [_P, _P, _P],

@@ -148,6 +148,76 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
   return ECC_OK;
 }
 
+// Block spectra for the tiled path: FFT_N x N(F_k placed with its window corner at
+// (0, 0)), float64 then rounded, full N x N planes (no symmetry assumed).
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out) {
+  std::lock_guard<std::mutex> g(plan->mu);
+  auto it = plan->tile_spectra.find(N);
+  if (it != plan->tile_spectra.end()) {
+    *out = it->second.get();
+    return ECC_OK;
+  }
+  const Transform* Tn = nullptr;
+  ECC_HIP(get_transform(plan->ctx, N, &Tn));
+  auto sp = std::make_unique<Spectrum>();
+  sp->Py = sp->Px = sp->ld = N;
+  sp->full = 1;
+  const int U = plan->U, Sz = plan->S;
+  DevBuf tmp, spec64;
+  ECC_HIP(tmp.ensure((size_t)U * Sz * N * sizeof(cx<double>)));
+  ECC_HIP(spec64.ensure((size_t)U * N * N * sizeof(cx<double>)));
+  ECC_HIP(sp->buf.ensure((size_t)U * N * N * sizeof(cx<float>)));
+  RowCfg rc = row_config(*Tn, N, sizeof(cx<double>));
+  ColCfg cc = col_config(*Tn, 2, sizeof(cx<double>), 256);
+  ECC_TRY(check_cfg_row(rc, *Tn, sizeof(cx<double>), "filter row"));
+  ECC_TRY(check_cfg_col(cc, *Tn, sizeof(cx<double>), "filter column", false));
+  ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
+                                   Sz, Sz, 0, tmp.as<cx<double>>(), (long long)Sz * N, N, N, 0,
+                                   Tn->desc, Tn->d())));
+  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, 0,
+                                   spec64.as<cx<double>>(), (long long)N * N, N, N, 0, Tn->desc,
+                                   Tn->d())));
+  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * N * N));
+  ECC_HIP(hipStreamSynchronize(st));
+  *out = sp.get();
+  plan->tile_spectra[N] = std::move(sp);
+  return ECC_OK;
+}
+
+struct TileChoice {
+  int N = 0, TV = 0, T = 0;
+  double cost = 0;   // modelled work units (see pick_tile)
+};
+
+// Block shape for the tiled path with the smallest modelled time: per block and
+// component, N column and T row transforms of length N (~ N (N + T) log2 N), times the
+// number of rounds of resident workgroups (256 CUs, LDS-limited blocks per CU).
+bool pick_tile(int R, int ny, int nx, int batch, TileChoice& best) {
+  static const int cand[][2] = {{64, 64}, {96, 64}, {128, 64}, {128, 96}};
+  bool found = false;
+  for (auto& c : cand) {
+    const int N = c[0], TV = c[1];
+    if (!tile_supported(N, TV)) continue;
+    const int T = std::min(TV, N - 2 * R);
+    if (T < 16) continue;
+    const size_t lds = tile_lds_bytes(N, TV);
+    const int per_cu = std::max<int>(1, (int)(kMaxLds / lds));
+    const long long blocks = (long long)((ny + T - 1) / T) * ((nx + T - 1) / T) * batch;
+    const long long slots = 256LL * per_cu;
+    const long long rounds = (blocks + slots - 1) / slots;
+    const double per_block = (double)N * (N + T) * std::log2((double)N);
+    const double cost = (double)rounds * per_block * per_cu;
+    if (!found || cost < best.cost) {
+      best.N = N;
+      best.TV = TV;
+      best.T = T;
+      best.cost = cost;
+      found = true;
+    }
+  }
+  return found;
+}
+
 ecc_status finish_plan(ecc_filter_plan p, hipStream_t st) {
   const size_t n = (size_t)p->U * p->S * p->S;
   ECC_HIP(p->comps32.ensure(n * sizeof(cx<float>)));
@@ -263,6 +333,14 @@ ecc_status ecc_set_stage_events(ecc_context ctx, void* const* events, int n) {
 ecc_status ecc_set_autotune(ecc_context ctx, int enable) {
   ECC_REQ(ctx, "NULL context");
   ctx->autotune = enable ? 1 : 0;
+  return ECC_OK;
+}
+
+ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy) {
+  ECC_REQ(ctx, "NULL context");
+  ECC_REQ(strategy == ECC_STRATEGY_AUTO || strategy == ECC_STRATEGY_TWO_PASS || strategy == ECC_STRATEGY_TILED,
+          "unknown strategy");
+  ctx->strategy = strategy;
   return ECC_OK;
 }
 
@@ -578,12 +656,43 @@ Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, 
   return fl;
 }
 
+// Strategy of a forward call: TILED needs a block shape; AUTO takes it when the block
+// side is at least the filter diameter (halo re-reads at most ~4x of the block) and the
+// one-kernel form is otherwise the cheaper; everything else runs TWO_PASS.
+ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx, int batch,
+                            ecc_strategy* used, TileChoice* tc) {
+  *used = ECC_STRATEGY_TWO_PASS;
+  if (op != ECC_CORRELATION) return ECC_OK;
+  const bool ok = pick_tile(plan->R, ny, nx, batch, *tc);
+  if (ctx->strategy == ECC_STRATEGY_TILED) {
+    if (!ok) return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
+    *used = ECC_STRATEGY_TILED;
+  } else if (ctx->strategy == ECC_STRATEGY_AUTO && ok && tc->T >= std::max(16, 2 * plan->R)) {
+    *used = ECC_STRATEGY_TILED;
+  }
+  return ECC_OK;
+}
+
 ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
                         const float* signal, int ld_signal, const float* field, int ld_field,
                         float* out, int ld_out, hipStream_t st, void* saved) {
+  const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
+  ecc_strategy strat;
+  TileChoice tc;
+  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc));
+  if (strat == ECC_STRATEGY_TILED) {
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp));
+    Field fl = make_field(plan, field, pF, ld_field, 1.0);
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_corr(st, tc.N, tc.TV, batch, signal, pS, ld_signal, fl, out, pO, ld_out, ny, nx,
+                             plan->R, tc.T, plan->U, 0, plan->d_weights.as<float>(),
+                             1.0f / ((float)tc.N * (float)tc.N), sp->buf.as<cx<float>>()));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
-  const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
   if (op == ECC_CORRELATION) {
     // components in chunks: the stack of one chunk is written and read back while it
     // is still resident in the last-level cache
@@ -637,6 +746,20 @@ ecc_status ecc_extended(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   DeviceGuard dg(ctx->device);
   return forward_impl(ctx, op, plan, batch, ny, nx, signal, ld_signal, field, ld_field, out, ld_out,
                       S(stream), nullptr);
+}
+
+ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx,
+                        ecc_strategy* strategy, int* fft_size, int* block) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(op == ECC_CORRELATION || op == ECC_CONVOLUTION, "unknown op");
+  ECC_TRY(validate_images(plan, 1, ny, nx));
+  ecc_strategy used;
+  TileChoice tc;
+  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, 1, &used, &tc));
+  if (strategy) *strategy = used;
+  if (fft_size) *fft_size = used == ECC_STRATEGY_TILED ? tc.N : fft_size_for(ctx, ny, plan->R);
+  if (block) *block = used == ECC_STRATEGY_TILED ? tc.T : 0;
+  return ECC_OK;
 }
 
 ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, const float* signal,

@@ -73,6 +73,7 @@ struct ecc_context_s {
   ecc::DevBuf angle_tab;    // cos/sin tables for matching
   int angle_tab_n = 0;
   int autotune = 0;
+  ecc_strategy strategy = ECC_STRATEGY_AUTO;
   std::map<std::string, int> tuned;   // shape key -> chosen FFT size
   std::vector<hipEvent_t> stage_events;   // measurement hook (see ecc_set_stage_events)
 };
@@ -99,4 +100,5 @@ struct ecc_filter_plan_s {
   int sig_norm = 0;   // divide the signal by field^2 (scale group)
   std::mutex mu;
   std::map<std::pair<int, int>, std::unique_ptr<Spectrum>> spectra;
+  std::map<int, std::unique_ptr<Spectrum>> tile_spectra;   // N -> U planes of N x N
 };

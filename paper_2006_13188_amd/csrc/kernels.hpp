@@ -110,6 +110,15 @@ hipError_t launch_corr_rows_fixed(hipStream_t s, int NR, int batch, const cx<flo
                                   int ldMul, float y2scale, int kofs, int accum, int Px,
                                   const cx<float>* tw);
 
+// ---- tiled (overlap-save) correlation: one workgroup per T x T output block, N x N
+// transforms on chip (N = 64, 96, 128; TV = 64 or 96 bounds T)
+bool tile_supported(int N, int TV);
+size_t tile_lds_bytes(int N, int TV);
+hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
+                            int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
+                            int nx, int R, int T, int U, int kofs, const float* w, float scale,
+                            const cx<float>* Fs);
+
 // LDS needed for a launch, in bytes (twiddles + transform buffers).
 size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);
 size_t lds_cols(const ColCfg& c, const FftDesc& d, size_t elem);

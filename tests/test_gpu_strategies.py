@@ -1,0 +1,137 @@
+"""Both evaluation strategies of the extended correlation against the float64 oracle.
+
+TWO_PASS is the paper's whole-image FFT form; TILED evaluates overlap-save blocks on chip.
+Each runs on its own context with the strategy forced, on shapes that span several
+blocks with ragged edges, every supported block size (N = 64, 96, 128), the largest
+radius that still has a block, batches, and the full 1024 x 1024 workload.
+Tolerance as in test_gpu_rotation: rel-L2 and rel-inf <= 1e-5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import blurred_noise, random_filter, rotation_config, theta_field
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+TWO_PASS, TILED = 1, 2
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def relinf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    import paper_2006_13188_amd as E_
+    assert torch.cuda.is_available()
+    E_.lib()
+    return E_
+
+
+@pytest.fixture(scope="module", params=[TWO_PASS, TILED], ids=["two_pass", "tiled"])
+def sctx(E, request):
+    c = E.Context(0)
+    c.set_strategy(request.param)
+    yield c, request.param
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def oracle_corr(img, filt, theta, K):
+    comps, _ = O.angular_components(filt, K)
+    return O.ext_corr_half(img.astype(np.float64), theta.astype(np.float64), O.half_components(comps))
+
+
+@pytest.mark.parametrize("shape,S,K", [
+    ((128, 128), 15, 8),     # small workload: N = 64 blocks
+    ((67, 93), 9, 3),
+    ((200, 173), 21, 10),    # N = 96
+    ((33, 33), 31, 12),      # one block larger than the image
+    ((150, 211), 63, 16),    # R = 31: N = 128
+    ((97, 130), 81, 6),      # R = 40: N = 128, T = 48 (tiled only when forced)
+])
+def test_correlation_parity(E, sctx, shape, S, K):
+    ctx, strat = sctx
+    img = blurred_noise(shape, 5)
+    filt = random_filter(S, 6, 4.0 * S / 15)
+    theta = theta_field(shape, 7)
+    plan = E.FilterPlan.rotation(ctx, dev(filt), K)
+    used, n, blk = ctx.describe(0, plan, *shape)
+    assert used == strat
+    if strat == TILED:
+        assert n in (64, 96, 128) and 16 <= blk <= n - (S - 1)
+    y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K)
+    assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+
+
+def test_batch(E, sctx):
+    ctx, _ = sctx
+    imgs = np.stack([blurred_noise((150, 131), 60 + i) for i in range(3)])
+    ths = np.stack([theta_field((150, 131), 70 + i) for i in range(3)])
+    filt = random_filter(17, 9, 4.5)
+    plan = E.FilterPlan.rotation(ctx, dev(filt), 7)
+    yb = host(E.ecc_extended(ctx, 0, plan, dev(imgs), dev(ths)))
+    for i in range(3):
+        ref = oracle_corr(imgs[i], filt, ths[i], 7)
+        assert rel2(yb[i].astype(np.float64), ref) <= TOL
+
+
+def test_strided_rows(E, sctx):
+    """Leading dimensions larger than the width (views into wider buffers)."""
+    import torch
+    ctx, _ = sctx
+    img = blurred_noise((120, 100), 11)
+    th = theta_field((120, 100), 12)
+    filt = random_filter(13, 13, 3.5)
+    plan = E.FilterPlan.rotation(ctx, dev(filt), 6)
+    Hw = torch.zeros((120, 131), device="cuda")
+    Tw = torch.zeros((120, 117), device="cuda")
+    Ow = torch.full((120, 109), 5.0, device="cuda")
+    Hw[:, :100] = dev(img)
+    Tw[:, :100] = dev(th)
+    E.ecc_extended(ctx, 0, plan, Hw[:, :100], Tw[:, :100], out=Ow[:, :100])
+    y = host(Ow)
+    ref = oracle_corr(img, filt, th, 6)
+    assert rel2(y[:, :100].astype(np.float64), ref) <= TOL
+    assert np.all(y[:, 100:] == 5.0)   # nothing written past nx
+
+
+def test_full_size(E, sctx):
+    img, filt, theta, K = rotation_config(1024, 31, 16, seeds=(10, 11, 12))
+    ctx, _ = sctx
+    plan = E.FilterPlan.rotation(ctx, dev(filt), K)
+    y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K)
+    assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+
+
+def test_auto_choice_and_unsupported_radius(E):
+    ctx = E.Context(0)
+    try:
+        plan = E.FilterPlan.rotation(ctx, dev(random_filter(31, 1, 8.0)), 16)
+        assert ctx.describe(0, plan, 1024, 1024) == (TILED, 96, 64)
+        assert ctx.describe(1, plan, 1024, 1024)[0] == TWO_PASS   # convolution
+        big = E.FilterPlan.rotation(ctx, dev(random_filter(121, 2, 30.0)), 4)   # R = 60
+        assert ctx.describe(0, big, 300, 300)[0] == TWO_PASS
+        ctx.set_strategy(TILED)
+        img = dev(blurred_noise((300, 300), 3))
+        with pytest.raises(E.EccError):
+            E.ecc_extended(ctx, 0, big, img, img)
+    finally:
+        ctx.close()
