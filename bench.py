@@ -13,7 +13,7 @@ Prints one JSON line: metric, value in Mpix*comp/s, the roofline of the dominant
 measured with HIP events on the library's stream, and the float64 CPU oracle timed on
 a bounded sample of the same workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -288,6 +290,12 @@ def main():
     }
     plan.close()
     ctx.close()
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, device="cuda")   # 256 MiB of float32
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     print(json.dumps(rec), flush=True)
 
 

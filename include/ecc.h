@@ -91,8 +91,9 @@ typedef struct {
  * must not be used by two host threads at once. Errors: INVALID_ARGUMENT (bad device
  * or NULL out), HIP. */
 ecc_status ecc_create(int hip_device, ecc_context* out);
-/* Waits for the device, then frees everything the context owns (plans made from it
- * must be destroyed first). NULL is accepted. */
+/* Waits for the device, then frees everything the context owns, including filter plans
+ * made from it that are still alive (their handles must not be used afterwards). NULL
+ * is accepted. */
 ecc_status ecc_destroy(ecc_context ctx);
 const char* ecc_status_string(ecc_status s);
 /* Message of the last failed call on this host thread ("" if none). */

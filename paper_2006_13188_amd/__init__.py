@@ -64,13 +64,18 @@ class Context:
     """Owns a libecc context on one HIP device."""
 
     def __init__(self, device: int = 0):
+        import weakref
         h = C.c_void_p()
         _check(lib().ecc_create(device, C.byref(h)))
         self.h = h
         self.device = device
+        self._plans = weakref.WeakSet()
 
     def close(self):
+        """Destroys the context; plans made from it are closed first."""
         if self.h:
+            for p in list(self._plans):
+                p.close()
             lib().ecc_destroy(self.h)
             self.h = None
 
@@ -101,6 +106,7 @@ class FilterPlan:
     def __init__(self, ctx: Context, h):
         self.ctx = ctx
         self.h = h
+        ctx._plans.add(self)
         S, K, M = C.c_int(), C.c_int(), C.c_int()
         _check(lib().ecc_filter_plan_info(h, C.byref(S), C.byref(K), C.byref(M)))
         self.S, self.K, self.M = S.value, K.value, M.value

@@ -35,9 +35,12 @@ ecc_status fail(ecc_status s, const std::string& msg) {
     if (!(cond)) return fail(ECC_ERR_INVALID_ARGUMENT, (msg));         \
   } while (0)
 
+// Makes the context's device current for one API call and clears any error state left
+// behind by earlier HIP calls of the caller, so launch checks report this call's errors.
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
+    (void)hipGetLastError();
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != dev) (void)hipSetDevice(dev);
   }
@@ -310,6 +313,8 @@ ecc_status ecc_destroy(ecc_context ctx) {
   if (!ctx) return ECC_OK;
   DeviceGuard dg(ctx->device);
   (void)hipDeviceSynchronize();
+  for (ecc_filter_plan p : ctx->plans) delete p;   // plans still alive go with the context
+  ctx->plans.clear();
   delete ctx;
   return ECC_OK;
 }
@@ -353,6 +358,7 @@ ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float*
   hipStream_t st = S(stream);
   auto plan = std::make_unique<ecc_filter_plan_s>();
   plan->ctx = ctx;
+  plan->device = ctx->device;
   plan->group = group;
   if (group == ECC_GROUP_ROTATION) {
     ECC_REQ(filter != nullptr, "filter is NULL");
@@ -423,6 +429,8 @@ ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float*
   }
   ECC_TRY(finish_plan(plan.get(), st));
   *out = plan.release();
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->plans.insert(*out);
   return ECC_OK;
 }
 
@@ -438,6 +446,7 @@ ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, con
   hipStream_t st = S(stream);
   auto plan = std::make_unique<ecc_filter_plan_s>();
   plan->ctx = ctx;
+  plan->device = ctx->device;
   plan->group = group;
   if (group == ECC_GROUP_SCALE) {
     ScaleSetup s{};
@@ -461,6 +470,8 @@ ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, con
   ECC_HIP(launch_f2d(st, reinterpret_cast<const cx<float>*>(comps), plan->comps64.as<cx<double>>(), (long long)n));
   ECC_TRY(finish_plan(plan.get(), st));
   *out = plan.release();
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->plans.insert(*out);
   return ECC_OK;
 }
 
@@ -482,8 +493,12 @@ ecc_status ecc_filter_plan_info(ecc_filter_plan plan, int* Sz, int* K, int* M) {
 
 ecc_status ecc_filter_plan_destroy(ecc_filter_plan plan) {
   if (!plan) return ECC_OK;
-  DeviceGuard dg(plan->ctx->device);
+  DeviceGuard dg(plan->device);
   (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> g(plan->ctx->mu);
+    plan->ctx->plans.erase(plan);
+  }
   delete plan;
   return ECC_OK;
 }

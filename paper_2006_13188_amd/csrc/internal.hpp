@@ -5,6 +5,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -76,6 +77,7 @@ struct ecc_context_s {
   ecc_strategy strategy = ECC_STRATEGY_AUTO;
   std::map<std::string, int> tuned;   // shape key -> chosen FFT size
   std::vector<hipEvent_t> stage_events;   // measurement hook (see ecc_set_stage_events)
+  std::set<ecc_filter_plan_s*> plans;     // live plans made from this context
 };
 
 struct Spectrum {
@@ -85,6 +87,7 @@ struct Spectrum {
 
 struct ecc_filter_plan_s {
   ecc_context ctx = nullptr;
+  int device = 0;
   ecc_group group = ECC_GROUP_ROTATION;
   int S = 0, R = 0, K = 0, U = 0, M = 0;
   ecc::DevBuf comps64;   // U x S x S complex128

@@ -46,19 +46,44 @@ __device__ __forceinline__ int at(int line, int pos) {
   return ROWS ? line * P + pos : pos * P + line;
 }
 
+// Pass-1 twiddles w^{r b} (w = exp(2 pi i / N), b < 8, r < N/8), float64 rounded once.
+template <int N>
+struct TileTwiddles {
+  float re[8][N / 8], im[8][N / 8];
+};
+template <int N>
+constexpr TileTwiddles<N> make_tile_twiddles() {
+  TileTwiddles<N> t{};
+  for (int b = 0; b < 8; ++b)
+    for (int r = 0; r < N / 8; ++r) {
+      t.re[b][r] = (float)cos_turn((long)r * b, N);
+      t.im[b][r] = (float)sin_turn((long)r * b, N);
+    }
+  return t;
+}
+__constant__ TileTwiddles<64> kTw64 = make_tile_twiddles<64>();
+__constant__ TileTwiddles<96> kTw96 = make_tile_twiddles<96>();
+__constant__ TileTwiddles<128> kTw128 = make_tile_twiddles<128>();
+template <int N>
+__device__ __forceinline__ const TileTwiddles<N>& tile_twiddles() {
+  if constexpr (N == 64) return kTw64;
+  else if constexpr (N == 96) return kTw96;
+  else return kTw128;
+}
+
 // Pass 0 of the transforms of `nlines` lines of the image in A, all at once: items
-// q = tid + 256 s -> line q mod NL (NL lines per item round), butterfly q / NL.
+// q = t + 256 s -> line q mod NL (NL lines per item round), butterfly q / NL.
 // Reads everything first, synchronises, then writes (the pass is not in place).
 template <int N, int DIR, bool ROWS, int NL>
-__device__ __forceinline__ void pass0_inplace(cx<float>* A, int nlines) {
+__device__ __forceinline__ void pass0_inplace(cx<float>* A, int t, int nlines, bool act) {
   constexpr int M = N / 8, P = N + 1;
   constexpr int NQ = (NL * M + kTileThreads - 1) / kTileThreads;
   cx<float> v[NQ][8];
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
-    const int q = threadIdx.x + s * kTileThreads;
+    const int q = t + s * kTileThreads;
     const int line = q % NL, b = q / NL;
-    if (b < M && line < nlines) {
+    if (act && b < M && line < nlines) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[s][r] = A[at<P, ROWS>(line, b + M * r)];
     }
@@ -66,9 +91,9 @@ __device__ __forceinline__ void pass0_inplace(cx<float>* A, int nlines) {
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
-    const int q = threadIdx.x + s * kTileThreads;
+    const int q = t + s * kTileThreads;
     const int line = q % NL, b = q / NL;
-    if (b < M && line < nlines) {
+    if (act && b < M && line < nlines) {
       dft<8, DIR, float>(v[s]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) A[at<P, ROWS>(line, 8 * b + r)] = v[s][r];
@@ -78,11 +103,11 @@ __device__ __forceinline__ void pass0_inplace(cx<float>* A, int nlines) {
 
 // Pass 1 in place for lines l + 32 i (i < NI, line < nlines), butterfly bq; tw holds
 // w^{r bq} for the inverse direction (conjugated for the forward one).
-template <int N, int DIR, bool ROWS, int NI>
+template <int N, int DIR, bool ROWS, int NI, bool SERIAL = false>
 __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw, int bq, int l,
                                               int nlines, int nstore) {
   constexpr int M = N / 8, P = N + 1;
-#pragma unroll
+#pragma unroll(SERIAL ? 1 : NI)
   for (int i = 0; i < NI; ++i) {
     const int line = l + 32 * i;
     if (line < nlines) {
@@ -100,33 +125,38 @@ __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw,
 }
 
 // N: transform length; TV: largest valid block side (a multiple of 32); SEPB: the row
-// pass-0 output goes to a second buffer of TV rows (else in place, one more barrier).
-template <int N, int TV, bool SEPB>
-__global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
+// pass-0 output goes to a second buffer of TV rows (else in place, one more barrier);
+// HALVES: 1 or 2 groups of 256 threads, each with its own LDS image, transforming
+// components c = c0 + half (c0 += HALVES) side by side; the groups' sums are added at
+// the end.
+template <int N, int TV, bool SEPB, int HALVES>
+__global__ void __launch_bounds__(kTileThreads * HALVES) k_tile_corr(TileArgs a) {
   constexpr int M = N / 8, P = N + 1;
   constexpr int NQ0 = (N * M + kTileThreads - 1) / kTileThreads;   // column pass-0 items
   constexpr int NQ2 = (TV * M + kTileThreads - 1) / kTileThreads;  // row pass-0 items
   constexpr int TR = TV / 32, RV = TV / 8;
+  constexpr int IMG = (SEPB ? N + TV : N) * P;                      // LDS image per group
+  constexpr bool PREFETCH = HALVES == 1 && N <= 96;
   extern __shared__ cx<float> lds_t[];
-  cx<float>* A = lds_t;
-  cx<float>* Bb = SEPB ? lds_t + N * P : lds_t;
-  const int t = threadIdx.x, bq = t >> 5, l = t & 31;
+  const int half = threadIdx.x / kTileThreads;
+  const int t = threadIdx.x - half * kTileThreads, bq = t >> 5, l = t & 31;
+  cx<float>* A = lds_t + half * IMG;
+  cx<float>* Bb = SEPB ? A + N * P : A;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
   const int img = lb / ntile, tile = lb - img * ntile;
   const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
   const int T = a.T;
 
-  // pass-1 twiddles w^{r bq}, w = exp(2 pi i / N), rounded from float64
   cx<float> tw[M];
+  {
+    const TileTwiddles<N>& tt = tile_twiddles<N>();
 #pragma unroll
-  for (int r = 0; r < M; ++r) {
-    double sn, cs;
-    sincospi(2.0 * (double)(r * bq) / (double)N, &sn, &cs);
-    tw[r] = mk((float)cs, (float)sn);
+    for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
   }
 
-  // ---- signal window into A (real part), zero outside the image
+  // ---- signal window into A (real part), zero outside the image; each group keeps
+  // its own copy and transforms it
   const float* Hb = a.H + (long long)img * a.planeH;
   for (int q = t; q < N * N; q += kTileThreads) {
     const int i = q / N, j = q - (q / N) * N;
@@ -137,11 +167,11 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
   }
   __syncthreads();
   // ---- forward 2D transform of the window: columns, then rows
-  pass0_inplace<N, -1, false, N>(A, N);
+  pass0_inplace<N, -1, false, N>(A, t, N, true);
   __syncthreads();
   pass1_inplace<N, -1, false, N / 32>(A, tw, bq, l, N, N);
   __syncthreads();
-  pass0_inplace<N, -1, true, N>(A, N);
+  pass0_inplace<N, -1, true, N>(A, t, N, true);
   __syncthreads();
   pass1_inplace<N, -1, true, N / 32>(A, tw, bq, l, N, N);
   __syncthreads();
@@ -155,7 +185,9 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
     for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? A[(b + M * r) * P + v] : mk(0.f, 0.f);
   }
 
-  // ---- per-pixel state of the row pass-1 outputs: pixel (l + 32 i, bq + 8 r)
+  // ---- per-pixel state of the row pass-1 outputs: pixel (l + 32 i, bq + 8 r). The
+  // phase of component c is e^{i (kofs + c) alpha}; group `half` starts at c = half and
+  // advances by HALVES components per step.
   float acc[TR][RV];
   cx<float> z[TR][RV], e1[TR][RV];
 #pragma unroll
@@ -168,42 +200,64 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
       const int u = l + 32 * i, x = bq + 8 * r;
       const int gy = y0 + u, gx = x0 + x;
       if (u < T && x < T && gy < a.ny && gx < a.nx) {
-        const double al = field_angle(a.fld, a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]);
-        double sn, cs;
-        sincos(al, &sn, &cs);
-        e1[i][r] = mk((float)cs, (float)sn);
-        sincos((double)a.kofs * al, &sn, &cs);
-        z[i][r] = mk((float)cs, (float)sn);
+        const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+        const int k0 = a.kofs + half;
+        cx<float> s1, s0;
+        if (a.fld.log_mode || a.kofs != 0) {
+          const double al = field_angle(a.fld, fv);
+          double sn, cs;
+          sincos(al, &sn, &cs);
+          s1 = mk((float)cs, (float)sn);
+          sincos((double)k0 * al, &sn, &cs);
+          s0 = mk((float)cs, (float)sn);
+        } else {
+          const float al = (float)a.fld.mul * fv + (float)a.fld.add;
+          float sn, cs;
+          sincosf(al, &sn, &cs);
+          s1 = mk(cs, sn);
+          s0 = half ? s1 : mk(1.f, 0.f);
+        }
+        z[i][r] = s0;
+        e1[i][r] = HALVES == 2 ? cmul(s1, s1) : s1;
       }
     }
   }
 
-  // filter spectrum values of the first component
-  cx<float> fs[NQ0][8];
+  // filter spectrum values of the first component (prefetching form)
+  cx<float> fs[PREFETCH ? NQ0 : 1][8];
+  if constexpr (PREFETCH) {
 #pragma unroll
-  for (int s = 0; s < NQ0; ++s) {
-    const int q = t + s * kTileThreads;
-    const int v = q % N, b = q / N;
+    for (int s = 0; s < NQ0; ++s) {
+      const int q = t + s * kTileThreads;
+      const int v = q % N, b = q / N;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) fs[s][r] = (b < M) ? a.Fs[(b + M * r) * N + v] : mk(0.f, 0.f);
+      for (int r = 0; r < 8; ++r) fs[s][r] = (b < M) ? a.Fs[(b + M * r) * N + v] : mk(0.f, 0.f);
+    }
   }
   __syncthreads();   // A is rewritten below
 
-  for (int c = 0; c < a.U; ++c) {
+  for (int c0 = 0; c0 < a.U; c0 += HALVES) {
+    const int c = c0 + half;
+    const bool act = c < a.U;
     // ---- column pass 0: product, inverse radix 8, A[8 b + r][v]
-    const cx<float>* Fn = a.Fs + (long long)(c + 1) * N * N;
+    const cx<float>* Fc = a.Fs + (long long)c * N * N;
     const bool more = c + 1 < a.U;
 #pragma unroll
     for (int s = 0; s < NQ0; ++s) {
       const int q = t + s * kTileThreads;
       const int v = q % N, b = q / N;
-      if (b < M) {
+      if (act && b < M) {
         cx<float> x[8];
+        if constexpr (PREFETCH) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], fs[s][r]);
-        if (more) {
+          for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], fs[s][r]);
+          if (more) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) fs[s][r] = Fn[(b + M * r) * N + v];   // next component
+            for (int r = 0; r < 8; ++r) fs[s][r] = Fc[N * N + (b + M * r) * N + v];   // next component
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], Fc[(b + M * r) * N + v]);
         }
         dft<8, +1, float>(x);
 #pragma unroll
@@ -212,7 +266,7 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
     }
     __syncthreads();
     // ---- column pass 1 (in place), rows < T kept
-    pass1_inplace<N, +1, false, N / 32>(A, tw, bq, l, N, T);
+    if (act) pass1_inplace<N, +1, false, N / 32>(A, tw, bq, l, N, T);
     __syncthreads();
     // ---- row pass 0 over the T valid rows
     if constexpr (SEPB) {
@@ -220,7 +274,7 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
       for (int s = 0; s < NQ2; ++s) {
         const int q = t + s * kTileThreads;
         const int u = q % TV, b = q / TV;
-        if (b < M && u < T) {
+        if (act && b < M && u < T) {
           cx<float> x[8];
 #pragma unroll
           for (int r = 0; r < 8; ++r) x[r] = A[u * P + b + M * r];
@@ -230,29 +284,49 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
         }
       }
     } else {
-      pass0_inplace<N, +1, true, TV>(A, T);
+      pass0_inplace<N, +1, true, TV>(A, t, T, act);
     }
     __syncthreads();
     // ---- row pass 1 and the per-pixel combination
-    const float wc = a.w[c];
+    if (act) {
+      const float wc = a.w[c];
 #pragma unroll
-    for (int i = 0; i < TR; ++i) {
-      const int u = l + 32 * i;
-      if (u < T) {
-        cx<float> x[M];
+      for (int i = 0; i < TR; ++i) {   // (acc, z, e1 are indexed by i: this loop stays unrolled)
+        const int u = l + 32 * i;
+        if (u < T) {
+          cx<float> x[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) x[r] = Bb[u * P + bq + 8 * r];
+          for (int r = 0; r < M; ++r) x[r] = Bb[u * P + bq + 8 * r];
 #pragma unroll
-        for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
-        dft<M, +1, float>(x);
+          for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
+          dft<M, +1, float>(x);
 #pragma unroll
-        for (int r = 0; r < RV; ++r) {
-          acc[i][r] += wc * (z[i][r].re * x[r].re - z[i][r].im * x[r].im);
-          z[i][r] = cmul(z[i][r], e1[i][r]);
+          for (int r = 0; r < RV; ++r) {
+            acc[i][r] += wc * (z[i][r].re * x[r].re - z[i][r].im * x[r].im);
+            z[i][r] = cmul(z[i][r], e1[i][r]);
+          }
         }
       }
     }
     if constexpr (!SEPB) __syncthreads();   // A is rewritten by the next column pass
+  }
+
+  if constexpr (HALVES == 2) {
+    // group 1 hands its sums to group 0 through its own (now idle) LDS image
+    float* xf = reinterpret_cast<float*>(lds_t + IMG);
+    __syncthreads();
+    if (half == 1) {
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int r = 0; r < RV; ++r) xf[(i * RV + r) * kTileThreads + t] = acc[i][r];
+    }
+    __syncthreads();
+    if (half == 1) return;
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int r = 0; r < RV; ++r) acc[i][r] += xf[(i * RV + r) * kTileThreads + t];
   }
 
   float* yb = a.y + (long long)img * a.planeY;
@@ -267,24 +341,210 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_corr(TileArgs a) {
   }
 }
 
-template <int N, int TV, bool SEPB>
+// Component pairs: 512 threads transform components c and c + 1 side by side, each in
+// its own LDS image (A[0], A[1]); TV = 64.
+//  * column pass 0: item (v, b) (column v, radix-8 butterfly b) is done for both
+//    components by the same thread, so a thread keeps the signal spectrum of its items
+//    once; items q < 512 NF are full (both components), the remaining REM items are
+//    dealt as single-component halves to threads t < 2 REM (per SIMD the load is equal).
+//  * column passes 1 and row passes 0: group g = t / 256 works on component c + g.
+//  * row pass 1: thread (row u = t mod 64, butterfly bq = t / 64) does both components;
+//    bq is uniform in a wave, so its twiddles come from scalar loads, and the thread owns
+//    the 8 pixels (u, bq + 8 r) for all components.
+template <int N>
+__global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
+  constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
+  constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
+  constexpr int NH = NF + (REM ? 1 : 0);
+  static_assert(REM * 2 <= 2 * kTileThreads, "remainder items exceed one round");
+  extern __shared__ cx<float> lds_t[];
+  const int t = threadIdx.x;
+  const int g = t / kTileThreads, tg = t - g * kTileThreads;
+  const int bq1 = tg >> 5, l1 = tg & 31;                       // column pass 1 mapping
+  const int u4 = t & 63;
+  const int bq4 = __builtin_amdgcn_readfirstlane(t >> 6);      // row pass 1 mapping
+  cx<float>* const A0 = lds_t;
+  cx<float>* const A1 = lds_t + N * P;
+  cx<float>* const Ag = g ? A1 : A0;
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int ntile = a.tx * a.ty;
+  const int img = lb / ntile, tile = lb - img * ntile;
+  const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
+  const int T = a.T;
+  const TileTwiddles<N>& tt = tile_twiddles<N>();
+
+  cx<float> tw1[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) tw1[r] = mk(tt.re[bq1][r], tt.im[bq1][r]);
+
+  // ---- signal window and its forward transform (each group on its own image)
+  const float* Hb = a.H + (long long)img * a.planeH;
+  for (int q = tg; q < N * N; q += kTileThreads) {
+    const int i = q / N, j = q - (q / N) * N;
+    const int gy = y0 - a.R + i, gx = x0 - a.R + j;
+    float h = 0.f;
+    if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) h = Hb[(long long)gy * a.ldH + gx];
+    Ag[i * P + j] = mk(h, 0.f);
+  }
+  __syncthreads();
+  pass0_inplace<N, -1, false, N>(Ag, tg, N, true);
+  __syncthreads();
+  pass1_inplace<N, -1, false, N / 32>(Ag, tw1, bq1, l1, N, N);
+  __syncthreads();
+  pass0_inplace<N, -1, true, N>(Ag, tg, N, true);
+  __syncthreads();
+  pass1_inplace<N, -1, true, N / 32>(Ag, tw1, bq1, l1, N, N);
+  __syncthreads();
+  // signal spectrum of this thread's column pass-0 items
+  cx<float> hs[NH][8];
+  int qv[NH], qb[NH];
+#pragma unroll
+  for (int s = 0; s < NH; ++s) {
+    int q = t + s * 2 * kTileThreads;
+    if (s == NF) q = NF * 2 * kTileThreads + (REM ? t % (REM ? REM : 1) : 0);
+    qv[s] = q % N;
+    qb[s] = q / N;
+    const bool ok = s < NF || t < 2 * REM;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) hs[s][r] = ok ? A0[(qb[s] + M * r) * P + qv[s]] : mk(0.f, 0.f);
+  }
+  const int hcomp = REM ? t / (REM ? REM : 1) : 0;   // component of the half item (t < 2 REM)
+
+  // ---- per-pixel state: pixel (u4, bq4 + 8 r), phase e^{i (kofs + c) alpha}
+  float acc[8];
+  cx<float> z[8], e1[8];
+  const bool rowok = u4 < T && y0 + u4 < a.ny;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    acc[r] = 0.f;
+    z[r] = mk(0.f, 0.f);
+    e1[r] = mk(0.f, 0.f);
+    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
+    if (rowok && x < T && gx < a.nx) {
+      const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+      if (a.fld.log_mode || a.kofs != 0) {
+        const double al = field_angle(a.fld, fv);
+        double sn, cs;
+        sincos(al, &sn, &cs);
+        e1[r] = mk((float)cs, (float)sn);
+        sincos((double)a.kofs * al, &sn, &cs);
+        z[r] = mk((float)cs, (float)sn);
+      } else {
+        float sn, cs;
+        sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
+        e1[r] = mk(cs, sn);
+        z[r] = mk(1.f, 0.f);
+      }
+    }
+  }
+  __syncthreads();   // the images are rewritten below
+
+  for (int c = 0; c < a.U; c += 2) {
+    const bool two = c + 1 < a.U;
+    const cx<float>* F0 = a.Fs + (long long)c * N * N;
+    // ---- column pass 0 for both components
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const bool full = s < NF;
+      if (full || t < 2 * REM) {
+        const int v = qv[s], b = qb[s];
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+          const bool mine = full ? (cc == 0 || two) : (cc == hcomp && (cc == 0 || two));
+          if (mine) {
+            const cx<float>* Fc = F0 + cc * N * N;
+            cx<float> x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], Fc[(b + M * r) * N + v]);
+            dft<8, +1, float>(x);
+            cx<float>* Ac = cc ? A1 : A0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) Ac[(8 * b + r) * P + v] = x[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const bool act = g == 0 || two;
+    // ---- column pass 1 (in place, rows < T kept) and row pass 0, group g on c + g
+    if (act) pass1_inplace<N, +1, false, N / 32>(Ag, tw1, bq1, l1, N, T);
+    __syncthreads();
+    pass0_inplace<N, +1, true, TV>(Ag, tg, T, act);
+    __syncthreads();
+    // ---- row pass 1 for both components and the per-pixel combination
+    if (u4 < T) {
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        if (cc == 0 || two) {
+          const cx<float>* Ac = cc ? A1 : A0;
+          cx<float> x[M];
+#pragma unroll
+          for (int r = 0; r < M; ++r) x[r] = Ac[u4 * P + bq4 + 8 * r];
+#pragma unroll
+          for (int r = 1; r < M; ++r) x[r] = cmul(x[r], mk(tt.re[bq4][r], tt.im[bq4][r]));
+          dft<M, +1, float>(x);
+          const float wc = a.w[c + cc];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            acc[r] += wc * (z[r].re * x[r].re - z[r].im * x[r].im);
+            z[r] = cmul(z[r], e1[r]);
+          }
+        }
+      }
+    }
+    __syncthreads();   // the images are rewritten by the next column pass
+  }
+
+  float* yb = a.y + (long long)img * a.planeY;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
+    if (rowok && x < T && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+  }
+}
+
+// LDS of a launch: HV = 1: one image (+ the separate row buffer); HV = 2: the pair
+// kernel's two images.
+template <int N, int TV, bool SEPB, int HV>
 constexpr size_t tile_lds() {
-  return (size_t)(SEPB ? N + TV : N) * (N + 1) * sizeof(cx<float>);
+  return HV == 2 ? (size_t)2 * N * (N + 1) * sizeof(cx<float>)
+                 : (size_t)(SEPB ? N + TV : N) * (N + 1) * sizeof(cx<float>);
+}
+
+template <int N, int TV, bool SEPB, int HV>
+hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
+  if constexpr (HV == 2) {
+    static_assert(TV == 64, "the pair kernel has 64 x 64 blocks");
+    hipLaunchKernelGGL((k_tile_corr_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
+                       (tile_lds<N, TV, SEPB, HV>()), s, a);
+  } else {
+    hipLaunchKernelGGL((k_tile_corr<N, TV, SEPB, 1>), dim3(nblk), dim3(kTileThreads),
+                       (tile_lds<N, TV, SEPB, HV>()), s, a);
+  }
+  return last();
+}
+
+template <int N, int TV, bool SEPB, int HV>
+hipError_t prepare_tile_kernel() {
+  if constexpr (HV == 2) return allow_lds(k_tile_corr_pair<N>);
+  else return allow_lds(k_tile_corr<N, TV, SEPB, 1>);
 }
 
 }  // namespace
 
-#define ECC_TILE_CONFIGS(X) X(64, 64, true) X(96, 64, true) X(128, 64, false) X(128, 96, false)
+// (N, TV, separate row buffer, 1 = one group per component / 2 = component pairs)
+#define ECC_TILE_CONFIGS(X) \
+  X(64, 64, true, 2) X(96, 64, false, 2) X(128, 64, false, 1) X(128, 96, false, 1)
 
 bool tile_supported(int N, int TV) {
-#define ECC_TS(n, tv, sb) if (N == n && TV == tv) return true;
+#define ECC_TS(n, tv, sb, hv) if (N == n && TV == tv) return true;
   ECC_TILE_CONFIGS(ECC_TS)
 #undef ECC_TS
   return false;
 }
 
 size_t tile_lds_bytes(int N, int TV) {
-#define ECC_TB(n, tv, sb) if (N == n && TV == tv) return tile_lds<n, tv, sb>();
+#define ECC_TB(n, tv, sb, hv) if (N == n && TV == tv) return tile_lds<n, tv, sb, hv>();
   ECC_TILE_CONFIGS(ECC_TB)
 #undef ECC_TB
   return 0;
@@ -316,12 +576,8 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   a.Fs = Fs;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-#define ECC_TL(n, tv, sb)                                                                      \
-  if (N == n && TV == tv) {                                                                   \
-    hipLaunchKernelGGL((k_tile_corr<n, tv, sb>), dim3((unsigned)nblk), dim3(kTileThreads),    \
-                       (tile_lds<n, tv, sb>()), s, a);                                           \
-    return last();                                                                             \
-  }
+#define ECC_TL(n, tv, sb, hv) \
+  if (N == n && TV == tv) return launch_tile_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
   ECC_TILE_CONFIGS(ECC_TL)
 #undef ECC_TL
   return hipErrorInvalidValue;
@@ -329,8 +585,8 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
 
 hipError_t prepare_tile_kernels() {
   hipError_t e = hipSuccess;
-#define ECC_TP(n, tv, sb) \
-  if (e == hipSuccess) e = allow_lds(k_tile_corr<n, tv, sb>);
+#define ECC_TP(n, tv, sb, hv) \
+  if (e == hipSuccess) e = prepare_tile_kernel<n, tv, sb, hv>();
   ECC_TILE_CONFIGS(ECC_TP)
 #undef ECC_TP
   return e;

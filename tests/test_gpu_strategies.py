@@ -135,3 +135,20 @@ def test_auto_choice_and_unsupported_radius(E):
             E.ecc_extended(ctx, 0, big, img, img)
     finally:
         ctx.close()
+
+
+def test_context_close_with_live_plans(E):
+    """Closing a context also closes its plans; later calls on other contexts are clean."""
+    ctx = E.Context(0)
+    plan = E.FilterPlan.rotation(ctx, dev(random_filter(9, 3, 2.0)), 3)
+    ctx.close()
+    assert plan.h is None
+    plan.close()   # no-op
+    ctx2 = E.Context(0)
+    try:
+        img, filt, theta, K = rotation_config(64, 9, 3)
+        p2 = E.FilterPlan.rotation(ctx2, dev(filt), K)
+        y = host(E.ecc_extended(ctx2, 0, p2, dev(img), dev(theta))).astype(np.float64)
+        assert rel2(y, oracle_corr(img, filt, theta, K)) <= TOL
+    finally:
+        ctx2.close()
