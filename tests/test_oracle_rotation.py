@@ -117,53 +117,63 @@ def test_full_band_components_reproduce_axis_pixels():
 
 # ---------------------------------------------------------------- rotation convention pins
 
-def test_rotation_matches_printed_dense_matrix():
-    """The basis {cos^2, sin^2, cos sin} example of Sec. 3 prints the matrix by which a
-    rotation by Theta maps the coefficient vector. Rotating the component form must
-    reproduce a filter whose coefficients are that matrix times the original ones."""
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                    "rotation_coefficient_matrices.txt")
+_EV_NS = {"cos": np.cos, "sin": np.sin, "exp": np.exp}
+
+
+def _ev(expr, **names):
+    return eval(expr, {"__builtins__": {}, **_EV_NS}, names)
+
+
+def _golden_examples():
+    """Blocks of the fixture: {'basis': [expr in phi], 'rows': [[expr in T]]}."""
+    blocks, cur = [], None
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("basis:"):
+            cur = {"basis": [e.strip() for e in line[len("basis:"):].split(",")], "rows": []}
+            blocks.append(cur)
+        else:
+            cur["rows"].append([e.strip() for e in line.split(",")])
+    return blocks
+
+
+def test_golden_fixture_shape():
+    ex = _golden_examples()
+    assert [len(b["basis"]) for b in ex] == [1, 3, 3]
+    assert all(len(b["rows"]) == len(b["basis"]) and all(len(r) == len(b["basis"]) for r in b["rows"])
+               for b in ex)
+
+
+@pytest.mark.parametrize("block", [0, 1, 2])
+def test_rotation_matches_printed_matrices(block):
+    """Sec. 3 prints, for three small bases, the matrix by which a rotation by Theta maps a
+    filter's coefficient vector. A filter prof(r) * sum_j a_j basis_j(phi) is split into
+    angular components by the plain angular DFT of its (band-limited) angular factor; the
+    oracle's rotated filter sum_k e^{-ik Theta} F_k must equal the same profile with the
+    coefficients (printed matrix) @ a."""
+    ex = _golden_examples()[block]
     S = 15
     R, xx, yy, r, phi, disk = _polar(S)
-    prof = np.exp(-r ** 2 / 18.0) * r
-    a = np.array([0.7, -1.3, 0.4])
-
-    def basis(ph):
-        return np.stack([np.cos(ph) ** 2, np.sin(ph) ** 2, np.cos(ph) * np.sin(ph)])
-
-    def printed(T):
-        c, s = np.cos(T), np.sin(T)
-        return np.array([[c * c, s * s, -c * s],
-                         [s * s, c * c, c * s],
-                         [np.sin(2 * T), -np.sin(2 * T), np.cos(2 * T)]])
-
-    # components: cos^2 = 1/2 + (e^{2i} + e^{-2i})/4, sin^2 = 1/2 - (...)/4,
-    # cos sin = (e^{2i} - e^{-2i}) / (4i)
-    coef = {0: (a[0] + a[1]) / 2, 2: (a[0] - a[1]) / 4 + a[2] / 4j, -2: (a[0] - a[1]) / 4 - a[2] / 4j}
-    K = 2
-    comps = np.zeros((5, S, S), complex)
-    for k, c in coef.items():
-        comps[k + K] = np.where(disk, c * prof * np.exp(1j * k * phi), 0)
+    prof = np.exp(-r ** 2 / 18.0) * (1.0 + r)
+    n = len(ex["basis"])
+    rng = np.random.default_rng(block)
+    a = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    K, M = 3, 64
+    phis = 2 * np.pi * np.arange(M) / M
+    ang = sum(a[j] * _ev(ex["basis"][j], phi=phis) for j in range(n))
+    comps = np.zeros((2 * K + 1, S, S), complex)
+    for k in range(-K, K + 1):
+        ck = np.mean(ang * np.exp(-1j * k * phis))
+        comps[k + K] = np.where(disk, prof * ck * np.exp(1j * k * phi), 0)
     for T in (0.3, 1.1, 2.5, -0.9):
-        rot = O.rotated_filter(comps, T)
-        ref = np.where(disk, prof * np.tensordot(printed(T) @ a, basis(phi), axes=1), 0)
-        assert np.allclose(rot, ref, atol=1e-12)
-
-
-def test_rotation_matches_printed_diagonal_matrix():
-    """Sec. 3 example n = 3: basis {e^{2i phi}, e^{-2i phi}, 1}, rotation by Theta is
-    diag(e^{-2i Theta}, e^{2i Theta}, 1) on the coefficients."""
-    S = 11
-    R, xx, yy, r, phi, disk = _polar(S)
-    prof = np.exp(-r ** 2 / 8.0)
-    a = np.array([0.3 + 0.2j, -0.5j, 1.1])
-    comps = np.zeros((5, S, S), complex)
-    comps[4] = np.where(disk, a[0] * prof * np.exp(2j * phi), 0)
-    comps[0] = np.where(disk, a[1] * prof * np.exp(-2j * phi), 0)
-    comps[2] = np.where(disk, a[2] * prof, 0)
-    T = 0.77
-    rot = O.rotated_filter(comps, T)
-    b = np.diag([np.exp(-2j * T), np.exp(2j * T), 1.0]) @ a
-    ref = np.where(disk, prof * (b[0] * np.exp(2j * phi) + b[1] * np.exp(-2j * phi) + b[2]), 0)
-    assert np.allclose(rot, ref, atol=1e-13)
+        mat = np.array([[_ev(e, T=T) for e in row] for row in ex["rows"]], complex)
+        b = mat @ a
+        ref = np.where(disk, prof * sum(b[j] * _ev(ex["basis"][j], phi=phi) for j in range(n)), 0)
+        assert np.allclose(O.rotated_filter(comps, T), ref, atol=1e-12)
 
 
 # ---------------------------------------------------------------- extended operators
