@@ -61,8 +61,9 @@ typedef enum {
  * the whole image, P >= n + R, with the per-pixel combination fused into the last
  * inverse pass. TILED: overlap-save blocks: each T x T block of outputs is computed from
  * an N x N window (N - 2R >= T) entirely on chip, per component, then combined per
- * pixel (block shapes exist for R <= 56). AUTO compares the two with a cost model.
- * Convolution, matching and the adjoint always use TWO_PASS. */
+ * pixel (block shapes exist for R <= 56). AUTO takes TILED when a block shape with side
+ * T >= 2R exists, choosing among those by a cost model (measured when the autotuner is
+ * on). Convolution, matching and the adjoint always use TWO_PASS. */
 typedef enum {
   ECC_STRATEGY_AUTO = 0,
   ECC_STRATEGY_TWO_PASS = 1,
@@ -71,6 +72,7 @@ typedef enum {
 
 typedef struct ecc_context_s* ecc_context;
 typedef struct ecc_filter_plan_s* ecc_filter_plan;
+typedef struct ecc_batch_plan_s* ecc_batch_plan;
 
 /* Parameters of the transformation group. Zero fields take the defaults shown. */
 typedef struct {
@@ -99,18 +101,21 @@ const char* ecc_status_string(ecc_status s);
 /* Message of the last failed call on this host thread ("" if none). */
 const char* ecc_last_error(void);
 
-/* FFT size used for an image side n and filter radius R: the smallest 7-smooth integer
- * >= n + R (zero-boundary linear correlation needs >= n + R), unless the autotuner
- * has chosen a larger one for this shape. */
+/* FFT size of the two-pass path for an image side n and filter radius R: the smallest
+ * 7-smooth integer >= n + R (zero-boundary linear correlation needs >= n + R). */
 ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
-/* Enables (1) or disables (0) timing-based choice of FFT sizes on first use of a shape. */
+/* Enables (1) or disables (0) the autotuner. When enabled, the next forward call (or
+ * ecc_describe) first times every compiled block shape of the tiled path on this device
+ * (once per context, a few milliseconds); block shapes are then chosen from the measured
+ * per-block costs instead of an operation count. */
 ecc_status ecc_set_autotune(ecc_context ctx, int enable);
 /* Sets the evaluation strategy of later ecc_extended correlations on this context.
  * TILED with a filter radius that has no block shape fails with UNSUPPORTED at the call. */
 ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy);
 /* Reports how ecc_extended(op, plan, ny x nx) would run on this context: the strategy,
  * the transform length (TILED: N; TWO_PASS: the column-direction size P_y) and the block
- * side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is enqueued. */
+ * side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is enqueued, except
+ * the autotuner's one-time calibration when it is enabled and has not run yet. */
 ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx,
                         ecc_strategy* strategy, int* fft_size, int* block);
 
@@ -211,6 +216,49 @@ ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int ba
 ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
                              const float* signal, const float* field, float* out, void* saved,
                              void* stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* One independent extended correlation of a batch (each instance one image with its own
+ * filter plan, size and fields). Pointers are device float32 arrays owned by the caller,
+ * rows of nx values with the given strides (in elements). */
+typedef struct {
+  ecc_op op;               /* ECC_CORRELATION (others run through the per-call path) */
+  ecc_filter_plan plan;
+  int ny, nx;
+  const float* signal;
+  int ld_signal;
+  const float* field;
+  int ld_field;
+  float* out;
+  int ld_out;
+} ecc_instance;
+
+/* Flags of ecc_batch_plan_create. */
+#define ECC_BATCH_AUTOTUNE 1     /* time every block shape on this device first (once per
+                                    context) and choose shapes from the measured costs */
+#define ECC_BATCH_PERSISTENT 2   /* persistent workgroups that loop over host-dealt block
+                                    lists instead of one workgroup per block */
+
+/* Builds a batch plan: every correlation instance that has a block shape (tiled path,
+ * the filter's radius R <= 56) is split into blocks; blocks of the same shape go into one
+ * kernel launch (at most four shapes), ordered longest first, and the launches are
+ * captured once into a HIP graph. Instances without a block shape, and convolutions,
+ * are kept for the per-call path. Plans must outlive the batch plan. Errors:
+ * INVALID_ARGUMENT (as ecc_extended for any instance), HIP. */
+ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,
+                                 ecc_batch_plan* out);
+/* Replaces the instances' pointers and strides (same count, ops, plans and sizes as at
+ * creation; checked). Synchronous: returns after the new descriptors are on the device;
+ * must not overlap a running ecc_batch_execute of the same plan. */
+ecc_status ecc_batch_update(ecc_batch_plan bp, const ecc_instance* inst, int n);
+/* Runs the whole batch on `stream`: one graph launch for the tiled instances, then the
+ * remaining instances one call each. */
+ecc_status ecc_batch_execute(ecc_batch_plan bp, void* stream);
+/* Number of instances in the graph, kernel launches in the graph, and blocks. Any output
+ * may be NULL. */
+ecc_status ecc_batch_info(ecc_batch_plan bp, int* graph_instances, int* launches, int* blocks);
+ecc_status ecc_batch_plan_destroy(ecc_batch_plan bp);
 
 #ifdef __cplusplus
 }

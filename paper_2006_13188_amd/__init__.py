@@ -11,14 +11,16 @@ import ctypes as C
 from typing import Optional
 
 from . import _lib
-from ._lib import (CONVOLUTION, CORRELATION, GROUP_ROTATION, GROUP_SCALE, PREC_FP32,
-                   STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_TWO_PASS, EccError, GroupParams)
+from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, GROUP_ROTATION,
+                   GROUP_SCALE, PREC_FP32, STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_TWO_PASS,
+                   EccError, GroupParams, Instance)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
-    "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED",
+    "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
+    "BATCH_PERSISTENT",
     "GroupParams",
 ]
 
@@ -293,3 +295,55 @@ class _Lazy:
 
 
 ExtConv = _Lazy()
+
+
+class BatchPlan:
+    """ecc_batch_plan: many independent correlations (each its own image, plan and sizes)
+    run as a few kernel launches captured in one HIP graph.
+
+    instances: list of (op, FilterPlan, signal, field, out) with 2D float32 device tensors.
+    The tensors and plans must stay alive while the batch plan is used."""
+
+    def __init__(self, ctx: Context, instances, flags: int = 0):
+        self.ctx = ctx
+        self._keep = list(instances)
+        arr = self._array(instances)
+        h = C.c_void_p()
+        _check(lib().ecc_batch_plan_create(ctx.h, arr, len(instances), flags, C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def _array(instances):
+        arr = (Instance * max(1, len(instances)))()
+        for i, (op, plan, sig, fld, out) in enumerate(instances):
+            for t, name in ((sig, "signal"), (fld, "field"), (out, "out")):
+                _img(t, name)
+                if t.dim() != 2:
+                    raise ValueError(f"{name} must be a 2D tensor")
+            arr[i] = Instance(op, plan.h, sig.shape[0], sig.shape[1], sig.data_ptr(), _ld(sig),
+                              fld.data_ptr(), _ld(fld), out.data_ptr(), _ld(out))
+        return arr
+
+    def update(self, instances):
+        arr = self._array(instances)
+        _check(lib().ecc_batch_update(self.h, arr, len(instances)))
+        self._keep = list(instances)
+
+    def execute(self, stream=None):
+        _check(lib().ecc_batch_execute(self.h, _stream(stream)))
+
+    def info(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().ecc_batch_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"graph_instances": a.value, "launches": b.value, "blocks": c.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecc_batch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,6 +27,25 @@ class GroupParams(C.Structure):
     ]
 
 
+class Instance(C.Structure):
+    """ecc_instance: one image of a batch (device pointers, strides in elements)."""
+    _fields_ = [
+        ("op", C.c_int),
+        ("plan", C.c_void_p),
+        ("ny", C.c_int),
+        ("nx", C.c_int),
+        ("signal", C.c_void_p),
+        ("ld_signal", C.c_int),
+        ("field", C.c_void_p),
+        ("ld_field", C.c_int),
+        ("out", C.c_void_p),
+        ("ld_out", C.c_int),
+    ]
+
+
+BATCH_AUTOTUNE, BATCH_PERSISTENT = 1, 2
+
+
 class EccError(RuntimeError):
     def __init__(self, status, text):
         super().__init__(f"libecc: {STATUS.get(status, status)}: {text}")
@@ -46,6 +65,11 @@ PROTOS = {
     "ecc_set_stage_events": [_P, C.POINTER(_P), _I],
     "ecc_set_strategy": [_P, _I],
     "ecc_describe": [_P, _I, _P, _I, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
+    "ecc_batch_plan_create": [_P, C.POINTER(Instance), _I, _I, C.POINTER(_P)],
+    "ecc_batch_update": [_P, C.POINTER(Instance), _I],
+    "ecc_batch_execute": [_P, _P],
+    "ecc_batch_info": [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
+    "ecc_batch_plan_destroy": [_P],
     "ecc_filter_plan_create": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_from_components": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_get_components": [_P, _P, _P],

@@ -7,50 +7,20 @@
 #include <string>
 #include <vector>
 
-#include "internal.hpp"
+#include "api_common.hpp"
 
 using namespace ecc;
 
-namespace {
-
 thread_local std::string g_err;
 
+namespace ecc {
 ecc_status fail(ecc_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace ecc
 
-#define ECC_HIP(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess) {                                                            \
-      if (e_ == hipErrorOutOfMemory)                                                   \
-        return fail(ECC_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of memory");    \
-      return fail(ECC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
-    }                                                                                  \
-  } while (0)
-
-#define ECC_REQ(cond, msg)                                             \
-  do {                                                                 \
-    if (!(cond)) return fail(ECC_ERR_INVALID_ARGUMENT, (msg));         \
-  } while (0)
-
-// Makes the context's device current for one API call and clears any error state left
-// behind by earlier HIP calls of the caller, so launch checks report this call's errors.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    (void)hipGetLastError();
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+namespace {
 
 int fft_size_for(ecc_context ctx, int n, int R) {
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -60,13 +30,16 @@ int fft_size_for(ecc_context ctx, int n, int R) {
   return next_smooth7(n + R);
 }
 
+}  // namespace
+namespace ecc {
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
   return pa < pb + nb && pb < pa + na;
 }
+}  // namespace ecc
+namespace {
 
-constexpr size_t kMaxLds = 160 * 1024;
 
 // complex row pitch rounded up to 16 elements (128 bytes)
 inline int pitch16(int n) { return (n + 15) & ~15; }
@@ -94,11 +67,7 @@ ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const
     return fail(ECC_ERR_UNSUPPORTED, std::string("transform too long for the ") + what + " kernel");
   return ECC_OK;
 }
-#define ECC_TRY(expr)                 \
-  do {                                \
-    ecc_status s_ = (expr);           \
-    if (s_ != ECC_OK) return s_;      \
-  } while (0)
+
 
 // records stage event i of the measurement hook, if set
 inline hipError_t mark_event(ecc_context ctx, int i, hipStream_t st) {
@@ -151,6 +120,8 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
   return ECC_OK;
 }
 
+}  // namespace
+namespace ecc {
 // Block spectra for the tiled path: FFT_N x N(F_k placed with its window corner at
 // (0, 0)), float64 then rounded, full N x N planes (no symmetry assumed).
 ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out) {
@@ -186,40 +157,12 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   plan->tile_spectra[N] = std::move(sp);
   return ECC_OK;
 }
+}  // namespace ecc
+namespace {
 
-struct TileChoice {
-  int N = 0, TV = 0, T = 0;
-  double cost = 0;   // modelled work units (see pick_tile)
-};
 
-// Block shape for the tiled path with the smallest modelled time: per block and
-// component, N column and T row transforms of length N (~ N (N + T) log2 N), times the
-// number of rounds of resident workgroups (256 CUs, LDS-limited blocks per CU).
-bool pick_tile(int R, int ny, int nx, int batch, TileChoice& best) {
-  static const int cand[][2] = {{64, 64}, {96, 64}, {128, 64}, {128, 96}};
-  bool found = false;
-  for (auto& c : cand) {
-    const int N = c[0], TV = c[1];
-    if (!tile_supported(N, TV)) continue;
-    const int T = std::min(TV, N - 2 * R);
-    if (T < 16) continue;
-    const size_t lds = tile_lds_bytes(N, TV);
-    const int per_cu = std::max<int>(1, (int)(kMaxLds / lds));
-    const long long blocks = (long long)((ny + T - 1) / T) * ((nx + T - 1) / T) * batch;
-    const long long slots = 256LL * per_cu;
-    const long long rounds = (blocks + slots - 1) / slots;
-    const double per_block = (double)N * (N + T) * std::log2((double)N);
-    const double cost = (double)rounds * per_block * per_cu;
-    if (!found || cost < best.cost) {
-      best.N = N;
-      best.TV = TV;
-      best.T = T;
-      best.cost = cost;
-      found = true;
-    }
-  }
-  return found;
-}
+
+
 
 ecc_status finish_plan(ecc_filter_plan p, hipStream_t st) {
   const size_t n = (size_t)p->U * p->S * p->S;
@@ -526,6 +469,8 @@ ecc_status geometry(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, hipSt
   return ECC_OK;
 }
 
+}  // namespace
+namespace ecc {
 ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx) {
   ECC_REQ(batch >= 1 && batch <= 65535, "batch must be in [1, 65535]");
   ECC_REQ(ny >= 1 && nx >= 1 && ny <= 4096 && nx <= 4096, "image sides must be in [1, 4096]");
@@ -533,6 +478,9 @@ ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx) {
           "filter window larger than the image");
   return ECC_OK;
 }
+}  // namespace ecc
+namespace {
+
 
 // Correlation-type stack: T_k = IFFT_y(Hh . filter product) for k = 0..U-1.
 // Forward transform of the signal (once) and the component stack for components
@@ -660,6 +608,8 @@ ecc_status corr_rows(ecc_filter_plan plan, const Geometry& g, int batch, const c
   return ECC_OK;
 }
 
+}  // namespace
+namespace ecc {
 Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, double mul_sign) {
   Field fl;
   fl.ptr = f;
@@ -670,28 +620,35 @@ Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, 
   fl.add = 0.0;
   return fl;
 }
+}  // namespace ecc
+namespace {
 
-// Strategy of a forward call: TILED needs a block shape; AUTO takes it when the block
-// side is at least the filter diameter (halo re-reads at most ~4x of the block) and the
-// one-kernel form is otherwise the cheaper; everything else runs TWO_PASS.
+
+// Strategy of a forward call: TILED needs a block shape; AUTO takes the tiled path when
+// a block shape with side >= the filter diameter exists (the halo then costs at most ~4x
+// the block in transform work); everything else runs TWO_PASS.
 ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx, int batch,
                             ecc_strategy* used, TileChoice* tc) {
   *used = ECC_STRATEGY_TWO_PASS;
   if (op != ECC_CORRELATION) return ECC_OK;
-  const bool ok = pick_tile(plan->R, ny, nx, batch, *tc);
   if (ctx->strategy == ECC_STRATEGY_TILED) {
-    if (!ok) return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
+    if (!pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, 16, *tc))
+      return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
     *used = ECC_STRATEGY_TILED;
-  } else if (ctx->strategy == ECC_STRATEGY_AUTO && ok && tc->T >= std::max(16, 2 * plan->R)) {
+  } else if (ctx->strategy == ECC_STRATEGY_AUTO &&
+             pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, 2 * plan->R, *tc)) {
     *used = ECC_STRATEGY_TILED;
   }
   return ECC_OK;
 }
 
+}  // namespace
+namespace ecc {
 ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
                         const float* signal, int ld_signal, const float* field, int ld_field,
                         float* out, int ld_out, hipStream_t st, void* saved) {
   const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
+  if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
   ecc_strategy strat;
   TileChoice tc;
   ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc));
@@ -738,6 +695,9 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   ECC_TRY(conv_finish(ctx, plan, g, batch, Bk, 1, C, out, pO, ld_out, st));
   return ECC_OK;
 }
+}  // namespace ecc
+namespace {
+
 
 }  // namespace
 
@@ -770,6 +730,10 @@ ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny
   ECC_TRY(validate_images(plan, 1, ny, nx));
   ecc_strategy used;
   TileChoice tc;
+  if (ctx->autotune) {
+    DeviceGuard dg(ctx->device);
+    ECC_TRY(calibrate_tiles(ctx, nullptr));
+  }
   ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, 1, &used, &tc));
   if (strategy) *strategy = used;
   if (fft_size) *fft_size = used == ECC_STRATEGY_TILED ? tc.N : fft_size_for(ctx, ny, plan->R);

@@ -1,0 +1,80 @@
+// Helpers shared by the host-side translation units of libecc (api.cpp, batch.cpp):
+// error reporting, device scoping, and the choice of block shapes for the tiled path.
+#pragma once
+#include <string>
+
+#include "internal.hpp"
+
+namespace ecc {
+
+// Records `msg` as this thread's last error text and returns `s`.
+ecc_status fail(ecc_status s, const std::string& msg);
+
+#define ECC_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (e_ == hipErrorOutOfMemory)                                                   \
+        return ::ecc::fail(ECC_ERR_OUT_OF_MEMORY, std::string(#expr) + ": out of memory"); \
+      return ::ecc::fail(ECC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                                  \
+  } while (0)
+
+#define ECC_REQ(cond, msg)                                                   \
+  do {                                                                       \
+    if (!(cond)) return ::ecc::fail(ECC_ERR_INVALID_ARGUMENT, (msg));        \
+  } while (0)
+
+#define ECC_TRY(expr)                 \
+  do {                                \
+    ecc_status s_ = (expr);           \
+    if (s_ != ECC_OK) return s_;      \
+  } while (0)
+
+// Makes the context's device current for one API call and clears any error state left
+// behind by earlier HIP calls of the caller, so launch checks report this call's errors.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetLastError();
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+// ---- tiled path
+struct TileChoice {
+  int N = 0, TV = 0, T = 0;
+  double cost = 0;   // modelled time (see pick_tile)
+};
+
+// Block shape for a correlation with filter radius R and U components over `batch`
+// images of ny x nx, among the shapes with block side >= max(16, min_T). `throughput`:
+// cost of a share of a large batch (no rounding to whole waves of workgroups) instead of
+// one launch on its own. Uses the context's measured per-block costs when the autotuner
+// has calibrated them, else a static operation count.
+bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool throughput, int min_T,
+               TileChoice& best);
+// Measures the per-block cost of every compiled block shape on the context's device
+// (once per context; later calls return at once).
+ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
+// Block spectra of a plan for transform length N (cached in the plan).
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out);
+// Per-pixel angle description of a plan's field argument.
+Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, double mul_sign);
+// Any forward operator call (validated arguments) on stream st.
+ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
+                        const float* signal, int ld_signal, const float* field, int ld_field,
+                        float* out, int ld_out, hipStream_t st, void* saved);
+ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx);
+bool overlaps(const void* a, size_t na, const void* b, size_t nb);
+
+}  // namespace ecc

@@ -1,0 +1,389 @@
+// Batches of independent extended correlations (many images, filters and band limits of
+// different sizes) run as a few captured kernel launches, and the block-shape chooser of
+// the tiled path with its on-device calibration.
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <functional>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+#include "api_common.hpp"
+
+using namespace ecc;
+
+namespace ecc {
+namespace {
+
+// compiled block shapes (N, TV) of the tiled path
+const int kShapes[][2] = {{64, 64}, {96, 64}, {128, 64}, {128, 96}};
+
+int cu_count(ecc_context ctx) {
+  if (ctx->num_cus <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0)
+      n = 256;
+    ctx->num_cus = n;
+  }
+  return ctx->num_cus;
+}
+
+int blocks_per_cu(ecc_context ctx, int N, int TV) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_pair(N, TV);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  DeviceGuard dg(ctx->device);
+  const int v = tile_blocks_per_cu(N, TV);
+  cache[key] = v;
+  return v;
+}
+
+}  // namespace
+
+bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool throughput, int min_T,
+               TileChoice& best) {
+  bool found = false;
+  const int cus = cu_count(ctx);
+  for (const auto& c : kShapes) {
+    const int N = c[0], TV = c[1];
+    if (!tile_supported(N, TV)) continue;
+    const int T = std::min(TV, N - 2 * R);
+    if (T < std::max(16, min_T)) continue;
+    const int per_cu = blocks_per_cu(ctx, N, TV);
+    const double blocks = (double)((ny + T - 1) / T) * (double)((nx + T - 1) / T) * batch;
+    const double slots = (double)cus * per_cu;
+    const double waves = throughput ? blocks / slots : std::ceil(blocks / slots);
+    double wave_cost;
+    auto it = ctx->tile_cost.find({N, TV});
+    if (ctx->tile_calibrated && it != ctx->tile_cost.end()) {
+      wave_cost = it->second.a + it->second.b * U;   // measured (ms per wave)
+    } else {
+      // operation count: per block and component N column + T row transforms of length
+      // N; the blocks sharing a CU share its arithmetic units
+      wave_cost = (double)N * (N + T) * std::log2((double)N) * per_cu * (1.0 + U);
+    }
+    const double cost = waves * wave_cost;
+    if (!found || cost < best.cost) {
+      best.N = N;
+      best.TV = TV;
+      best.T = T;
+      best.cost = cost;
+      found = true;
+    }
+  }
+  return found;
+}
+
+ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st) {
+  if (ctx->tile_calibrated) return ECC_OK;
+  DeviceGuard dg(ctx->device);
+  const int cus = cu_count(ctx);
+  const int R = 3;           // any radius leaves the per-block work unchanged
+  const int Ulo = 2, Uhi = 8;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ECC_HIP(hipEventCreate(&e0));
+  ECC_HIP(hipEventCreate(&e1));
+  ecc_status status = ECC_OK;
+  for (const auto& c : kShapes) {
+    const int N = c[0], TV = c[1];
+    if (!tile_supported(N, TV)) continue;
+    const int T = std::min(TV, N - 2 * R);
+    const int per_cu = blocks_per_cu(ctx, N, TV);
+    const long long slots = (long long)cus * per_cu;
+    const int side = (int)std::ceil(std::sqrt(2.0 * (double)slots));   // >= 2 full waves
+    const int n = side * T;
+    const double waves = std::ceil((double)side * side / (double)slots);
+    DevBuf img, fld, out, spec, w;
+    hipError_t e = img.ensure((size_t)n * n * sizeof(float));
+    if (e == hipSuccess) e = fld.ensure((size_t)n * n * sizeof(float));
+    if (e == hipSuccess) e = out.ensure((size_t)n * n * sizeof(float));
+    if (e == hipSuccess) e = spec.ensure((size_t)Uhi * N * N * sizeof(cx<float>));
+    if (e == hipSuccess) e = w.ensure(Uhi * sizeof(float));
+    if (e == hipSuccess) e = hipMemsetAsync(img.p, 0, (size_t)n * n * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(fld.p, 0, (size_t)n * n * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(spec.p, 0, (size_t)Uhi * N * N * sizeof(cx<float>), st);
+    if (e == hipSuccess) e = hipMemsetAsync(w.p, 0, Uhi * sizeof(float), st);
+    Field fl{fld.as<float>(), 0, n, 0, 1.0, 0.0};
+    double best[2] = {1e30, 1e30};
+    for (int u = 0; u < 2 && e == hipSuccess; ++u) {
+      const int U = u ? Uhi : Ulo;
+      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {   // first run warms up
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess)
+          e = launch_tile_corr(st, N, TV, 1, img.as<float>(), 0, n, fl, out.as<float>(), 0, n, n, n, R, T, U,
+                               0, w.as<float>(), 1.f, spec.as<cx<float>>());
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rep > 0) best[u] = std::min(best[u], (double)ms / waves);
+      }
+    }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      status = fail(ECC_ERR_HIP, std::string("block-shape calibration: ") + hipGetErrorString(e));
+      break;
+    }
+    ecc_context_s::TileCost tcost;
+    tcost.b = std::max(0.0, (best[1] - best[0]) / (Uhi - Ulo));
+    tcost.a = std::max(0.0, best[0] - Ulo * tcost.b);
+    ctx->tile_cost[{N, TV}] = tcost;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == ECC_OK) ctx->tile_calibrated = true;
+  return status;
+}
+
+}  // namespace ecc
+
+// =====================================================================================
+struct ecc_batch_plan_s {
+  ecc_context ctx = nullptr;
+  int flags = 0;
+  std::vector<ecc_instance> inst;
+  struct Shape {
+    int N = 0, TV = 0, nwg = 0, nitems = 0;
+    std::vector<int> members;        // instance indices, in descriptor order
+    std::vector<int> T;              // block side per member
+    DevBuf descs, items, off;
+  };
+  std::deque<Shape> shapes;         // deque: elements own device buffers and never move
+  std::vector<int> rest;             // instances for the per-call path
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nblocks = 0;
+  ~ecc_batch_plan_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+namespace {
+
+ecc_status check_instance(ecc_context ctx, const ecc_instance& in) {
+  ECC_REQ(in.plan && in.plan->ctx == ctx, "instance plan is NULL or belongs to another context");
+  ECC_REQ(in.op == ECC_CORRELATION || in.op == ECC_CONVOLUTION, "unknown op");
+  ECC_REQ(in.signal && in.field && in.out, "NULL image pointer");
+  ECC_TRY(validate_images(in.plan, 1, in.ny, in.nx));
+  ECC_REQ(in.ld_signal >= in.nx && in.ld_field >= in.nx && in.ld_out >= in.nx, "row strides must be >= nx");
+  const size_t bo = (size_t)in.ny * in.ld_out * sizeof(float);
+  ECC_REQ(!overlaps(in.out, bo, in.signal, (size_t)in.ny * in.ld_signal * sizeof(float)) &&
+              !overlaps(in.out, bo, in.field, (size_t)in.ny * in.ld_field * sizeof(float)),
+          "out aliases an input");
+  return ECC_OK;
+}
+
+TileArgs make_desc(const ecc_instance& in, int N, int T, const Spectrum* sp) {
+  TileArgs a{};
+  a.H = in.signal;
+  a.planeH = 0;
+  a.ldH = in.ld_signal;
+  a.fld = make_field(in.plan, in.field, 0, in.ld_field, 1.0);
+  a.y = in.out;
+  a.planeY = 0;
+  a.ldY = in.ld_out;
+  a.ny = in.ny;
+  a.nx = in.nx;
+  a.R = in.plan->R;
+  a.T = T;
+  a.tx = (in.nx + T - 1) / T;
+  a.ty = (in.ny + T - 1) / T;
+  a.U = in.plan->U;
+  a.kofs = 0;
+  a.w = in.plan->d_weights.as<float>();
+  a.scale = 1.0f / ((float)N * (float)N);
+  a.Fs = sp->buf.as<cx<float>>();
+  return a;
+}
+
+ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
+  for (auto& sh : bp->shapes) {
+    std::vector<TileArgs> d;
+    for (size_t m = 0; m < sh.members.size(); ++m) {
+      const ecc_instance& in = bp->inst[sh.members[m]];
+      const Spectrum* sp = nullptr;
+      ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp));
+      d.push_back(make_desc(in, sh.N, sh.T[m], sp));
+    }
+    ECC_HIP(sh.descs.ensure(d.size() * sizeof(TileArgs)));
+    ECC_HIP(hipMemcpy(sh.descs.p, d.data(), d.size() * sizeof(TileArgs), hipMemcpyHostToDevice));
+  }
+  return ECC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,
+                                 ecc_batch_plan* out) {
+  ECC_REQ(ctx && out, "NULL argument");
+  *out = nullptr;
+  ECC_REQ(n >= 0 && n <= (1 << 20) && (n == 0 || inst), "bad instance list");
+  ECC_REQ((flags & ~(ECC_BATCH_AUTOTUNE | ECC_BATCH_PERSISTENT)) == 0, "unknown flags");
+  for (int i = 0; i < n; ++i) ECC_TRY(check_instance(ctx, inst[i]));
+  DeviceGuard dg(ctx->device);
+  auto bp = std::make_unique<ecc_batch_plan_s>();
+  bp->ctx = ctx;
+  bp->flags = flags;
+  bp->inst.assign(inst, inst + n);
+  ECC_HIP(hipStreamCreateWithFlags(&bp->cs, hipStreamNonBlocking));
+  if (flags & ECC_BATCH_AUTOTUNE) ECC_TRY(calibrate_tiles(ctx, bp->cs));
+
+  // ---- block shape per instance
+  std::map<std::pair<int, int>, int> shape_of;
+  for (int i = 0; i < n; ++i) {
+    const ecc_instance& in = inst[i];
+    TileChoice tc;
+    const int R = in.plan->R;
+    const int min_T = ctx->strategy == ECC_STRATEGY_AUTO ? 2 * R : 16;
+    const bool tiled = in.op == ECC_CORRELATION && ctx->strategy != ECC_STRATEGY_TWO_PASS &&
+                       pick_tile(ctx, R, in.plan->U, in.ny, in.nx, 1, true, min_T, tc);
+    if (!tiled) {
+      bp->rest.push_back(i);
+      continue;
+    }
+    auto key = std::make_pair(tc.N, tc.TV);
+    auto it = shape_of.find(key);
+    if (it == shape_of.end()) {
+      it = shape_of.emplace(key, (int)bp->shapes.size()).first;
+      bp->shapes.emplace_back();
+      bp->shapes.back().N = tc.N;
+      bp->shapes.back().TV = tc.TV;
+    }
+    bp->shapes[it->second].members.push_back(i);
+    bp->shapes[it->second].T.push_back(tc.T);
+  }
+  ECC_TRY(upload_descs(bp.get(), bp->cs));
+
+  // ---- block lists, longest first
+  const int cus = cu_count(ctx);
+  for (auto& sh : bp->shapes) {
+    struct Item {
+      int desc, block, cost;
+    };
+    std::vector<Item> items;
+    for (size_t m = 0; m < sh.members.size(); ++m) {
+      const ecc_instance& in = inst[sh.members[m]];
+      const int T = sh.T[m];
+      const int nb = ((in.ny + T - 1) / T) * ((in.nx + T - 1) / T);
+      for (int b = 0; b < nb; ++b) items.push_back({(int)m, b, in.plan->U});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    sh.nitems = (int)items.size();
+    bp->nblocks += sh.nitems;
+    std::vector<int2> list;
+    std::vector<int> off;
+    if (flags & ECC_BATCH_PERSISTENT) {
+      // deal the blocks to the least-loaded resident workgroup (greedy, longest first)
+      const int nwg = std::max(1, std::min<int>(sh.nitems, cus * blocks_per_cu(ctx, sh.N, sh.TV)));
+      std::vector<std::vector<int2>> per(nwg);
+      using Load = std::pair<long long, int>;
+      std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+      for (int w = 0; w < nwg; ++w) pq.push({0, w});
+      for (const Item& it : items) {
+        Load l = pq.top();
+        pq.pop();
+        per[l.second].push_back(make_int2(it.desc, it.block));
+        pq.push({l.first + it.cost + 1, l.second});
+      }
+      off.push_back(0);
+      for (auto& v : per) {
+        list.insert(list.end(), v.begin(), v.end());
+        off.push_back((int)list.size());
+      }
+      sh.nwg = nwg;
+    } else {
+      for (const Item& it : items) list.push_back(make_int2(it.desc, it.block));
+      sh.nwg = sh.nitems;
+    }
+    ECC_HIP(sh.items.ensure(std::max<size_t>(1, list.size()) * sizeof(int2)));
+    if (!list.empty()) ECC_HIP(hipMemcpy(sh.items.p, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if (!off.empty()) {
+      ECC_HIP(sh.off.ensure(off.size() * sizeof(int)));
+      ECC_HIP(hipMemcpy(sh.off.p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+  }
+
+  // ---- capture the launches once
+  bool any = false;
+  for (auto& sh : bp->shapes) any = any || sh.nitems > 0;
+  if (any) {
+    ECC_HIP(hipStreamBeginCapture(bp->cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (auto& sh : bp->shapes) {
+      if (sh.nitems == 0 || e != hipSuccess) continue;
+      e = launch_tile_batch(bp->cs, sh.N, sh.TV, sh.nwg, sh.descs.as<TileArgs>(),
+                            (flags & ECC_BATCH_PERSISTENT) ? sh.off.as<int>() : nullptr, sh.items.as<int2>());
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(bp->cs, &g);
+    bp->graph = g;
+    ECC_HIP(e);
+    ECC_HIP(e2);
+    ECC_HIP(hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0));
+  }
+  *out = bp.release();
+  return ECC_OK;
+}
+
+ecc_status ecc_batch_update(ecc_batch_plan bp, const ecc_instance* inst, int n) {
+  ECC_REQ(bp && (n == 0 || inst), "NULL argument");
+  ECC_REQ(n == (int)bp->inst.size(), "instance count differs from the plan");
+  for (int i = 0; i < n; ++i) {
+    const ecc_instance& a = inst[i];
+    const ecc_instance& b = bp->inst[i];
+    ECC_REQ(a.op == b.op && a.plan == b.plan && a.ny == b.ny && a.nx == b.nx,
+            "instance op, plan or size differs from the plan");
+    ECC_TRY(check_instance(bp->ctx, a));
+  }
+  DeviceGuard dg(bp->ctx->device);
+  ECC_HIP(hipStreamSynchronize(bp->cs));
+  bp->inst.assign(inst, inst + n);
+  ECC_TRY(upload_descs(bp, bp->cs));
+  return ECC_OK;
+}
+
+ecc_status ecc_batch_execute(ecc_batch_plan bp, void* stream) {
+  ECC_REQ(bp, "NULL batch plan");
+  DeviceGuard dg(bp->ctx->device);
+  hipStream_t st = S(stream);
+  if (bp->exec) ECC_HIP(hipGraphLaunch(bp->exec, st));
+  for (int i : bp->rest) {
+    const ecc_instance& in = bp->inst[i];
+    ECC_TRY(forward_impl(bp->ctx, in.op, in.plan, 1, in.ny, in.nx, in.signal, in.ld_signal, in.field,
+                         in.ld_field, in.out, in.ld_out, st, nullptr));
+  }
+  return ECC_OK;
+}
+
+ecc_status ecc_batch_info(ecc_batch_plan bp, int* graph_instances, int* launches, int* blocks) {
+  ECC_REQ(bp, "NULL batch plan");
+  int gi = 0, nl = 0;
+  for (auto& sh : bp->shapes) {
+    gi += (int)sh.members.size();
+    nl += sh.nitems > 0 ? 1 : 0;
+  }
+  if (graph_instances) *graph_instances = gi;
+  if (launches) *launches = nl;
+  if (blocks) *blocks = bp->nblocks;
+  return ECC_OK;
+}
+
+ecc_status ecc_batch_plan_destroy(ecc_batch_plan bp) {
+  if (!bp) return ECC_OK;
+  DeviceGuard dg(bp->ctx->device);
+  if (bp->cs) (void)hipStreamSynchronize(bp->cs);
+  (void)hipDeviceSynchronize();
+  delete bp;
+  return ECC_OK;
+}
+
+}  // extern "C"

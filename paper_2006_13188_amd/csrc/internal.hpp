@@ -78,6 +78,13 @@ struct ecc_context_s {
   std::map<std::string, int> tuned;   // shape key -> chosen FFT size
   std::vector<hipEvent_t> stage_events;   // measurement hook (see ecc_set_stage_events)
   std::set<ecc_filter_plan_s*> plans;     // live plans made from this context
+  // measured cost of one full wave of blocks of each tiled shape (N, TV): t = a + b U (ms)
+  struct TileCost {
+    double a = 0, b = 0;
+  };
+  std::map<std::pair<int, int>, TileCost> tile_cost;
+  bool tile_calibrated = false;
+  int num_cus = 0;
 };
 
 struct Spectrum {

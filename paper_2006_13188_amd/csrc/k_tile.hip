@@ -26,19 +26,6 @@ namespace {
 
 constexpr int kTileThreads = 256;
 
-struct TileArgs {
-  const float* H;
-  long long planeH;
-  int ldH;
-  Field fld;
-  float* y;
-  long long planeY;
-  int ldY;
-  int ny, nx, R, T, tx, ty, U, kofs;
-  const float* w;
-  float scale;
-  const cx<float>* Fs;   // U spectra of N x N
-};
 
 // element pos of line `line` in an LDS image of pitch P: along a row (ROWS) or a column
 template <int P, bool ROWS>
@@ -124,27 +111,23 @@ __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw,
   }
 }
 
-// N: transform length; TV: largest valid block side (a multiple of 32); SEPB: the row
-// pass-0 output goes to a second buffer of TV rows (else in place, one more barrier);
-// HALVES: 1 or 2 groups of 256 threads, each with its own LDS image, transforming
-// components c = c0 + half (c0 += HALVES) side by side; the groups' sums are added at
-// the end.
-template <int N, int TV, bool SEPB, int HALVES>
-__global__ void __launch_bounds__(kTileThreads * HALVES) k_tile_corr(TileArgs a) {
+// One block (image img, block index `tile`) with one group of 256 threads, components one
+// after another. N: transform length; TV: largest valid block side (a multiple of 32);
+// SEPB: the row pass-0 output goes to a second buffer of TV rows (else in place, one
+// more barrier). Called by every thread of the workgroup.
+template <int N, int TV, bool SEPB>
+__device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
+  constexpr int HALVES = 1;
   constexpr int M = N / 8, P = N + 1;
   constexpr int NQ0 = (N * M + kTileThreads - 1) / kTileThreads;   // column pass-0 items
   constexpr int NQ2 = (TV * M + kTileThreads - 1) / kTileThreads;  // row pass-0 items
   constexpr int TR = TV / 32, RV = TV / 8;
   constexpr int IMG = (SEPB ? N + TV : N) * P;                      // LDS image per group
   constexpr bool PREFETCH = HALVES == 1 && N <= 96;
-  extern __shared__ cx<float> lds_t[];
-  const int half = threadIdx.x / kTileThreads;
+  const int half = 0;
   const int t = threadIdx.x - half * kTileThreads, bq = t >> 5, l = t & 31;
   cx<float>* A = lds_t + half * IMG;
   cx<float>* Bb = SEPB ? A + N * P : A;
-  const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  const int ntile = a.tx * a.ty;
-  const int img = lb / ntile, tile = lb - img * ntile;
   const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
   const int T = a.T;
 
@@ -155,8 +138,8 @@ __global__ void __launch_bounds__(kTileThreads * HALVES) k_tile_corr(TileArgs a)
     for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
   }
 
-  // ---- signal window into A (real part), zero outside the image; each group keeps
-  // its own copy and transforms it
+  __syncthreads();   // the LDS image may still be in use by the previous block
+  // ---- signal window into A (real part), zero outside the image
   const float* Hb = a.H + (long long)img * a.planeH;
   for (int q = t; q < N * N; q += kTileThreads) {
     const int i = q / N, j = q - (q / N) * N;
@@ -311,24 +294,6 @@ __global__ void __launch_bounds__(kTileThreads * HALVES) k_tile_corr(TileArgs a)
     if constexpr (!SEPB) __syncthreads();   // A is rewritten by the next column pass
   }
 
-  if constexpr (HALVES == 2) {
-    // group 1 hands its sums to group 0 through its own (now idle) LDS image
-    float* xf = reinterpret_cast<float*>(lds_t + IMG);
-    __syncthreads();
-    if (half == 1) {
-#pragma unroll
-      for (int i = 0; i < TR; ++i)
-#pragma unroll
-        for (int r = 0; r < RV; ++r) xf[(i * RV + r) * kTileThreads + t] = acc[i][r];
-    }
-    __syncthreads();
-    if (half == 1) return;
-#pragma unroll
-    for (int i = 0; i < TR; ++i)
-#pragma unroll
-      for (int r = 0; r < RV; ++r) acc[i][r] += xf[(i * RV + r) * kTileThreads + t];
-  }
-
   float* yb = a.y + (long long)img * a.planeY;
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
@@ -352,12 +317,11 @@ __global__ void __launch_bounds__(kTileThreads * HALVES) k_tile_corr(TileArgs a)
 //    bq is uniform in a wave, so its twiddles come from scalar loads, and the thread owns
 //    the 8 pixels (u, bq + 8 r) for all components.
 template <int N>
-__global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
+__device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
   constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
   constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
   constexpr int NH = NF + (REM ? 1 : 0);
   static_assert(REM * 2 <= 2 * kTileThreads, "remainder items exceed one round");
-  extern __shared__ cx<float> lds_t[];
   const int t = threadIdx.x;
   const int g = t / kTileThreads, tg = t - g * kTileThreads;
   const int bq1 = tg >> 5, l1 = tg & 31;                       // column pass 1 mapping
@@ -366,9 +330,6 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
   cx<float>* const A0 = lds_t;
   cx<float>* const A1 = lds_t + N * P;
   cx<float>* const Ag = g ? A1 : A0;
-  const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  const int ntile = a.tx * a.ty;
-  const int img = lb / ntile, tile = lb - img * ntile;
   const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
   const int T = a.T;
   const TileTwiddles<N>& tt = tile_twiddles<N>();
@@ -377,6 +338,7 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
 #pragma unroll
   for (int r = 0; r < M; ++r) tw1[r] = mk(tt.re[bq1][r], tt.im[bq1][r]);
 
+  __syncthreads();   // the LDS images may still be in use by the previous block
   // ---- signal window and its forward transform (each group on its own image)
   const float* Hb = a.H + (long long)img * a.planeH;
   for (int q = tg; q < N * N; q += kTileThreads) {
@@ -503,6 +465,54 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
   }
 }
 
+// One workgroup per block of a (batch of) image(s).
+template <int N, int TV, bool SEPB>
+__global__ void __launch_bounds__(kTileThreads) k_tile_corr_one(TileArgs a) {
+  extern __shared__ cx<float> lds_t[];
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int ntile = a.tx * a.ty;
+  corr_block_one<N, TV, SEPB>(a, lb / ntile, lb % ntile, lds_t);
+}
+template <int N>
+__global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
+  extern __shared__ cx<float> lds_t[];
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int ntile = a.tx * a.ty;
+  corr_block_pair<N>(a, lb / ntile, lb % ntile, lds_t);
+}
+
+// Batches of independent instances (every instance one image); item = (descriptor
+// index, block index).
+// Item-table form: workgroup b runs item b. The host orders the items by decreasing
+// cost, so the hardware dispatcher, which starts workgroups in order as CUs free up,
+// schedules them longest first.
+template <int N, int TV, bool SEPB, int HV>
+__global__ void __launch_bounds__(HV * kTileThreads) k_tile_items(const TileArgs* __restrict__ descs,
+                                                                 const int2* __restrict__ items) {
+  extern __shared__ cx<float> lds_t[];
+  const int2 it = items[blockIdx.x];
+  const TileArgs& a = descs[it.x];
+  if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
+  else corr_block_one<N, TV, SEPB>(a, 0, it.y, lds_t);
+}
+
+// Persistent form: workgroup w runs the blocks items[off[w] .. off[w+1]) one after
+// another (the host deals the items over the workgroups, longest first).
+template <int N, int TV, bool SEPB, int HV>
+__global__ void __launch_bounds__(HV * kTileThreads) k_tile_batch(const TileArgs* __restrict__ descs,
+                                                                 const int* __restrict__ off,
+                                                                 const int2* __restrict__ items) {
+  extern __shared__ cx<float> lds_t[];
+  const int w = blockIdx.x;
+  const int i0 = off[w], i1 = off[w + 1];
+  for (int i = i0; i < i1; ++i) {
+    const int2 it = items[i];
+    const TileArgs& a = descs[it.x];
+    if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
+    else corr_block_one<N, TV, SEPB>(a, 0, it.y, lds_t);
+  }
+}
+
 // LDS of a launch: HV = 1: one image (+ the separate row buffer); HV = 2: the pair
 // kernel's two images.
 template <int N, int TV, bool SEPB, int HV>
@@ -518,7 +528,7 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
     hipLaunchKernelGGL((k_tile_corr_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   } else {
-    hipLaunchKernelGGL((k_tile_corr<N, TV, SEPB, 1>), dim3(nblk), dim3(kTileThreads),
+    hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB>), dim3(nblk), dim3(kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
   return last();
@@ -526,8 +536,11 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
 
 template <int N, int TV, bool SEPB, int HV>
 hipError_t prepare_tile_kernel() {
+  hipError_t e = allow_lds(k_tile_batch<N, TV, SEPB, HV>);
+  if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV>);
+  if (e != hipSuccess) return e;
   if constexpr (HV == 2) return allow_lds(k_tile_corr_pair<N>);
-  else return allow_lds(k_tile_corr<N, TV, SEPB, 1>);
+  else return allow_lds(k_tile_corr_one<N, TV, SEPB>);
 }
 
 }  // namespace
@@ -580,6 +593,53 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   if (N == n && TV == tv) return launch_tile_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
   ECC_TILE_CONFIGS(ECC_TL)
 #undef ECC_TL
+  return hipErrorInvalidValue;
+}
+
+int tile_threads(int N, int TV) {
+#define ECC_TT(n, tv, sb, hv) if (N == n && TV == tv) return hv * kTileThreads;
+  ECC_TILE_CONFIGS(ECC_TT)
+#undef ECC_TT
+  return 0;
+}
+
+int tile_blocks_per_cu(int N, int TV) {
+  int nb = 0;
+#define ECC_TO(n, tv, sb, hv)                                                                   \
+  if (N == n && TV == tv) {                                                                     \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_items<n, tv, sb, hv>,          \
+                                                     hv * kTileThreads,                        \
+                                                     tile_lds<n, tv, sb, hv>()) != hipSuccess)  \
+      nb = 1;                                                                                   \
+    return nb > 0 ? nb : 1;                                                                     \
+  }
+  ECC_TILE_CONFIGS(ECC_TO)
+#undef ECC_TO
+  return 1;
+}
+
+hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileArgs* descs, const int* off,
+                             const int2* items) {
+  if (nwg < 1) return hipErrorInvalidValue;
+  if (off == nullptr) {   // item-table form: one workgroup per item
+#define ECC_TIT(n, tv, sb, hv)                                                                   \
+  if (N == n && TV == tv) {                                                                     \
+    hipLaunchKernelGGL((k_tile_items<n, tv, sb, hv>), dim3(nwg), dim3(hv * kTileThreads),        \
+                       (tile_lds<n, tv, sb, hv>()), s, descs, items);                            \
+    return last();                                                                               \
+  }
+    ECC_TILE_CONFIGS(ECC_TIT)
+#undef ECC_TIT
+    return hipErrorInvalidValue;
+  }
+#define ECC_TBL(n, tv, sb, hv)                                                                   \
+  if (N == n && TV == tv) {                                                                     \
+    hipLaunchKernelGGL((k_tile_batch<n, tv, sb, hv>), dim3(nwg), dim3(hv * kTileThreads),        \
+                       (tile_lds<n, tv, sb, hv>()), s, descs, off, items);                       \
+    return last();                                                                               \
+  }
+  ECC_TILE_CONFIGS(ECC_TBL)
+#undef ECC_TBL
   return hipErrorInvalidValue;
 }
 

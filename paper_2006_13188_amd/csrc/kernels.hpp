@@ -112,8 +112,28 @@ hipError_t launch_corr_rows_fixed(hipStream_t s, int NR, int batch, const cx<flo
 
 // ---- tiled (overlap-save) correlation: one workgroup per T x T output block, N x N
 // transforms on chip (N = 64, 96, 128; TV = 64 or 96 bounds T)
+struct TileArgs {          // one correlation job (batch of images of one shape)
+  const float* H;
+  long long planeH;
+  int ldH;
+  Field fld;
+  float* y;
+  long long planeY;
+  int ldY;
+  int ny, nx, R, T, tx, ty, U, kofs;   // tx, ty: blocks across and down
+  const float* w;
+  float scale;
+  const cx<float>* Fs;     // U block spectra of N x N
+};
 bool tile_supported(int N, int TV);
 size_t tile_lds_bytes(int N, int TV);
+int tile_threads(int N, int TV);
+int tile_blocks_per_cu(int N, int TV);   // resident workgroups per CU (occupancy query)
+// batches: item = (descriptor index, block index). Persistent form (off != NULL): nwg
+// workgroups, workgroup w runs items[off[w] .. off[w+1]). Item-table form (off == NULL):
+// nwg = number of items, workgroup b runs item b.
+hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileArgs* descs, const int* off,
+                             const int2* items);
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,

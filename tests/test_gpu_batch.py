@@ -1,0 +1,144 @@
+"""Batched execution (many uneven correlations in one captured graph) against the float64
+oracle and against one call per instance.
+
+Instances have different image shapes (square and rectangular, ragged against every
+block size), filter sizes 7..63 and band limits; one convolution and one filter too large
+for a block shape exercise the per-call remainder. The graph is replayed several times
+with unrelated eager GPU work in between, and every replay is checked. Tolerance:
+rel-L2 and rel-inf <= 1e-5 against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import batch_instance
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+SHAPES = [(64, 64, 7, 4), (97, 130, 15, 6), (200, 173, 21, 10), (130, 90, 63, 12), (75, 75, 9, 3),
+          (160, 230, 31, 16), (66, 201, 35, 8), (128, 128, 13, 24), (99, 64, 41, 5), (181, 77, 11, 7)]
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def relinf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    import paper_2006_13188_amd as E_
+    assert torch.cuda.is_available()
+    E_.lib()
+    return E_
+
+
+@pytest.fixture(scope="module")
+def setup(E):
+    import torch
+    ctx = E.Context(0)
+    data, insts, refs = [], [], []
+    for i, (ny, nx, S, K) in enumerate(SHAPES):
+        img, filt, th = batch_instance(i, ny, nx, S)
+        plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), K)
+        H, T = torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda()
+        out = torch.full((ny, nx), float("nan"), device="cuda")
+        comps, _ = O.angular_components(filt, K)
+        refs.append(O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
+        insts.append((E.CORRELATION, plan, H, T, out))
+        data.append((img, filt, th, K))
+    # per-call remainder: a convolution and a filter with no block shape (R = 60)
+    img, filt, th = batch_instance(50, 130, 140, 121)
+    plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), 3)
+    comps, _ = O.angular_components(filt, 3)
+    out = torch.full((130, 140), float("nan"), device="cuda")
+    insts.append((E.CORRELATION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
+    refs.append(O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
+    img, filt, th = batch_instance(51, 90, 100, 15)
+    plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), 5)
+    comps, _ = O.angular_components(filt, 5)
+    out = torch.full((90, 100), float("nan"), device="cuda")
+    insts.append((E.CONVOLUTION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
+    refs.append(O.ext_conv_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
+    yield ctx, insts, refs
+    ctx.close()
+
+
+def check_all(insts, refs):
+    import torch
+    torch.cuda.synchronize()
+    for (op, plan, H, T, out), ref in zip(insts, refs):
+        y = out.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(y))
+        assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (H.shape, rel2(y, ref), relinf(y, ref))
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3], ids=["table", "table_autotune", "persistent",
+                                                     "persistent_autotune"])
+def test_batch_matches_oracle_over_replays(E, setup, flags):
+    import torch
+    ctx, insts, refs = setup
+    for *_, out in insts:
+        out.fill_(float("nan"))
+    bp = E.BatchPlan(ctx, insts, flags)
+    info = bp.info()
+    assert info["graph_instances"] == len(SHAPES) and 1 <= info["launches"] <= 4
+    for rep in range(3):
+        for *_, out in insts:
+            out.fill_(float("nan"))
+        bp.execute()
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")   # eager work
+        check_all(insts, refs)
+        assert torch.isfinite(junk).all()
+    bp.close()
+
+
+def test_batch_agrees_with_per_call(E, setup):
+    """One call per instance gives the same values (the block shape chosen for a lone
+    call may differ from the batch's, so up to float32 rounding)."""
+    import torch
+    ctx, insts, refs = setup
+    bp = E.BatchPlan(ctx, insts, 0)
+    bp.execute()
+    torch.cuda.synchronize()
+    for op, plan, H, T, out in insts:
+        y = E.ecc_extended(ctx, op, plan, H, T)
+        torch.cuda.synchronize()
+        assert float((y - out).abs().max()) <= 1e-6 * float(out.abs().max())
+    bp.close()
+
+
+def test_batch_update_pointers(E, setup):
+    import torch
+    ctx, insts, refs = setup
+    bp = E.BatchPlan(ctx, insts, 0)
+    outs2 = [torch.full_like(o, float("nan")) for *_, o in insts]
+    insts2 = [(op, plan, H, T, o2) for (op, plan, H, T, _), o2 in zip(insts, outs2)]
+    bp.update(insts2)
+    bp.execute()
+    check_all(insts2, refs)
+    with pytest.raises(E.EccError):
+        bp.update(insts2[:-1])                       # count differs
+    bad = list(insts2)
+    op, plan, H, T, o = bad[0]
+    bad[0] = (op, plan, H[:-1], T[:-1], o[:-1])      # size differs
+    with pytest.raises(E.EccError):
+        bp.update(bad)
+    bp.close()
+
+
+def test_empty_and_invalid_batches(E, setup):
+    import torch
+    ctx, insts, refs = setup
+    bp = E.BatchPlan(ctx, [], 0)
+    bp.execute()
+    assert bp.info() == {"graph_instances": 0, "launches": 0, "blocks": 0}
+    bp.close()
+    op, plan, H, T, out = insts[0]
+    with pytest.raises(E.EccError):
+        E.BatchPlan(ctx, [(op, plan, H, T, H)], 0)   # aliasing
+    with pytest.raises(E.EccError):
+        E.BatchPlan(ctx, [(op, plan, H, T, out)], 64)   # unknown flag
