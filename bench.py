@@ -98,6 +98,64 @@ def cpu_model():
     return platform.processor()
 
 
+def batch_workload(E, timeit):
+    """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
+    per-instance seeds): one graph-captured batch execution against one call per
+    instance, plans and spectra built beforehand; sampled pixels of a few instances
+    checked against the definition."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from synthetic import batch_instance, batch_shapes
+
+    shapes = batch_shapes(256, 42)
+    ctx = E.Context(0)
+    insts, keep = [], []
+    work = 0
+    for i, (ny, nx, S, K) in enumerate(shapes):
+        img, filt, th = batch_instance(i, ny, nx, S)
+        plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), K)
+        H, T = torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda()
+        out = torch.empty_like(H)
+        insts.append((E.CORRELATION, plan, H, T, out))
+        keep.append((img, filt, th, K))
+        work += ny * nx * (2 * K + 1)
+    res = {"instances": 256, "Mpix_comp": round(work / 1e6, 1)}
+    seq_ms = timeit(lambda: [E.ecc_extended(ctx, op, p, h, t, out=o) for op, p, h, t, o in insts], reps=5)
+    res["sequential_ms"] = round(seq_ms, 3)
+    for name, flags in (("graph_item_table", E.BATCH_AUTOTUNE),
+                        ("graph_persistent", E.BATCH_AUTOTUNE | E.BATCH_PERSISTENT)):
+        bp = E.BatchPlan(ctx, insts, flags)
+        ms = timeit(bp.execute, reps=10)
+        res[name + "_ms"] = round(ms, 3)
+        res[name + "_info"] = bp.info()
+        bp.close()
+    best = min(res["graph_item_table_ms"], res["graph_persistent_ms"])
+    res["speedup_vs_sequential"] = round(seq_ms / best, 3)
+    res["Mpix_comp_per_s"] = round(work / (best * 1e-3) / 1e6, 1)
+    # the last run was the persistent graph: spot-check its outputs
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for i in rng.choice(256, 4, replace=False):
+        img, filt, th, K = keep[i]
+        y = insts[i][4].cpu().numpy().astype(np.float64)
+        comps, _ = O.angular_components(filt, K)
+        R = (filt.shape[0] - 1) // 2
+        Hp = np.pad(img.astype(np.float64), R)
+        for _ in range(4):
+            a, b = int(rng.integers(0, img.shape[0])), int(rng.integers(0, img.shape[1]))
+            Ft = O.rotated_filter(comps, float(th[a, b]))
+            ref = float(np.sum(Hp[a:a + 2 * R + 1, b:b + 2 * R + 1] * np.conj(Ft)).real)
+            worst = max(worst, abs(y[a, b] - ref) / float(np.max(np.abs(y))))
+    res["sampled_max_abs_err_over_max"] = worst
+    for _, p, *_ in insts:
+        p.close()
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +309,7 @@ def main():
         mplan.close()
         plan2.close()
         ctx2.close()
+        extras["batch_256"] = batch_workload(E, timeit)
 
     cpu = None
     if not args.no_cpu:
