@@ -181,12 +181,18 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
                             int ld_scale, float* out, int ld_out, ecc_precision prec,
                             void* stream);
 
-/* Rotation-independent matching (Sec. 5.2 in band-limited form): the correlation
+/* Rotation-independent matching (Sec. 5 in band-limited form): the correlation
  * response at n_angles equispaced angles 2 pi m / n_angles,
  * C(p, m) = sum_k w_k Re(e^{2 pi i k m / n_angles} (H star F_k)(p)); best_score = max_m C,
  * best_index = the smallest maximising m. 2K+1 <= n_angles <= 64.
  * signal: device float32 ny x nx (stride ld); best_score (float32) and best_index
- * (int32): device ny x nx with stride ld_out. */
+ * (int32): device ny x nx with stride ld_out.
+ * With a block shape (TILED / AUTO strategy) the components are computed block by block
+ * into a per-pixel stack in the context's workspace (ny nx round4(2K+2) floats) and the
+ * angle search is a dense product done by `prec`: ECC_PREC_FP32 (float32 multiply-adds),
+ * ECC_PREC_MFMA_FP16_HILO (matrix cores, float16 hi + lo operands, float32 accumulation;
+ * ~1e-6 relative), ECC_PREC_MFMA_BF16_HILO (bfloat16 hi + lo; ~1e-5 relative). The
+ * two-pass strategy supports ECC_PREC_FP32 only (else UNSUPPORTED). */
 ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
                                const float* signal, int ld, int n_angles, float* best_score,
                                int* best_index, int ld_out, ecc_precision prec, void* stream);

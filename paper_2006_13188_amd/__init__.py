@@ -12,14 +12,15 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, GROUP_ROTATION,
-                   GROUP_SCALE, PREC_FP32, STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_TWO_PASS,
-                   EccError, GroupParams, Instance)
+                   GROUP_SCALE, PREC_FP32, PREC_MFMA_BF16_HILO, PREC_MFMA_FP16_HILO, STRATEGY_AUTO,
+                   STRATEGY_TILED, STRATEGY_TWO_PASS, EccError, GroupParams, Instance)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
     "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
+    "PREC_MFMA_FP16_HILO", "PREC_MFMA_BF16_HILO",
     "BATCH_PERSISTENT",
     "GroupParams",
 ]
@@ -197,14 +198,17 @@ def ecc_scale_smooth(ctx: Context, plan: FilterPlan, signal, scale, out=None, st
     return out
 
 
-def ecc_match_rotations(ctx: Context, plan: FilterPlan, signal, n_angles=64, stream=None):
+def ecc_match_rotations(ctx: Context, plan: FilterPlan, signal, n_angles=64, precision=PREC_FP32,
+                        stream=None):
+    """Best angle score and index per pixel (precision: PREC_FP32, PREC_MFMA_FP16_HILO or
+    PREC_MFMA_BF16_HILO for the angle search)."""
     import torch
     _img(signal, "signal")
     ny, nx = signal.shape
     score = torch.empty((ny, nx), dtype=torch.float32, device=signal.device)
     index = torch.empty((ny, nx), dtype=torch.int32, device=signal.device)
     _check(lib().ecc_match_rotations(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), n_angles,
-                                     _ptr(score), _ptr(index), nx, PREC_FP32, _stream(stream)))
+                                     _ptr(score), _ptr(index), nx, precision, _stream(stream)))
     return score, index
 
 

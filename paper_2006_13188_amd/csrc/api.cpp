@@ -776,12 +776,52 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
   ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
   ECC_REQ(plan->group == ECC_GROUP_ROTATION, "matching needs a rotation plan");
   ECC_REQ(signal && best_score && best_index, "NULL pointer");
-  if (prec != ECC_PREC_FP32) return fail(ECC_ERR_UNSUPPORTED, "precision not implemented");
+  ECC_REQ(prec == ECC_PREC_FP32 || prec == ECC_PREC_MFMA_FP16_HILO || prec == ECC_PREC_MFMA_BF16_HILO,
+          "unknown precision");
   ECC_TRY(validate_images(plan, 1, ny, nx));
   ECC_REQ(ld >= nx && ld_out >= nx, "row strides must be >= nx");
   ECC_REQ(n_angles >= 2 * plan->K + 1 && n_angles <= 64, "need 2K+1 <= n_angles <= 64");
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
+  if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
+  const int R = plan->R, U = plan->U;
+  TileChoice tc;
+  bool tiled = false;
+  if (ctx->strategy != ECC_STRATEGY_TWO_PASS)
+    tiled = pick_tile(ctx, R, U, ny, nx, 1, false, ctx->strategy == ECC_STRATEGY_AUTO ? 2 * R : 16, tc);
+  if (ctx->strategy == ECC_STRATEGY_TILED && !tiled)
+    return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
+  if (tiled) {
+    // component stack G_c(p) by blocks, then the angle search (float32 or matrix cores)
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp));
+    if (plan->match_tab_A != n_angles) {
+      std::vector<float> tab(64 * 64, 0.f);
+      for (int m = 0; m < n_angles; ++m)
+        for (int c = 0; c < U; ++c) {
+          const long double a = 2.0L * 3.14159265358979323846264338327950288L * ((long long)c * m % n_angles) / n_angles;
+          tab[m * 64 + 2 * c] = (float)(plan->weights[c] * cosl(a));
+          tab[m * 64 + 2 * c + 1] = (float)(-plan->weights[c] * sinl(a));
+        }
+      ECC_HIP(plan->match_tab.ensure(tab.size() * sizeof(float)));
+      ECC_HIP(hipMemcpy(plan->match_tab.p, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
+      plan->match_tab_A = n_angles;
+    }
+    const int spx = (2 * U + 3) & ~3;
+    const long long npix = (long long)ny * nx;
+    ECC_HIP(ctx->ws.ensure((size_t)npix * spx * sizeof(float)));
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_stack(st, tc.N, tc.TV, signal, ld, ny, nx, R, tc.T, U, 1.0f / ((float)tc.N * (float)tc.N),
+                              sp->buf.as<cx<float>>(), ctx->ws.as<float>(), spx));
+    mark(ctx, 1, st);
+    const int pc = prec == ECC_PREC_FP32 ? 0 : (prec == ECC_PREC_MFMA_FP16_HILO ? 1 : 2);
+    ECC_HIP(launch_match_angles(st, pc, ctx->ws.as<float>(), spx, U, npix, n_angles, plan->match_tab.as<float>(),
+                                best_score, best_index, ld_out, nx));
+    mark(ctx, 2, st);
+    return ECC_OK;
+  }
+  if (prec != ECC_PREC_FP32)
+    return fail(ECC_ERR_UNSUPPORTED, "the matrix-core angle search needs the tiled component stack");
   if (ctx->angle_tab_n != n_angles) {
     std::vector<float> tab(128, 0.f);
     for (int t = 0; t < n_angles; ++t) {

@@ -111,4 +111,6 @@ struct ecc_filter_plan_s {
   std::mutex mu;
   std::map<std::pair<int, int>, std::unique_ptr<Spectrum>> spectra;
   std::map<int, std::unique_ptr<Spectrum>> tile_spectra;   // N -> U planes of N x N
+  ecc::DevBuf match_tab;       // angle-search matrix [64][64] for match_tab_A angles
+  int match_tab_A = 0;
 };

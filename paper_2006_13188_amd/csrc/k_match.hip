@@ -1,0 +1,229 @@
+// Angle search of rotation-invariant matching over a component stack (section 5 in the
+// band-limited form): for every pixel p and angle m < A,
+//   C(p, m) = sum_c Re(e^{2 pi i c m / A} w_c G_c(p))
+//           = sum_k D[m][k] g_k(p),  g = (Re G_0, Im G_0, Re G_1, ...),
+//   D[m][2c] = w_c cos(2 pi c m / A),  D[m][2c+1] = -w_c sin(2 pi c m / A),
+// a dense [A x 2U] by [2U x pixels] product, then the maximum over m and the first m
+// attaining it. Three forms:
+//   * float32 fused multiply-adds, one thread per pixel;
+//   * matrix cores (16x16x16 MFMA) with float16 operands split into hi + lo parts:
+//     D g = D_hi g_hi + D_hi g_lo + D_lo g_hi (the lo*lo term, ~2^-22 relative, dropped),
+//     accumulated in float32; g is scaled per group of 16 pixels by a power of two so
+//     that its largest magnitude lies in [2^10, 2^11) (lo parts stay normal numbers);
+//   * the same with bfloat16 hi + lo parts (about 2^-16 relative per product).
+#include "kcommon.hpp"
+
+namespace ecc {
+
+namespace {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short bf4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int UMAX>
+__global__ void __launch_bounds__(256) k_match_angles_f32(const float* __restrict__ stack, int spx, int U,
+                                                          long long npix, int A, const float* __restrict__ dtab,
+                                                          float* __restrict__ score, int* __restrict__ index,
+                                                          int ldOut, int nx) {
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= npix) return;
+  float g[2 * UMAX];
+  const float* src = stack + p * spx;
+#pragma unroll
+  for (int k = 0; k < 2 * UMAX; k += 4) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < 2 * U) v = *reinterpret_cast<const float4*>(src + k);
+    g[k] = v.x;
+    g[k + 1] = (k + 1 < 2 * U) ? v.y : 0.f;
+    g[k + 2] = (k + 2 < 2 * U) ? v.z : 0.f;
+    g[k + 3] = (k + 3 < 2 * U) ? v.w : 0.f;
+  }
+  float best = -INFINITY;
+  int bi = 0;
+  for (int m = 0; m < A; ++m) {
+    const float* d = dtab + m * 64;
+    float c = 0.f;
+#pragma unroll
+    for (int k = 0; k < 2 * UMAX; ++k) c = fmaf(g[k], d[k], c);
+    if (c > best) {
+      best = c;
+      bi = m;
+    }
+  }
+  const long long y = p / nx, x = p - y * nx;
+  score[y * ldOut + x] = best;
+  index[y * ldOut + x] = bi;
+}
+
+__device__ __forceinline__ short bf16_bits(float x) {   // round to nearest even
+  const unsigned u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
+
+template <bool BF16>
+struct Split;
+template <>
+struct Split<false> {
+  typedef half4_t T;
+  static __device__ __forceinline__ void split(const float* v, T& hi, T& lo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const _Float16 h = (_Float16)v[j];
+      hi[j] = h;
+      lo[j] = (_Float16)(v[j] - (float)h);
+    }
+  }
+  static __device__ __forceinline__ f4_t mma(T a, T b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Split<true> {
+  typedef bf4_t T;
+  static __device__ __forceinline__ void split(const float* v, T& hi, T& lo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const short h = bf16_bits(v[j]);
+      hi[j] = h;
+      lo[j] = bf16_bits(v[j] - bf16_value(h));
+    }
+  }
+  static __device__ __forceinline__ f4_t mma(T a, T b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// One wave per group of 16 pixels (grid-stride over groups). C^T = D (A_mat, M = angles)
+// times g (B_mat, N = pixels): lane l holds D rows 16 mt + l%16, columns 16 s + 4 (l/16)
+// .. + 3, and g of pixel l%16, entries 16 s + 4 (l/16) .. + 3; the result C^T[16 mt +
+// 4 (l/16) + j][l%16] comes back in lane l.
+template <bool BF16, int MT, int KS>
+__global__ void __launch_bounds__(256) k_match_angles_mfma(const float* __restrict__ stack, int spx, int U,
+                                                           long long npix, int A, const float* __restrict__ dtab,
+                                                           float* __restrict__ score, int* __restrict__ index,
+                                                           int ldOut, int nx) {
+  using SP = Split<BF16>;
+  typedef typename SP::T OT;
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lq = l >> 4;
+  OT dh[MT][KS], dl[MT][KS];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = dtab[(16 * mt + lr) * 64 + 16 * s + 4 * lq + j];
+      SP::split(v, dh[mt][s], dl[mt][s]);
+    }
+  const long long ngroups = (npix + 15) / 16;
+  const long long wstep = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long grp = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp < ngroups;
+       grp += wstep) {
+    const long long p = grp * 16 + lr;
+    float v[KS][4];
+    float mx = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 16 * s + 4 * lq;
+      float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (p < npix && k < 2 * U) q = *reinterpret_cast<const float4*>(stack + p * spx + k);
+      v[s][0] = q.x;
+      v[s][1] = (k + 1 < 2 * U) ? q.y : 0.f;
+      v[s][2] = (k + 2 < 2 * U) ? q.z : 0.f;
+      v[s][3] = (k + 3 < 2 * U) ? q.w : 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) mx = fmaxf(mx, fabsf(v[s][j]));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    int ex = 0;
+    (void)frexpf(mx, &ex);
+    const float f = mx > 0.f ? ldexpf(1.f, 11 - ex) : 1.f;   // mx * f in [2^10, 2^11)
+    OT gh[KS], gl[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      float w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = v[s][j] * f;
+      SP::split(w, gh[s], gl[s]);
+    }
+    float best = -INFINITY;
+    int bi = 0;
+    const float inv = 1.f / f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        acc = SP::mma(dh[mt][s], gh[s], acc);
+        acc = SP::mma(dh[mt][s], gl[s], acc);
+        acc = SP::mma(dl[mt][s], gh[s], acc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = 16 * mt + 4 * lq + j;
+        const float c = acc[j] * inv;
+        if (m < A && c > best) {
+          best = c;
+          bi = m;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      const float ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lq == 0 && p < npix) {
+      const long long y = p / nx, x = p - y * nx;
+      score[y * ldOut + x] = best;
+      index[y * ldOut + x] = bi;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int spx, int U, long long npix,
+                               int A, const float* dtab, float* score, int* index, int ldOut, int nx) {
+  if (U < 1 || 2 * U > 64 || A < 1 || A > 64 || spx < 2 * U || (spx & 3) || npix < 1) return hipErrorInvalidValue;
+  if (prec == 0) {
+    const unsigned grid = (unsigned)((npix + 255) / 256);
+#define ECC_MF(UM)                                                                                         \
+  hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, spx, U, npix, A, dtab, \
+                     score, index, ldOut, nx)
+    if (U <= 8) ECC_MF(8);
+    else if (U <= 16) ECC_MF(16);
+    else ECC_MF(32);
+#undef ECC_MF
+    return last();
+  }
+  if (prec != 1 && prec != 2) return hipErrorInvalidValue;
+  const int MT = (A + 15) / 16, KS = (2 * U + 15) / 16;
+  const long long groups = (npix + 15) / 16;
+  const unsigned grid = (unsigned)std::min<long long>((groups + 3) / 4, 256LL * 8);
+#define ECC_MM(BF, mt, ks)                                                                                    \
+  if (MT == mt && KS == ks) {                                                                                 \
+    hipLaunchKernelGGL((k_match_angles_mfma<BF, mt, ks>), dim3(grid), dim3(256), 0, s, stack, spx, U, npix, A, \
+                       dtab, score, index, ldOut, nx);                                                        \
+    return last();                                                                                            \
+  }
+#define ECC_MM_KS(BF, mt) ECC_MM(BF, mt, 1) ECC_MM(BF, mt, 2) ECC_MM(BF, mt, 3) ECC_MM(BF, mt, 4)
+  if (prec == 1) {
+    ECC_MM_KS(false, 1) ECC_MM_KS(false, 2) ECC_MM_KS(false, 3) ECC_MM_KS(false, 4)
+  } else {
+    ECC_MM_KS(true, 1) ECC_MM_KS(true, 2) ECC_MM_KS(true, 3) ECC_MM_KS(true, 4)
+  }
+#undef ECC_MM_KS
+#undef ECC_MM
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ecc

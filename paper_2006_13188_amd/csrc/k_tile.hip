@@ -115,7 +115,7 @@ __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw,
 // after another. N: transform length; TV: largest valid block side (a multiple of 32);
 // SEPB: the row pass-0 output goes to a second buffer of TV rows (else in place, one
 // more barrier). Called by every thread of the workgroup.
-template <int N, int TV, bool SEPB>
+template <int N, int TV, bool SEPB, bool STACK = false>
 __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
   constexpr int HALVES = 1;
   constexpr int M = N / 8, P = N + 1;
@@ -182,7 +182,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
       e1[i][r] = mk(0.f, 0.f);
       const int u = l + 32 * i, x = bq + 8 * r;
       const int gy = y0 + u, gx = x0 + x;
-      if (u < T && x < T && gy < a.ny && gx < a.nx) {
+      if (!STACK && u < T && x < T && gy < a.ny && gx < a.nx) {
         const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
         const int k0 = a.kofs + half;
         cx<float> s1, s0;
@@ -283,10 +283,20 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
 #pragma unroll
           for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
           dft<M, +1, float>(x);
+          if constexpr (STACK) {
 #pragma unroll
-          for (int r = 0; r < RV; ++r) {
-            acc[i][r] += wc * (z[i][r].re * x[r].re - z[i][r].im * x[r].im);
-            z[i][r] = cmul(z[i][r], e1[i][r]);
+            for (int r = 0; r < RV; ++r) {
+              const int xx = bq + 8 * r, gy = y0 + u, gx = x0 + xx;
+              if (xx < T && gy < a.ny && gx < a.nx)
+                *reinterpret_cast<float2*>(a.stack + ((long long)gy * a.nx + gx) * a.spx + 2 * c) =
+                    make_float2(x[r].re * a.scale, x[r].im * a.scale);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < RV; ++r) {
+              acc[i][r] += wc * (z[i][r].re * x[r].re - z[i][r].im * x[r].im);
+              z[i][r] = cmul(z[i][r], e1[i][r]);
+            }
           }
         }
       }
@@ -294,14 +304,16 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     if constexpr (!SEPB) __syncthreads();   // A is rewritten by the next column pass
   }
 
-  float* yb = a.y + (long long)img * a.planeY;
+  if constexpr (!STACK) {
+    float* yb = a.y + (long long)img * a.planeY;
 #pragma unroll
-  for (int i = 0; i < TR; ++i) {
+    for (int i = 0; i < TR; ++i) {
 #pragma unroll
-    for (int r = 0; r < RV; ++r) {
-      const int u = l + 32 * i, x = bq + 8 * r;
-      const int gy = y0 + u, gx = x0 + x;
-      if (u < T && x < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[i][r] * a.scale;
+      for (int r = 0; r < RV; ++r) {
+        const int u = l + 32 * i, x = bq + 8 * r;
+        const int gy = y0 + u, gx = x0 + x;
+        if (u < T && x < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[i][r] * a.scale;
+      }
     }
   }
 }
@@ -316,7 +328,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
 //  * row pass 1: thread (row u = t mod 64, butterfly bq = t / 64) does both components;
 //    bq is uniform in a wave, so its twiddles come from scalar loads, and the thread owns
 //    the 8 pixels (u, bq + 8 r) for all components.
-template <int N>
+template <int N, bool STACK = false>
 __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
   constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
   constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
@@ -382,7 +394,7 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     z[r] = mk(0.f, 0.f);
     e1[r] = mk(0.f, 0.f);
     const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
-    if (rowok && x < T && gx < a.nx) {
+    if (!STACK && rowok && x < T && gx < a.nx) {
       const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
       if (a.fld.log_mode || a.kofs != 0) {
         const double al = field_angle(a.fld, fv);
@@ -445,11 +457,21 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
 #pragma unroll
           for (int r = 1; r < M; ++r) x[r] = cmul(x[r], mk(tt.re[bq4][r], tt.im[bq4][r]));
           dft<M, +1, float>(x);
-          const float wc = a.w[c + cc];
+          if constexpr (STACK) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            acc[r] += wc * (z[r].re * x[r].re - z[r].im * x[r].im);
-            z[r] = cmul(z[r], e1[r]);
+            for (int r = 0; r < 8; ++r) {
+              const int xx = bq4 + 8 * r, gx = x0 + xx;
+              if (rowok && xx < T && gx < a.nx)
+                *reinterpret_cast<float2*>(a.stack + ((long long)(y0 + u4) * a.nx + gx) * a.spx + 2 * (c + cc)) =
+                    make_float2(x[r].re * a.scale, x[r].im * a.scale);
+            }
+          } else {
+            const float wc = a.w[c + cc];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+              acc[r] += wc * (z[r].re * x[r].re - z[r].im * x[r].im);
+              z[r] = cmul(z[r], e1[r]);
+            }
           }
         }
       }
@@ -457,11 +479,13 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     __syncthreads();   // the images are rewritten by the next column pass
   }
 
-  float* yb = a.y + (long long)img * a.planeY;
+  if constexpr (!STACK) {
+    float* yb = a.y + (long long)img * a.planeY;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
-    if (rowok && x < T && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+    for (int r = 0; r < 8; ++r) {
+      const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
+      if (rowok && x < T && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+    }
   }
 }
 
@@ -479,6 +503,21 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
   corr_block_pair<N>(a, lb / ntile, lb % ntile, lds_t);
+}
+
+// Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
+// a.stack[(y * nx + x) * spx + 2c] (interleaved re, im; spx floats per pixel).
+template <int N, int TV, bool SEPB>
+__global__ void __launch_bounds__(kTileThreads) k_tile_stack_one(TileArgs a) {
+  extern __shared__ cx<float> lds_t[];
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  corr_block_one<N, TV, SEPB, true>(a, 0, lb, lds_t);
+}
+template <int N>
+__global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a) {
+  extern __shared__ cx<float> lds_t[];
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  corr_block_pair<N, true>(a, 0, lb, lds_t);
 }
 
 // Batches of independent instances (every instance one image); item = (descriptor
@@ -535,8 +574,24 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
 }
 
 template <int N, int TV, bool SEPB, int HV>
+hipError_t launch_stack_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
+  if constexpr (HV == 2) {
+    hipLaunchKernelGGL((k_tile_stack_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
+                       (tile_lds<N, TV, SEPB, HV>()), s, a);
+  } else {
+    hipLaunchKernelGGL((k_tile_stack_one<N, TV, SEPB>), dim3(nblk), dim3(kTileThreads),
+                       (tile_lds<N, TV, SEPB, HV>()), s, a);
+  }
+  return last();
+}
+
+template <int N, int TV, bool SEPB, int HV>
 hipError_t prepare_tile_kernel() {
   hipError_t e = allow_lds(k_tile_batch<N, TV, SEPB, HV>);
+  if (e == hipSuccess) {
+    if constexpr (HV == 2) e = allow_lds(k_tile_stack_pair<N>);
+    else e = allow_lds(k_tile_stack_one<N, TV, SEPB>);
+  }
   if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV>);
   if (e != hipSuccess) return e;
   if constexpr (HV == 2) return allow_lds(k_tile_corr_pair<N>);
@@ -568,7 +623,7 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
                             const cx<float>* Fs) {
   if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
-  TileArgs a;
+  TileArgs a{};
   a.H = H;
   a.planeH = planeH;
   a.ldH = ldH;
@@ -593,6 +648,31 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   if (N == n && TV == tv) return launch_tile_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
   ECC_TILE_CONFIGS(ECC_TL)
 #undef ECC_TL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
+                             int T, int U, float scale, const cx<float>* Fs, float* stack, int spx) {
+  if (T < 1 || T > TV || T > N - 2 * R || spx < 2 * U || (spx & 1)) return hipErrorInvalidValue;
+  TileArgs a{};
+  a.H = H;
+  a.ldH = ldH;
+  a.ny = ny;
+  a.nx = nx;
+  a.R = R;
+  a.T = T;
+  a.tx = (nx + T - 1) / T;
+  a.ty = (ny + T - 1) / T;
+  a.U = U;
+  a.scale = scale;
+  a.Fs = Fs;
+  a.stack = stack;
+  a.spx = spx;
+  const long long nblk = (long long)a.tx * a.ty;
+#define ECC_TSK(n, tv, sb, hv) \
+  if (N == n && TV == tv) return launch_stack_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
+  ECC_TILE_CONFIGS(ECC_TSK)
+#undef ECC_TSK
   return hipErrorInvalidValue;
 }
 
