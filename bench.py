@@ -98,6 +98,56 @@ def cpu_model():
     return platform.processor()
 
 
+def matching_precisions(E, ctx, stream, timeit):
+    """64-angle rotation matching of a 1024^2 scene with a 63x63 pattern (K = 16): the
+    component stack by blocks, then the angle search in float32, float16 hi/lo and
+    bfloat16 hi/lo on matrix cores; time per call and per stage, and the error of each
+    against the float64 oracle (full image)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from synthetic import matching_scene
+
+    scene, pat, _ = matching_scene(N, 63)
+    Hs = torch.from_numpy(scene).cuda()
+    mplan = E.FilterPlan.rotation(ctx, torch.from_numpy(pat).cuda(), K)
+    comps, _ = O.angular_components(pat, K)
+    ref, _, Cref = O.match_rotations(scene.astype(np.float64), comps, 64)
+    srt = np.sort(Cref, axis=0)
+    scale = float(np.max(np.abs(Cref)))
+    res = {"workload": "64-angle rotation matching, 1024x1024 scene, 63x63 pattern, K=16"}
+    for name, prec in (("fp32", E.PREC_FP32), ("fp16_hilo", E.PREC_MFMA_FP16_HILO),
+                       ("bf16_hilo", E.PREC_MFMA_BF16_HILO)):
+        fn = lambda: E.ecc_match_rotations(ctx, mplan, Hs, 64, precision=prec)   # noqa: E731
+        fn()
+        ms = timeit(fn, reps=20)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        for e in evs:
+            e.record(stream)
+        torch.cuda.synchronize()
+        arr = (C.c_void_p * 3)(*[C.c_void_p(e.cuda_event) for e in evs])
+        E.lib().ecc_set_stage_events(ctx.h, arr, 3)
+        score, index = fn()
+        E.lib().ecc_set_stage_events(ctx.h, None, 0)
+        torch.cuda.synchronize()
+        sc = score.cpu().numpy().astype(np.float64)
+        ix = index.cpu().numpy()
+        clear = (srt[-1] - srt[-2]) > 1e-3 * scale
+        res[name] = {
+            "ms": round(ms, 4),
+            "stack_ms": round(evs[0].elapsed_time(evs[1]), 4),
+            "angle_search_ms": round(evs[1].elapsed_time(evs[2]), 4),
+            "score_max_abs_err_over_max": float(np.max(np.abs(sc - ref)) / np.max(np.abs(ref))),
+            "index_agreement_where_margin_gt_1e-3": float(np.mean(ix[clear] == np.argmax(Cref, axis=0)[clear])),
+        }
+    res["speedup_fp16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["fp16_hilo"]["ms"], 3)
+    res["speedup_bf16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["bf16_hilo"]["ms"], 3)
+    res["angle_search_speedup_fp16_hilo"] = round(res["fp32"]["angle_search_ms"] / res["fp16_hilo"]["angle_search_ms"], 3)
+    mplan.close()
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -299,14 +349,7 @@ def main():
         conv_ms = timeit(lambda: E.ecc_extended(ctx, E.CONVOLUTION, plan, H, TH, out2))
         extras["convolution_ms"] = round(conv_ms, 4)
         extras["convolution_Mpix_comp_s"] = round(N * N * (2 * K + 1) / (conv_ms * 1e-3) / 1e6, 1)
-        from synthetic import matching_scene
-        scene, pat, _ = matching_scene(N, 63)
-        Hs = torch.from_numpy(scene).cuda()
-        mplan = E.FilterPlan.rotation(ctx, torch.from_numpy(pat).cuda(), K)
-        E.ecc_match_rotations(ctx, mplan, Hs, 64)
-        match_ms = timeit(lambda: E.ecc_match_rotations(ctx, mplan, Hs, 64), reps=20)
-        extras["matching_64_angles_ms"] = round(match_ms, 4)
-        mplan.close()
+        extras["mixed_precision"] = matching_precisions(E, ctx, stream, timeit)
         plan2.close()
         ctx2.close()
         extras["batch_256"] = batch_workload(E, timeit)

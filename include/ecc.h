@@ -63,7 +63,8 @@ typedef enum {
  * an N x N window (N - 2R >= T) entirely on chip, per component, then combined per
  * pixel (block shapes exist for R <= 56). AUTO takes TILED when a block shape with side
  * T >= 2R exists, choosing among those by a cost model (measured when the autotuner is
- * on). Convolution, matching and the adjoint always use TWO_PASS. */
+ * on). Correlation, convolution, scale smoothing and matching have both forms; the
+ * adjoint always uses TWO_PASS. */
 typedef enum {
   ECC_STRATEGY_AUTO = 0,
   ECC_STRATEGY_TWO_PASS = 1,

@@ -124,9 +124,10 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
 namespace ecc {
 // Block spectra for the tiled path: FFT_N x N(F_k placed with its window corner at
 // (0, 0)), float64 then rounded, full N x N planes (no symmetry assumed).
-ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out) {
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, bool conv) {
   std::lock_guard<std::mutex> g(plan->mu);
-  auto it = plan->tile_spectra.find(N);
+  const int key = conv ? -N : N;
+  auto it = plan->tile_spectra.find(key);
   if (it != plan->tile_spectra.end()) {
     *out = it->second.get();
     return ECC_OK;
@@ -137,6 +138,8 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   sp->Py = sp->Px = sp->ld = N;
   sp->full = 1;
   const int U = plan->U, Sz = plan->S;
+  // correlation: F_k with its window corner at (0, 0); convolution: offset x at x - R
+  const int shift = conv ? -2 * plan->R : 0;
   DevBuf tmp, spec64;
   ECC_HIP(tmp.ensure((size_t)U * Sz * N * sizeof(cx<double>)));
   ECC_HIP(spec64.ensure((size_t)U * N * N * sizeof(cx<double>)));
@@ -146,15 +149,15 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   ECC_TRY(check_cfg_row(rc, *Tn, sizeof(cx<double>), "filter row"));
   ECC_TRY(check_cfg_col(cc, *Tn, sizeof(cx<double>), "filter column", false));
   ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
-                                   Sz, Sz, 0, tmp.as<cx<double>>(), (long long)Sz * N, N, N, 0,
+                                   Sz, Sz, shift, tmp.as<cx<double>>(), (long long)Sz * N, N, N, 0,
                                    Tn->desc, Tn->d())));
-  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, 0,
+  ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, shift,
                                    spec64.as<cx<double>>(), (long long)N * N, N, N, 0, Tn->desc,
                                    Tn->d())));
   ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * N * N));
   ECC_HIP(hipStreamSynchronize(st));
   *out = sp.get();
-  plan->tile_spectra[N] = std::move(sp);
+  plan->tile_spectra[key] = std::move(sp);
   return ECC_OK;
 }
 }  // namespace ecc
@@ -630,13 +633,14 @@ namespace {
 ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx, int batch,
                             ecc_strategy* used, TileChoice* tc) {
   *used = ECC_STRATEGY_TWO_PASS;
-  if (op != ECC_CORRELATION) return ECC_OK;
+  auto pick = [&](int min_T) {
+    return op == ECC_CORRELATION ? pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, min_T, *tc)
+                                 : pick_tile_conv(ctx, plan->R, plan->U, ny, nx, batch, min_T, *tc);
+  };
   if (ctx->strategy == ECC_STRATEGY_TILED) {
-    if (!pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, 16, *tc))
-      return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
+    if (!pick(16)) return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
     *used = ECC_STRATEGY_TILED;
-  } else if (ctx->strategy == ECC_STRATEGY_AUTO &&
-             pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, 2 * plan->R, *tc)) {
+  } else if (ctx->strategy == ECC_STRATEGY_AUTO && pick(2 * plan->R)) {
     *used = ECC_STRATEGY_TILED;
   }
   return ECC_OK;
@@ -652,6 +656,32 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   ecc_strategy strat;
   TileChoice tc;
   ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc));
+  if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION) {
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, true));
+    TileConvArgs ca{};
+    ca.H = signal;
+    ca.planeH = pS;
+    ca.ldH = ld_signal;
+    ca.fld = make_field(plan, field, pF, ld_field, 1.0);
+    ca.sig_norm = 0;
+    ca.nsig = 1;
+    ca.y = out;
+    ca.planeY = pO;
+    ca.ldY = ld_out;
+    ca.ny = ny;
+    ca.nx = nx;
+    ca.R = plan->R;
+    ca.T = tc.T;
+    ca.U = plan->U;
+    ca.w = plan->d_weights.as<float>();
+    ca.scale = 1.0f / ((float)tc.N * (float)tc.N);
+    ca.Fs = sp->buf.as<cx<float>>();
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_conv(st, tc.N, tc.TV, batch, ca));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   if (strat == ECC_STRATEGY_TILED) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp));
@@ -757,6 +787,36 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
           "out aliases an input");
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
+  TileChoice tc;
+  bool tiled = false;
+  if (ctx->strategy != ECC_STRATEGY_TWO_PASS)
+    tiled = pick_tile_conv(ctx, plan->R, plan->U, ny, nx, 1, ctx->strategy == ECC_STRATEGY_AUTO ? 2 * plan->R : 16, tc);
+  if (ctx->strategy == ECC_STRATEGY_TILED && !tiled)
+    return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
+  if (tiled) {
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, true));
+    TileConvArgs ca{};
+    ca.H = signal;
+    ca.ldH = ld_signal;
+    ca.fld = make_field(plan, scale_, 0, ld_scale, 1.0);
+    ca.sig_norm = 1;
+    ca.nsig = 2;
+    ca.y = out;
+    ca.ldY = ld_out;
+    ca.ny = ny;
+    ca.nx = nx;
+    ca.R = plan->R;
+    ca.T = tc.T;
+    ca.U = plan->U;
+    ca.w = plan->d_weights.as<float>();
+    ca.scale = 1.0f;
+    ca.Fs = sp->buf.as<cx<float>>();
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_conv(st, tc.N, tc.TV, 1, ca));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   const long long pB = 2LL * plan->U * ny * g.Px, pC = 2LL * ny * g.Px;

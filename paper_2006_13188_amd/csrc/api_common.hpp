@@ -66,8 +66,11 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
 // Measures the per-block cost of every compiled block shape on the context's device
 // (once per context; later calls return at once).
 ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
-// Block spectra of a plan for transform length N (cached in the plan).
-ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out);
+// Same choice for the tiled convolution (static operation count).
+bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best);
+// Block spectra of a plan for transform length N (cached in the plan): for correlation
+// (F_k with its window corner at (0, 0)) or convolution (offset x at (x - R) mod N).
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, bool conv = false);
 // Per-pixel angle description of a plan's field argument.
 Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, double mul_sign);
 // Any forward operator call (validated arguments) on stream st.

@@ -78,6 +78,28 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
   return found;
 }
 
+bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best) {
+  bool found = false;
+  const int cus = cu_count(ctx);
+  for (const auto& c : kShapes) {
+    const int N = c[0], TV = c[1];
+    if (!tconv_supported(N, TV)) continue;
+    const int T = std::min(TV, N - 2 * R);
+    if (T < std::max(16, min_T)) continue;
+    const double blocks = (double)((ny + T - 1) / T) * (double)((nx + T - 1) / T) * batch;
+    // per block and component 2N forward transforms of length N, one workgroup per CU
+    const double cost = std::ceil(blocks / cus) * (double)N * (2 * N) * std::log2((double)N) * (1.0 + U);
+    if (!found || cost < best.cost) {
+      best.N = N;
+      best.TV = TV;
+      best.T = T;
+      best.cost = cost;
+      found = true;
+    }
+  }
+  return found;
+}
+
 ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st) {
   if (ctx->tile_calibrated) return ECC_OK;
   DeviceGuard dg(ctx->device);

@@ -346,12 +346,14 @@ hipError_t prepare_corr_kernels();
 hipError_t prepare_conv_kernels();
 hipError_t prepare_fixed_kernels();
 hipError_t prepare_tile_kernels();
+hipError_t prepare_tconv_kernels();
 
 hipError_t prepare_kernels() {
   hipError_t e = prepare_corr_kernels();
   if (e == hipSuccess) e = prepare_conv_kernels();
   if (e == hipSuccess) e = prepare_fixed_kernels();
   if (e == hipSuccess) e = prepare_tile_kernels();
+  if (e == hipSuccess) e = prepare_tconv_kernels();
 #define ECC_ALLOW(...) if (e == hipSuccess) e = allow_lds(__VA_ARGS__)
 #define ECC_ALLOW_NB(KN) ECC_ALLOW(KN<1>); ECC_ALLOW(KN<2>); ECC_ALLOW(KN<4>)
 #define ECC_ALLOW_NB_E(KN, E) ECC_ALLOW(KN<1, E>); ECC_ALLOW(KN<2, E>); ECC_ALLOW(KN<4, E>)

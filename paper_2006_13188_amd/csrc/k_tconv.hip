@@ -1,0 +1,236 @@
+// Tiled (overlap-save) extended convolution: every workgroup owns one T x T block of
+// output pixels and computes it on chip.
+//
+// For component c the block's N x N window of the modulated signal
+// m_c(q) = s(q) e^{-i c alpha(q)} (q = (y0 - R + i, x0 - R + j), zero outside the image) is
+// transformed, multiplied by the block spectrum of F_c and accumulated over components
+// with the weights w_c in the frequency domain (one register accumulator per frequency
+// bin, owned by the same thread for all components); one inverse transform at the end
+// gives y = Re sum_c w_c (m_c * F_c) (section 4, extended convolution by Fourier-domain
+// products). F_c is placed at circular index (x - R) mod N for its offsets x in [-R, R],
+// so circular output index u < N - 2R is the linear convolution at y0 + u.
+//
+// With two signals (scale group, ratio form of eq. normalization) the numerator signal
+// H / f^2 and the denominator signal 1 / f^2 share the phases; both are accumulated and
+// the output is the ratio of the two real parts.
+#include <type_traits>
+
+#include "tile_common.hpp"
+
+namespace ecc {
+
+namespace {
+
+// NT threads (256 or 512); LS = NT / 8 threads share each pass-1 butterfly index.
+template <int N, int TV, int NSIG, int NT>
+__device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
+  constexpr int M = N / 8, P = N + 1, LS = NT / 8;
+  constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
+  constexpr int NI = N / LS;                   // pass-1 lines per thread
+  constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
+  const int t = threadIdx.x, l = t % LS;
+  // with 512 threads the butterfly index is the wave index: uniform, so its twiddles sit
+  // in scalar registers
+  const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
+  const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
+  const int T = a.T;
+  const TileTwiddles<N>& tt = tile_twiddles<N>();
+  cx<float> tw[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+
+  float out0[TR][RV], out1[TR][RV];
+  const float* Hb = a.H + (long long)img * a.planeH;
+  __syncthreads();   // the LDS image may still be in use by the previous block
+  // one signal at a time (the denominator signal of the ratio form reuses the registers)
+  auto one_signal = [&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    // ---- window pixels of this thread's column pass-0 items: z = s(q) e^{-i c alpha(q)}
+    // for the current component c (starting at c = 0), advanced by e1 = e^{-i alpha}
+    cx<float> z[NQ0][8], e1[NQ0][8];
+#pragma unroll
+    for (int s = 0; s < NQ0; ++s) {
+      const int q = t + s * NT;
+      const int v = q % N, b = q / N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int gy = y0 - a.R + b + M * r, gx = x0 - a.R + v;
+        z[s][r] = mk(0.f, 0.f);
+        e1[s][r] = mk(0.f, 0.f);
+        if (b < M && gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) {
+          const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+          float sn, cs;
+          if (a.fld.log_mode) {
+            double dsn, dcs;
+            sincos(field_angle(a.fld, fv), &dsn, &dcs);
+            sn = (float)dsn;
+            cs = (float)dcs;
+          } else {
+            sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
+          }
+          e1[s][r] = mk(cs, -sn);
+          const float wn = a.sig_norm ? 1.f / (fv * fv) : 1.f;
+          z[s][r] = mk(g == 0 ? Hb[(long long)gy * a.ldH + gx] * wn : wn, 0.f);
+        }
+      }
+    }
+    cx<float> Z[NI][M];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int r = 0; r < M; ++r) Z[i][r] = mk(0.f, 0.f);
+
+    for (int c = 0; c < a.U; ++c) {
+      const cx<float>* Fc = a.Fs + (long long)c * N * N;
+      const float wc = a.w[c];
+      // ---- forward transform of m_c: column pass 0 from registers
+#pragma unroll
+      for (int s = 0; s < NQ0; ++s) {
+        const int q = t + s * NT;
+        const int v = q % N, b = q / N;
+        if (b < M) {
+          cx<float> x[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            x[r] = z[s][r];
+            z[s][r] = cmul(z[s][r], e1[s][r]);
+          }
+          dft<8, -1, float>(x);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
+        }
+      }
+      __syncthreads();
+      pass1_inplace<N, -1, false, NI, NT>(A, tw, bq, l, N, N);
+      __syncthreads();
+      pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
+      __syncthreads();
+      // ---- row pass 1 and the weighted product with the filter spectrum
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int u = l + LS * i;
+        cx<float> x[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[r] = A[u * P + bq + 8 * r];
+#pragma unroll
+        for (int r = 1; r < M; ++r) x[r] = cmulc(x[r], tw[r]);
+        dft<M, -1, float>(x);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          const cx<float> pr = cmul(x[r], Fc[u * N + bq + 8 * r]);
+          Z[i][r].re += wc * pr.re;
+          Z[i][r].im += wc * pr.im;
+        }
+      }
+      __syncthreads();   // the image is rewritten next
+    }
+
+    // ---- inverse transform; real parts of the T x T block
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int r = 0; r < M; ++r) A[(l + LS * i) * P + bq + 8 * r] = Z[i][r];
+    __syncthreads();
+    pass0_inplace<N, +1, false, N, NT>(A, t, N, true);
+    __syncthreads();
+    pass1_inplace<N, +1, false, NI, NT>(A, tw, bq, l, N, T);
+    __syncthreads();
+    pass0_inplace<N, +1, true, TV, NT>(A, t, T, true);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const int u = l + LS * i;
+      cx<float> x[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) x[r] = (u < T) ? A[u * P + bq + 8 * r] : mk(0.f, 0.f);
+#pragma unroll
+      for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
+      dft<M, +1, float>(x);
+#pragma unroll
+      for (int r = 0; r < RV; ++r) {
+        if constexpr (g == 0) out0[i][r] = x[r].re;
+        else out1[i][r] = x[r].re;
+      }
+    }
+    __syncthreads();
+    };
+  one_signal(std::integral_constant<int, 0>());
+  if constexpr (NSIG == 2) one_signal(std::integral_constant<int, 1>());
+  float* yb = a.y + (long long)img * a.planeY;
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+#pragma unroll
+    for (int r = 0; r < RV; ++r) {
+      const int u = l + LS * i, x = bq + 8 * r;
+      const int gy = y0 + u, gx = x0 + x;
+      if (u < T && x < T && gy < a.ny && gx < a.nx)
+        yb[(long long)gy * a.ldY + gx] = NSIG == 2 ? out0[i][r] / out1[i][r] : out0[i][r] * a.scale;
+    }
+  }
+}
+
+// threads per workgroup: 512 when every pass divides evenly (N = 64, 128), else 256
+template <int N>
+constexpr int tconv_threads() {
+  return N == 96 ? 256 : 512;
+}
+
+template <int N, int TV, int NSIG>
+__global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a) {
+  extern __shared__ cx<float> lds_c[];
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int ntile = a.tx * a.ty;
+  conv_block_one<N, TV, NSIG, tconv_threads<N>()>(a, lb / ntile, lb % ntile, lds_c);
+}
+
+template <int N>
+constexpr size_t tconv_lds() {
+  return (size_t)N * (N + 1) * sizeof(cx<float>);
+}
+
+}  // namespace
+
+#define ECC_TCONV_CONFIGS(X) X(64, 64) X(96, 64) X(128, 64) X(128, 96)
+
+bool tconv_supported(int N, int TV) {
+#define ECC_CS(n, tv) if (N == n && TV == tv) return true;
+  ECC_TCONV_CONFIGS(ECC_CS)
+#undef ECC_CS
+  return false;
+}
+
+hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a0) {
+  TileConvArgs a = a0;
+  if (a.T < 1 || a.T > TV || a.T > N - 2 * a.R || (a.nsig != 1 && a.nsig != 2)) return hipErrorInvalidValue;
+  a.tx = (a.nx + a.T - 1) / a.T;
+  a.ty = (a.ny + a.T - 1) / a.T;
+  const long long nblk = (long long)a.tx * a.ty * batch;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+#define ECC_CL(n, tv)                                                                              \
+  if (N == n && TV == tv) {                                                                       \
+    if (a.nsig == 1)                                                                              \
+      hipLaunchKernelGGL((k_tile_conv<n, tv, 1>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
+                         tconv_lds<n>(), s, a);                                                   \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_tile_conv<n, tv, 2>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
+                         tconv_lds<n>(), s, a);                                                   \
+    return last();                                                                                \
+  }
+  ECC_TCONV_CONFIGS(ECC_CL)
+#undef ECC_CL
+  return hipErrorInvalidValue;
+}
+
+size_t tconv_lds_bytes(int N) { return (size_t)N * (N + 1) * sizeof(cx<float>); }
+
+hipError_t prepare_tconv_kernels() {
+  hipError_t e = hipSuccess;
+#define ECC_CP(n, tv)                                              \
+  if (e == hipSuccess) e = allow_lds(k_tile_conv<n, tv, 1>);       \
+  if (e == hipSuccess) e = allow_lds(k_tile_conv<n, tv, 2>);
+  ECC_TCONV_CONFIGS(ECC_CP)
+#undef ECC_CP
+  return e;
+}
+
+}  // namespace ecc

@@ -18,98 +18,11 @@
 // last pass works in place). A 2D transform is a column pass pair then a row pass pair
 // on an LDS image of N rows with an odd pitch (conflict-free both along rows and
 // columns). Only the T valid rows are carried from the column to the row transforms.
-#include "kcommon.hpp"
+#include "tile_common.hpp"
 
 namespace ecc {
 
 namespace {
-
-constexpr int kTileThreads = 256;
-
-
-// element pos of line `line` in an LDS image of pitch P: along a row (ROWS) or a column
-template <int P, bool ROWS>
-__device__ __forceinline__ int at(int line, int pos) {
-  return ROWS ? line * P + pos : pos * P + line;
-}
-
-// Pass-1 twiddles w^{r b} (w = exp(2 pi i / N), b < 8, r < N/8), float64 rounded once.
-template <int N>
-struct TileTwiddles {
-  float re[8][N / 8], im[8][N / 8];
-};
-template <int N>
-constexpr TileTwiddles<N> make_tile_twiddles() {
-  TileTwiddles<N> t{};
-  for (int b = 0; b < 8; ++b)
-    for (int r = 0; r < N / 8; ++r) {
-      t.re[b][r] = (float)cos_turn((long)r * b, N);
-      t.im[b][r] = (float)sin_turn((long)r * b, N);
-    }
-  return t;
-}
-__constant__ TileTwiddles<64> kTw64 = make_tile_twiddles<64>();
-__constant__ TileTwiddles<96> kTw96 = make_tile_twiddles<96>();
-__constant__ TileTwiddles<128> kTw128 = make_tile_twiddles<128>();
-template <int N>
-__device__ __forceinline__ const TileTwiddles<N>& tile_twiddles() {
-  if constexpr (N == 64) return kTw64;
-  else if constexpr (N == 96) return kTw96;
-  else return kTw128;
-}
-
-// Pass 0 of the transforms of `nlines` lines of the image in A, all at once: items
-// q = t + 256 s -> line q mod NL (NL lines per item round), butterfly q / NL.
-// Reads everything first, synchronises, then writes (the pass is not in place).
-template <int N, int DIR, bool ROWS, int NL>
-__device__ __forceinline__ void pass0_inplace(cx<float>* A, int t, int nlines, bool act) {
-  constexpr int M = N / 8, P = N + 1;
-  constexpr int NQ = (NL * M + kTileThreads - 1) / kTileThreads;
-  cx<float> v[NQ][8];
-#pragma unroll
-  for (int s = 0; s < NQ; ++s) {
-    const int q = t + s * kTileThreads;
-    const int line = q % NL, b = q / NL;
-    if (act && b < M && line < nlines) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) v[s][r] = A[at<P, ROWS>(line, b + M * r)];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < NQ; ++s) {
-    const int q = t + s * kTileThreads;
-    const int line = q % NL, b = q / NL;
-    if (act && b < M && line < nlines) {
-      dft<8, DIR, float>(v[s]);
-#pragma unroll
-      for (int r = 0; r < 8; ++r) A[at<P, ROWS>(line, 8 * b + r)] = v[s][r];
-    }
-  }
-}
-
-// Pass 1 in place for lines l + 32 i (i < NI, line < nlines), butterfly bq; tw holds
-// w^{r bq} for the inverse direction (conjugated for the forward one).
-template <int N, int DIR, bool ROWS, int NI, bool SERIAL = false>
-__device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw, int bq, int l,
-                                              int nlines, int nstore) {
-  constexpr int M = N / 8, P = N + 1;
-#pragma unroll(SERIAL ? 1 : NI)
-  for (int i = 0; i < NI; ++i) {
-    const int line = l + 32 * i;
-    if (line < nlines) {
-      cx<float> x[M];
-#pragma unroll
-      for (int r = 0; r < M; ++r) x[r] = A[at<P, ROWS>(line, bq + 8 * r)];
-#pragma unroll
-      for (int r = 1; r < M; ++r) x[r] = (DIR > 0) ? cmul(x[r], tw[r]) : cmulc(x[r], tw[r]);
-      dft<M, DIR, float>(x);
-#pragma unroll
-      for (int r = 0; r < M; ++r)
-        if (bq + 8 * r < nstore) A[at<P, ROWS>(line, bq + 8 * r)] = x[r];
-    }
-  }
-}
 
 // One block (image img, block index `tile`) with one group of 256 threads, components one
 // after another. N: transform length; TV: largest valid block side (a multiple of 32);

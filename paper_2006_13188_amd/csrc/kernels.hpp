@@ -149,6 +149,26 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
                             const cx<float>* Fs);
 
+// ---- tiled (overlap-save) convolution: one workgroup (256 threads) per T x T block
+struct TileConvArgs {
+  const float* H;
+  long long planeH;
+  int ldH;
+  Field fld;               // phase e^{-i c alpha}
+  int sig_norm;            // signal divided by field^2
+  int nsig;                // 1: y = scale Re sum; 2: ratio of the sums for H/f^2 and 1/f^2
+  float* y;
+  long long planeY;
+  int ldY;
+  int ny, nx, R, T, tx, ty, U;   // tx, ty set by the launcher
+  const float* w;
+  float scale;
+  const cx<float>* Fs;     // U block spectra of N x N, F_c at (x - R) mod N
+};
+bool tconv_supported(int N, int TV);
+size_t tconv_lds_bytes(int N);
+hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);
+
 // LDS needed for a launch, in bytes (twiddles + transform buffers).
 size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);
 size_t lds_cols(const ColCfg& c, const FftDesc& d, size_t elem);

@@ -1,4 +1,5 @@
-"""Both evaluation strategies of the extended correlation against the float64 oracle.
+"""Both evaluation strategies of the extended correlation and convolution (and the
+scale-group smoothing) against the float64 oracle.
 
 TWO_PASS is the paper's whole-image FFT form; TILED evaluates overlap-save blocks on chip.
 Each runs on its own context with the strategy forced, on shapes that span several
@@ -9,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synthetic import blurred_noise, random_filter, rotation_config, theta_field
+from synthetic import blurred_noise, random_filter, rotation_config, scale_field, theta_field
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -52,9 +53,10 @@ def host(t):
     return t.cpu().numpy()
 
 
-def oracle_corr(img, filt, theta, K):
+def oracle_corr(img, filt, theta, K, op=0):
     comps, _ = O.angular_components(filt, K)
-    return O.ext_corr_half(img.astype(np.float64), theta.astype(np.float64), O.half_components(comps))
+    f = O.ext_corr_half if op == 0 else O.ext_conv_half
+    return f(img.astype(np.float64), theta.astype(np.float64), O.half_components(comps))
 
 
 @pytest.mark.parametrize("shape,S,K", [
@@ -65,30 +67,32 @@ def oracle_corr(img, filt, theta, K):
     ((150, 211), 63, 16),    # R = 31: N = 128
     ((97, 130), 81, 6),      # R = 40: N = 128, T = 48 (tiled only when forced)
 ])
-def test_correlation_parity(E, sctx, shape, S, K):
+@pytest.mark.parametrize("op", [0, 1], ids=["corr", "conv"])
+def test_forward_parity(E, sctx, op, shape, S, K):
     ctx, strat = sctx
     img = blurred_noise(shape, 5)
     filt = random_filter(S, 6, 4.0 * S / 15)
     theta = theta_field(shape, 7)
     plan = E.FilterPlan.rotation(ctx, dev(filt), K)
-    used, n, blk = ctx.describe(0, plan, *shape)
+    used, n, blk = ctx.describe(op, plan, *shape)
     assert used == strat
     if strat == TILED:
         assert n in (64, 96, 128) and 16 <= blk <= n - (S - 1)
-    y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
-    ref = oracle_corr(img, filt, theta, K)
+    y = host(E.ecc_extended(ctx, op, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K, op)
     assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
 
 
-def test_batch(E, sctx):
+@pytest.mark.parametrize("op", [0, 1], ids=["corr", "conv"])
+def test_batch(E, sctx, op):
     ctx, _ = sctx
     imgs = np.stack([blurred_noise((150, 131), 60 + i) for i in range(3)])
     ths = np.stack([theta_field((150, 131), 70 + i) for i in range(3)])
     filt = random_filter(17, 9, 4.5)
     plan = E.FilterPlan.rotation(ctx, dev(filt), 7)
-    yb = host(E.ecc_extended(ctx, 0, plan, dev(imgs), dev(ths)))
+    yb = host(E.ecc_extended(ctx, op, plan, dev(imgs), dev(ths)))
     for i in range(3):
-        ref = oracle_corr(imgs[i], filt, ths[i], 7)
+        ref = oracle_corr(imgs[i], filt, ths[i], 7, op)
         assert rel2(yb[i].astype(np.float64), ref) <= TOL
 
 
@@ -112,12 +116,13 @@ def test_strided_rows(E, sctx):
     assert np.all(y[:, 100:] == 5.0)   # nothing written past nx
 
 
-def test_full_size(E, sctx):
+@pytest.mark.parametrize("op", [0, 1], ids=["corr", "conv"])
+def test_full_size(E, sctx, op):
     img, filt, theta, K = rotation_config(1024, 31, 16, seeds=(10, 11, 12))
     ctx, _ = sctx
     plan = E.FilterPlan.rotation(ctx, dev(filt), K)
-    y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
-    ref = oracle_corr(img, filt, theta, K)
+    y = host(E.ecc_extended(ctx, op, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K, op)
     assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
 
 
@@ -126,7 +131,7 @@ def test_auto_choice_and_unsupported_radius(E):
     try:
         plan = E.FilterPlan.rotation(ctx, dev(random_filter(31, 1, 8.0)), 16)
         assert ctx.describe(0, plan, 1024, 1024) == (TILED, 96, 64)
-        assert ctx.describe(1, plan, 1024, 1024)[0] == TWO_PASS   # convolution
+        assert ctx.describe(1, plan, 1024, 1024)[0] == TILED      # convolution
         big = E.FilterPlan.rotation(ctx, dev(random_filter(121, 2, 30.0)), 4)   # R = 60
         assert ctx.describe(0, big, 300, 300)[0] == TWO_PASS
         ctx.set_strategy(TILED)
@@ -152,3 +157,46 @@ def test_context_close_with_live_plans(E):
         assert rel2(y, oracle_corr(img, filt, theta, K)) <= TOL
     finally:
         ctx2.close()
+
+
+SMALLP = dict(sigma0=1.0, scale_min=1.0, scale_max=2.0, components=12, period_factor=1.5)
+
+
+@pytest.mark.parametrize("shape", [(64, 80), (141, 97)])
+def test_scale_smooth_parity(E, sctx, shape):
+    """Ratio form of the scale-adaptive smoothing (two signals sharing the phases)."""
+    ctx, _ = sctx
+    plan = E.FilterPlan.scale(ctx, **SMALLP)
+    img = blurred_noise(shape, 30)
+    s = scale_field(shape, 31, 1.0, 2.0, sigma=4.0)
+    y = host(E.ecc_scale_smooth(ctx, plan, dev(img), dev(s))).astype(np.float64)
+    ref, _, _ = O.scale_smooth_fft(img.astype(np.float64), s.astype(np.float64), O.ScaleParams(1.0, 1.0, 2.0, 12, 1.5))
+    assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+
+
+def test_scale_extended_convolution(E, sctx):
+    ctx, _ = sctx
+    plan = E.FilterPlan.scale(ctx, **SMALLP)
+    img = blurred_noise((120, 90), 33)
+    s = scale_field((120, 90), 34, 1.0, 2.0, sigma=3.0)
+    y = host(E.ecc_extended(ctx, E.CONVOLUTION, plan, dev(img), dev(s))).astype(np.float64)
+    comps, w, om1 = O.scale_components(O.ScaleParams(1.0, 1.0, 2.0, 12, 1.5))
+    ref = O.ext_conv_half(img.astype(np.float64), om1 * np.log(s.astype(np.float64)), comps, w)
+    assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL
+
+
+@pytest.fixture(scope="module")
+def scale_full():
+    from synthetic import scale_config
+    img, s = scale_config(2048)
+    ref, _, _ = O.scale_smooth_fft(img.astype(np.float64), s.astype(np.float64), O.ScaleParams())
+    return img, s, ref
+
+
+def test_scale_full_size(E, sctx, scale_full):
+    """2048^2 scale-adaptive smoothing, 24 components (65 x 65 support), s in [1, 8]."""
+    ctx, _ = sctx
+    img, s, ref = scale_full
+    plan = E.FilterPlan.scale(ctx)
+    y = host(E.ecc_scale_smooth(ctx, plan, dev(img), dev(s))).astype(np.float64)
+    assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
