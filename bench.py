@@ -148,6 +148,30 @@ def matching_precisions(E, ctx, stream, timeit):
     return res
 
 
+def scale_workload(E, timeit):
+    """Scale-adaptive smoothing of a 2048^2 image (blurred noise + blocks, s in [1, 8],
+    Gaussian sigma0 = 1 px, 24 log-radial components, 65 x 65 support): both strategies."""
+    import torch
+
+    from synthetic import scale_config
+
+    img, s = scale_config(2048)
+    Hs, Ss = torch.from_numpy(img).cuda(), torch.from_numpy(s).cuda()
+    res = {"workload": "scale-adaptive smoothing, 2048x2048, 24 components (13 computed), ratio form"}
+    for name, strat in (("tiled", TILED), ("two_pass", TWO_PASS)):
+        c = E.Context(0)
+        c.set_strategy(strat)
+        plan = E.FilterPlan.scale(c)
+        out = torch.empty_like(Hs)
+        E.ecc_scale_smooth(c, plan, Hs, Ss, out=out)
+        ms = timeit(lambda: E.ecc_scale_smooth(c, plan, Hs, Ss, out=out), reps=10)
+        res[name + "_ms"] = round(ms, 4)
+        res[name + "_Mpix_comp_s"] = round(2048 * 2048 * 24 / (ms * 1e-3) / 1e6, 1)
+        plan.close()
+        c.close()
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -350,6 +374,7 @@ def main():
         extras["convolution_ms"] = round(conv_ms, 4)
         extras["convolution_Mpix_comp_s"] = round(N * N * (2 * K + 1) / (conv_ms * 1e-3) / 1e6, 1)
         extras["mixed_precision"] = matching_precisions(E, ctx, stream, timeit)
+        extras["scale_smoothing_2048"] = scale_workload(E, timeit)
         plan2.close()
         ctx2.close()
         extras["batch_256"] = batch_workload(E, timeit)

@@ -219,7 +219,8 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
 ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int batch, int ny,
                                    int nx, size_t* bytes);
 /* Forward extended convolution that also writes the per-component row spectra of the
- * modulated signal into `saved` (ecc_backward_saved_size bytes, device). */
+ * modulated signal into `saved` (ecc_backward_saved_size bytes, device). Always runs the
+ * two-pass form (whose intermediate the stack is); equal to ecc_extended up to rounding. */
 ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
                              const float* signal, const float* field, float* out, void* saved,
                              void* stream);

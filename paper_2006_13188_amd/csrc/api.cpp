@@ -656,6 +656,7 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   ecc_strategy strat;
   TileChoice tc;
   ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc));
+  if (saved) strat = ECC_STRATEGY_TWO_PASS;   // the saved stack is the two-pass form's row stack
   if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, true));

@@ -24,22 +24,22 @@ namespace ecc {
 
 namespace {
 
-// One block (image img, block index `tile`) with one group of 256 threads, components one
-// after another. N: transform length; TV: largest valid block side (a multiple of 32);
-// SEPB: the row pass-0 output goes to a second buffer of TV rows (else in place, one
-// more barrier). Called by every thread of the workgroup.
-template <int N, int TV, bool SEPB, bool STACK = false>
+// One block (image img, block index `tile`) with one group of NT threads (256 or 512),
+// components one after another. N: transform length; TV: largest valid block side (a
+// multiple of 32); SEPB: the row pass-0 output goes to a second buffer of TV rows (else
+// in place, one more barrier); STACK: write the components instead of combining them.
+// LS = NT / 8 threads share each pass-1 butterfly index (with 512 threads it is the wave
+// index, so the twiddles are scalar). Called by every thread of the workgroup.
+template <int N, int TV, bool SEPB, bool STACK = false, int NT = kTileThreads>
 __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
-  constexpr int HALVES = 1;
-  constexpr int M = N / 8, P = N + 1;
-  constexpr int NQ0 = (N * M + kTileThreads - 1) / kTileThreads;   // column pass-0 items
-  constexpr int NQ2 = (TV * M + kTileThreads - 1) / kTileThreads;  // row pass-0 items
-  constexpr int TR = TV / 32, RV = TV / 8;
-  constexpr int IMG = (SEPB ? N + TV : N) * P;                      // LDS image per group
-  constexpr bool PREFETCH = HALVES == 1 && N <= 96;
-  const int half = 0;
-  const int t = threadIdx.x - half * kTileThreads, bq = t >> 5, l = t & 31;
-  cx<float>* A = lds_t + half * IMG;
+  constexpr int M = N / 8, P = N + 1, LS = NT / 8;
+  constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
+  constexpr int NQ2 = (TV * M + NT - 1) / NT;  // row pass-0 items
+  constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
+  constexpr bool PREFETCH = NT == kTileThreads && N <= 96;
+  const int t = threadIdx.x, l = t % LS;
+  const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
+  cx<float>* A = lds_t;
   cx<float>* Bb = SEPB ? A + N * P : A;
   const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
   const int T = a.T;
@@ -54,7 +54,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   __syncthreads();   // the LDS image may still be in use by the previous block
   // ---- signal window into A (real part), zero outside the image
   const float* Hb = a.H + (long long)img * a.planeH;
-  for (int q = t; q < N * N; q += kTileThreads) {
+  for (int q = t; q < N * N; q += NT) {
     const int i = q / N, j = q - (q / N) * N;
     const int gy = y0 - a.R + i, gx = x0 - a.R + j;
     float h = 0.f;
@@ -63,27 +63,27 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   }
   __syncthreads();
   // ---- forward 2D transform of the window: columns, then rows
-  pass0_inplace<N, -1, false, N>(A, t, N, true);
+  pass0_inplace<N, -1, false, N, NT>(A, t, N, true);
   __syncthreads();
-  pass1_inplace<N, -1, false, N / 32>(A, tw, bq, l, N, N);
+  pass1_inplace<N, -1, false, N / LS, NT>(A, tw, bq, l, N, N);
   __syncthreads();
-  pass0_inplace<N, -1, true, N>(A, t, N, true);
+  pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
   __syncthreads();
-  pass1_inplace<N, -1, true, N / 32>(A, tw, bq, l, N, N);
+  pass1_inplace<N, -1, true, N / LS, NT>(A, tw, bq, l, N, N);
   __syncthreads();
   // signal spectrum values of this thread's column pass-0 items, kept for all components
   cx<float> hs[NQ0][8];
 #pragma unroll
   for (int s = 0; s < NQ0; ++s) {
-    const int q = t + s * kTileThreads;
+    const int q = t + s * NT;
     const int v = q % N, b = q / N;
 #pragma unroll
     for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? A[(b + M * r) * P + v] : mk(0.f, 0.f);
   }
 
   // ---- per-pixel state of the row pass-1 outputs: pixel (l + 32 i, bq + 8 r). The
-  // phase of component c is e^{i (kofs + c) alpha}; group `half` starts at c = half and
-  // advances by HALVES components per step.
+  // phase of component c is e^{i (kofs + c) alpha}, advanced by one factor e^{i alpha}
+  // per component.
   float acc[TR][RV];
   cx<float> z[TR][RV], e1[TR][RV];
 #pragma unroll
@@ -93,11 +93,11 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
       acc[i][r] = 0.f;
       z[i][r] = mk(0.f, 0.f);
       e1[i][r] = mk(0.f, 0.f);
-      const int u = l + 32 * i, x = bq + 8 * r;
+      const int u = l + LS * i, x = bq + 8 * r;
       const int gy = y0 + u, gx = x0 + x;
       if (!STACK && u < T && x < T && gy < a.ny && gx < a.nx) {
         const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
-        const int k0 = a.kofs + half;
+        const int k0 = a.kofs;
         cx<float> s1, s0;
         if (a.fld.log_mode || a.kofs != 0) {
           const double al = field_angle(a.fld, fv);
@@ -111,10 +111,10 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
           float sn, cs;
           sincosf(al, &sn, &cs);
           s1 = mk(cs, sn);
-          s0 = half ? s1 : mk(1.f, 0.f);
+          s0 = mk(1.f, 0.f);
         }
         z[i][r] = s0;
-        e1[i][r] = HALVES == 2 ? cmul(s1, s1) : s1;
+        e1[i][r] = s1;
       }
     }
   }
@@ -124,7 +124,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   if constexpr (PREFETCH) {
 #pragma unroll
     for (int s = 0; s < NQ0; ++s) {
-      const int q = t + s * kTileThreads;
+      const int q = t + s * NT;
       const int v = q % N, b = q / N;
 #pragma unroll
       for (int r = 0; r < 8; ++r) fs[s][r] = (b < M) ? a.Fs[(b + M * r) * N + v] : mk(0.f, 0.f);
@@ -132,15 +132,14 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   }
   __syncthreads();   // A is rewritten below
 
-  for (int c0 = 0; c0 < a.U; c0 += HALVES) {
-    const int c = c0 + half;
+  for (int c = 0; c < a.U; ++c) {
     const bool act = c < a.U;
     // ---- column pass 0: product, inverse radix 8, A[8 b + r][v]
     const cx<float>* Fc = a.Fs + (long long)c * N * N;
     const bool more = c + 1 < a.U;
 #pragma unroll
     for (int s = 0; s < NQ0; ++s) {
-      const int q = t + s * kTileThreads;
+      const int q = t + s * NT;
       const int v = q % N, b = q / N;
       if (act && b < M) {
         cx<float> x[8];
@@ -162,13 +161,13 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     }
     __syncthreads();
     // ---- column pass 1 (in place), rows < T kept
-    if (act) pass1_inplace<N, +1, false, N / 32>(A, tw, bq, l, N, T);
+    if (act) pass1_inplace<N, +1, false, N / LS, NT>(A, tw, bq, l, N, T);
     __syncthreads();
     // ---- row pass 0 over the T valid rows
     if constexpr (SEPB) {
 #pragma unroll
       for (int s = 0; s < NQ2; ++s) {
-        const int q = t + s * kTileThreads;
+        const int q = t + s * NT;
         const int u = q % TV, b = q / TV;
         if (act && b < M && u < T) {
           cx<float> x[8];
@@ -180,7 +179,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
         }
       }
     } else {
-      pass0_inplace<N, +1, true, TV>(A, t, T, act);
+      pass0_inplace<N, +1, true, TV, NT>(A, t, T, act);
     }
     __syncthreads();
     // ---- row pass 1 and the per-pixel combination
@@ -188,7 +187,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
       const float wc = a.w[c];
 #pragma unroll
       for (int i = 0; i < TR; ++i) {   // (acc, z, e1 are indexed by i: this loop stays unrolled)
-        const int u = l + 32 * i;
+        const int u = l + LS * i;
         if (u < T) {
           cx<float> x[M];
 #pragma unroll
@@ -223,7 +222,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     for (int i = 0; i < TR; ++i) {
 #pragma unroll
       for (int r = 0; r < RV; ++r) {
-        const int u = l + 32 * i, x = bq + 8 * r;
+        const int u = l + LS * i, x = bq + 8 * r;
         const int gy = y0 + u, gx = x0 + x;
         if (u < T && x < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[i][r] * a.scale;
       }
@@ -402,13 +401,20 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   }
 }
 
+// Threads of a launch: the pair form has 2 x 256; the one-group form 512 for N = 128
+// (every pass divides evenly, and two waves per SIMD hide latency) and 256 otherwise.
+template <int N, int HV>
+constexpr int tile_nt() {
+  return HV == 2 ? 2 * kTileThreads : (N == 128 ? 512 : kTileThreads);
+}
+
 // One workgroup per block of a (batch of) image(s).
 template <int N, int TV, bool SEPB>
-__global__ void __launch_bounds__(kTileThreads) k_tile_corr_one(TileArgs a) {
+__global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_corr_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  corr_block_one<N, TV, SEPB>(a, lb / ntile, lb % ntile, lds_t);
+  corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, lb / ntile, lb % ntile, lds_t);
 }
 template <int N>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
@@ -421,10 +427,10 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
 // Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
 // a.stack[(y * nx + x) * spx + 2c] (interleaved re, im; spx floats per pixel).
 template <int N, int TV, bool SEPB>
-__global__ void __launch_bounds__(kTileThreads) k_tile_stack_one(TileArgs a) {
+__global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_stack_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  corr_block_one<N, TV, SEPB, true>(a, 0, lb, lds_t);
+  corr_block_one<N, TV, SEPB, true, tile_nt<N, 1>()>(a, 0, lb, lds_t);
 }
 template <int N>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a) {
@@ -439,19 +445,19 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a
 // cost, so the hardware dispatcher, which starts workgroups in order as CUs free up,
 // schedules them longest first.
 template <int N, int TV, bool SEPB, int HV>
-__global__ void __launch_bounds__(HV * kTileThreads) k_tile_items(const TileArgs* __restrict__ descs,
+__global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_items(const TileArgs* __restrict__ descs,
                                                                  const int2* __restrict__ items) {
   extern __shared__ cx<float> lds_t[];
   const int2 it = items[blockIdx.x];
   const TileArgs& a = descs[it.x];
   if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
-  else corr_block_one<N, TV, SEPB>(a, 0, it.y, lds_t);
+  else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
 }
 
 // Persistent form: workgroup w runs the blocks items[off[w] .. off[w+1]) one after
 // another (the host deals the items over the workgroups, longest first).
 template <int N, int TV, bool SEPB, int HV>
-__global__ void __launch_bounds__(HV * kTileThreads) k_tile_batch(const TileArgs* __restrict__ descs,
+__global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_batch(const TileArgs* __restrict__ descs,
                                                                  const int* __restrict__ off,
                                                                  const int2* __restrict__ items) {
   extern __shared__ cx<float> lds_t[];
@@ -461,7 +467,7 @@ __global__ void __launch_bounds__(HV * kTileThreads) k_tile_batch(const TileArgs
     const int2 it = items[i];
     const TileArgs& a = descs[it.x];
     if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
-    else corr_block_one<N, TV, SEPB>(a, 0, it.y, lds_t);
+    else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
   }
 }
 
@@ -480,7 +486,7 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
     hipLaunchKernelGGL((k_tile_corr_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   } else {
-    hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB>), dim3(nblk), dim3(kTileThreads),
+    hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB>), dim3(nblk), dim3(tile_nt<N, 1>()),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
   return last();
@@ -492,7 +498,7 @@ hipError_t launch_stack_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) 
     hipLaunchKernelGGL((k_tile_stack_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   } else {
-    hipLaunchKernelGGL((k_tile_stack_one<N, TV, SEPB>), dim3(nblk), dim3(kTileThreads),
+    hipLaunchKernelGGL((k_tile_stack_one<N, TV, SEPB>), dim3(nblk), dim3(tile_nt<N, 1>()),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
   return last();
@@ -590,7 +596,7 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
 }
 
 int tile_threads(int N, int TV) {
-#define ECC_TT(n, tv, sb, hv) if (N == n && TV == tv) return hv * kTileThreads;
+#define ECC_TT(n, tv, sb, hv) if (N == n && TV == tv) return tile_nt<n, hv>();
   ECC_TILE_CONFIGS(ECC_TT)
 #undef ECC_TT
   return 0;
@@ -601,7 +607,7 @@ int tile_blocks_per_cu(int N, int TV) {
 #define ECC_TO(n, tv, sb, hv)                                                                   \
   if (N == n && TV == tv) {                                                                     \
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_items<n, tv, sb, hv>,          \
-                                                     hv * kTileThreads,                        \
+                                                     tile_nt<n, hv>(),                         \
                                                      tile_lds<n, tv, sb, hv>()) != hipSuccess)  \
       nb = 1;                                                                                   \
     return nb > 0 ? nb : 1;                                                                     \
@@ -617,7 +623,7 @@ hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileAr
   if (off == nullptr) {   // item-table form: one workgroup per item
 #define ECC_TIT(n, tv, sb, hv)                                                                   \
   if (N == n && TV == tv) {                                                                     \
-    hipLaunchKernelGGL((k_tile_items<n, tv, sb, hv>), dim3(nwg), dim3(hv * kTileThreads),        \
+    hipLaunchKernelGGL((k_tile_items<n, tv, sb, hv>), dim3(nwg), dim3(tile_nt<n, hv>()),         \
                        (tile_lds<n, tv, sb, hv>()), s, descs, items);                            \
     return last();                                                                               \
   }
@@ -627,7 +633,7 @@ hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileAr
   }
 #define ECC_TBL(n, tv, sb, hv)                                                                   \
   if (N == n && TV == tv) {                                                                     \
-    hipLaunchKernelGGL((k_tile_batch<n, tv, sb, hv>), dim3(nwg), dim3(hv * kTileThreads),        \
+    hipLaunchKernelGGL((k_tile_batch<n, tv, sb, hv>), dim3(nwg), dim3(tile_nt<n, hv>()),         \
                        (tile_lds<n, tv, sb, hv>()), s, descs, off, items);                       \
     return last();                                                                               \
   }

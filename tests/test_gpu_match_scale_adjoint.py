@@ -188,9 +188,10 @@ def test_saved_stack_matches_recompute(E, ctx):
     plan = E.FilterPlan.rotation(ctx, dev(random_filter(S, 98, 2.5)), K)
     nbytes = E.ecc_backward_saved_size(ctx, plan, B, n, n)
     saved = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    y1 = E.ecc_extended_save(ctx, plan, dev(imgs), dev(ths), saved)
-    y2 = E.ecc_extended(ctx, E.CONVOLUTION, plan, dev(imgs), dev(ths))
-    assert np.array_equal(host(y1), host(y2))
+    y1 = host(E.ecc_extended_save(ctx, plan, dev(imgs), dev(ths), saved))
+    y2 = host(E.ecc_extended(ctx, E.CONVOLUTION, plan, dev(imgs), dev(ths)))
+    # the saving forward runs the two-pass form; the default call may take the tiled one
+    assert np.max(np.abs(y1 - y2)) <= 1e-6 * np.max(np.abs(y2))
     a = E.ecc_extended_backward(ctx, plan, dev(imgs), dev(ths), dev(g), saved=saved)
     b = E.ecc_extended_backward(ctx, plan, dev(imgs), dev(ths), dev(g), saved=None)
     for x, y in zip(a, b):
