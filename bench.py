@@ -13,7 +13,8 @@ Prints one JSON line: metric, value in Mpix*comp/s, the roofline of the dominant
 measured with HIP events on the library's stream, and the float64 CPU oracle timed on
 a bounded sample of the same workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--copy-calibration]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
+                  [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -172,6 +173,42 @@ def scale_workload(E, timeit):
     return res
 
 
+def adjoint_workload(E, ctx, timeit):
+    """Forward + hand-written adjoint of the extended convolution through the autograd
+    function: 16 images of 512^2, a shared 21x21 filter (K = 12, 13 complex components),
+    gradients for the signal, the components and the angle field; with the modulated
+    stack kept from the forward pass and with it recomputed (checkpointing); peak memory
+    of each."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from synthetic import adjoint_config
+
+    imgs, thetas, filt, g = adjoint_config()
+    comps, _ = O.angular_components(filt, 12)
+    half = torch.from_numpy(O.half_components(comps).astype(np.complex64)).cuda()
+    H = torch.from_numpy(imgs).cuda().requires_grad_(True)
+    T = torch.from_numpy(thetas).cuda().requires_grad_(True)
+    Cc = half.clone().requires_grad_(True)
+    G = torch.from_numpy(g).cuda()
+    res = {"workload": "extended convolution forward + adjoint, 16 x 512^2, 21x21 filter, K=12"}
+    for name, ckpt in (("saved_stack", False), ("checkpointed", True)):
+        def step():
+            y = E.ExtConv.apply(H, T, Cc, ctx, ckpt)
+            torch.autograd.grad(y, (H, T, Cc), G)
+        step()
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        step()
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated() - base
+        ms = timeit(step, reps=10)
+        res[name] = {"fwd_bwd_ms": round(ms, 3), "peak_extra_MiB": round(peak / 2 ** 20, 1)}
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -237,6 +274,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of side workloads: two_pass,conv,matching,scale,adjoint,batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
@@ -359,8 +398,11 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    if not args.no_extras:
-        # the paper's two-pass form on the same workload, and the other operations
+    want = set() if args.no_extras else (
+        {"two_pass", "conv", "matching", "scale", "adjoint", "batch"} if args.extras == "all"
+        else set(args.extras.split(",")))
+    if "two_pass" in want:
+        # the paper's two-pass form on the same workload
         ctx2 = E.Context(0)
         ctx2.set_strategy(TWO_PASS)
         plan2 = E.FilterPlan.rotation(ctx2, Fd, K)
@@ -370,13 +412,20 @@ def main():
         extras["two_pass_fft_size"] = ctx2.fft_size(N, (S - 1) // 2)
         extras["two_pass_vs_default_max_abs_diff_over_max"] = float(
             (out2 - out).abs().max().item() / out.abs().max().item())
-        conv_ms = timeit(lambda: E.ecc_extended(ctx, E.CONVOLUTION, plan, H, TH, out2))
-        extras["convolution_ms"] = round(conv_ms, 4)
-        extras["convolution_Mpix_comp_s"] = round(N * N * (2 * K + 1) / (conv_ms * 1e-3) / 1e6, 1)
-        extras["mixed_precision"] = matching_precisions(E, ctx, stream, timeit)
-        extras["scale_smoothing_2048"] = scale_workload(E, timeit)
         plan2.close()
         ctx2.close()
+    if "conv" in want:
+        out3 = torch.empty_like(H)
+        conv_ms = timeit(lambda: E.ecc_extended(ctx, E.CONVOLUTION, plan, H, TH, out3))
+        extras["convolution_ms"] = round(conv_ms, 4)
+        extras["convolution_Mpix_comp_s"] = round(N * N * (2 * K + 1) / (conv_ms * 1e-3) / 1e6, 1)
+    if "matching" in want:
+        extras["mixed_precision"] = matching_precisions(E, ctx, stream, timeit)
+    if "scale" in want:
+        extras["scale_smoothing_2048"] = scale_workload(E, timeit)
+    if "adjoint" in want:
+        extras["adjoint_16x512"] = adjoint_workload(E, ctx, timeit)
+    if "batch" in want:
         extras["batch_256"] = batch_workload(E, timeit)
 
     cpu = None

@@ -189,7 +189,7 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
  * signal: device float32 ny x nx (stride ld); best_score (float32) and best_index
  * (int32): device ny x nx with stride ld_out.
  * With a block shape (TILED / AUTO strategy) the components are computed block by block
- * into a per-pixel stack in the context's workspace (ny nx round4(2K+2) floats) and the
+ * into a stack in the context's workspace (K+1 planes of ny nx complex64) and the
  * angle search is a dense product done by `prec`: ECC_PREC_FP32 (float32 multiply-adds),
  * ECC_PREC_MFMA_FP16_HILO (matrix cores, float16 hi + lo operands, float32 accumulation;
  * ~1e-6 relative), ECC_PREC_MFMA_BF16_HILO (bfloat16 hi + lo; ~1e-5 relative). The

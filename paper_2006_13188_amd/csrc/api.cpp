@@ -868,15 +868,14 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
       ECC_HIP(hipMemcpy(plan->match_tab.p, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
       plan->match_tab_A = n_angles;
     }
-    const int spx = (2 * U + 3) & ~3;
     const long long npix = (long long)ny * nx;
-    ECC_HIP(ctx->ws.ensure((size_t)npix * spx * sizeof(float)));
+    ECC_HIP(ctx->ws.ensure((size_t)npix * U * sizeof(cx<float>)));
     mark(ctx, 0, st);
     ECC_HIP(launch_tile_stack(st, tc.N, tc.TV, signal, ld, ny, nx, R, tc.T, U, 1.0f / ((float)tc.N * (float)tc.N),
-                              sp->buf.as<cx<float>>(), ctx->ws.as<float>(), spx));
+                              sp->buf.as<cx<float>>(), ctx->ws.as<float>()));
     mark(ctx, 1, st);
     const int pc = prec == ECC_PREC_FP32 ? 0 : (prec == ECC_PREC_MFMA_FP16_HILO ? 1 : 2);
-    ECC_HIP(launch_match_angles(st, pc, ctx->ws.as<float>(), spx, U, npix, n_angles, plan->match_tab.as<float>(),
+    ECC_HIP(launch_match_angles(st, pc, ctx->ws.as<float>(), U, npix, n_angles, plan->match_tab.as<float>(),
                                 best_score, best_index, ld_out, nx));
     mark(ctx, 2, st);
     return ECC_OK;

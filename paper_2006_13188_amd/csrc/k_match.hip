@@ -21,23 +21,20 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
+// The stack holds U planes of npix complex values (component-major).
 template <int UMAX>
-__global__ void __launch_bounds__(256) k_match_angles_f32(const float* __restrict__ stack, int spx, int U,
+__global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restrict__ stack, int U,
                                                           long long npix, int A, const float* __restrict__ dtab,
                                                           float* __restrict__ score, int* __restrict__ index,
                                                           int ldOut, int nx) {
   const long long p = blockIdx.x * 256LL + threadIdx.x;
   if (p >= npix) return;
   float g[2 * UMAX];
-  const float* src = stack + p * spx;
 #pragma unroll
-  for (int k = 0; k < 2 * UMAX; k += 4) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (k < 2 * U) v = *reinterpret_cast<const float4*>(src + k);
-    g[k] = v.x;
-    g[k + 1] = (k + 1 < 2 * U) ? v.y : 0.f;
-    g[k + 2] = (k + 2 < 2 * U) ? v.z : 0.f;
-    g[k + 3] = (k + 3 < 2 * U) ? v.w : 0.f;
+  for (int c = 0; c < UMAX; ++c) {
+    const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
+    g[2 * c] = v.x;
+    g[2 * c + 1] = v.y;
   }
   float best = -INFINITY;
   int bi = 0;
@@ -100,7 +97,7 @@ struct Split<true> {
 // .. + 3, and g of pixel l%16, entries 16 s + 4 (l/16) .. + 3; the result C^T[16 mt +
 // 4 (l/16) + j][l%16] comes back in lane l.
 template <bool BF16, int MT, int KS>
-__global__ void __launch_bounds__(256) k_match_angles_mfma(const float* __restrict__ stack, int spx, int U,
+__global__ void __launch_bounds__(256) k_match_angles_mfma(const float2* __restrict__ stack, int U,
                                                            long long npix, int A, const float* __restrict__ dtab,
                                                            float* __restrict__ score, int* __restrict__ index,
                                                            int ldOut, int nx) {
@@ -127,13 +124,13 @@ __global__ void __launch_bounds__(256) k_match_angles_mfma(const float* __restri
     float mx = 0.f;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int k = 16 * s + 4 * lq;
-      float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (p < npix && k < 2 * U) q = *reinterpret_cast<const float4*>(stack + p * spx + k);
-      v[s][0] = q.x;
-      v[s][1] = (k + 1 < 2 * U) ? q.y : 0.f;
-      v[s][2] = (k + 2 < 2 * U) ? q.z : 0.f;
-      v[s][3] = (k + 3 < 2 * U) ? q.w : 0.f;
+      const int c = 8 * s + 2 * lq;   // entries 2c .. 2c + 3 = components c and c + 1
+      const float2 q0 = (p < npix && c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
+      const float2 q1 = (p < npix && c + 1 < U) ? stack[(c + 1) * npix + p] : make_float2(0.f, 0.f);
+      v[s][0] = q0.x;
+      v[s][1] = q0.y;
+      v[s][2] = q1.x;
+      v[s][3] = q1.y;
 #pragma unroll
       for (int j = 0; j < 4; ++j) mx = fmaxf(mx, fabsf(v[s][j]));
     }
@@ -191,13 +188,14 @@ __global__ void __launch_bounds__(256) k_match_angles_mfma(const float* __restri
 
 }  // namespace
 
-hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int spx, int U, long long npix,
-                               int A, const float* dtab, float* score, int* index, int ldOut, int nx) {
-  if (U < 1 || 2 * U > 64 || A < 1 || A > 64 || spx < 2 * U || (spx & 3) || npix < 1) return hipErrorInvalidValue;
+hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int U, long long npix, int A,
+                               const float* dtab, float* score, int* index, int ldOut, int nx) {
+  if (U < 1 || 2 * U > 64 || A < 1 || A > 64 || npix < 1) return hipErrorInvalidValue;
+  const float2* stack = reinterpret_cast<const float2*>(stackf);
   if (prec == 0) {
     const unsigned grid = (unsigned)((npix + 255) / 256);
 #define ECC_MF(UM)                                                                                         \
-  hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, spx, U, npix, A, dtab, \
+  hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, A, dtab,      \
                      score, index, ldOut, nx)
     if (U <= 8) ECC_MF(8);
     else if (U <= 16) ECC_MF(16);
@@ -211,7 +209,7 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int 
   const unsigned grid = (unsigned)std::min<long long>((groups + 3) / 4, 256LL * 8);
 #define ECC_MM(BF, mt, ks)                                                                                    \
   if (MT == mt && KS == ks) {                                                                                 \
-    hipLaunchKernelGGL((k_match_angles_mfma<BF, mt, ks>), dim3(grid), dim3(256), 0, s, stack, spx, U, npix, A, \
+    hipLaunchKernelGGL((k_match_angles_mfma<BF, mt, ks>), dim3(grid), dim3(256), 0, s, stack, U, npix, A,      \
                        dtab, score, index, ldOut, nx);                                                        \
     return last();                                                                                            \
   }

@@ -200,7 +200,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
             for (int r = 0; r < RV; ++r) {
               const int xx = bq + 8 * r, gy = y0 + u, gx = x0 + xx;
               if (xx < T && gy < a.ny && gx < a.nx)
-                *reinterpret_cast<float2*>(a.stack + ((long long)gy * a.nx + gx) * a.spx + 2 * c) =
+                *reinterpret_cast<float2*>(a.stack + 2 * ((long long)c * a.ny * a.nx + (long long)gy * a.nx + gx)) =
                     make_float2(x[r].re * a.scale, x[r].im * a.scale);
             }
           } else {
@@ -374,7 +374,8 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
             for (int r = 0; r < 8; ++r) {
               const int xx = bq4 + 8 * r, gx = x0 + xx;
               if (rowok && xx < T && gx < a.nx)
-                *reinterpret_cast<float2*>(a.stack + ((long long)(y0 + u4) * a.nx + gx) * a.spx + 2 * (c + cc)) =
+                *reinterpret_cast<float2*>(a.stack + 2 * ((long long)(c + cc) * a.ny * a.nx +
+                                                          (long long)(y0 + u4) * a.nx + gx)) =
                     make_float2(x[r].re * a.scale, x[r].im * a.scale);
             }
           } else {
@@ -425,7 +426,8 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
 }
 
 // Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
-// a.stack[(y * nx + x) * spx + 2c] (interleaved re, im; spx floats per pixel).
+// plane c of a.stack (interleaved re, im; planes of ny nx pixels, so the stores of one
+// component fill whole rows while the block is processed).
 template <int N, int TV, bool SEPB>
 __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_stack_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
@@ -571,8 +573,8 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
 }
 
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack, int spx) {
-  if (T < 1 || T > TV || T > N - 2 * R || spx < 2 * U || (spx & 1)) return hipErrorInvalidValue;
+                             int T, int U, float scale, const cx<float>* Fs, float* stack) {
+  if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
   TileArgs a{};
   a.H = H;
   a.ldH = ldH;
@@ -586,7 +588,6 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
   a.scale = scale;
   a.Fs = Fs;
   a.stack = stack;
-  a.spx = spx;
   const long long nblk = (long long)a.tx * a.ty;
 #define ECC_TSK(n, tv, sb, hv) \
   if (N == n && TV == tv) return launch_stack_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);

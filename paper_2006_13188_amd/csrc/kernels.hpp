@@ -124,20 +124,19 @@ struct TileArgs {          // one correlation job (batch of images of one shape)
   const float* w;
   float scale;
   const cx<float>* Fs;     // U block spectra of N x N
-  float* stack;            // component stacks (matching): spx floats per pixel, or NULL
-  int spx;
+  float* stack;            // component stacks (matching): U planes of ny nx (re, im), or NULL
 };
 bool tile_supported(int N, int TV);
 size_t tile_lds_bytes(int N, int TV);
 int tile_threads(int N, int TV);
-// component stack of one image: stack[(y nx + x) spx + 2c .. +1] = G_c(y, x) * scale
+// component stack of one image: stack[2 (c ny nx + y nx + x) .. +1] = G_c(y, x) * scale
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack, int spx);
+                             int T, int U, float scale, const cx<float>* Fs, float* stack);
 // angle search over a component stack: score = max_m sum_c Re(e^{2 pi i c m / A} w_c G_c),
 // index = first maximising m; prec 0 = float32 FMA, 1 = float16 hi/lo MFMA, 2 = bfloat16
 // hi/lo MFMA. dtab: float32 [64][64] (angle m, stack entry k) = w_{k/2} cos / -w_{k/2} sin.
-hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int spx, int U, long long npix,
-                               int A, const float* dtab, float* score, int* index, int ldOut, int nx);
+hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int U, long long npix, int A,
+                               const float* dtab, float* score, int* index, int ldOut, int nx);
 int tile_blocks_per_cu(int N, int TV);   // resident workgroups per CU (occupancy query)
 // batches: item = (descriptor index, block index). Persistent form (off != NULL): nwg
 // workgroups, workgroup w runs items[off[w] .. off[w+1]). Item-table form (off == NULL):
