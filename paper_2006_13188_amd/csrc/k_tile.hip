@@ -52,25 +52,10 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   }
 
   __syncthreads();   // the LDS image may still be in use by the previous block
-  // ---- signal window into A (real part), zero outside the image
-  const float* Hb = a.H + (long long)img * a.planeH;
-  for (int q = t; q < N * N; q += NT) {
-    const int i = q / N, j = q - (q / N) * N;
-    const int gy = y0 - a.R + i, gx = x0 - a.R + j;
-    float h = 0.f;
-    if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) h = Hb[(long long)gy * a.ldH + gx];
-    A[i * P + j] = mk(h, 0.f);
-  }
+  // ---- signal window into A (real part) and its forward 2D transform
+  load_window<N, NT>(A, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
   __syncthreads();
-  // ---- forward 2D transform of the window: columns, then rows
-  pass0_inplace<N, -1, false, N, NT>(A, t, N, true);
-  __syncthreads();
-  pass1_inplace<N, -1, false, N / LS, NT>(A, tw, bq, l, N, N);
-  __syncthreads();
-  pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
-  __syncthreads();
-  pass1_inplace<N, -1, true, N / LS, NT>(A, tw, bq, l, N, N);
-  __syncthreads();
+  forward_2d<N, NT>(A, t);
   // signal spectrum values of this thread's column pass-0 items, kept for all components
   cx<float> hs[NQ0][8];
 #pragma unroll
@@ -263,24 +248,11 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   for (int r = 0; r < M; ++r) tw1[r] = mk(tt.re[bq1][r], tt.im[bq1][r]);
 
   __syncthreads();   // the LDS images may still be in use by the previous block
-  // ---- signal window and its forward transform (each group on its own image)
-  const float* Hb = a.H + (long long)img * a.planeH;
-  for (int q = tg; q < N * N; q += kTileThreads) {
-    const int i = q / N, j = q - (q / N) * N;
-    const int gy = y0 - a.R + i, gx = x0 - a.R + j;
-    float h = 0.f;
-    if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) h = Hb[(long long)gy * a.ldH + gx];
-    Ag[i * P + j] = mk(h, 0.f);
-  }
+  // ---- signal window and its forward transform, by all 512 threads on image A0 (A1 is
+  // only the working image of the second component)
+  load_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
   __syncthreads();
-  pass0_inplace<N, -1, false, N>(Ag, tg, N, true);
-  __syncthreads();
-  pass1_inplace<N, -1, false, N / 32>(Ag, tw1, bq1, l1, N, N);
-  __syncthreads();
-  pass0_inplace<N, -1, true, N>(Ag, tg, N, true);
-  __syncthreads();
-  pass1_inplace<N, -1, true, N / 32>(Ag, tw1, bq1, l1, N, N);
-  __syncthreads();
+  forward_2d<N, 2 * kTileThreads>(A0, t);
   // signal spectrum of this thread's column pass-0 items
   cx<float> hs[NH][8];
   int qv[NH], qb[NH];

@@ -99,5 +99,55 @@ __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw,
   }
 }
 
+// Loads the N x N window of H (rows y0 - R + i, columns x0 - R + j, zero outside the
+// ny x nx image) into the LDS image A as (h, 0), with NT threads, eight loads in flight
+// per thread before their LDS stores.
+template <int N, int NT>
+__device__ __forceinline__ void load_window(cx<float>* A, const float* Hb, int ldH, int ny, int nx, int y0,
+                                            int x0, int R, int t) {
+  constexpr int P = N + 1, NW = (N * N + NT - 1) / NT, CH = 8;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NW; k0 += CH) {
+    float h[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int q = t + (k0 + k) * NT;
+      const int i = q / N, j = q - i * N;
+      const int gy = y0 - R + i, gx = x0 - R + j;
+      h[k] = 0.f;
+      if (q < N * N && gy >= 0 && gy < ny && gx >= 0 && gx < nx) h[k] = Hb[(long long)gy * ldH + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int q = t + (k0 + k) * NT;
+      if (q < N * N) {
+        const int i = q / N, j = q - i * N;
+        A[i * P + j] = mk(h[k], 0.f);
+      }
+    }
+  }
+}
+
+// Forward 2D transform (columns, then rows) of the image in A with NT threads; every
+// thread of the workgroup calls it. Ends with a barrier.
+template <int N, int NT>
+__device__ __forceinline__ void forward_2d(cx<float>* A, int t) {
+  constexpr int M = N / 8, LS = NT / 8, NI = (N + LS - 1) / LS;
+  const int l = t % LS;
+  const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
+  const TileTwiddles<N>& tt = tile_twiddles<N>();
+  cx<float> tw[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+  pass0_inplace<N, -1, false, N, NT>(A, t, N, true);
+  __syncthreads();
+  pass1_inplace<N, -1, false, NI, NT>(A, tw, bq, l, N, N);
+  __syncthreads();
+  pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
+  __syncthreads();
+  pass1_inplace<N, -1, true, NI, NT>(A, tw, bq, l, N, N);
+  __syncthreads();
+}
+
 }  // namespace
 }  // namespace ecc
