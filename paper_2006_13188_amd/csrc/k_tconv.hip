@@ -26,7 +26,7 @@ template <int N, int TV, int NSIG, int NT>
 __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
-  constexpr int NI = N / LS;                   // pass-1 lines per thread
+  constexpr int NI = (N + LS - 1) / LS;        // pass-1 lines per thread (line < N checked)
   constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
   const int t = threadIdx.x, l = t % LS;
   // with 512 threads the butterfly index is the wave index: uniform, so its twiddles sit
@@ -109,17 +109,19 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         const int u = l + LS * i;
-        cx<float> x[M];
+        if (N % LS == 0 || u < N) {
+          cx<float> x[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) x[r] = A[u * P + bq + 8 * r];
+          for (int r = 0; r < M; ++r) x[r] = A[u * P + bq + 8 * r];
 #pragma unroll
-        for (int r = 1; r < M; ++r) x[r] = cmulc(x[r], tw[r]);
-        dft<M, -1, float>(x);
+          for (int r = 1; r < M; ++r) x[r] = cmulc(x[r], tw[r]);
+          dft<M, -1, float>(x);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-          const cx<float> pr = cmul(x[r], Fc[u * N + bq + 8 * r]);
-          Z[i][r].re += wc * pr.re;
-          Z[i][r].im += wc * pr.im;
+          for (int r = 0; r < M; ++r) {
+            const cx<float> pr = cmul(x[r], Fc[u * N + bq + 8 * r]);
+            Z[i][r].re += wc * pr.re;
+            Z[i][r].im += wc * pr.im;
+          }
         }
       }
       __syncthreads();   // the image is rewritten next
@@ -129,7 +131,8 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int r = 0; r < M; ++r) A[(l + LS * i) * P + bq + 8 * r] = Z[i][r];
+      for (int r = 0; r < M; ++r)
+        if (N % LS == 0 || l + LS * i < N) A[(l + LS * i) * P + bq + 8 * r] = Z[i][r];
     __syncthreads();
     pass0_inplace<N, +1, false, N, NT>(A, t, N, true);
     __syncthreads();
@@ -169,10 +172,11 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
   }
 }
 
-// threads per workgroup: 512 when every pass divides evenly (N = 64, 128), else 256
+// threads per workgroup: 512 (two waves per SIMD; for N = 96 some passes leave a quarter
+// of the lanes idle, which costs less than one wave per SIMD)
 template <int N>
 constexpr int tconv_threads() {
-  return N == 96 ? 256 : 512;
+  return 512;
 }
 
 template <int N, int TV, int NSIG>
