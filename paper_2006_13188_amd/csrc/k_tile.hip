@@ -122,26 +122,46 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     // ---- column pass 0: product, inverse radix 8, A[8 b + r][v]
     const cx<float>* Fc = a.Fs + (long long)c * N * N;
     const bool more = c + 1 < a.U;
+    // without the register prefetch, the pass's filter-spectrum loads are issued in two
+    // groups of items ahead of their products (a latency per group, not per item)
+    constexpr int GQ = PREFETCH ? 1 : (NQ0 + 1) / 2;
 #pragma unroll
-    for (int s = 0; s < NQ0; ++s) {
-      const int q = t + s * NT;
-      const int v = q % N, b = q / N;
-      if (act && b < M) {
-        cx<float> x[8];
-        if constexpr (PREFETCH) {
+    for (int s0 = 0; s0 < NQ0; s0 += GQ) {
+      cx<float> fl[GQ][8];
+      if constexpr (!PREFETCH) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], fs[s][r]);
-          if (more) {
+        for (int g2 = 0; g2 < GQ; ++g2) {
+          const int q = t + (s0 + g2) * NT;
+          const int v = q % N, b = q / N;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) fs[s][r] = Fc[N * N + (b + M * r) * N + v];   // next component
+          for (int r = 0; r < 8; ++r) {
+            fl[g2][r] = mk(0.f, 0.f);
+            if (s0 + g2 < NQ0 && act && b < M) fl[g2][r] = Fc[(b + M * r) * N + v];
           }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], Fc[(b + M * r) * N + v]);
         }
-        dft<8, +1, float>(x);
+      }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
+      for (int g2 = 0; g2 < GQ; ++g2) {
+        const int s = s0 + g2;
+        const int q = t + s * NT;
+        const int v = q % N, b = q / N;
+        if (s < NQ0 && act && b < M) {
+          cx<float> x[8];
+          if constexpr (PREFETCH) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], fs[s][r]);
+            if (more) {
+#pragma unroll
+              for (int r = 0; r < 8; ++r) fs[s][r] = Fc[N * N + (b + M * r) * N + v];   // next component
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], fl[g2][r]);
+          }
+          dft<8, +1, float>(x);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
+        }
       }
     }
     __syncthreads();
