@@ -135,6 +135,21 @@ __device__ __forceinline__ void dft_odd_prime(cx<T>* v) {
   }
 }
 
+// a * exp(DIR 2 pi i m / R); m is a constant once the caller's loops are unrolled, and
+// the factors 1, -1 and +-i cost no arithmetic (a product with an exact 0 or 1 would
+// still be computed: the compiler may not drop it because of signed zeros).
+template <int R, int DIR, typename T>
+__device__ __forceinline__ cx<T> twiddle_const(cx<T> a, int m) {
+  const int r = ((m % R) + R) % R;
+  if (r == 0) return a;
+  if (2 * r == R) return mk(-a.re, -a.im);
+  if (4 * r == R) return mul_i<DIR>(a);
+  if (4 * r == 3 * R) return mul_i<-DIR>(a);
+  return cmul(a, mk<T>(T(cos_turn(r, R)), T(DIR * sin_turn(r, R))));
+}
+
+// Cooley-Tukey split R = R1 R2: R2 transforms of length R1 over n1 (inputs v[R2 n1 + n2]),
+// twiddles, then R1 transforms of length R2.
 template <int R1, int R2, int DIR, typename T>
 __device__ __forceinline__ void dft_composite(cx<T>* v) {
   constexpr int R = R1 * R2;
@@ -146,14 +161,7 @@ __device__ __forceinline__ void dft_composite(cx<T>* v) {
     for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
     dft<R1, DIR, T>(t);
 #pragma unroll
-    for (int q1 = 0; q1 < R1; ++q1) {
-      if (n2 * q1 == 0) {
-        y[n2][q1] = t[q1];
-      } else {
-        const cx<T> w = mk<T>(T(cos_turn(n2 * q1, R)), T(DIR * sin_turn(n2 * q1, R)));
-        y[n2][q1] = cmul(t[q1], w);
-      }
-    }
+    for (int q1 = 0; q1 < R1; ++q1) y[n2][q1] = twiddle_const<R, DIR, T>(t[q1], n2 * q1);
   }
 #pragma unroll
   for (int q1 = 0; q1 < R1; ++q1) {
@@ -166,6 +174,53 @@ __device__ __forceinline__ void dft_composite(cx<T>* v) {
   }
 }
 
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+// inverse of a modulo m (gcd(a, m) = 1, m > 1)
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+// largest power of a prime dividing R (R itself when R is a prime power)
+constexpr int prime_power_part(int R) {
+  const int p = smallest_factor(R);
+  int q = 1;
+  while (R % (q * p) == 0) q *= p;
+  return q;
+}
+
+// Prime-factor (Good-Thomas) split of R = R1 R2 with gcd(R1, R2) = 1: input index
+// (R2 n1 + R1 n2) mod R and output index (R2 (R2^-1 mod R1) q1 + R1 (R1^-1 mod R2) q2)
+// mod R (Chinese remainders) turn the transform into plain length-R1 and length-R2
+// transforms with no twiddle factors.
+template <int R1, int R2, int DIR, typename T>
+__device__ __forceinline__ void dft_prime_factor(cx<T>* v) {
+  constexpr int R = R1 * R2;
+  constexpr int C1 = R2 * inv_mod(R2 % R1, R1), C2 = R1 * inv_mod(R1 % R2, R2);
+  cx<T> y[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[(R2 * n1 + R1 * n2) % R];
+    dft<R1, DIR, T>(y[n2]);
+  }
+#pragma unroll
+  for (int q1 = 0; q1 < R1; ++q1) {
+    cx<T> u[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) u[n2] = y[n2][q1];
+    dft<R2, DIR, T>(u);
+#pragma unroll
+    for (int q2 = 0; q2 < R2; ++q2) v[(C1 * q1 + C2 * q2) % R] = u[q2];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 1) {
@@ -173,6 +228,34 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     const cx<T> a = v[0], b = v[1];
     v[0] = a + b;
     v[1] = a - b;
+  } else if constexpr (R == 3) {
+    // with a = v1 + v2, b = v1 - v2: X0 = v0 + a, X1,2 = v0 - a/2 +- DIR i (sqrt(3)/2) b,
+    // the last product folded into fused multiply-adds
+    constexpr T h = T(-cos_turn(1, 3)), sn = T(DIR * sin_turn(1, 3));
+    const cx<T> a = v[1] + v[2], b = v[1] - v[2];
+    const cx<T> A = mk(fmadd(-h, a.re, v[0].re), fmadd(-h, a.im, v[0].im));
+    v[0] = v[0] + a;
+    v[1] = mk(fmadd(-sn, b.im, A.re), fmadd(sn, b.re, A.im));
+    v[2] = mk(fmadd(sn, b.im, A.re), fmadd(-sn, b.re, A.im));
+  } else if constexpr (R == 8) {
+    // radix 2 over two length-4 transforms (even and odd samples): X_k = E_k + W^k O_k,
+    // X_{k+4} = E_k - W^k O_k with W = exp(DIR 2 pi i / 8) = c (1 + DIR i), W^2 = DIR i,
+    // W^3 = c (-1 + DIR i); the factor c is folded into fused multiply-adds
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4, DIR, T>(e);
+    dft<4, DIR, T>(o);
+    constexpr T c = T(cos_turn(1, 8)), d = T(DIR);
+    const T p1 = o[1].re - d * o[1].im, q1 = o[1].im + d * o[1].re;    // W O_1 / c
+    const T p3 = -o[3].re - d * o[3].im, q3 = d * o[3].re - o[3].im;   // W^3 O_3 / c
+    const cx<T> w2 = mul_i<DIR>(o[2]);
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[2] = e[2] + w2;
+    v[6] = e[2] - w2;
+    v[1] = mk(fmadd(c, p1, e[1].re), fmadd(c, q1, e[1].im));
+    v[5] = mk(fmadd(-c, p1, e[1].re), fmadd(-c, q1, e[1].im));
+    v[3] = mk(fmadd(c, p3, e[3].re), fmadd(c, q3, e[3].im));
+    v[7] = mk(fmadd(-c, p3, e[3].re), fmadd(-c, q3, e[3].im));
   } else if constexpr (R == 4) {
     const cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
     const cx<T> s13 = v[1] + v[3], d13 = mul_i<DIR>(v[1] - v[3]);
@@ -182,6 +265,8 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     v[3] = d02 - d13;
   } else if constexpr (smallest_factor(R) == R) {
     dft_odd_prime<R, DIR, T>(v);
+  } else if constexpr (prime_power_part(R) != R) {
+    dft_prime_factor<prime_power_part(R), R / prime_power_part(R), DIR, T>(v);
   } else if constexpr (R % 4 == 0 && R != 4) {
     dft_composite<4, R / 4, DIR, T>(v);
   } else {
