@@ -136,7 +136,7 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
     __syncthreads();
     pass0_inplace<N, +1, false, N, NT>(A, t, N, true);
     __syncthreads();
-    pass1_inplace<N, +1, false, NI, NT>(A, tw, bq, l, N, T);
+    pass1_inplace<N, +1, false, NI, NT, TV / 8>(A, tw, bq, l, N, T);
     __syncthreads();
     pass0_inplace<N, +1, true, TV, NT>(A, t, T, true);
     __syncthreads();

@@ -52,10 +52,23 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   }
 
   __syncthreads();   // the LDS image may still be in use by the previous block
-  // ---- signal window into A (real part) and its forward 2D transform
-  load_window<N, NT>(A, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
-  __syncthreads();
-  forward_2d<N, NT>(A, t);
+  // field values of this thread's output pixels (l + LS i, bq + 8 r), loaded just before
+  // the window so that the two latencies overlap
+  float fvs[STACK ? 1 : TR][RV];
+  if constexpr (!STACK) {
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int r = 0; r < RV; ++r) {
+        const int u = l + LS * i, x = bq + 8 * r;
+        const int gy = y0 + u, gx = x0 + x;
+        fvs[i][r] = (u < T && x < T && gy < a.ny && gx < a.nx)
+                        ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
+                        : 0.f;
+      }
+  }
+  // ---- forward 2D transform of the signal window
+  forward_window<N, NT>(A, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
   // signal spectrum values of this thread's column pass-0 items, kept for all components
   cx<float> hs[NQ0][8];
 #pragma unroll
@@ -63,10 +76,10 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     const int q = t + s * NT;
     const int v = q % N, b = q / N;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? A[(b + M * r) * P + v] : mk(0.f, 0.f);
+    for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? window_spectrum<N>(A, b + M * r, v) : mk(0.f, 0.f);
   }
 
-  // ---- per-pixel state of the row pass-1 outputs: pixel (l + 32 i, bq + 8 r). The
+  // ---- per-pixel state of the row pass-1 outputs: pixel (l + LS i, bq + 8 r). The
   // phase of component c is e^{i (kofs + c) alpha}, advanced by one factor e^{i alpha}
   // per component.
   float acc[TR][RV];
@@ -81,7 +94,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
       const int u = l + LS * i, x = bq + 8 * r;
       const int gy = y0 + u, gx = x0 + x;
       if (!STACK && u < T && x < T && gy < a.ny && gx < a.nx) {
-        const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+        const float fv = fvs[STACK ? 0 : i][r];
         const int k0 = a.kofs;
         cx<float> s1, s0;
         if (a.fld.log_mode || a.kofs != 0) {
@@ -166,7 +179,7 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     }
     __syncthreads();
     // ---- column pass 1 (in place), rows < T kept
-    if (act) pass1_inplace<N, +1, false, N / LS, NT>(A, tw, bq, l, N, T);
+    if (act) pass1_inplace<N, +1, false, N / LS, NT, TV / 8>(A, tw, bq, l, N, T);
     __syncthreads();
     // ---- row pass 0 over the T valid rows
     if constexpr (SEPB) {
@@ -268,11 +281,20 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   for (int r = 0; r < M; ++r) tw1[r] = mk(tt.re[bq1][r], tt.im[bq1][r]);
 
   __syncthreads();   // the LDS images may still be in use by the previous block
-  // ---- signal window and its forward transform, by all 512 threads on image A0 (A1 is
+  // field values of this thread's output pixels (u4, bq4 + 8 r), loaded just before the
+  // window so that the two latencies overlap
+  const bool rowok = u4 < T && y0 + u4 < a.ny;
+  float fvs[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
+    fvs[r] = (!STACK && rowok && x < T && gx < a.nx)
+                 ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
+                 : 0.f;
+  }
+  // ---- forward transform of the signal window, by all 512 threads on image A0 (A1 is
   // only the working image of the second component)
-  load_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
-  __syncthreads();
-  forward_2d<N, 2 * kTileThreads>(A0, t);
+  forward_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
   // signal spectrum of this thread's column pass-0 items
   cx<float> hs[NH][8];
   int qv[NH], qb[NH];
@@ -284,22 +306,21 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     qb[s] = q / N;
     const bool ok = s < NF || t < 2 * REM;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) hs[s][r] = ok ? A0[(qb[s] + M * r) * P + qv[s]] : mk(0.f, 0.f);
+    for (int r = 0; r < 8; ++r) hs[s][r] = ok ? window_spectrum<N>(A0, qb[s] + M * r, qv[s]) : mk(0.f, 0.f);
   }
   const int hcomp = REM ? t / (REM ? REM : 1) : 0;   // component of the half item (t < 2 REM)
 
   // ---- per-pixel state: pixel (u4, bq4 + 8 r), phase e^{i (kofs + c) alpha}
   float acc[8];
   cx<float> z[8], e1[8];
-  const bool rowok = u4 < T && y0 + u4 < a.ny;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     acc[r] = 0.f;
     z[r] = mk(0.f, 0.f);
     e1[r] = mk(0.f, 0.f);
-    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
+    const int x = bq4 + 8 * r, gx = x0 + x;
     if (!STACK && rowok && x < T && gx < a.nx) {
-      const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+      const float fv = fvs[r];
       if (a.fld.log_mode || a.kofs != 0) {
         const double al = field_angle(a.fld, fv);
         double sn, cs;
@@ -345,7 +366,7 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     __syncthreads();
     const bool act = g == 0 || two;
     // ---- column pass 1 (in place, rows < T kept) and row pass 0, group g on c + g
-    if (act) pass1_inplace<N, +1, false, N / 32>(Ag, tw1, bq1, l1, N, T);
+    if (act) pass1_inplace<N, +1, false, N / 32, kTileThreads, TV / 8>(Ag, tw1, bq1, l1, N, T);
     __syncthreads();
     pass0_inplace<N, +1, true, TV>(Ag, tg, T, act);
     __syncthreads();

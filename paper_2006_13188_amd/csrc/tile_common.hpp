@@ -77,8 +77,9 @@ __device__ __forceinline__ void pass0_inplace(cx<float>* A, int t, int nlines, b
 
 // Pass 1 in place for lines l + LS i (i < NI, line < nlines), butterfly bq (LS = NT / 8
 // threads share a butterfly index); tw holds w^{r bq} for the inverse direction
-// (conjugated for the forward one).
-template <int N, int DIR, bool ROWS, int NI, int NT = kTileThreads>
+// (conjugated for the forward one). Outputs bq + 8 r are stored for r < RS (a bound known
+// at compile time, so the others are not computed) and bq + 8 r < nstore.
+template <int N, int DIR, bool ROWS, int NI, int NT = kTileThreads, int RS = N / 8>
 __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw, int bq, int l,
                                               int nlines, int nstore) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
@@ -94,7 +95,7 @@ __device__ __forceinline__ void pass1_inplace(cx<float>* A, const cx<float>* tw,
       dft<M, DIR, float>(x);
 #pragma unroll
       for (int r = 0; r < M; ++r)
-        if (bq + 8 * r < nstore) A[at<P, ROWS>(line, bq + 8 * r)] = x[r];
+        if (r < RS && bq + 8 * r < nstore) A[at<P, ROWS>(line, bq + 8 * r)] = x[r];
     }
   }
 }
@@ -126,6 +127,92 @@ __device__ __forceinline__ void load_window(cx<float>* A, const float* Hb, int l
       }
     }
   }
+}
+
+// Length-8 DFT of real inputs x (sign DIR): X_0 .. X_7 with X_{8-k} = conj(X_k), from the
+// even/odd split of the complex form with the imaginary inputs known to be zero.
+template <int DIR>
+__device__ __forceinline__ void rdft8(const float* x, cx<float>* X) {
+  constexpr float c = float(cos_turn(1, 8)), d = float(DIR);
+  const float a0 = x[0] + x[4], a1 = x[0] - x[4], a2 = x[2] + x[6], a3 = x[2] - x[6];
+  const float a4 = x[1] + x[5], a5 = x[1] - x[5], a6 = x[3] + x[7], a7 = x[3] - x[7];
+  const float e0 = a0 + a2, e2 = a0 - a2, o0 = a4 + a6, o2 = a4 - a6;
+  const float dm = a5 - a7, sp = a5 + a7;
+  X[0] = mk(e0 + o0, 0.f);
+  X[4] = mk(e0 - o0, 0.f);
+  X[2] = mk(e2, d * o2);
+  X[6] = mk(e2, -d * o2);
+  const float r1 = fmadd(c, dm, a1), r3 = fmadd(-c, dm, a1);
+  const float i1 = fmadd(c, sp, a3), i3 = fmadd(c, sp, -a3);
+  X[1] = mk(r1, d * i1);
+  X[7] = mk(r1, -d * i1);
+  X[3] = mk(r3, d * i3);
+  X[5] = mk(r3, -d * i3);
+}
+
+// Forward 2D transform of the block's N x N window of the real signal H (rows
+// y0 - R + i, columns x0 - R + j, zero outside the ny x nx image) into A, every thread
+// of the workgroup taking part. Column pass 0 reads the window straight from memory
+// (real radix 8, all loads of a thread in flight together); since the window is real,
+// S[N - k][l] = conj(S[k][(N - l) mod N]), so only rows k <= N/2 are transformed along
+// the rows (window_spectrum supplies the others). Ends with a barrier.
+template <int N, int NT>
+__device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, int ldH, int ny, int nx, int y0,
+                                               int x0, int R, int t) {
+  constexpr int M = N / 8, P = N + 1, LS = NT / 8, NI = (N + LS - 1) / LS, H2 = N / 2 + 1;
+  constexpr int NQ = (N * M + NT - 1) / NT;   // column pass-0 items of a thread
+  constexpr int G = NQ < 4 ? NQ : 4;          // items whose loads are in flight together
+  const int l = t % LS;
+  const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
+#pragma unroll
+  for (int s0 = 0; s0 < NQ; s0 += G) {
+    float h[G][8];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int q = t + (s0 + g) * NT;
+      const int v = q % N, b = q / N;
+      const int gx = x0 - R + v;
+      const bool colok = s0 + g < NQ && b < M && gx >= 0 && gx < nx;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int gy = y0 - R + b + M * r;
+        h[g][r] = (colok && gy >= 0 && gy < ny) ? Hb[(long long)gy * ldH + gx] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int q = t + (s0 + g) * NT;
+      const int v = q % N, b = q / N;
+      if (s0 + g < NQ && b < M) {
+        cx<float> X[8];
+        rdft8<-1>(h[g], X);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = X[r];
+      }
+    }
+  }
+  const TileTwiddles<N>& tt = tile_twiddles<N>();
+  cx<float> tw[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+  __syncthreads();
+  pass1_inplace<N, -1, false, NI, NT, (H2 + 7) / 8>(A, tw, bq, l, N, H2);
+  __syncthreads();
+  pass0_inplace<N, -1, true, H2, NT>(A, t, H2, true);
+  __syncthreads();
+  pass1_inplace<N, -1, true, NI, NT>(A, tw, bq, l, H2, N);
+  __syncthreads();
+}
+
+// Spectrum value S[k][v] of a window transformed by forward_window.
+template <int N>
+__device__ __forceinline__ cx<float> window_spectrum(const cx<float>* A, int k, int v) {
+  constexpr int P = N + 1;
+  const bool up = k > N / 2;
+  const int row = up ? N - k : k;
+  const int col = (up && v != 0) ? N - v : v;
+  const cx<float> s = A[row * P + col];
+  return mk(s.re, up ? -s.im : s.im);
 }
 
 // Forward 2D transform (columns, then rows) of the image in A with NT threads; every
