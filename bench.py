@@ -83,8 +83,11 @@ def stored_traffic(kernel_tag):
     h = re.search(r"source sha256: ([0-9a-f]{64}) \(([^)]+)\)", text)
     if not m or not h:
         return None
-    src = os.path.join(ROOT, h.group(2))
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+    # sha256 of the listed sources (the kernel and the headers it is built from) concatenated
+    srcs = [os.path.join(ROOT, f.strip()) for f in h.group(2).split(",")]
+    if not all(os.path.exists(f) for f in srcs):
+        return None
+    if hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest() != h.group(1):
         return None
     return float(m.group(1))
 
