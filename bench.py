@@ -54,13 +54,14 @@ def alg_bytes_corr(ny, nx, Py, Px, U):
 
 
 def alg_flops_tiled(ny, nx, n, t, U):
-    """Algorithmic FP32 flops of one tiled launch: per block, the forward 2D transform
-    (2n transforms), and per component n column + t row inverse transforms (5 n log2 n
-    each), the spectral product (6 n^2) and the per-pixel combination (10 t^2)."""
+    """Algorithmic FP32 flops of one tiled launch: per block, the forward 2D transform of
+    the real window (half of 2n complex transforms of 5 n log2 n each), and per component
+    n column + t row inverse transforms, the spectral product (6 n^2) and the per-pixel
+    combination (10 t^2)."""
     import math
     blocks = ((ny + t - 1) // t) * ((nx + t - 1) // t)
     f1 = 5.0 * n * math.log2(n)
-    per_block = 2 * n * f1 + U * ((n + t) * f1 + 6.0 * n * n + 10.0 * t * t)
+    per_block = n * f1 + U * ((n + t) * f1 + 6.0 * n * n + 10.0 * t * t)
     return blocks * per_block
 
 
