@@ -135,15 +135,19 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   const Transform* Tn = nullptr;
   ECC_HIP(get_transform(plan->ctx, N, &Tn));
   auto sp = std::make_unique<Spectrum>();
-  sp->Py = sp->Px = sp->ld = N;
+  sp->Py = sp->Px = N;
   sp->full = 1;
   const int U = plan->U, Sz = plan->S;
-  // correlation: F_k with its window corner at (0, 0); convolution: offset x at x - R
+  // correlation: F_k with its window corner at (0, 0), planes of N x N; convolution:
+  // offset x at x - R, planes of tconv_plane(N) values with row pitch N + 1
   const int shift = conv ? -2 * plan->R : 0;
+  sp->ld = conv ? tconv_pitch(N) : N;
+  const long long plane = conv ? (long long)tconv_plane(N) : (long long)N * N;
   DevBuf tmp, spec64;
   ECC_HIP(tmp.ensure((size_t)U * Sz * N * sizeof(cx<double>)));
-  ECC_HIP(spec64.ensure((size_t)U * N * N * sizeof(cx<double>)));
-  ECC_HIP(sp->buf.ensure((size_t)U * N * N * sizeof(cx<float>)));
+  ECC_HIP(spec64.ensure((size_t)U * plane * sizeof(cx<double>)));
+  ECC_HIP(sp->buf.ensure((size_t)U * plane * sizeof(cx<float>)));
+  if (conv) ECC_HIP(hipMemsetAsync(spec64.p, 0, (size_t)U * plane * sizeof(cx<double>), st));
   RowCfg rc = row_config(*Tn, N, sizeof(cx<double>));
   ColCfg cc = col_config(*Tn, 2, sizeof(cx<double>), 256);
   ECC_TRY(check_cfg_row(rc, *Tn, sizeof(cx<double>), "filter row"));
@@ -152,9 +156,8 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
                                    Sz, Sz, shift, tmp.as<cx<double>>(), (long long)Sz * N, N, N, 0,
                                    Tn->desc, Tn->d())));
   ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, shift,
-                                   spec64.as<cx<double>>(), (long long)N * N, N, N, 0, Tn->desc,
-                                   Tn->d())));
-  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * N * N));
+                                   spec64.as<cx<double>>(), plane, sp->ld, N, 0, Tn->desc, Tn->d())));
+  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * plane));
   ECC_HIP(hipStreamSynchronize(st));
   *out = sp.get();
   plan->tile_spectra[key] = std::move(sp);

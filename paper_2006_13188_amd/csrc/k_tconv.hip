@@ -21,10 +21,31 @@ namespace ecc {
 
 namespace {
 
+// LDS copy of the block spectrum of one component: for N <= 96 it fits beside the
+// transform image (2 x 75 KB for N = 96), and the plane is brought in by direct
+// memory-to-LDS loads (1 KB per wave instruction) issued at the start of the component's
+// forward transform, so that its latency is hidden behind three transform passes. A
+// separate LDS object, so that the compiler can tell its loads from the image's.
+constexpr bool tconv_dma(int N) { return N <= 96; }
+template <int N>
+__shared__ cx<float> conv_spec_lds[tconv_plane(N)];
+
+template <int N, int NT>
+__device__ __forceinline__ void stream_spectrum(const cx<float>* src) {
+  constexpr int NCH = tconv_plane(N) / 128;   // 1 KB pieces: 64 lanes x 16 bytes
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int ch = w; ch < NCH; ch += NT / 64)
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + ch * 128 + 2 * lane),
+                                     (__attribute__((address_space(3))) void*)(conv_spec_lds<N> + ch * 128),
+                                     16, 0, 0);
+}
+
 // NT threads (256 or 512); LS = NT / 8 threads share each pass-1 butterfly index.
 template <int N, int TV, int NSIG, int NT>
 __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
+  constexpr bool DMA = tconv_dma(N);
+  constexpr int FP = tconv_pitch(N), FPL = tconv_plane(N);
   constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
   constexpr int NI = (N + LS - 1) / LS;        // pass-1 lines per thread (line < N checked)
   constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
@@ -81,7 +102,8 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
       for (int r = 0; r < M; ++r) Z[i][r] = mk(0.f, 0.f);
 
     for (int c = 0; c < a.U; ++c) {
-      const cx<float>* Fc = a.Fs + (long long)c * N * N;
+      const cx<float>* Fc = a.Fs + (long long)c * FPL;
+      if constexpr (DMA) stream_spectrum<N, NT>(Fc);
       const float wc = a.w[c];
       // ---- forward transform of m_c: column pass 0 from registers
 #pragma unroll
@@ -100,10 +122,12 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
           for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
         }
       }
-      __syncthreads();
+      // (barriers for LDS data only: the spectrum copy stays in flight across them)
+      lds_barrier();
       pass1_inplace<N, -1, false, NI, NT>(A, tw, bq, l, N, N);
-      __syncthreads();
-      pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
+      lds_barrier();
+      pass0_inplace<N, -1, true, N, NT, true>(A, t, N, true);
+      if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0);   // this wave's spectrum pieces are in LDS
       __syncthreads();
       // ---- row pass 1 and the weighted product with the filter spectrum
 #pragma unroll
@@ -118,7 +142,7 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
           dft<M, -1, float>(x);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
-            const cx<float> pr = cmul(x[r], Fc[u * N + bq + 8 * r]);
+            const cx<float> pr = cmul(x[r], DMA ? conv_spec_lds<N>[u * FP + bq + 8 * r] : Fc[u * FP + bq + 8 * r]);
             Z[i][r].re += wc * pr.re;
             Z[i][r].im += wc * pr.im;
           }
@@ -179,18 +203,19 @@ constexpr int tconv_threads() {
   return 512;
 }
 
+// the transform image: a static LDS object of its own (with the spectrum copy beside it
+// for N <= 96), so that the compiler orders the spectrum's memory-to-LDS loads only
+// against the spectrum's reads
+template <int N>
+__shared__ cx<float> conv_img_lds[N * (N + 1)];
+
 template <int N, int TV, int NSIG>
 __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a) {
-  extern __shared__ cx<float> lds_c[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  conv_block_one<N, TV, NSIG, tconv_threads<N>()>(a, lb / ntile, lb % ntile, lds_c);
+  conv_block_one<N, TV, NSIG, tconv_threads<N>()>(a, lb / ntile, lb % ntile, conv_img_lds<N>);
 }
 
-template <int N>
-constexpr size_t tconv_lds() {
-  return (size_t)N * (N + 1) * sizeof(cx<float>);
-}
 
 }  // namespace
 
@@ -214,10 +239,10 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   if (N == n && TV == tv) {                                                                       \
     if (a.nsig == 1)                                                                              \
       hipLaunchKernelGGL((k_tile_conv<n, tv, 1>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
-                         tconv_lds<n>(), s, a);                                                   \
+                         0, s, a);                                                                \
     else                                                                                          \
       hipLaunchKernelGGL((k_tile_conv<n, tv, 2>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
-                         tconv_lds<n>(), s, a);                                                   \
+                         0, s, a);                                                                \
     return last();                                                                                \
   }
   ECC_TCONV_CONFIGS(ECC_CL)
@@ -225,16 +250,13 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   return hipErrorInvalidValue;
 }
 
-size_t tconv_lds_bytes(int N) { return (size_t)N * (N + 1) * sizeof(cx<float>); }
-
-hipError_t prepare_tconv_kernels() {
-  hipError_t e = hipSuccess;
-#define ECC_CP(n, tv)                                              \
-  if (e == hipSuccess) e = allow_lds(k_tile_conv<n, tv, 1>);       \
-  if (e == hipSuccess) e = allow_lds(k_tile_conv<n, tv, 2>);
-  ECC_TCONV_CONFIGS(ECC_CP)
-#undef ECC_CP
-  return e;
+// LDS per workgroup (all static: the transform image, and the spectrum copy for N <= 96)
+size_t tconv_lds_bytes(int N) {
+  return (size_t)N * (N + 1) * sizeof(cx<float>) +
+         (tconv_dma(N) ? (size_t)tconv_plane(N) * sizeof(cx<float>) : 0);
 }
+
+// the kernels use static LDS only: nothing to set up
+hipError_t prepare_tconv_kernels() { return hipSuccess; }
 
 }  // namespace ecc

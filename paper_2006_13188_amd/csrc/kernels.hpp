@@ -149,6 +149,12 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
                             const cx<float>* Fs);
 
 // ---- tiled (overlap-save) convolution: one workgroup (256 threads) per T x T block
+// Block spectra of the tiled convolution: per component a plane of N rows of pitch N + 1
+// complex64 values, the plane rounded up to a multiple of 128 values (1 KB), so that a
+// plane can be copied into LDS in whole 1 KB pieces with the odd pitch kept.
+constexpr int tconv_pitch(int N) { return N + 1; }
+constexpr int tconv_plane(int N) { return (N * (N + 1) + 127) / 128 * 128; }
+
 struct TileConvArgs {
   const float* H;
   long long planeH;
@@ -162,7 +168,8 @@ struct TileConvArgs {
   int ny, nx, R, T, tx, ty, U;   // tx, ty set by the launcher
   const float* w;
   float scale;
-  const cx<float>* Fs;     // U block spectra of N x N, F_c at (x - R) mod N
+  const cx<float>* Fs;     // U block spectra (tconv_plane(N) values apart, pitch N + 1),
+                           // F_c at (x - R) mod N
 };
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);

@@ -14,6 +14,17 @@ namespace {
 constexpr int kTileThreads = 256;
 
 
+// Workgroup barrier for data exchanged through LDS only: waits for this wave's LDS
+// operations (lgkmcnt = 0; vmcnt and expcnt left at their maxima), not for its memory
+// loads, so that memory-to-LDS copies can stay in flight across it; the signal fences keep
+// the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // element pos of line `line` in an LDS image of pitch P: along a row (ROWS) or a column
 template <int P, bool ROWS>
 __device__ __forceinline__ int at(int line, int pos) {
@@ -48,7 +59,7 @@ __device__ __forceinline__ const TileTwiddles<N>& tile_twiddles() {
 // Pass 0 of the transforms of `nlines` lines of the image in A, all at once: items
 // q = t + NT s -> line q mod NL (NL lines per item round), butterfly q / NL.
 // Reads everything first, synchronises, then writes (the pass is not in place).
-template <int N, int DIR, bool ROWS, int NL, int NT = kTileThreads>
+template <int N, int DIR, bool ROWS, int NL, int NT = kTileThreads, bool LDSB = false>
 __device__ __forceinline__ void pass0_inplace(cx<float>* A, int t, int nlines, bool act) {
   constexpr int M = N / 8, P = N + 1;
   constexpr int NQ = (NL * M + NT - 1) / NT;
@@ -62,7 +73,8 @@ __device__ __forceinline__ void pass0_inplace(cx<float>* A, int t, int nlines, b
       for (int r = 0; r < 8; ++r) v[s][r] = A[at<P, ROWS>(line, b + M * r)];
     }
   }
-  __syncthreads();
+  if constexpr (LDSB) lds_barrier();
+  else __syncthreads();
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
     const int q = t + s * NT;
