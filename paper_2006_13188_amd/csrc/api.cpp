@@ -124,9 +124,17 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
 namespace ecc {
 // Block spectra for the tiled path: FFT_N x N(F_k placed with its window corner at
 // (0, 0)), float64 then rounded, full N x N planes (no symmetry assumed).
-ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, bool conv) {
+bool rotation_parity(ecc_filter_plan plan) {
+  if (plan->group != ECC_GROUP_ROTATION || !plan->symmetric || (int)plan->parity.size() != plan->U) return false;
+  for (int k = 0; k < plan->U; ++k)
+    if (plan->parity[k] != ((k % 2) ? -1.f : 1.f)) return false;
+  return true;
+}
+
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode) {
   std::lock_guard<std::mutex> g(plan->mu);
-  const int key = conv ? -N : N;
+  const bool conv = mode == SPEC_CONV;
+  const int key = mode * 1000 + N;
   auto it = plan->tile_spectra.find(key);
   if (it != plan->tile_spectra.end()) {
     *out = it->second.get();
@@ -140,7 +148,7 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   const int U = plan->U, Sz = plan->S;
   // correlation: F_k with its window corner at (0, 0), planes of N x N; convolution:
   // offset x at x - R, planes of tconv_plane(N) values with row pitch N + 1
-  const int shift = conv ? -2 * plan->R : 0;
+  const int shift = conv ? -2 * plan->R : mode == SPEC_CENTRED ? -plan->R : 0;
   sp->ld = conv ? tconv_pitch(N) : N;
   const long long plane = conv ? (long long)tconv_plane(N) : (long long)N * N;
   DevBuf tmp, spec64;
@@ -662,7 +670,7 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   if (saved) strat = ECC_STRATEGY_TWO_PASS;   // the saved stack is the two-pass form's row stack
   if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION) {
     const Spectrum* sp = nullptr;
-    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, true));
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
     TileConvArgs ca{};
     ca.H = signal;
     ca.planeH = pS;
@@ -688,12 +696,13 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   }
   if (strat == ECC_STRATEGY_TILED) {
     const Spectrum* sp = nullptr;
-    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp));
+    const bool sym = tile_symmetric(tc.N, tc.TV) && rotation_parity(plan);
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, sym ? SPEC_CENTRED : SPEC_CORR));
     Field fl = make_field(plan, field, pF, ld_field, 1.0);
     mark(ctx, 0, st);
     ECC_HIP(launch_tile_corr(st, tc.N, tc.TV, batch, signal, pS, ld_signal, fl, out, pO, ld_out, ny, nx,
                              plan->R, tc.T, plan->U, 0, plan->d_weights.as<float>(),
-                             1.0f / ((float)tc.N * (float)tc.N), sp->buf.as<cx<float>>()));
+                             1.0f / ((float)tc.N * (float)tc.N), sp->buf.as<cx<float>>(), sym));
     mark(ctx, 1, st);
     return ECC_OK;
   }
@@ -799,7 +808,7 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
     return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
   if (tiled) {
     const Spectrum* sp = nullptr;
-    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, true));
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
     TileConvArgs ca{};
     ca.H = signal;
     ca.ldH = ld_signal;

@@ -69,8 +69,12 @@ ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
 // Same choice for the tiled convolution (static operation count).
 bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best);
 // Block spectra of a plan for transform length N (cached in the plan): for correlation
-// (F_k with its window corner at (0, 0)) or convolution (offset x at (x - R) mod N).
-ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, bool conv = false);
+// (F_k with its window corner at (0, 0)), convolution (offset x at (x - R) mod N, padded
+// planes) or the symmetric correlation form (centred: offset x at x mod N).
+enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2 };
+ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode = SPEC_CORR);
+// rotation plans: F_k(-x) = (-1)^k F_k(x), components k = 0 .. U - 1
+bool rotation_parity(ecc_filter_plan plan);
 // Per-pixel angle description of a plan's field argument.
 Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, double mul_sign);
 // Any forward operator call (validated arguments) on stream st.

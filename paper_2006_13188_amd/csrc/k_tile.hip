@@ -258,11 +258,25 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
 //  * row pass 1: thread (row u = t mod 64, butterfly bq = t / 64) does both components;
 //    bq is uniform in a wave, so its twiddles come from scalar loads, and the thread owns
 //    the 8 pixels (u, bq + 8 r) for all components.
-template <int N, bool STACK = false>
+//
+// SYM (rotation filters, N = 96): the spectra are those of the centred components F~_c
+// (offset x at x mod N), for which F~_c(-w) = (-1)^c F~_c(w); the window spectrum is taken
+// as h'(w) = h(w) e^{2 pi i (w_y + w_x) R / N}, which gives the same products
+// h'(w) conj(F~_c(w)) = h(w) conj(f_c(w)) and satisfies h'(-w) = conj(h'(w)) (real
+// window). A thread then does an item and its mirror item (column -v, rows -k) from one
+// set of filter-spectrum loads: the mirror products are (-1)^c conj(h'(w) F~_c(w)), which
+// halves the spectrum reads of column pass 0.
+template <int N, bool STACK = false, bool SYM = false>
 __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
   constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
   constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
-  constexpr int NH = NF + (REM ? 1 : 0);
+  constexpr int NH = SYM ? 2 : NF + (REM ? 1 : 0);
+  // SYM: item pairs (item, mirror) apart from the 4 self-mirrored items (v in {0, N/2},
+  // b in {0, M/2}); thread t does pair t for both components, and the remaining pairs and
+  // the self-mirrored items are dealt as single-component units to threads t < NX
+  constexpr int NPAIR = (NL - 4) / 2, NX = 2 * (NPAIR - 2 * kTileThreads) + 8;
+  static_assert(!SYM || (N == 96 && NPAIR >= 2 * kTileThreads && NX <= 2 * kTileThreads),
+                "symmetric pair form: N = 96");
   static_assert(REM * 2 <= 2 * kTileThreads, "remainder items exceed one round");
   const int t = threadIdx.x;
   const int g = t / kTileThreads, tg = t - g * kTileThreads;
@@ -298,17 +312,55 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   // signal spectrum of this thread's column pass-0 items
   cx<float> hs[NH][8];
   int qv[NH], qb[NH];
+  int hcomp = 0;      // component of the half item (t < 2 REM), or of the extra unit (SYM)
+  bool xpair = false;  // SYM: the extra unit is an item pair (else a self-mirrored item)
+  if constexpr (SYM) {
+    // canonical item of pair p: b in 1 .. M/2 - 1 (all columns), then b = 0 and b = M/2
+    // with columns 1 .. N/2 - 1
+    auto pair_item = [&](int p, int& v, int& b) {
+      constexpr int NB = (M / 2 - 1) * N;
+      if (p < NB) {
+        b = 1 + p / N;
+        v = p % N;
+      } else {
+        const int p2 = p - NB;
+        b = p2 < N / 2 - 1 ? 0 : M / 2;
+        v = 1 + (p2 < N / 2 - 1 ? p2 : p2 - (N / 2 - 1));
+      }
+    };
+    pair_item(t, qv[0], qb[0]);
+    const int e = t < NX ? t : 0;
+    hcomp = e & 1;
+    xpair = e < 2 * (NPAIR - 2 * kTileThreads);
+    if (xpair) {
+      pair_item(2 * kTileThreads + e / 2, qv[1], qb[1]);
+    } else {
+      const int sf = (e - 2 * (NPAIR - 2 * kTileThreads)) / 2;
+      qv[1] = (sf & 1) * (N / 2);
+      qb[1] = (sf >> 1) * (M / 2);
+    }
+    const TilePhases<96>& ph = kPh96;
 #pragma unroll
-  for (int s = 0; s < NH; ++s) {
-    int q = t + s * 2 * kTileThreads;
-    if (s == NF) q = NF * 2 * kTileThreads + (REM ? t % (REM ? REM : 1) : 0);
-    qv[s] = q % N;
-    qb[s] = q / N;
-    const bool ok = s < NF || t < 2 * REM;
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int r = 0; r < 8; ++r) hs[s][r] = ok ? window_spectrum<N>(A0, qb[s] + M * r, qv[s]) : mk(0.f, 0.f);
+      for (int r = 0; r < 8; ++r) {
+        const int k = qb[s] + M * r;
+        const int m = ((k + qv[s]) * a.R) % N;
+        hs[s][r] = cmul(window_spectrum<N>(A0, k, qv[s]), mk(ph.re[m], ph.im[m]));
+      }
+  } else {
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      int q = t + s * 2 * kTileThreads;
+      if (s == NF) q = NF * 2 * kTileThreads + (REM ? t % (REM ? REM : 1) : 0);
+      qv[s] = q % N;
+      qb[s] = q / N;
+      const bool ok = s < NF || t < 2 * REM;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) hs[s][r] = ok ? window_spectrum<N>(A0, qb[s] + M * r, qv[s]) : mk(0.f, 0.f);
+    }
+    hcomp = REM ? t / (REM ? REM : 1) : 0;
   }
-  const int hcomp = REM ? t / (REM ? REM : 1) : 0;   // component of the half item (t < 2 REM)
 
   // ---- per-pixel state: pixel (u4, bq4 + 8 r), phase e^{i (kofs + c) alpha}
   float acc[8];
@@ -342,6 +394,41 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     const bool two = c + 1 < a.U;
     const cx<float>* F0 = a.Fs + (long long)c * N * N;
     // ---- column pass 0 for both components
+    if constexpr (SYM) {
+      // unit: slot s (0: this thread's pair, both components; 1: the extra unit), component cc
+      auto unit = [&](int s, int cc, bool pair, float par) {
+        const int v = qv[s], b = qb[s];
+        const cx<float>* Fc = F0 + cc * N * N;
+        cx<float>* Ac = cc ? A1 : A0;
+        cx<float> f[8], x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) f[r] = Fc[(b + M * r) * N + v];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], f[r]);
+        dft<8, +1, float>(x);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) Ac[(8 * b + r) * P + v] = x[r];
+        if (pair) {
+          // mirror item (column -v, butterfly -b mod M): its element r' holds row -(b + M r),
+          // r' = 7 - r for b > 0 and (8 - r) mod 8 for b = 0
+          cx<float> g[8], y[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const cx<float> hf = cmul(hs[s][r], f[r]);
+            g[r] = mk(par * hf.re, -par * hf.im);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) y[j] = b == 0 ? g[(8 - j) & 7] : g[7 - j];
+          dft<8, +1, float>(y);
+          const int vm = v == 0 ? 0 : N - v, bm = b == 0 ? 0 : M - b;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) Ac[(8 * bm + r) * P + vm] = y[r];
+        }
+      };
+      unit(0, 0, true, 1.f);
+      if (two) unit(0, 1, true, -1.f);
+      if (t < NX && (hcomp == 0 || two)) unit(1, hcomp, xpair, hcomp ? -1.f : 1.f);
+    } else
 #pragma unroll
     for (int s = 0; s < NH; ++s) {
       const bool full = s < NF;
@@ -430,12 +517,12 @@ __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_corr_one(TileArgs a)
   const int ntile = a.tx * a.ty;
   corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, lb / ntile, lb % ntile, lds_t);
 }
-template <int N>
+template <int N, bool SYM = false>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  corr_block_pair<N>(a, lb / ntile, lb % ntile, lds_t);
+  corr_block_pair<N, false, SYM>(a, lb / ntile, lb % ntile, lds_t);
 }
 
 // Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
@@ -495,9 +582,16 @@ constexpr size_t tile_lds() {
 }
 
 template <int N, int TV, bool SEPB, int HV>
-hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
+hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, bool sym) {
   if constexpr (HV == 2) {
     static_assert(TV == 64, "the pair kernel has 64 x 64 blocks");
+    if constexpr (N == 96) {
+      if (sym) {
+        hipLaunchKernelGGL((k_tile_corr_pair<N, true>), dim3(nblk), dim3(2 * kTileThreads),
+                           (tile_lds<N, TV, SEPB, HV>()), s, a);
+        return last();
+      }
+    }
     hipLaunchKernelGGL((k_tile_corr_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   } else {
@@ -555,8 +649,9 @@ size_t tile_lds_bytes(int N, int TV) {
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
-                            const cx<float>* Fs) {
+                            const cx<float>* Fs, bool sym) {
   if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
+  if (sym && (!tile_symmetric(N, TV) || kofs != 0)) return hipErrorInvalidValue;
   TileArgs a{};
   a.H = H;
   a.planeH = planeH;
@@ -579,11 +674,13 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
 #define ECC_TL(n, tv, sb, hv) \
-  if (N == n && TV == tv) return launch_tile_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
+  if (N == n && TV == tv) return launch_tile_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a, sym);
   ECC_TILE_CONFIGS(ECC_TL)
 #undef ECC_TL
   return hipErrorInvalidValue;
 }
+
+bool tile_symmetric(int N, int TV) { return N == 96 && TV == 64; }
 
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
                              int T, int U, float scale, const cx<float>* Fs, float* stack) {

@@ -127,6 +127,9 @@ struct TileArgs {          // one correlation job (batch of images of one shape)
   float* stack;            // component stacks (matching): U planes of ny nx (re, im), or NULL
 };
 bool tile_supported(int N, int TV);
+// block shapes with the symmetric pair form (rotation filters: centred block spectra with
+// F~_c(-w) = (-1)^c F~_c(w), component offset 0)
+bool tile_symmetric(int N, int TV);
 size_t tile_lds_bytes(int N, int TV);
 int tile_threads(int N, int TV);
 // component stack of one image: stack[2 (c ny nx + y nx + x) .. +1] = G_c(y, x) * scale
@@ -146,7 +149,7 @@ hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileAr
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
-                            const cx<float>* Fs);
+                            const cx<float>* Fs, bool sym = false);
 
 // ---- tiled (overlap-save) convolution: one workgroup (256 threads) per T x T block
 // Block spectra of the tiled convolution: per component a plane of N rows of pitch N + 1

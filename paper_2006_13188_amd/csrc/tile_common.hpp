@@ -216,6 +216,22 @@ __device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, in
   __syncthreads();
 }
 
+// exp(2 pi i m / N), m < N, float64 values rounded once
+template <int N>
+struct TilePhases {
+  float re[N], im[N];
+};
+template <int N>
+constexpr TilePhases<N> make_tile_phases() {
+  TilePhases<N> t{};
+  for (int m = 0; m < N; ++m) {
+    t.re[m] = (float)cos_turn(m, N);
+    t.im[m] = (float)sin_turn(m, N);
+  }
+  return t;
+}
+__constant__ TilePhases<96> kPh96 = make_tile_phases<96>();
+
 // Spectrum value S[k][v] of a window transformed by forward_window.
 template <int N>
 __device__ __forceinline__ cx<float> window_spectrum(const cx<float>* A, int k, int v) {
