@@ -200,3 +200,29 @@ def test_scale_full_size(E, sctx, scale_full):
     plan = E.FilterPlan.scale(ctx)
     y = host(E.ecc_scale_smooth(ctx, plan, dev(img), dev(s))).astype(np.float64)
     assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+
+
+def test_tiled_symmetric_and_general_pair_forms(E):
+    """At N = 96 a rotation plan runs the symmetric pair form (centred block spectra, one
+    set of spectrum loads per item and its mirror) and a plan built from the same
+    components runs the general pair form (no parity assumed): both match the oracle, on a
+    shape with ragged blocks and an odd number of components."""
+    ctx = E.Context(0)
+    ctx.set_strategy(TILED)
+    try:
+        shape, S, K = (200, 173), 21, 10
+        img = blurred_noise(shape, 31)
+        filt = random_filter(S, 32, 4.0 * S / 15)
+        theta = theta_field(shape, 33)
+        plan_r = E.FilterPlan.rotation(ctx, dev(filt), K)
+        plan_c = E.FilterPlan.from_components(ctx, plan_r.components())
+        assert ctx.describe(0, plan_r, *shape)[1:] == ctx.describe(0, plan_c, *shape)[1:]
+        assert ctx.describe(0, plan_r, *shape)[1] == 96
+        ref = oracle_corr(img, filt, theta, K)
+        for plan in (plan_r, plan_c):
+            y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
+            assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+        plan_r.close()
+        plan_c.close()
+    finally:
+        ctx.close()
