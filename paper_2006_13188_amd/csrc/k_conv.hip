@@ -202,16 +202,19 @@ __global__ void __launch_bounds__(256) k_conv_rows_inv(
 
 // ---------------------------------------------------------------------------------
 // adjoint of the convolution w.r.t. the components: D_k(u, v) = sum_b Gh_b(u, v) conj(FFT_y(B_{k,b})(u, v))
-// (fixed batch order, no atomics).
+// (fixed batch order, no atomics). With lacc the batch sum is kept in LDS beside the
+// transform buffer (every thread owns the same elements for all b) and D is written once;
+// otherwise D is read and written per image.
 template <int NB>
 __global__ void __launch_bounds__(512) k_grad_filter_cols(
     const cx<float>* __restrict__ Bk, long long planeBk, long long planeBimg, int ldB,
     const cx<float>* __restrict__ Gh, long long planeGimg, int ldG, cx<float>* __restrict__ D,
     long long planeDk, int ldD, int ny, int Px, int W, int batch, FftDesc d,
-    const cx<float>* __restrict__ tw, int lgB) {
+    const cx<float>* __restrict__ tw, int lgB, int lacc) {
   extern __shared__ cx<float> smem_f[];
   cx<float>* twl = smem_f;
   cx<float>* buf = smem_f + lds_tw_pad(d.twsize);
+  cx<float>* acc = buf + ((long long)d.P << lgB);
   stage_twiddles(twl, tw, d.twsize);
   const int B = 1 << lgB, Py = d.P, nthr = blockDim.x, TF = nthr >> lgB;
   const int c = threadIdx.x & (B - 1), f = threadIdx.x >> lgB;
@@ -242,12 +245,22 @@ __global__ void __launch_bounds__(512) k_grad_filter_cols(
           gv = conj(G[(long long)um * ldG + (Px - v)]);
         }
         const cx<float> p = cmulc(gv, buf[e]);
-        cx<float>* dst = Dk + (long long)u * ldD + v;
-        if (b == 0) *dst = p;
-        else *dst = *dst + p;
+        if (lacc) {
+          acc[e] = b == 0 ? p : acc[e] + p;
+        } else {
+          cx<float>* dst = Dk + (long long)u * ldD + v;
+          if (b == 0) *dst = p;
+          else *dst = *dst + p;
+        }
       }
     }
     __syncthreads();
+  }
+  if (lacc) {
+    for (int e = threadIdx.x; e < Py * B; e += nthr) {
+      const int u = e >> lgB, v = v0 + (e & (B - 1));
+      if (v < Px) Dk[(long long)u * ldD + v] = acc[e];
+    }
   }
 }
 
@@ -315,10 +328,14 @@ hipError_t launch_grad_filter_cols(hipStream_t s, const ColCfg& c, int batch,
   (void)Py;
   const int B = 1 << c.lgB;
   dim3 grid((Px + B - 1) / B, U), block(c.nthr);
-  const size_t lds = lds_cols(c, d, sizeof(cx<float>));
+  // the batch sum in LDS when it fits beside the transform buffer
+  const size_t lds0 = lds_cols(c, d, sizeof(cx<float>));
+  const size_t lds1 = lds0 + ((size_t)d.P << c.lgB) * sizeof(cx<float>);
+  const int lacc = lds1 <= 160 * 1024 ? 1 : 0;
+  const size_t lds = lacc ? lds1 : lds0;
   ECC_NB_SWITCH(c.NB, hipLaunchKernelGGL(k_grad_filter_cols<NB>, grid, block, lds, s, Bk, planeBk,
                                          planeBimg, ldB, Gh, planeGimg, ldG, D, planeDk, ldD, ny,
-                                         Px, Px / 2 + 1, batch, d, tw, c.lgB));
+                                         Px, Px / 2 + 1, batch, d, tw, c.lgB, lacc));
   return last();
 }
 

@@ -210,14 +210,18 @@ def test_tiled_symmetric_and_general_pair_forms(E):
     ctx = E.Context(0)
     ctx.set_strategy(TILED)
     try:
-        shape, S, K = (200, 173), 21, 10
-        img = blurred_noise(shape, 31)
+        S, K = 31, 10
         filt = random_filter(S, 32, 4.0 * S / 15)
-        theta = theta_field(shape, 33)
         plan_r = E.FilterPlan.rotation(ctx, dev(filt), K)
         plan_c = E.FilterPlan.from_components(ctx, plan_r.components())
+        # a shape with ragged blocks that the chooser runs with N = 96 transforms
+        shapes = [sh for sh in ((520, 491), (700, 653), (1024, 1000))
+                  if ctx.describe(0, plan_r, *sh)[1] == 96]
+        assert shapes, "no candidate shape runs N = 96 blocks"
+        shape = shapes[0]
         assert ctx.describe(0, plan_r, *shape)[1:] == ctx.describe(0, plan_c, *shape)[1:]
-        assert ctx.describe(0, plan_r, *shape)[1] == 96
+        img = blurred_noise(shape, 31)
+        theta = theta_field(shape, 33)
         ref = oracle_corr(img, filt, theta, K)
         for plan in (plan_r, plan_c):
             y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
