@@ -148,11 +148,19 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   const int U = plan->U, Sz = plan->S;
   // correlation: F_k with its window corner at (0, 0), planes of N x N; convolution:
   // offset x at x - R, planes of tconv_plane(N) values with row pitch N + 1
-  const int shift = conv ? -2 * plan->R : mode == SPEC_CENTRED ? -plan->R : 0;
+  const bool centred = mode == SPEC_CENTRED || mode == SPEC_CENTRED_CONJ;
+  const bool cconj = mode == SPEC_CORR_CONJ || mode == SPEC_CENTRED_CONJ;
+  const int shift = conv ? -2 * plan->R : centred ? -plan->R : 0;
   sp->ld = conv ? tconv_pitch(N) : N;
   const long long plane = conv ? (long long)tconv_plane(N) : (long long)N * N;
-  DevBuf tmp, spec64;
+  DevBuf tmp, spec64, ccomps;
   ECC_HIP(tmp.ensure((size_t)U * Sz * N * sizeof(cx<double>)));
+  const cx<double>* src = plan->comps64.as<cx<double>>();
+  if (cconj) {
+    ECC_HIP(ccomps.ensure((size_t)U * Sz * Sz * sizeof(cx<double>)));
+    ECC_HIP(launch_conj_d(st, src, ccomps.as<cx<double>>(), (long long)U * Sz * Sz));
+    src = ccomps.as<cx<double>>();
+  }
   ECC_HIP(spec64.ensure((size_t)U * plane * sizeof(cx<double>)));
   ECC_HIP(sp->buf.ensure((size_t)U * plane * sizeof(cx<float>)));
   if (conv) ECC_HIP(hipMemsetAsync(spec64.p, 0, (size_t)U * plane * sizeof(cx<double>), st));
@@ -160,7 +168,7 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   ColCfg cc = col_config(*Tn, 2, sizeof(cx<double>), 256);
   ECC_TRY(check_cfg_row(rc, *Tn, sizeof(cx<double>), "filter row"));
   ECC_TRY(check_cfg_col(cc, *Tn, sizeof(cx<double>), "filter column", false));
-  ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
+  ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, src, (long long)Sz * Sz, Sz,
                                    Sz, Sz, shift, tmp.as<cx<double>>(), (long long)Sz * N, N, N, 0,
                                    Tn->desc, Tn->d())));
   ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, shift,
@@ -968,7 +976,27 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
   const long long pI = (long long)ny * nx;
   const float scl = 1.0f / ((float)Py * (float)Px);
   // grad_signal and grad_field: A_k = IFFT(Gh(w) Fh_k(-w)) combined with e^{-ik theta}
-  if (grad_signal || grad_field) {
+  ecc_strategy cstrat = ECC_STRATEGY_TWO_PASS;
+  TileChoice ctc;
+  ECC_TRY(resolve_strategy(ctx, ECC_CORRELATION, plan, ny, nx, batch, &cstrat, &ctc));
+  if ((grad_signal || grad_field) && cstrat == ECC_STRATEGY_TILED && tile_has_y2(ctc.N, ctc.TV)) {
+    // on chip: the tiled correlation of grad_out with F_k (spectra of conj F_k), phase
+    // e^{-ik theta}, and the field part as its second output
+    const bool sym = tile_symmetric(ctc.N, ctc.TV) && rotation_parity(plan);
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, ctc.N, st, &sp, sym ? SPEC_CENTRED_CONJ : SPEC_CORR_CONJ));
+    Field fl = make_field(plan, field, pI, nx, -1.0);
+    DevBuf tmp;
+    float* gs = grad_signal;
+    if (!gs) {
+      ECC_HIP(tmp.ensure((size_t)batch * pI * sizeof(float)));
+      gs = tmp.as<float>();
+    }
+    ECC_HIP(launch_tile_corr(st, ctc.N, ctc.TV, batch, grad_out, pI, nx, fl, gs, pI, nx, ny, nx, R, ctc.T, U, 0,
+                             plan->d_weights.as<float>(), 1.0f / ((float)ctc.N * (float)ctc.N),
+                             sp->buf.as<cx<float>>(), sym, grad_field, grad_field ? signal : nullptr, pI, nx));
+    if (tmp.p) ECC_HIP(hipStreamSynchronize(st));
+  } else if (grad_signal || grad_field) {
     cx<float>* T;
     long long pTk, pTi;
     ECC_TRY(corr_stack(ctx, plan, g, batch, grad_out, pI, nx, 2, st, &T, &pTk, &pTi));

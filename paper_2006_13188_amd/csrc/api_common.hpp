@@ -70,8 +70,9 @@ ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
 bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best);
 // Block spectra of a plan for transform length N (cached in the plan): for correlation
 // (F_k with its window corner at (0, 0)), convolution (offset x at (x - R) mod N, padded
-// planes) or the symmetric correlation form (centred: offset x at x mod N).
-enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2 };
+// planes) or the symmetric correlation form (centred: offset x at x mod N); the _CONJ
+// modes are those of conj(F_k) (the adjoint correlates with F_k itself).
+enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2, SPEC_CORR_CONJ = 3, SPEC_CENTRED_CONJ = 4 };
 ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode = SPEC_CORR);
 // rotation plans: F_k(-x) = (-1)^k F_k(x), components k = 0 .. U - 1
 bool rotation_parity(ecc_filter_plan plan);

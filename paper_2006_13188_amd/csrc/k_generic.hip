@@ -234,6 +234,10 @@ __global__ void k_d2f(const cx<double>* __restrict__ in, cx<float>* __restrict__
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = mk((float)in[i].re, (float)in[i].im);
 }
+__global__ void k_conj_d(const cx<double>* __restrict__ in, cx<double>* __restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = conj(in[i]);
+}
 __global__ void k_f2d(const cx<float>* __restrict__ in, cx<double>* __restrict__ out, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -333,6 +337,10 @@ hipError_t launch_scale_components(hipStream_t s, double sigma0, double u_lo, do
 
 hipError_t launch_d2f(hipStream_t s, const cx<double>* in, cx<float>* out, long long n) {
   hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+  return last();
+}
+hipError_t launch_conj_d(hipStream_t s, const cx<double>* in, cx<double>* out, long long n) {
+  hipLaunchKernelGGL(k_conj_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
   return last();
 }
 hipError_t launch_f2d(hipStream_t s, const cx<float>* in, cx<double>* out, long long n) {

@@ -266,7 +266,10 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
 // window). A thread then does an item and its mirror item (column -v, rows -k) from one
 // set of filter-spectrum loads: the mirror products are (-1)^c conj(h'(w) F~_c(w)), which
 // halves the spectrum reads of column pass 0.
-template <int N, bool STACK = false, bool SYM = false>
+//
+// Y2: also accumulate sum_c w_c (kofs + c) Im(z_c G_c) and write it times mulsig as the
+// second output y2 (the field part of the adjoint).
+template <int N, bool STACK = false, bool SYM = false, bool Y2 = false>
 __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
   constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
   constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
@@ -363,11 +366,12 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   }
 
   // ---- per-pixel state: pixel (u4, bq4 + 8 r), phase e^{i (kofs + c) alpha}
-  float acc[8];
+  float acc[8], acc2[Y2 ? 8 : 1];
   cx<float> z[8], e1[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     acc[r] = 0.f;
+    if constexpr (Y2) acc2[r] = 0.f;
     z[r] = mk(0.f, 0.f);
     e1[r] = mk(0.f, 0.f);
     const int x = bq4 + 8 * r, gx = x0 + x;
@@ -480,9 +484,11 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
             }
           } else {
             const float wc = a.w[c + cc];
+            const float wk = Y2 ? wc * (float)(a.kofs + c + cc) : 0.f;
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
               acc[r] += wc * (z[r].re * x[r].re - z[r].im * x[r].im);
+              if constexpr (Y2) acc2[r] += wk * (z[r].re * x[r].im + z[r].im * x[r].re);
               z[r] = cmul(z[r], e1[r]);
             }
           }
@@ -497,7 +503,12 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
-      if (rowok && x < T && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+      if (rowok && x < T && gx < a.nx) {
+        yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+        if constexpr (Y2)
+          a.y2[(long long)img * a.planeY + (long long)gy * a.ldY + gx] =
+              acc2[r] * a.scale * a.mulsig[(long long)img * a.planeMul + (long long)gy * a.ldMul + gx];
+      }
     }
   }
 }
@@ -517,12 +528,12 @@ __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_corr_one(TileArgs a)
   const int ntile = a.tx * a.ty;
   corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, lb / ntile, lb % ntile, lds_t);
 }
-template <int N, bool SYM = false>
+template <int N, bool SYM = false, bool Y2 = false>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  corr_block_pair<N, false, SYM>(a, lb / ntile, lb % ntile, lds_t);
+  corr_block_pair<N, false, SYM, Y2>(a, lb / ntile, lb % ntile, lds_t);
 }
 
 // Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
@@ -585,16 +596,19 @@ template <int N, int TV, bool SEPB, int HV>
 hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, bool sym) {
   if constexpr (HV == 2) {
     static_assert(TV == 64, "the pair kernel has 64 x 64 blocks");
+    constexpr size_t lds = tile_lds<N, TV, SEPB, HV>();
+    const dim3 g(nblk), b(2 * kTileThreads);
     if constexpr (N == 96) {
       if (sym) {
-        hipLaunchKernelGGL((k_tile_corr_pair<N, true>), dim3(nblk), dim3(2 * kTileThreads),
-                           (tile_lds<N, TV, SEPB, HV>()), s, a);
+        if (a.y2) hipLaunchKernelGGL((k_tile_corr_pair<N, true, true>), g, b, lds, s, a);
+        else hipLaunchKernelGGL((k_tile_corr_pair<N, true>), g, b, lds, s, a);
         return last();
       }
     }
-    hipLaunchKernelGGL((k_tile_corr_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
-                       (tile_lds<N, TV, SEPB, HV>()), s, a);
+    if (a.y2) hipLaunchKernelGGL((k_tile_corr_pair<N, false, true>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((k_tile_corr_pair<N>), g, b, lds, s, a);
   } else {
+    if (a.y2) return hipErrorInvalidValue;   // the one-group form has no second output
     hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB>), dim3(nblk), dim3(tile_nt<N, 1>()),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
@@ -649,9 +663,11 @@ size_t tile_lds_bytes(int N, int TV) {
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
-                            const cx<float>* Fs, bool sym) {
+                            const cx<float>* Fs, bool sym, float* y2, const float* mulsig,
+                            long long planeMul, int ldMul) {
   if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
   if (sym && (!tile_symmetric(N, TV) || kofs != 0)) return hipErrorInvalidValue;
+  if (y2 && (!tile_has_y2(N, TV) || !mulsig)) return hipErrorInvalidValue;
   TileArgs a{};
   a.H = H;
   a.planeH = planeH;
@@ -671,6 +687,10 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   a.w = w;
   a.scale = scale;
   a.Fs = Fs;
+  a.y2 = y2;
+  a.mulsig = mulsig;
+  a.planeMul = planeMul;
+  a.ldMul = ldMul;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
 #define ECC_TL(n, tv, sb, hv) \
@@ -681,6 +701,12 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
 }
 
 bool tile_symmetric(int N, int TV) { return N == 96 && TV == 64; }
+bool tile_has_y2(int N, int TV) {
+#define ECC_TY(n, tv, sb, hv) if (N == n && TV == tv) return hv == 2;
+  ECC_TILE_CONFIGS(ECC_TY)
+#undef ECC_TY
+  return false;
+}
 
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
                              int T, int U, float scale, const cx<float>* Fs, float* stack) {

@@ -84,6 +84,7 @@ hipError_t launch_synth_rotation(hipStream_t s, const float* F, int S, int K, co
 hipError_t launch_scale_components(hipStream_t s, double sigma0, double u_lo, double u_hi,
                                    double L, int n, int R, cx<double>* comps);
 hipError_t launch_d2f(hipStream_t s, const cx<double>* in, cx<float>* out, long long n);
+hipError_t launch_conj_d(hipStream_t s, const cx<double>* in, cx<double>* out, long long n);   // out = conj(in)
 hipError_t launch_f2d(hipStream_t s, const cx<float>* in, cx<double>* out, long long n);
 
 // ---- adjoint helpers
@@ -125,6 +126,12 @@ struct TileArgs {          // one correlation job (batch of images of one shape)
   float scale;
   const cx<float>* Fs;     // U block spectra of N x N
   float* stack;            // component stacks (matching): U planes of ny nx (re, im), or NULL
+  // second output (adjoint w.r.t. the field): y2 = scale * mulsig * sum_c w_c (kofs + c)
+  // Im(e^{i (kofs + c) alpha} G_c), or NULL
+  float* y2;
+  const float* mulsig;
+  long long planeMul;
+  int ldMul;
 };
 bool tile_supported(int N, int TV);
 // block shapes with the symmetric pair form (rotation filters: centred block spectra with
@@ -149,7 +156,10 @@ hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileAr
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
-                            const cx<float>* Fs, bool sym = false);
+                            const cx<float>* Fs, bool sym = false, float* y2 = nullptr,
+                            const float* mulsig = nullptr, long long planeMul = 0, int ldMul = 0);
+// block shapes whose correlation kernel can also write the second (y2) output
+bool tile_has_y2(int N, int TV);
 
 // ---- tiled (overlap-save) convolution: one workgroup (256 threads) per T x T block
 // Block spectra of the tiled convolution: per component a plane of N rows of pitch N + 1

@@ -230,3 +230,35 @@ def test_tiled_symmetric_and_general_pair_forms(E):
         plan_c.close()
     finally:
         ctx.close()
+
+
+def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
+    """The signal and field parts of the convolution adjoint run as a tiled correlation
+    with a second output (symmetric pair form at N = 96 for a rotation plan); they agree
+    with the two-pass adjoint, itself checked against the float64 oracle on small images."""
+    import torch
+    cts = [E.Context(0), E.Context(0)]
+    cts[0].set_strategy(TILED)
+    cts[1].set_strategy(TWO_PASS)
+    try:
+        S, K = 31, 6
+        filt = random_filter(S, 41, 4.0 * S / 15)
+        plans = [E.FilterPlan.rotation(c, dev(filt), K) for c in cts]
+        shapes = [sh for sh in ((520, 491), (700, 653), (1024, 1000))
+                  if cts[0].describe(0, plans[0], *sh)[1] == 96]
+        assert shapes, "no candidate shape runs N = 96 blocks"
+        shape = shapes[0]
+        img = blurred_noise(shape, 42)[None]
+        th = theta_field(shape, 43)[None]
+        g = np.random.default_rng(44).standard_normal((1,) + shape).astype(np.float32)
+        outs = []
+        for c, p in zip(cts, plans):
+            gs, gc, gf = E.ecc_extended_backward(c, p, dev(img), dev(th), dev(g))
+            outs.append((host(gs).astype(np.float64), host(gf).astype(np.float64)))
+        for a, b in zip(outs[0], outs[1]):
+            assert rel2(a, b) <= TOL and relinf(a, b) <= 2 * TOL, (rel2(a, b), relinf(a, b))
+        for p in plans:
+            p.close()
+    finally:
+        for c in cts:
+            c.close()
