@@ -1010,7 +1010,34 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, gs, pI, nx, scl, grad_field, signal, pI, nx, st));
     if (tmp.p) ECC_HIP(hipStreamSynchronize(st));
   }
-  if (grad_comps) {
+  ecc_strategy vstrat = ECC_STRATEGY_TWO_PASS;
+  TileChoice vtc;
+  if (grad_comps) ECC_TRY(resolve_strategy(ctx, ECC_CONVOLUTION, plan, ny, nx, batch, &vstrat, &vtc));
+  if (grad_comps && vstrat == ECC_STRATEGY_TILED && tgradf_supported(vtc.N, vtc.TV)) {
+    // on chip: per block and component the S x S lags of the gradient against the
+    // modulated signal, then a fixed-order sum over the blocks (the saved stack, if any,
+    // is not needed)
+    TileGradFArgs ga{};
+    ga.H = signal;
+    ga.planeH = pI;
+    ga.ldH = nx;
+    ga.fld = make_field(plan, field, pI, nx, 1.0);
+    ga.G = grad_out;
+    ga.planeG = pI;
+    ga.ldG = nx;
+    ga.ny = ny;
+    ga.nx = nx;
+    ga.R = R;
+    ga.T = vtc.T;
+    ga.U = U;
+    const long long nblk = (long long)((ny + vtc.T - 1) / vtc.T) * ((nx + vtc.T - 1) / vtc.T) * batch;
+    ECC_REQ(nblk <= 0x7fffffffLL, "too many blocks");
+    ECC_HIP(ctx->ws.ensure((size_t)nblk * U * Sz * Sz * sizeof(cx<float>)));
+    ga.part = ctx->ws.as<cx<float>>();
+    ECC_HIP(launch_tile_gradf(st, vtc.N, vtc.TV, batch, ga));
+    ECC_HIP(launch_gradf_reduce(st, ga.part, (int)nblk, U, Sz, plan->d_weights.as<float>(),
+                                1.0f / ((float)vtc.N * (float)vtc.N), reinterpret_cast<cx<float>*>(grad_comps)));
+  } else if (grad_comps) {
     // stack B_k (saved or recomputed), Gh full spectra of grad_out, D_k, small inverse
     const long long pBk = (long long)ny * Px, pBi = pBk * U;
     const long long pA = (long long)ny * W, pG = (long long)Py * W;

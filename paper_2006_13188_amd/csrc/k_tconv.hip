@@ -196,6 +196,141 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
   }
 }
 
+// Filter part of the adjoint, one block: the block's gradient g (window rows/columns
+// [R, R + T), zero elsewhere) is transformed once and kept in registers as
+// G'(w) = G(w) e^{-2 pi i (w_y + w_x) R / N} (the phase shifts the lags by R, so that the
+// lags [-R, R] become the first S = 2R + 1 circular indices); per component the modulated
+// window m_k = H e^{-ik alpha} is transformed forward as in the convolution, the product
+// G' conj(M_k) is transformed back with only the first S rows and columns formed, and the
+// S x S lags are written to the block's partial sums.
+template <int N, int TV, int NT>
+__device__ __forceinline__ void gradf_block(const TileGradFArgs& a, int img, int tile, int blk, cx<float>* A) {
+  constexpr int M = N / 8, P = N + 1, LS = NT / 8;
+  constexpr int NQ0 = (N * M + NT - 1) / NT;
+  constexpr int NI = (N + LS - 1) / LS;
+  const int t = threadIdx.x, l = t % LS;
+  const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
+  const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
+  const int S = 2 * a.R + 1;
+  const TileTwiddles<N>& tt = tile_twiddles<N>();
+  cx<float> tw[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+
+  __syncthreads();   // the LDS image may still be in use by the previous block
+  // ---- spectrum of the block's gradient (window rows y0 - R + i; only the block is nonzero)
+  forward_window<N, NT>(A, a.G + (long long)img * a.planeG, a.ldG, min(a.ny, y0 + a.T), min(a.nx, x0 + a.T),
+                        y0, x0, a.R, t, y0, x0);
+  const TilePhases<N>& ph = tile_phases<N>();
+  cx<float> gs[NI][M];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int u = l + LS * i, v = bq + 8 * r;
+      gs[i][r] = mk(0.f, 0.f);
+      if (N % LS == 0 || u < N) {
+        const int m = ((u + v) * a.R) % N;
+        gs[i][r] = cmulc(window_spectrum<N>(A, u, v), mk(ph.re[m], ph.im[m]));
+      }
+    }
+  // ---- window pixels of this thread's column pass-0 items: z = H(q) e^{-i c alpha(q)}
+  const float* Hb = a.H + (long long)img * a.planeH;
+  cx<float> z[NQ0][8], e1[NQ0][8];
+#pragma unroll
+  for (int s = 0; s < NQ0; ++s) {
+    const int q = t + s * NT;
+    const int v = q % N, b = q / N;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int gy = y0 - a.R + b + M * r, gx = x0 - a.R + v;
+      z[s][r] = mk(0.f, 0.f);
+      e1[s][r] = mk(0.f, 0.f);
+      if (b < M && gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) {
+        const float fv = a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx];
+        float sn, cs;
+        if (a.fld.log_mode) {
+          double dsn, dcs;
+          sincos(field_angle(a.fld, fv), &dsn, &dcs);
+          sn = (float)dsn;
+          cs = (float)dcs;
+        } else {
+          sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
+        }
+        e1[s][r] = mk(cs, -sn);
+        z[s][r] = mk(Hb[(long long)gy * a.ldH + gx], 0.f);
+      }
+    }
+  }
+  __syncthreads();   // A is rewritten below
+
+  cx<float>* out = a.part + (long long)blk * a.U * S * S;
+  for (int c = 0; c < a.U; ++c) {
+    // ---- forward transform of m_c (column pass 0 from registers)
+#pragma unroll
+    for (int s = 0; s < NQ0; ++s) {
+      const int q = t + s * NT;
+      const int v = q % N, b = q / N;
+      if (b < M) {
+        cx<float> x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          x[r] = z[s][r];
+          z[s][r] = cmul(z[s][r], e1[s][r]);
+        }
+        dft<8, -1, float>(x);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
+      }
+    }
+    __syncthreads();
+    pass1_inplace<N, -1, false, NI, NT>(A, tw, bq, l, N, N);
+    __syncthreads();
+    pass0_inplace<N, -1, true, N, NT>(A, t, N, true);
+    __syncthreads();
+    // ---- row pass 1, then the product G' conj(M_c) in place
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int u = l + LS * i;
+      if (N % LS == 0 || u < N) {
+        cx<float> x[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[r] = A[u * P + bq + 8 * r];
+#pragma unroll
+        for (int r = 1; r < M; ++r) x[r] = cmulc(x[r], tw[r]);
+        dft<M, -1, float>(x);
+#pragma unroll
+        for (int r = 0; r < M; ++r) A[u * P + bq + 8 * r] = cmulc(gs[i][r], x[r]);
+      }
+    }
+    __syncthreads();
+    // ---- inverse transform, first S rows and columns only
+    pass0_inplace<N, +1, false, N, NT>(A, t, N, true);
+    __syncthreads();
+    pass1_inplace<N, +1, false, NI, NT>(A, tw, bq, l, N, S);
+    __syncthreads();
+    pass0_inplace<N, +1, true, N, NT>(A, t, S, true);
+    __syncthreads();
+    cx<float>* oc = out + (long long)c * S * S;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int u = l + LS * i;
+      if (u < S) {
+        cx<float> x[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[r] = A[u * P + bq + 8 * r];
+#pragma unroll
+        for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
+        dft<M, +1, float>(x);
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+          if (bq + 8 * r < S) oc[u * S + bq + 8 * r] = x[r];
+      }
+    }
+    __syncthreads();   // the image is rewritten by the next component
+  }
+}
+
 // threads per workgroup: 512 (two waves per SIMD; for N = 96 some passes leave a quarter
 // of the lanes idle, which costs less than one wave per SIMD)
 template <int N>
@@ -208,6 +343,30 @@ constexpr int tconv_threads() {
 // against the spectrum's reads
 template <int N>
 __shared__ cx<float> conv_img_lds[N * (N + 1)];
+
+template <int N, int TV>
+__global__ void __launch_bounds__(tconv_threads<N>()) k_tile_gradf(TileGradFArgs a) {
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int ntile = a.tx * a.ty;
+  gradf_block<N, TV, tconv_threads<N>()>(a, lb / ntile, lb % ntile, lb, conv_img_lds<N>);
+}
+
+// one thread per (component, lag): sum over the blocks in block order
+__global__ void k_gradf_reduce(const cx<float>* __restrict__ part, int nblk, int U, int S,
+                               const float* __restrict__ w, float scale, cx<float>* __restrict__ out) {
+  const int n = U * S * S;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int k = idx / (S * S);
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const cx<float> v = part[(long long)b * n + idx];
+    re += v.re;
+    im += v.im;
+  }
+  const double f = (double)w[k] * scale;
+  out[idx] = mk((float)(re * f), (float)(im * f));
+}
 
 template <int N, int TV, int NSIG>
 __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a) {
@@ -248,6 +407,33 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   ECC_TCONV_CONFIGS(ECC_CL)
 #undef ECC_CL
   return hipErrorInvalidValue;
+}
+
+bool tgradf_supported(int N, int TV) { return tconv_supported(N, TV); }
+
+hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const TileGradFArgs& a0) {
+  TileGradFArgs a = a0;
+  if (a.T < 1 || a.T > TV || a.T > N - 2 * a.R || a.R < 0) return hipErrorInvalidValue;
+  a.tx = (a.nx + a.T - 1) / a.T;
+  a.ty = (a.ny + a.T - 1) / a.T;
+  const long long nblk = (long long)a.tx * a.ty * batch;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+#define ECC_GL(n, tv)                                                                                     \
+  if (N == n && TV == tv) {                                                                              \
+    hipLaunchKernelGGL((k_tile_gradf<n, tv>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), 0, s, a);  \
+    return last();                                                                                       \
+  }
+  ECC_TCONV_CONFIGS(ECC_GL)
+#undef ECC_GL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gradf_reduce(hipStream_t s, const cx<float>* part, int nblk, int U, int S, const float* w,
+                               float scale, cx<float>* out) {
+  const int n = U * S * S;
+  hipLaunchKernelGGL(k_gradf_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nblk, U, S, w,
+                     scale, out);
+  return last();
 }
 
 // LDS per workgroup (all static: the transform image, and the spectrum copy for N <= 96)

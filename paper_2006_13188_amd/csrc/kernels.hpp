@@ -184,6 +184,26 @@ struct TileConvArgs {
   const cx<float>* Fs;     // U block spectra (tconv_plane(N) values apart, pitch N + 1),
                            // F_c at (x - R) mod N
 };
+// Filter part of the convolution adjoint on chip (section 4 adjoint of the extended
+// convolution): per block of outputs and component k, the lags x in [-R, R]^2 of
+// sum_{p in block} g(p) conj(M_k(p - x)), M_k = H e^{-ik theta}, written as partial sums
+// part[block][k][R + x_y][R + x_x] (complex, unnormalised: times 1 / N^2).
+struct TileGradFArgs {
+  const float* H;          // signal
+  long long planeH;
+  int ldH;
+  Field fld;               // phase e^{-i k alpha}
+  const float* G;          // gradient of the output
+  long long planeG;
+  int ldG;
+  cx<float>* part;         // blocks x U x S x S
+  int ny, nx, R, T, tx, ty, U;
+};
+bool tgradf_supported(int N, int TV);
+hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const TileGradFArgs& a);
+// out[k][a][b] = w_k * scale * sum over nblk blocks of part[block][k][a][b] (block order fixed)
+hipError_t launch_gradf_reduce(hipStream_t s, const cx<float>* part, int nblk, int U, int S, const float* w,
+                               float scale, cx<float>* out);
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);
 hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);

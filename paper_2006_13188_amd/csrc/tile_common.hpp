@@ -168,9 +168,10 @@ __device__ __forceinline__ void rdft8(const float* x, cx<float>* X) {
 // (real radix 8, all loads of a thread in flight together); since the window is real,
 // S[N - k][l] = conj(S[k][(N - l) mod N]), so only rows k <= N/2 are transformed along
 // the rows (window_spectrum supplies the others). Ends with a barrier.
+// (rows and columns of H outside [ylo, ny) x [xlo, nx) are taken as zero)
 template <int N, int NT>
 __device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, int ldH, int ny, int nx, int y0,
-                                               int x0, int R, int t) {
+                                               int x0, int R, int t, int ylo = 0, int xlo = 0) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8, NI = (N + LS - 1) / LS, H2 = N / 2 + 1;
   constexpr int NQ = (N * M + NT - 1) / NT;   // column pass-0 items of a thread
   constexpr int G = NQ < 4 ? NQ : 4;          // items whose loads are in flight together
@@ -184,11 +185,11 @@ __device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, in
       const int q = t + (s0 + g) * NT;
       const int v = q % N, b = q / N;
       const int gx = x0 - R + v;
-      const bool colok = s0 + g < NQ && b < M && gx >= 0 && gx < nx;
+      const bool colok = s0 + g < NQ && b < M && gx >= xlo && gx < nx;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int gy = y0 - R + b + M * r;
-        h[g][r] = (colok && gy >= 0 && gy < ny) ? Hb[(long long)gy * ldH + gx] : 0.f;
+        h[g][r] = (colok && gy >= ylo && gy < ny) ? Hb[(long long)gy * ldH + gx] : 0.f;
       }
     }
 #pragma unroll
@@ -230,7 +231,15 @@ constexpr TilePhases<N> make_tile_phases() {
   }
   return t;
 }
+__constant__ TilePhases<64> kPh64 = make_tile_phases<64>();
 __constant__ TilePhases<96> kPh96 = make_tile_phases<96>();
+__constant__ TilePhases<128> kPh128 = make_tile_phases<128>();
+template <int N>
+__device__ __forceinline__ const TilePhases<N>& tile_phases() {
+  if constexpr (N == 64) return kPh64;
+  else if constexpr (N == 96) return kPh96;
+  else return kPh128;
+}
 
 // Spectrum value S[k][v] of a window transformed by forward_window.
 template <int N>

@@ -234,8 +234,9 @@ def test_tiled_symmetric_and_general_pair_forms(E):
 
 def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
     """The signal and field parts of the convolution adjoint run as a tiled correlation
-    with a second output (symmetric pair form at N = 96 for a rotation plan); they agree
-    with the two-pass adjoint, itself checked against the float64 oracle on small images."""
+    with a second output (symmetric pair form at N = 96 for a rotation plan) and the
+    filter part as per-block lag sums; all three agree with the two-pass adjoint, itself
+    checked against the float64 oracle on small images."""
     import torch
     cts = [E.Context(0), E.Context(0)]
     cts[0].set_strategy(TILED)
@@ -254,9 +255,12 @@ def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
         outs = []
         for c, p in zip(cts, plans):
             gs, gc, gf = E.ecc_extended_backward(c, p, dev(img), dev(th), dev(g))
-            outs.append((host(gs).astype(np.float64), host(gf).astype(np.float64)))
-        for a, b in zip(outs[0], outs[1]):
+            outs.append((host(gs).astype(np.float64), host(gf).astype(np.float64),
+                         host(gc).astype(np.complex128)))
+        for a, b in zip(outs[0][:2], outs[1][:2]):
             assert rel2(a, b) <= TOL and relinf(a, b) <= 2 * TOL, (rel2(a, b), relinf(a, b))
+        # the filter part: per-block lags summed on chip against the two-pass column form
+        assert rel2(outs[0][2], outs[1][2]) <= TOL, rel2(outs[0][2], outs[1][2])
         for p in plans:
             p.close()
     finally:
