@@ -318,8 +318,9 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   int hcomp = 0;      // component of the half item (t < 2 REM), or of the extra unit (SYM)
   bool xpair = false;  // SYM: the extra unit is an item pair (else a self-mirrored item)
   if constexpr (SYM) {
-    // canonical item of pair p: b in 1 .. M/2 - 1 (all columns), then b = 0 and b = M/2
-    // with columns 1 .. N/2 - 1
+    // canonical item of pair p: b in 1 .. M/2 - 1 (all columns), then b = M/2 and b = 0
+    // with columns 1 .. N/2 - 1 (the b = 0 pairs, whose mirror order differs, come last
+    // and so fall to the extra units only)
     auto pair_item = [&](int p, int& v, int& b) {
       constexpr int NB = (M / 2 - 1) * N;
       if (p < NB) {
@@ -327,10 +328,11 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
         v = p % N;
       } else {
         const int p2 = p - NB;
-        b = p2 < N / 2 - 1 ? 0 : M / 2;
+        b = p2 < N / 2 - 1 ? M / 2 : 0;
         v = 1 + (p2 < N / 2 - 1 ? p2 : p2 - (N / 2 - 1));
       }
     };
+    static_assert((M / 2 - 1) * N + N / 2 - 1 >= 2 * kTileThreads, "b = 0 pairs beyond the base units");
     pair_item(t, qv[0], qb[0]);
     const int e = t < NX ? t : 0;
     hcomp = e & 1;
@@ -400,7 +402,7 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     // ---- column pass 0 for both components
     if constexpr (SYM) {
       // unit: slot s (0: this thread's pair, both components; 1: the extra unit), component cc
-      auto unit = [&](int s, int cc, bool pair, float par) {
+      auto unit = [&](int s, int cc, bool pair, float par, bool maybe_b0) {
         const int v = qv[s], b = qb[s];
         const cx<float>* Fc = F0 + cc * N * N;
         cx<float>* Ac = cc ? A1 : A0;
@@ -422,16 +424,16 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
             g[r] = mk(par * hf.re, -par * hf.im);
           }
 #pragma unroll
-          for (int j = 0; j < 8; ++j) y[j] = b == 0 ? g[(8 - j) & 7] : g[7 - j];
+          for (int j = 0; j < 8; ++j) y[j] = (maybe_b0 && b == 0) ? g[(8 - j) & 7] : g[7 - j];
           dft<8, +1, float>(y);
           const int vm = v == 0 ? 0 : N - v, bm = b == 0 ? 0 : M - b;
 #pragma unroll
           for (int r = 0; r < 8; ++r) Ac[(8 * bm + r) * P + vm] = y[r];
         }
       };
-      unit(0, 0, true, 1.f);
-      if (two) unit(0, 1, true, -1.f);
-      if (t < NX && (hcomp == 0 || two)) unit(1, hcomp, xpair, hcomp ? -1.f : 1.f);
+      unit(0, 0, true, 1.f, false);
+      if (two) unit(0, 1, true, -1.f, false);
+      if (t < NX && (hcomp == 0 || two)) unit(1, hcomp, xpair, hcomp ? -1.f : 1.f, true);
     } else
 #pragma unroll
     for (int s = 0; s < NH; ++s) {
