@@ -266,3 +266,27 @@ def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
     finally:
         for c in cts:
             c.close()
+
+
+@pytest.mark.parametrize("K", [0, 1, 2])
+def test_tiled_symmetric_pair_form_few_components(E, K):
+    """The symmetric pair form with one component (K = 0: only the first half of a pair),
+    two (one full pair) and three (a pair and a half pair), against the oracle."""
+    ctx = E.Context(0)
+    ctx.set_strategy(TILED)
+    try:
+        S = 31
+        filt = random_filter(S, 50 + K, 4.0 * S / 15)
+        plan = E.FilterPlan.rotation(ctx, dev(filt), K)
+        shapes = [sh for sh in ((520, 491), (700, 653), (1024, 1000))
+                  if ctx.describe(0, plan, *sh)[1] == 96]
+        assert shapes, "no candidate shape runs N = 96 blocks"
+        shape = shapes[0]
+        img = blurred_noise(shape, 60 + K)
+        theta = theta_field(shape, 70 + K)
+        y = host(E.ecc_extended(ctx, 0, plan, dev(img), dev(theta))).astype(np.float64)
+        ref = oracle_corr(img, filt, theta, K)
+        assert rel2(y, ref) <= TOL and relinf(y, ref) <= TOL, (rel2(y, ref), relinf(y, ref))
+        plan.close()
+    finally:
+        ctx.close()
