@@ -52,20 +52,20 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   }
 
   __syncthreads();   // the LDS image may still be in use by the previous block
-  // field values of this thread's output pixels (l + LS i, bq + 8 r), loaded just before
-  // the window so that the two latencies overlap
-  float fvs[STACK ? 1 : TR][RV];
+  // field values of the block, loaded just before the window (so that the two latencies
+  // overlap) with consecutive lanes along rows; they reach the threads that own the pixels
+  // (rows l + LS i, columns bq + 8 r) through LDS below
+  constexpr int FPT = (TV * TV + NT - 1) / NT, FL = TV + 1;   // per thread; LDS pitch
+  float fco[STACK ? 1 : FPT];
   if constexpr (!STACK) {
 #pragma unroll
-    for (int i = 0; i < TR; ++i)
-#pragma unroll
-      for (int r = 0; r < RV; ++r) {
-        const int u = l + LS * i, x = bq + 8 * r;
-        const int gy = y0 + u, gx = x0 + x;
-        fvs[i][r] = (u < T && x < T && gy < a.ny && gx < a.nx)
-                        ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
-                        : 0.f;
-      }
+    for (int k = 0; k < FPT; ++k) {
+      const int e = t + NT * k, row = e / TV, col = e % TV;
+      const int gy = y0 + row, gx = x0 + col;
+      fco[k] = (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx)
+                   ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
+                   : 0.f;
+    }
   }
   // ---- forward 2D transform of the signal window
   forward_window<N, NT>(A, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
@@ -77,6 +77,24 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     const int v = q % N, b = q / N;
 #pragma unroll
     for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? window_spectrum<N>(A, b + M * r, v) : mk(0.f, 0.f);
+  }
+  float fvs[STACK ? 1 : TR][RV];
+  if constexpr (!STACK) {
+    float* fl = reinterpret_cast<float*>(A);
+    __syncthreads();   // the spectrum reads above are done
+#pragma unroll
+    for (int k = 0; k < FPT; ++k) {
+      const int e = t + NT * k;
+      if (e < TV * TV) fl[(e / TV) * FL + e % TV] = fco[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+      for (int r = 0; r < RV; ++r) {
+        const int u = l + LS * i;
+        fvs[i][r] = u < TV ? fl[u * FL + bq + 8 * r] : 0.f;
+      }
   }
 
   // ---- per-pixel state of the row pass-1 outputs: pixel (l + LS i, bq + 8 r). The
@@ -214,13 +232,9 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
           for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
           dft<M, +1, float>(x);
           if constexpr (STACK) {
+            // back into the image (the positions this thread read), stored below along rows
 #pragma unroll
-            for (int r = 0; r < RV; ++r) {
-              const int xx = bq + 8 * r, gy = y0 + u, gx = x0 + xx;
-              if (xx < T && gy < a.ny && gx < a.nx)
-                *reinterpret_cast<float2*>(a.stack + 2 * ((long long)c * a.ny * a.nx + (long long)gy * a.nx + gx)) =
-                    make_float2(x[r].re * a.scale, x[r].im * a.scale);
-            }
+            for (int r = 0; r < RV; ++r) Bb[u * P + bq + 8 * r] = x[r];
           } else {
 #pragma unroll
             for (int r = 0; r < RV; ++r) {
@@ -231,19 +245,49 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
         }
       }
     }
-    if constexpr (!SEPB) __syncthreads();   // A is rewritten by the next column pass
+    // A is rewritten by the next column pass (stack form: a barrier for LDS only, so that
+    // this component's stack stores are not waited for)
+    if constexpr (STACK) {
+      // the T x T block of G_c, with consecutive lanes along rows
+      __syncthreads();
+      float* dst = a.stack + 2 * (long long)c * a.ny * a.nx;
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        const int e = t + NT * k, row = e / TV, col = e % TV;
+        const int gy = y0 + row, gx = x0 + col;
+        if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) {
+          const cx<float> v = Bb[row * P + col];
+          *reinterpret_cast<float2*>(dst + 2 * ((long long)gy * a.nx + gx)) = make_float2(v.re * a.scale, v.im * a.scale);
+        }
+      }
+      lds_barrier();   // the image is rewritten next; the stores are not waited for
+    } else if constexpr (!SEPB) {
+      __syncthreads();   // A is rewritten by the next column pass
+    }
   }
 
   if constexpr (!STACK) {
-    float* yb = a.y + (long long)img * a.planeY;
+    // outputs through LDS, then stored along rows
+    float* ob = reinterpret_cast<float*>(A);
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
 #pragma unroll
       for (int r = 0; r < RV; ++r) {
-        const int u = l + LS * i, x = bq + 8 * r;
-        const int gy = y0 + u, gx = x0 + x;
-        if (u < T && x < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = acc[i][r] * a.scale;
+        const int u = l + LS * i;
+        if (u < TV) ob[u * FL + bq + 8 * r] = acc[i][r] * a.scale;
       }
+    }
+    __syncthreads();
+    float* yb = a.y + (long long)img * a.planeY;
+    // (the thread index through a lane shuffle: the compiler would otherwise keep the
+    // field loads' addresses, which are the same expressions, live through the loop)
+    const int ts = __shfl(t, t & 63);
+#pragma unroll
+    for (int k = 0; k < FPT; ++k) {
+      const int e = ts + NT * k, row = e / TV, col = e % TV;
+      const int gy = y0 + row, gx = x0 + col;
+      if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = ob[row * FL + col];
     }
   }
 }
@@ -298,20 +342,37 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   for (int r = 0; r < M; ++r) tw1[r] = mk(tt.re[bq1][r], tt.im[bq1][r]);
 
   __syncthreads();   // the LDS images may still be in use by the previous block
-  // field values of this thread's output pixels (u4, bq4 + 8 r), loaded just before the
-  // window so that the two latencies overlap
+  // field values of the block, loaded just before the window (so that the two latencies
+  // overlap) with consecutive lanes along rows; they reach the threads that own the pixels
+  // (row u4, columns bq4 + 8 r) through LDS below
   const bool rowok = u4 < T && y0 + u4 < a.ny;
-  float fvs[8];
+  constexpr int FPT = TV * TV / (2 * kTileThreads), FL = TV + 1;   // per thread; LDS pitch
+  float fco[STACK ? 1 : FPT];
+  if constexpr (!STACK) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
-    fvs[r] = (!STACK && rowok && x < T && gx < a.nx)
-                 ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
-                 : 0.f;
+    for (int i = 0; i < FPT; ++i) {
+      const int e = t + 2 * kTileThreads * i, row = e / TV, col = e % TV;
+      const int gy = y0 + row, gx = x0 + col;
+      fco[i] = (row < T && col < T && gy < a.ny && gx < a.nx)
+                   ? a.fld.ptr[(long long)img * a.fld.plane + (long long)gy * a.fld.ld + gx]
+                   : 0.f;
+    }
   }
   // ---- forward transform of the signal window, by all 512 threads on image A0 (A1 is
   // only the working image of the second component)
   forward_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
+  float fvs[8];
+  if constexpr (!STACK) {
+    float* fl = reinterpret_cast<float*>(A1);   // A1 is free until the component loop
+#pragma unroll
+    for (int i = 0; i < FPT; ++i) {
+      const int e = t + 2 * kTileThreads * i;
+      fl[(e / TV) * FL + e % TV] = fco[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) fvs[r] = fl[u4 * FL + bq4 + 8 * r];
+  }
   // signal spectrum of this thread's column pass-0 items
   cx<float> hs[NH][8];
   int qv[NH], qb[NH];
@@ -476,14 +537,10 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
           for (int r = 1; r < M; ++r) x[r] = cmul(x[r], mk(tt.re[bq4][r], tt.im[bq4][r]));
           dft<M, +1, float>(x);
           if constexpr (STACK) {
+            // back into the image (the positions this thread read), stored below along rows
+            cx<float>* Aw = cc ? A1 : A0;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-              const int xx = bq4 + 8 * r, gx = x0 + xx;
-              if (rowok && xx < T && gx < a.nx)
-                *reinterpret_cast<float2*>(a.stack + 2 * ((long long)(c + cc) * a.ny * a.nx +
-                                                          (long long)(y0 + u4) * a.nx + gx)) =
-                    make_float2(x[r].re * a.scale, x[r].im * a.scale);
-            }
+            for (int r = 0; r < 8; ++r) Aw[u4 * P + bq4 + 8 * r] = x[r];
           } else {
             const float wc = a.w[c + cc];
             const float wk = Y2 ? wc * (float)(a.kofs + c + cc) : 0.f;
@@ -497,19 +554,55 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
         }
       }
     }
-    __syncthreads();   // the images are rewritten by the next column pass
+    if constexpr (STACK) {
+      // the pair's T x T blocks of G_c and G_{c+1}, with consecutive lanes along rows
+      __syncthreads();
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        if (cc == 0 || two) {
+          const cx<float>* Ar = cc ? A1 : A0;
+          float* dst = a.stack + 2 * (long long)(c + cc) * a.ny * a.nx;
+#pragma unroll
+          for (int i = 0; i < FPT; ++i) {
+            const int e = t + 2 * kTileThreads * i, row = e / TV, col = e % TV;
+            const int gy = y0 + row, gx = x0 + col;
+            if (row < T && col < T && gy < a.ny && gx < a.nx) {
+              const cx<float> v = Ar[row * P + col];
+              *reinterpret_cast<float2*>(dst + 2 * ((long long)gy * a.nx + gx)) =
+                  make_float2(v.re * a.scale, v.im * a.scale);
+            }
+          }
+        }
+      }
+      lds_barrier();   // the images are rewritten next; the stores are not waited for
+    } else {
+      __syncthreads();   // the images are rewritten by the next column pass
+    }
   }
 
   if constexpr (!STACK) {
-    float* yb = a.y + (long long)img * a.planeY;
+    // outputs through LDS (free after the last barrier), then stored along rows
+    float* ob = reinterpret_cast<float*>(A0);
+    float* ob2 = reinterpret_cast<float*>(A1);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const int x = bq4 + 8 * r, gy = y0 + u4, gx = x0 + x;
-      if (rowok && x < T && gx < a.nx) {
-        yb[(long long)gy * a.ldY + gx] = acc[r] * a.scale;
+      ob[u4 * FL + bq4 + 8 * r] = acc[r] * a.scale;
+      if constexpr (Y2) ob2[u4 * FL + bq4 + 8 * r] = acc2[r] * a.scale;
+    }
+    __syncthreads();
+    float* yb = a.y + (long long)img * a.planeY;
+    // (the thread index through a lane shuffle: the compiler would otherwise keep the
+    // field loads' addresses, which are the same expressions, live through the loop)
+    const int ts = __shfl(t, t & 63);
+#pragma unroll
+    for (int i = 0; i < FPT; ++i) {
+      const int e = ts + 2 * kTileThreads * i, row = e / TV, col = e % TV;
+      const int gy = y0 + row, gx = x0 + col;
+      if (row < T && col < T && gy < a.ny && gx < a.nx) {
+        yb[(long long)gy * a.ldY + gx] = ob[row * FL + col];
         if constexpr (Y2)
           a.y2[(long long)img * a.planeY + (long long)gy * a.ldY + gx] =
-              acc2[r] * a.scale * a.mulsig[(long long)img * a.planeMul + (long long)gy * a.ldMul + gx];
+              ob2[row * FL + col] * a.mulsig[(long long)img * a.planeMul + (long long)gy * a.ldMul + gx];
       }
     }
   }
