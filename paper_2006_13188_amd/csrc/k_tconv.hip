@@ -183,16 +183,25 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
     };
   one_signal(std::integral_constant<int, 0>());
   if constexpr (NSIG == 2) one_signal(std::integral_constant<int, 1>());
-  float* yb = a.y + (long long)img * a.planeY;
+  // outputs through LDS (the image is free after the last barrier), then stored with
+  // consecutive lanes along rows (a wave's lanes above are rows of one column)
+  constexpr int FL = TV + 1, FPT = (TV * TV + NT - 1) / NT;
+  float* ob = reinterpret_cast<float*>(A);
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
 #pragma unroll
     for (int r = 0; r < RV; ++r) {
-      const int u = l + LS * i, x = bq + 8 * r;
-      const int gy = y0 + u, gx = x0 + x;
-      if (u < T && x < T && gy < a.ny && gx < a.nx)
-        yb[(long long)gy * a.ldY + gx] = NSIG == 2 ? out0[i][r] / out1[i][r] : out0[i][r] * a.scale;
+      const int u = l + LS * i;
+      if (u < TV) ob[u * FL + bq + 8 * r] = NSIG == 2 ? out0[i][r] / out1[i][r] : out0[i][r] * a.scale;
     }
+  }
+  __syncthreads();
+  float* yb = a.y + (long long)img * a.planeY;
+#pragma unroll
+  for (int k = 0; k < FPT; ++k) {
+    const int e = t + NT * k, row = e / TV, col = e % TV;
+    const int gy = y0 + row, gx = x0 + col;
+    if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = ob[row * FL + col];
   }
 }
 
