@@ -405,15 +405,21 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
       qv[1] = (sf & 1) * (N / 2);
       qb[1] = (sf >> 1) * (M / 2);
     }
+    // the phase e^{2 pi i (k + v) R / N} of element r (row k = b + M r) advances by the
+    // uniform factor e^{2 pi i M R / N} from r to r + 1: one table read per item
     const TilePhases<96>& ph = kPh96;
+    const int ms = (M * a.R) % N;
+    const cx<float> step = mk(ph.re[ms], ph.im[ms]);
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+      const int m0 = ((qb[s] + qv[s]) * a.R) % N;
+      cx<float> pr = mk(ph.re[m0], ph.im[m0]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int k = qb[s] + M * r;
-        const int m = ((k + qv[s]) * a.R) % N;
-        hs[s][r] = cmul(window_spectrum<N>(A0, k, qv[s]), mk(ph.re[m], ph.im[m]));
+        hs[s][r] = cmul(window_spectrum<N>(A0, qb[s] + M * r, qv[s]), pr);
+        pr = cmul(pr, step);
       }
+    }
   } else {
 #pragma unroll
     for (int s = 0; s < NH; ++s) {
