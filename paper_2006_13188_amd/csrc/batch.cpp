@@ -231,8 +231,10 @@ ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
     for (size_t m = 0; m < sh.members.size(); ++m) {
       const ecc_instance& in = bp->inst[sh.members[m]];
       const Spectrum* sp = nullptr;
-      ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp));
+      const bool sym = tile_symmetric(sh.N, sh.TV) && rotation_parity(in.plan);
+      ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp, sym ? SPEC_CENTRED : SPEC_CORR));
       d.push_back(make_desc(in, sh.N, sh.T[m], sp));
+      d.back().sym = sym ? 1 : 0;
     }
     ECC_HIP(sh.descs.ensure(d.size() * sizeof(TileArgs)));
     ECC_HIP(hipMemcpy(sh.descs.p, d.data(), d.size() * sizeof(TileArgs), hipMemcpyHostToDevice));

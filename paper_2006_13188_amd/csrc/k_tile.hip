@@ -664,8 +664,14 @@ __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_items(const TileArg
   extern __shared__ cx<float> lds_t[];
   const int2 it = items[blockIdx.x];
   const TileArgs& a = descs[it.x];
-  if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
-  else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
+  if constexpr (HV == 2 && N == 96) {
+    if (a.sym) corr_block_pair<N, false, true>(a, 0, it.y, lds_t);
+    else corr_block_pair<N>(a, 0, it.y, lds_t);
+  } else if constexpr (HV == 2) {
+    corr_block_pair<N>(a, 0, it.y, lds_t);
+  } else {
+    corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
+  }
 }
 
 // Persistent form: workgroup w runs the blocks items[off[w] .. off[w+1]) one after
@@ -680,8 +686,14 @@ __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_batch(const TileArg
   for (int i = i0; i < i1; ++i) {
     const int2 it = items[i];
     const TileArgs& a = descs[it.x];
-    if constexpr (HV == 2) corr_block_pair<N>(a, 0, it.y, lds_t);
-    else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
+    if constexpr (HV == 2 && N == 96) {
+      if (a.sym) corr_block_pair<N, false, true>(a, 0, it.y, lds_t);
+      else corr_block_pair<N>(a, 0, it.y, lds_t);
+    } else if constexpr (HV == 2) {
+      corr_block_pair<N>(a, 0, it.y, lds_t);
+    } else {
+      corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
+    }
   }
 }
 
@@ -737,8 +749,17 @@ hipError_t prepare_tile_kernel() {
   }
   if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV>);
   if (e != hipSuccess) return e;
-  if constexpr (HV == 2) return allow_lds(k_tile_corr_pair<N>);
-  else return allow_lds(k_tile_corr_one<N, TV, SEPB>);
+  if constexpr (HV == 2) {
+    e = allow_lds(k_tile_corr_pair<N>);
+    if (e == hipSuccess) e = allow_lds(k_tile_corr_pair<N, false, true>);
+    if constexpr (N == 96) {
+      if (e == hipSuccess) e = allow_lds(k_tile_corr_pair<N, true>);
+      if (e == hipSuccess) e = allow_lds(k_tile_corr_pair<N, true, true>);
+    }
+    return e;
+  } else {
+    return allow_lds(k_tile_corr_one<N, TV, SEPB>);
+  }
 }
 
 }  // namespace

@@ -132,6 +132,7 @@ struct TileArgs {          // one correlation job (batch of images of one shape)
   const float* mulsig;
   long long planeMul;
   int ldMul;
+  int sym;                 // batch descriptors: the symmetric pair form (centred spectra)
 };
 bool tile_supported(int N, int TV);
 // block shapes with the symmetric pair form (rotation filters: centred block spectra with
