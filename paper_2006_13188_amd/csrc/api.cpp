@@ -875,7 +875,8 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
   if (tiled) {
     // component stack G_c(p) by blocks, then the angle search (float32 or matrix cores)
     const Spectrum* sp = nullptr;
-    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp));
+    const bool sym = tile_symmetric(tc.N, tc.TV) && rotation_parity(plan);
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, sym ? SPEC_CENTRED : SPEC_CORR));
     if (plan->match_tab_A != n_angles) {
       std::vector<float> tab(64 * 64, 0.f);
       for (int m = 0; m < n_angles; ++m)
@@ -892,7 +893,7 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
     ECC_HIP(ctx->ws.ensure((size_t)npix * U * sizeof(cx<float>)));
     mark(ctx, 0, st);
     ECC_HIP(launch_tile_stack(st, tc.N, tc.TV, signal, ld, ny, nx, R, tc.T, U, 1.0f / ((float)tc.N * (float)tc.N),
-                              sp->buf.as<cx<float>>(), ctx->ws.as<float>()));
+                              sp->buf.as<cx<float>>(), ctx->ws.as<float>(), sym));
     mark(ctx, 1, st);
     const int pc = prec == ECC_PREC_FP32 ? 0 : (prec == ECC_PREC_MFMA_FP16_HILO ? 1 : 2);
     ECC_HIP(launch_match_angles(st, pc, ctx->ws.as<float>(), U, npix, n_angles, plan->match_tab.as<float>(),

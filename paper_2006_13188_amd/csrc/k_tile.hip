@@ -30,8 +30,15 @@ namespace {
 // in place, one more barrier); STACK: write the components instead of combining them.
 // LS = NT / 8 threads share each pass-1 butterfly index (with 512 threads it is the wave
 // index, so the twiddles are scalar). Called by every thread of the workgroup.
-template <int N, int TV, bool SEPB, bool STACK = false, int NT = kTileThreads>
+//
+// SYM (rotation filters, N = 128, 512 threads): centred spectra and mirror items as in the
+// pair form below; thread t does mirror pairs t and 512 + t (t < 510), threads 510 and 511
+// do two of the four self-mirrored items through the same code (the mirror of such an item
+// is the item itself, so the second transform rewrites the same values), and the other two
+// are single units of lanes in waves 0 and 1.
+template <int N, int TV, bool SEPB, bool STACK = false, int NT = kTileThreads, bool SYM = false>
 __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
+  static_assert(!SYM || (N == 128 && NT == 512 && !SEPB), "symmetric one-group form: N = 128, 512 threads");
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
   constexpr int NQ2 = (TV * M + NT - 1) / NT;  // row pass-0 items
@@ -70,13 +77,53 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
   // ---- forward 2D transform of the signal window
   forward_window<N, NT>(A, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
   // signal spectrum values of this thread's column pass-0 items, kept for all components
-  cx<float> hs[NQ0][8];
+  constexpr int NHS = SYM ? 3 : NQ0;
+  cx<float> hs[NHS][8];
+  int sv[SYM ? 3 : 1], sb[SYM ? 3 : 1];   // SYM: items of slots A, B, C
+  if constexpr (SYM) {
+    // canonical item of pair p: b in 1 .. M/2 - 1 (all columns), then b = M/2 and b = 0
+    // with columns 1 .. N/2 - 1
+    constexpr int NB = (M / 2 - 1) * N, NPAIR = (N * M - 4) / 2;
+    static_assert(NPAIR == 2 * NT - 2, "pair count");
+    auto pair_item = [&](int p, int& v, int& b) {
+      if (p < NB) {
+        b = 1 + p / N;
+        v = p % N;
+      } else {
+        const int p2 = p - NB;
+        b = p2 < N / 2 - 1 ? M / 2 : 0;
+        v = 1 + (p2 < N / 2 - 1 ? p2 : p2 - (N / 2 - 1));
+      }
+    };
+    auto self_item = [&](int f, int& v, int& b) {
+      v = (f & 1) * (N / 2);
+      b = (f >> 1) * (M / 2);
+    };
+    pair_item(t, sv[0], sb[0]);
+    if (t < NT - 2) pair_item(NT + t, sv[1], sb[1]);
+    else self_item(t - (NT - 2), sv[1], sb[1]);
+    self_item(t == 127 ? 3 : 2, sv[2], sb[2]);
+    const TilePhases<N>& ph = tile_phases<N>();
+    const int ms = (M * a.R) % N;
+    const cx<float> step = mk(ph.re[ms], ph.im[ms]);
 #pragma unroll
-  for (int s = 0; s < NQ0; ++s) {
-    const int q = t + s * NT;
-    const int v = q % N, b = q / N;
+    for (int s = 0; s < 3; ++s) {
+      const int m0 = ((sb[s] + sv[s]) * a.R) % N;
+      cx<float> pr = mk(ph.re[m0], ph.im[m0]);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? window_spectrum<N>(A, b + M * r, v) : mk(0.f, 0.f);
+      for (int r = 0; r < 8; ++r) {
+        hs[s][r] = cmul(window_spectrum<N>(A, sb[s] + M * r, sv[s]), pr);
+        pr = cmul(pr, step);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < NQ0; ++s) {
+      const int q = t + s * NT;
+      const int v = q % N, b = q / N;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) hs[s][r] = (b < M) ? window_spectrum<N>(A, b + M * r, v) : mk(0.f, 0.f);
+    }
   }
   float fvs[STACK ? 1 : TR][RV];
   if constexpr (!STACK) {
@@ -156,6 +203,37 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     // without the register prefetch, the pass's filter-spectrum loads are issued in two
     // groups of items ahead of their products (a latency per group, not per item)
     constexpr int GQ = PREFETCH ? 1 : (NQ0 + 1) / 2;
+    if constexpr (SYM) {
+      const float par = (c & 1) ? -1.f : 1.f;   // (-1)^c (components from offset 0)
+      auto unit = [&](int s, bool pair, bool maybe_b0) {
+        const int v = sv[s], b = sb[s];
+        cx<float> f[8], x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) f[r] = Fc[(b + M * r) * N + v];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = cmulc(hs[s][r], f[r]);
+        dft<8, +1, float>(x);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) A[(8 * b + r) * P + v] = x[r];
+        if (pair) {
+          cx<float> g[8], y[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const cx<float> hf = cmul(hs[s][r], f[r]);
+            g[r] = mk(par * hf.re, -par * hf.im);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) y[j] = (maybe_b0 && b == 0) ? g[(8 - j) & 7] : g[7 - j];
+          dft<8, +1, float>(y);
+          const int vm = v == 0 ? 0 : N - v, bm = b == 0 ? 0 : M - b;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) A[(8 * bm + r) * P + vm] = y[r];
+        }
+      };
+      unit(0, true, false);
+      unit(1, true, true);
+      if (t == 63 || t == 127) unit(2, false, false);
+    } else
 #pragma unroll
     for (int s0 = 0; s0 < NQ0; s0 += GQ) {
       cx<float> fl[GQ][8];
@@ -622,12 +700,12 @@ constexpr int tile_nt() {
 }
 
 // One workgroup per block of a (batch of) image(s).
-template <int N, int TV, bool SEPB>
+template <int N, int TV, bool SEPB, bool SYM = false>
 __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_corr_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, lb / ntile, lb % ntile, lds_t);
+  corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), SYM>(a, lb / ntile, lb % ntile, lds_t);
 }
 template <int N, bool SYM = false, bool Y2 = false>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a) {
@@ -640,17 +718,17 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_corr_pair(TileArgs a)
 // Component stacks for matching: block `lb` of one image writes G_c(p) * scale, c < U, to
 // plane c of a.stack (interleaved re, im; planes of ny nx pixels, so the stores of one
 // component fill whole rows while the block is processed).
-template <int N, int TV, bool SEPB>
+template <int N, int TV, bool SEPB, bool SYM = false>
 __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_stack_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  corr_block_one<N, TV, SEPB, true, tile_nt<N, 1>()>(a, 0, lb, lds_t);
+  corr_block_one<N, TV, SEPB, true, tile_nt<N, 1>(), SYM>(a, 0, lb, lds_t);
 }
-template <int N>
+template <int N, bool SYM = false>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  corr_block_pair<N, true>(a, 0, lb, lds_t);
+  corr_block_pair<N, true, SYM>(a, 0, lb, lds_t);
 }
 
 // Batches of independent instances (every instance one image); item = (descriptor
@@ -669,6 +747,9 @@ __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_items(const TileArg
     else corr_block_pair<N>(a, 0, it.y, lds_t);
   } else if constexpr (HV == 2) {
     corr_block_pair<N>(a, 0, it.y, lds_t);
+  } else if constexpr (N == 128 && !SEPB) {
+    if (a.sym) corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), true>(a, 0, it.y, lds_t);
+    else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
   } else {
     corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
   }
@@ -691,6 +772,9 @@ __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_batch(const TileArg
       else corr_block_pair<N>(a, 0, it.y, lds_t);
     } else if constexpr (HV == 2) {
       corr_block_pair<N>(a, 0, it.y, lds_t);
+    } else if constexpr (N == 128 && !SEPB) {
+      if (a.sym) corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), true>(a, 0, it.y, lds_t);
+      else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
     } else {
       corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
     }
@@ -722,6 +806,13 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, b
     else hipLaunchKernelGGL((k_tile_corr_pair<N>), g, b, lds, s, a);
   } else {
     if (a.y2) return hipErrorInvalidValue;   // the one-group form has no second output
+    if constexpr (N == 128 && !SEPB) {
+      if (sym) {
+        hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB, true>), dim3(nblk), dim3(tile_nt<N, 1>()),
+                           (tile_lds<N, TV, SEPB, HV>()), s, a);
+        return last();
+      }
+    }
     hipLaunchKernelGGL((k_tile_corr_one<N, TV, SEPB>), dim3(nblk), dim3(tile_nt<N, 1>()),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
@@ -729,11 +820,27 @@ hipError_t launch_tile_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, b
 }
 
 template <int N, int TV, bool SEPB, int HV>
-hipError_t launch_stack_kernel(hipStream_t s, unsigned nblk, const TileArgs& a) {
+hipError_t launch_stack_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, bool sym) {
   if constexpr (HV == 2) {
+    if constexpr (N == 96) {
+      if (sym) {
+        hipLaunchKernelGGL((k_tile_stack_pair<N, true>), dim3(nblk), dim3(2 * kTileThreads),
+                           (tile_lds<N, TV, SEPB, HV>()), s, a);
+        return last();
+      }
+    }
+    if (sym) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_stack_pair<N>), dim3(nblk), dim3(2 * kTileThreads),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   } else {
+    if constexpr (N == 128 && !SEPB) {
+      if (sym) {
+        hipLaunchKernelGGL((k_tile_stack_one<N, TV, SEPB, true>), dim3(nblk), dim3(tile_nt<N, 1>()),
+                           (tile_lds<N, TV, SEPB, HV>()), s, a);
+        return last();
+      }
+    }
+    if (sym) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_stack_one<N, TV, SEPB>), dim3(nblk), dim3(tile_nt<N, 1>()),
                        (tile_lds<N, TV, SEPB, HV>()), s, a);
   }
@@ -744,8 +851,17 @@ template <int N, int TV, bool SEPB, int HV>
 hipError_t prepare_tile_kernel() {
   hipError_t e = allow_lds(k_tile_batch<N, TV, SEPB, HV>);
   if (e == hipSuccess) {
-    if constexpr (HV == 2) e = allow_lds(k_tile_stack_pair<N>);
-    else e = allow_lds(k_tile_stack_one<N, TV, SEPB>);
+    if constexpr (HV == 2) {
+      e = allow_lds(k_tile_stack_pair<N>);
+      if constexpr (N == 96) {
+        if (e == hipSuccess) e = allow_lds(k_tile_stack_pair<N, true>);
+      }
+    } else {
+      e = allow_lds(k_tile_stack_one<N, TV, SEPB>);
+      if constexpr (N == 128 && !SEPB) {
+        if (e == hipSuccess) e = allow_lds(k_tile_stack_one<N, TV, SEPB, true>);
+      }
+    }
   }
   if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV>);
   if (e != hipSuccess) return e;
@@ -758,7 +874,11 @@ hipError_t prepare_tile_kernel() {
     }
     return e;
   } else {
-    return allow_lds(k_tile_corr_one<N, TV, SEPB>);
+    e = allow_lds(k_tile_corr_one<N, TV, SEPB>);
+    if constexpr (N == 128 && !SEPB) {
+      if (e == hipSuccess) e = allow_lds(k_tile_corr_one<N, TV, SEPB, true>);
+    }
+    return e;
   }
 }
 
@@ -822,7 +942,7 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   return hipErrorInvalidValue;
 }
 
-bool tile_symmetric(int N, int TV) { return N == 96 && TV == 64; }
+bool tile_symmetric(int N, int TV) { return (N == 96 && TV == 64) || N == 128; }
 bool tile_has_y2(int N, int TV) {
 #define ECC_TY(n, tv, sb, hv) if (N == n && TV == tv) return hv == 2;
   ECC_TILE_CONFIGS(ECC_TY)
@@ -831,8 +951,9 @@ bool tile_has_y2(int N, int TV) {
 }
 
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack) {
+                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym) {
   if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
+  if (sym && !tile_symmetric(N, TV)) return hipErrorInvalidValue;
   TileArgs a{};
   a.H = H;
   a.ldH = ldH;
@@ -848,7 +969,7 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
   a.stack = stack;
   const long long nblk = (long long)a.tx * a.ty;
 #define ECC_TSK(n, tv, sb, hv) \
-  if (N == n && TV == tv) return launch_stack_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a);
+  if (N == n && TV == tv) return launch_stack_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a, sym);
   ECC_TILE_CONFIGS(ECC_TSK)
 #undef ECC_TSK
   return hipErrorInvalidValue;

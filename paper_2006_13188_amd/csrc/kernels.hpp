@@ -142,7 +142,7 @@ size_t tile_lds_bytes(int N, int TV);
 int tile_threads(int N, int TV);
 // component stack of one image: stack[2 (c ny nx + y nx + x) .. +1] = G_c(y, x) * scale
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack);
+                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym = false);
 // angle search over a component stack: score = max_m sum_c Re(e^{2 pi i c m / A} w_c G_c),
 // index = first maximising m; prec 0 = float32 FMA, 1 = float16 hi/lo MFMA, 2 = bfloat16
 // hi/lo MFMA. dtab: float32 [64][64] (angle m, stack entry k) = w_{k/2} cos / -w_{k/2} sin.
