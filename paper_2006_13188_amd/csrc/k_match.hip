@@ -21,15 +21,21 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-// The stack holds U planes of npix complex values (component-major).
+// The stack holds U planes of npix complex values (component-major). UMAX >= U (the
+// components beyond U are zero and their products are not formed past UMAX); the table
+// rows of the A angles are staged in LDS (read as broadcasts).
 template <int UMAX>
 __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restrict__ stack, int U,
                                                           long long npix, int A, const float* __restrict__ dtab,
                                                           float* __restrict__ score, int* __restrict__ index,
                                                           int ldOut, int nx) {
+  constexpr int K2 = 2 * UMAX;
+  __shared__ float dl[64 * K2];
+  for (int i = threadIdx.x; i < A * K2; i += 256) dl[i] = dtab[(i / K2) * 64 + i % K2];
+  __syncthreads();
   const long long p = blockIdx.x * 256LL + threadIdx.x;
   if (p >= npix) return;
-  float g[2 * UMAX];
+  float g[K2];
 #pragma unroll
   for (int c = 0; c < UMAX; ++c) {
     const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
@@ -38,11 +44,12 @@ __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restri
   }
   float best = -INFINITY;
   int bi = 0;
+#pragma unroll 2
   for (int m = 0; m < A; ++m) {
-    const float* d = dtab + m * 64;
+    const float* d = dl + m * K2;
     float c = 0.f;
 #pragma unroll
-    for (int k = 0; k < 2 * UMAX; ++k) c = fmaf(g[k], d[k], c);
+    for (int k = 0; k < K2; ++k) c = fmaf(g[k], d[k], c);
     if (c > best) {
       best = c;
       bi = m;
@@ -197,8 +204,12 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int
 #define ECC_MF(UM)                                                                                         \
   hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, A, dtab,      \
                      score, index, ldOut, nx)
-    if (U <= 8) ECC_MF(8);
+    if (U <= 4) ECC_MF(4);
+    else if (U <= 8) ECC_MF(8);
+    else if (U <= 12) ECC_MF(12);
     else if (U <= 16) ECC_MF(16);
+    else if (U <= 18) ECC_MF(18);
+    else if (U <= 24) ECC_MF(24);
     else ECC_MF(32);
 #undef ECC_MF
     return last();
