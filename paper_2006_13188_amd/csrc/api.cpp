@@ -1033,11 +1033,13 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     ga.U = U;
     const long long nblk = (long long)((ny + vtc.T - 1) / vtc.T) * ((nx + vtc.T - 1) / vtc.T) * batch;
     ECC_REQ(nblk <= 0x7fffffffLL, "too many blocks");
-    ECC_HIP(ctx->ws.ensure((size_t)nblk * U * Sz * Sz * sizeof(cx<float>)));
+    const size_t pbytes = ((size_t)nblk * U * Sz * Sz * sizeof(cx<float>) + 255) / 256 * 256;
+    ECC_HIP(ctx->ws.ensure(pbytes + gradf_reduce_scratch(U, Sz)));
     ga.part = ctx->ws.as<cx<float>>();
     ECC_HIP(launch_tile_gradf(st, vtc.N, vtc.TV, batch, ga));
     ECC_HIP(launch_gradf_reduce(st, ga.part, (int)nblk, U, Sz, plan->d_weights.as<float>(),
-                                1.0f / ((float)vtc.N * (float)vtc.N), reinterpret_cast<cx<float>*>(grad_comps)));
+                                1.0f / ((float)vtc.N * (float)vtc.N), reinterpret_cast<cx<float>*>(grad_comps),
+                                static_cast<char*>(ctx->ws.p) + pbytes));
   } else if (grad_comps) {
     // stack B_k (saved or recomputed), Gh full spectra of grad_out, D_k, small inverse
     const long long pBk = (long long)ny * Px, pBi = pBk * U;

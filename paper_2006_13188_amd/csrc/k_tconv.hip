@@ -360,20 +360,33 @@ __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_gradf(TileGradFArgs
   gradf_block<N, TV, tconv_threads<N>()>(a, lb / ntile, lb % ntile, lb, conv_img_lds<N>);
 }
 
-// one thread per (component, lag): sum over the blocks in block order
-__global__ void k_gradf_reduce(const cx<float>* __restrict__ part, int nblk, int U, int S,
-                               const float* __restrict__ w, float scale, cx<float>* __restrict__ out) {
-  const int n = U * S * S;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the block partials in a fixed order, in two stages: stage 1, thread (value, chunk)
+// adds the blocks of its chunk in block order (float64); stage 2 adds the chunks in order.
+constexpr int kGradfChunks = 64;
+__global__ void k_gradf_partial(const cx<float>* __restrict__ part, int nblk, int n, cx<double>* __restrict__ tmp) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x, ch = blockIdx.y;
   if (idx >= n) return;
-  const int k = idx / (S * S);
+  const int b0 = (int)((long long)nblk * ch / kGradfChunks), b1 = (int)((long long)nblk * (ch + 1) / kGradfChunks);
   double re = 0.0, im = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+#pragma unroll 4
+  for (int b = b0; b < b1; ++b) {
     const cx<float> v = part[(long long)b * n + idx];
     re += v.re;
     im += v.im;
   }
-  const double f = (double)w[k] * scale;
+  tmp[(long long)ch * n + idx] = mk(re, im);
+}
+__global__ void k_gradf_final(const cx<double>* __restrict__ tmp, int n, int S, const float* __restrict__ w,
+                              float scale, cx<float>* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int ch = 0; ch < kGradfChunks; ++ch) {
+    const cx<double> v = tmp[(long long)ch * n + idx];
+    re += v.re;
+    im += v.im;
+  }
+  const double f = (double)w[idx / (S * S)] * scale;
   out[idx] = mk((float)(re * f), (float)(im * f));
 }
 
@@ -437,11 +450,17 @@ hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const Tile
   return hipErrorInvalidValue;
 }
 
+size_t gradf_reduce_scratch(int U, int S) { return (size_t)kGradfChunks * U * S * S * sizeof(cx<double>); }
+
 hipError_t launch_gradf_reduce(hipStream_t s, const cx<float>* part, int nblk, int U, int S, const float* w,
-                               float scale, cx<float>* out) {
+                               float scale, cx<float>* out, void* scratch) {
   const int n = U * S * S;
-  hipLaunchKernelGGL(k_gradf_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nblk, U, S, w,
-                     scale, out);
+  cx<double>* tmp = static_cast<cx<double>*>(scratch);
+  hipLaunchKernelGGL(k_gradf_partial, dim3((unsigned)((n + 255) / 256), kGradfChunks), dim3(256), 0, s, part,
+                     nblk, n, tmp);
+  hipError_t e = last();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gradf_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tmp, n, S, w, scale, out);
   return last();
 }
 

@@ -202,9 +202,12 @@ struct TileGradFArgs {
 };
 bool tgradf_supported(int N, int TV);
 hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const TileGradFArgs& a);
-// out[k][a][b] = w_k * scale * sum over nblk blocks of part[block][k][a][b] (block order fixed)
+// out[k][a][b] = w_k * scale * sum over nblk blocks of part[block][k][a][b] (order fixed:
+// 64 chunks of consecutive blocks, each summed in block order, then the chunks in order;
+// float64 sums); scratch: gradf_reduce_scratch(U, S) bytes of device memory
+size_t gradf_reduce_scratch(int U, int S);
 hipError_t launch_gradf_reduce(hipStream_t s, const cx<float>* part, int nblk, int U, int S, const float* w,
-                               float scale, cx<float>* out);
+                               float scale, cx<float>* out, void* scratch);
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);
 hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);
