@@ -10,9 +10,11 @@
 // products). F_c is placed at circular index (x - R) mod N for its offsets x in [-R, R],
 // so circular output index u < N - 2R is the linear convolution at y0 + u.
 //
-// With two signals (scale group, ratio form of eq. normalization) the numerator signal
-// H / f^2 and the denominator signal 1 / f^2 share the phases; both are accumulated and
-// the output is the ratio of the two real parts.
+// With two signals (scale group, ratio form of eq. normalization) the kernel runs twice:
+// first for the numerator signal H / f^2 (raw real parts written), then for the
+// denominator signal 1 / f^2, dividing the stored numerator by its own result. (Two
+// launches rather than one block doing both: the per-thread state of one signal already
+// fills the register file at N = 128.)
 #include <type_traits>
 
 #include "tile_common.hpp"
@@ -41,7 +43,7 @@ __device__ __forceinline__ void stream_spectrum(const cx<float>* src) {
 }
 
 // NT threads (256 or 512); LS = NT / 8 threads share each pass-1 butterfly index.
-template <int N, int TV, int NSIG, int NT>
+template <int N, int TV, int NT>
 __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr bool DMA = tconv_dma(N);
@@ -60,12 +62,11 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
 #pragma unroll
   for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
 
-  float out0[TR][RV], out1[TR][RV];
+  float out0[TR][RV];
   const float* Hb = a.H + (long long)img * a.planeH;
+  const bool den = a.step == 2;   // the denominator signal 1 / f^2 (no image)
   __syncthreads();   // the LDS image may still be in use by the previous block
-  // one signal at a time (the denominator signal of the ratio form reuses the registers)
-  auto one_signal = [&](auto gc) {
-    constexpr int g = decltype(gc)::value;
+  {
     // ---- window pixels of this thread's column pass-0 items: z = s(q) e^{-i c alpha(q)}
     // for the current component c (starting at c = 0), advanced by e1 = e^{-i alpha}
     cx<float> z[NQ0][8], e1[NQ0][8];
@@ -91,7 +92,7 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
           }
           e1[s][r] = mk(cs, -sn);
           const float wn = a.sig_norm ? 1.f / (fv * fv) : 1.f;
-          z[s][r] = mk(g == 0 ? Hb[(long long)gy * a.ldH + gx] * wn : wn, 0.f);
+          z[s][r] = mk(den ? wn : Hb[(long long)gy * a.ldH + gx] * wn, 0.f);
         }
       }
     }
@@ -174,15 +175,10 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
       for (int r = 1; r < M; ++r) x[r] = cmul(x[r], tw[r]);
       dft<M, +1, float>(x);
 #pragma unroll
-      for (int r = 0; r < RV; ++r) {
-        if constexpr (g == 0) out0[i][r] = x[r].re;
-        else out1[i][r] = x[r].re;
-      }
+      for (int r = 0; r < RV; ++r) out0[i][r] = x[r].re;
     }
     __syncthreads();
-    };
-  one_signal(std::integral_constant<int, 0>());
-  if constexpr (NSIG == 2) one_signal(std::integral_constant<int, 1>());
+  }
   // outputs through LDS (the image is free after the last barrier), then stored with
   // consecutive lanes along rows (a wave's lanes above are rows of one column)
   constexpr int FL = TV + 1, FPT = (TV * TV + NT - 1) / NT;
@@ -192,7 +188,7 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
 #pragma unroll
     for (int r = 0; r < RV; ++r) {
       const int u = l + LS * i;
-      if (u < TV) ob[u * FL + bq + 8 * r] = NSIG == 2 ? out0[i][r] / out1[i][r] : out0[i][r] * a.scale;
+      if (u < TV) ob[u * FL + bq + 8 * r] = a.step == 0 ? out0[i][r] * a.scale : out0[i][r];
     }
   }
   __syncthreads();
@@ -201,7 +197,10 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
   for (int k = 0; k < FPT; ++k) {
     const int e = t + NT * k, row = e / TV, col = e % TV;
     const int gy = y0 + row, gx = x0 + col;
-    if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) yb[(long long)gy * a.ldY + gx] = ob[row * FL + col];
+    if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) {
+      float* yp = yb + (long long)gy * a.ldY + gx;
+      *yp = den ? *yp / ob[row * FL + col] : ob[row * FL + col];   // numerator / denominator
+    }
   }
 }
 
@@ -390,11 +389,11 @@ __global__ void k_gradf_final(const cx<double>* __restrict__ tmp, int n, int S, 
   out[idx] = mk((float)(re * f), (float)(im * f));
 }
 
-template <int N, int TV, int NSIG>
+template <int N, int TV>
 __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  conv_block_one<N, TV, NSIG, tconv_threads<N>()>(a, lb / ntile, lb % ntile, conv_img_lds<N>);
+  conv_block_one<N, TV, tconv_threads<N>()>(a, lb / ntile, lb % ntile, conv_img_lds<N>);
 }
 
 
@@ -416,15 +415,17 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   a.ty = (a.ny + a.T - 1) / a.T;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  // nsig = 2: the numerator pass, then the denominator pass dividing into it
 #define ECC_CL(n, tv)                                                                              \
   if (N == n && TV == tv) {                                                                       \
-    if (a.nsig == 1)                                                                              \
-      hipLaunchKernelGGL((k_tile_conv<n, tv, 1>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
-                         0, s, a);                                                                \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_tile_conv<n, tv, 2>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), \
-                         0, s, a);                                                                \
-    return last();                                                                                \
+    for (int step = (a.nsig == 1 ? 0 : 1); step <= (a.nsig == 1 ? 0 : 2); ++step) {              \
+      a.step = step;                                                                              \
+      hipLaunchKernelGGL((k_tile_conv<n, tv>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), 0, \
+                         s, a);                                                                   \
+      const hipError_t e = last();                                                                \
+      if (e != hipSuccess) return e;                                                              \
+    }                                                                                             \
+    return hipSuccess;                                                                            \
   }
   ECC_TCONV_CONFIGS(ECC_CL)
 #undef ECC_CL

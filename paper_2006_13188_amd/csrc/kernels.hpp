@@ -176,6 +176,7 @@ struct TileConvArgs {
   Field fld;               // phase e^{-i c alpha}
   int sig_norm;            // signal divided by field^2
   int nsig;                // 1: y = scale Re sum; 2: ratio of the sums for H/f^2 and 1/f^2
+  int step;                // set by the launcher: 0 plain, 1 numerator, 2 denominator
   float* y;
   long long planeY;
   int ldY;
