@@ -103,7 +103,8 @@ const char* ecc_status_string(ecc_status s);
 const char* ecc_last_error(void);
 
 /* FFT size of the two-pass path for an image side n and filter radius R: the smallest
- * 7-smooth integer >= n + R (zero-boundary linear correlation needs >= n + R). */
+ * 7-smooth integer >= max(n + R, 16) (zero-boundary linear correlation needs >= n + R;
+ * the floor of 16 keeps every transform at two passes or more). */
 ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
 /* Enables (1) or disables (0) the autotuner. When enabled, the next forward call (or
  * ecc_describe) first times every compiled block shape of the tiled path on this device
@@ -169,7 +170,9 @@ ecc_status ecc_filter_plan_destroy(ecc_filter_plan plan);
  * Rotation: correlation y = Re sum_k w_k e^{i k theta} (H star F_k), convolution
  * y = Re sum_k w_k (H e^{-i k theta}) * F_k, with w_0 = 1, w_k = 2 (k and -k together).
  * Only ECC_PREC_FP32 is implemented. Errors: INVALID_ARGUMENT (sizes, strides, NULL,
- * aliasing, filter larger than the image), UNSUPPORTED (precision), HIP. */
+ * aliasing, filter larger than the image), UNSUPPORTED (precision; or the two-pass
+ * strategy where its transform length, ecc_fft_size(n, R), exceeds 4096 along rows: the
+ * block strategy covers the largest images for radii up to 56), HIP. */
 ecc_status ecc_extended(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny,
                         int nx, const float* signal, int ld_signal, const float* field,
                         int ld_field, float* out, int ld_out, ecc_precision prec, void* stream);

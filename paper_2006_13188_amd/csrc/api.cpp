@@ -27,7 +27,9 @@ int fft_size_for(ecc_context ctx, int n, int R) {
   const std::string key = std::to_string(n) + ":" + std::to_string(R);
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) return it->second;
-  return next_smooth7(n + R);
+  // at least 16: every transform then has two or more passes (zero padding beyond n + R
+  // changes nothing in the result)
+  return next_smooth7(std::max(n + R, 16));
 }
 
 }  // namespace
