@@ -339,12 +339,14 @@ __device__ __forceinline__ void gradf_block(const TileGradFArgs& a, int img, int
   }
 }
 
-// threads per workgroup: 512 (two waves per SIMD; for N = 96 some passes leave a quarter
-// of the lanes idle, which costs less than one wave per SIMD)
+// threads per workgroup of the convolution: 768 for N = 96 (three waves per SIMD; the 96
+// rows x 8 butterflies of the pass-1 phases are exactly one item per thread), else 512
 template <int N>
 constexpr int tconv_threads() {
-  return 512;
+  return N == 96 ? 768 : 512;
 }
+// the filter-gradient kernel keeps 512 (two waves per SIMD)
+constexpr int tgradf_threads() { return 512; }
 
 // the transform image: a static LDS object of its own (with the spectrum copy beside it
 // for N <= 96), so that the compiler orders the spectrum's memory-to-LDS loads only
@@ -353,10 +355,10 @@ template <int N>
 __shared__ cx<float> conv_img_lds[N * (N + 1)];
 
 template <int N, int TV>
-__global__ void __launch_bounds__(tconv_threads<N>()) k_tile_gradf(TileGradFArgs a) {
+__global__ void __launch_bounds__(tgradf_threads()) k_tile_gradf(TileGradFArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  gradf_block<N, TV, tconv_threads<N>()>(a, lb / ntile, lb % ntile, lb, conv_img_lds<N>);
+  gradf_block<N, TV, tgradf_threads()>(a, lb / ntile, lb % ntile, lb, conv_img_lds<N>);
 }
 
 // Sum of the block partials in a fixed order, in two stages: stage 1, thread (value, chunk)
@@ -443,7 +445,7 @@ hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const Tile
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
 #define ECC_GL(n, tv)                                                                                     \
   if (N == n && TV == tv) {                                                                              \
-    hipLaunchKernelGGL((k_tile_gradf<n, tv>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), 0, s, a);  \
+    hipLaunchKernelGGL((k_tile_gradf<n, tv>), dim3((unsigned)nblk), dim3(tgradf_threads()), 0, s, a);    \
     return last();                                                                                       \
   }
   ECC_TCONV_CONFIGS(ECC_GL)
