@@ -602,11 +602,23 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
       }
     }
     __syncthreads();
-    const bool act = g == 0 || two;
-    // ---- column pass 1 (in place, rows < T kept) and row pass 0, group g on c + g
-    if (act) pass1_inplace<N, +1, false, N / 32, kTileThreads, TV / 8>(Ag, tw1, bq1, l1, N, T);
+    // ---- column pass 1 (in place, rows < T kept) and row pass 0, group g on c + g; at
+    // N = 96 a last odd component is shared by both groups (columns, then rows, split in
+    // halves)
+    if (N != 96 || two) {
+      if (g == 0 || two) pass1_inplace<N, +1, false, N / 32, kTileThreads, TV / 8>(Ag, tw1, bq1, l1, N, T);
+    } else {
+      constexpr int HN = N / 2;
+      pass1_inplace<N, +1, false, (HN + 31) / 32, kTileThreads, TV / 8>(A0 + g * HN, tw1, bq1, l1, HN, T);
+    }
     __syncthreads();
-    pass0_inplace<N, +1, true, TV>(Ag, tg, T, act);
+    if (N != 96 || two) {
+      pass0_inplace<N, +1, true, TV>(Ag, tg, T, g == 0 || two);
+    } else {
+      constexpr int HT = TV / 2;
+      const int nl = g ? T - HT : (T < HT ? T : HT);
+      pass0_inplace<N, +1, true, HT>(A0 + g * HT * P, tg, nl, nl > 0);
+    }
     __syncthreads();
     // ---- row pass 1 for both components and the per-pixel combination
     if (u4 < T) {
