@@ -65,6 +65,24 @@ def alg_flops_tiled(ny, nx, n, t, U):
     return blocks * per_block
 
 
+def alg_flops_tiled_conv(ny, nx, n, t, U):
+    """Algorithmic FP32 flops of one tiled convolution launch: per block and component,
+    the forward 2D transform of the modulated complex window (2n transforms of
+    5 n log2 n), the phase recurrence and the spectral product with accumulation
+    (6 n^2 each); per block one inverse transform (n column + t row transforms)."""
+    import math
+    blocks = ((ny + t - 1) // t) * ((nx + t - 1) // t)
+    f1 = 5.0 * n * math.log2(n)
+    return blocks * (U * (2 * n * f1 + 12.0 * n * n) + (n + t) * f1)
+
+
+def alu_roofline(flops, ms):
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP32_TFLOPS, 4), "frac_of_nonpacked_fp32": round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "alg_flops": flops}
+
+
 def two_pass_min_bytes(ny, nx, Py, Px, U):
     """Whole-path algorithmic bytes at the minimum padding P = N + R (12 B/px + (U+1)
     planes of filter spectrum read and inter-pass write + read)."""
@@ -174,6 +192,17 @@ def matching_precisions(E, ctx, stream, timeit):
     res["speedup_fp16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["fp16_hilo"]["ms"], 3)
     res["speedup_bf16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["bf16_hilo"]["ms"], 3)
     res["angle_search_speedup_fp16_hilo"] = round(res["fp32"]["angle_search_ms"] / res["fp16_hilo"]["angle_search_ms"], 3)
+    # angle search. Float32: 64 angles x 2 (K + 1) fused multiply-adds per pixel on the
+    # vector units (ALU-bound). Matrix cores: the products take a few microseconds at the
+    # float16/bfloat16 rate, so the bound is HBM: the stack read (K + 1 complex planes) and
+    # the score and index written.
+    res["fp32"]["angle_search_roofline"] = alu_roofline(N * N * 2.0 * 64 * 2 * (K + 1),
+                                                        res["fp32"]["angle_search_ms"])
+    ab = N * N * (8 * (K + 1) + 8)
+    for name in ("fp16_hilo", "bf16_hilo"):
+        gbs = ab / (res[name]["angle_search_ms"] * 1e-3) / 1e9
+        res[name]["angle_search_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                              "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "alg_bytes": ab}
     mplan.close()
     return res
 
@@ -197,6 +226,11 @@ def scale_workload(E, timeit):
         ms = timeit(lambda: E.ecc_scale_smooth(c, plan, Hs, Ss, out=out), reps=10)
         res[name + "_ms"] = round(ms, 4)
         res[name + "_Mpix_comp_s"] = round(2048 * 2048 * 24 / (ms * 1e-3) / 1e6, 1)
+        cs, cn, cb = c.describe(E.CONVOLUTION, plan, 2048, 2048)
+        if strat == TILED and cs == TILED:
+            # the ratio form is two launches (numerator, denominator) of 13 components
+            res[name + "_roofline"] = dict(alu_roofline(2 * alg_flops_tiled_conv(2048, 2048, cn, cb, 13), ms),
+                                           block={"transform": cn, "side": cb})
         plan.close()
         c.close()
     return res
@@ -451,6 +485,11 @@ def main():
         conv_ms = timeit(lambda: E.ecc_extended(ctx, E.CONVOLUTION, plan, H, TH, out3))
         extras["convolution_ms"] = round(conv_ms, 4)
         extras["convolution_Mpix_comp_s"] = round(N * N * (2 * K + 1) / (conv_ms * 1e-3) / 1e6, 1)
+        cs, cn, cb = ctx.describe(E.CONVOLUTION, plan, N, N)
+        if cs == TILED:
+            # one launch per call: its algorithmic flops over the whole call's time
+            extras["convolution_roofline"] = dict(alu_roofline(alg_flops_tiled_conv(N, N, cn, cb, U), conv_ms),
+                                                  block={"transform": cn, "side": cb})
     if "matching" in want:
         extras["mixed_precision"] = matching_precisions(E, ctx, stream, timeit)
     if "scale" in want:
