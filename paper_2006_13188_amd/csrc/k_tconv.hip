@@ -42,7 +42,7 @@ __device__ __forceinline__ void stream_spectrum(const cx<float>* src) {
                                      16, 0, 0);
 }
 
-// NT threads (256 or 512); LS = NT / 8 threads share each pass-1 butterfly index.
+// NT threads (512 or 768); LS = NT / 8 threads share each pass-1 butterfly index.
 template <int N, int TV, int NT>
 __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
@@ -53,7 +53,7 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
   constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
   const int t = threadIdx.x, l = t % LS;
   // with 512 threads the butterfly index is the wave index: uniform, so its twiddles sit
-  // in scalar registers
+  // in scalar registers (with 768 a wave straddles two indices)
   const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
   const int y0 = (tile / a.tx) * a.T, x0 = (tile % a.tx) * a.T;
   const int T = a.T;
