@@ -437,17 +437,32 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     }
   }
   // ---- forward transform of the signal window, by all 512 threads on image A0 (A1 is
-  // only the working image of the second component)
-  forward_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t);
-  float fvs[8];
-  if constexpr (!STACK) {
-    float* fl = reinterpret_cast<float*>(A1);   // A1 is free until the component loop
+  // only the working image of the second component). While the window loads are in
+  // flight the field values go to A1 (free until the component loop), in the common case
+  // (angle field, components from k = 0) already as the phase step e^{i alpha}; the
+  // transform's barriers order these writes before the reads below.
+  const bool fast = !a.fld.log_mode && a.kofs == 0;
+  auto stage_field = [&]() {
+    if constexpr (!STACK) {
+      float2* fl = reinterpret_cast<float2*>(A1);
 #pragma unroll
-    for (int i = 0; i < FPT; ++i) {
-      const int e = t + 2 * kTileThreads * i;
-      fl[(e / TV) * FL + e % TV] = fco[i];
+      for (int i = 0; i < FPT; ++i) {
+        const int e = t + 2 * kTileThreads * i;
+        float2 v = make_float2(fco[i], 0.f);
+        if (fast) {
+          float sn, cs;
+          sincosf((float)a.fld.mul * fco[i] + (float)a.fld.add, &sn, &cs);
+          v = make_float2(cs, sn);
+        }
+        fl[(e / TV) * FL + e % TV] = v;
+      }
     }
-    __syncthreads();
+  };
+  forward_window<N, 2 * kTileThreads>(A0, a.H + (long long)img * a.planeH, a.ldH, a.ny, a.nx, y0, x0, a.R, t,
+                                      0, 0, stage_field);
+  float2 fvs[8];
+  if constexpr (!STACK) {
+    const float2* fl = reinterpret_cast<const float2*>(A1);
 #pragma unroll
     for (int r = 0; r < 8; ++r) fvs[r] = fl[u4 * FL + bq4 + 8 * r];
   }
@@ -523,19 +538,17 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
     e1[r] = mk(0.f, 0.f);
     const int x = bq4 + 8 * r, gx = x0 + x;
     if (!STACK && rowok && x < T && gx < a.nx) {
-      const float fv = fvs[r];
-      if (a.fld.log_mode || a.kofs != 0) {
+      const float fv = fvs[r].x;
+      if (fast) {   // staged as e^{i alpha}
+        e1[r] = mk(fvs[r].x, fvs[r].y);
+        z[r] = mk(1.f, 0.f);
+      } else {      // staged as the field value: log-scale angle or components from kofs
         const double al = field_angle(a.fld, fv);
         double sn, cs;
         sincos(al, &sn, &cs);
         e1[r] = mk((float)cs, (float)sn);
         sincos((double)a.kofs * al, &sn, &cs);
         z[r] = mk((float)cs, (float)sn);
-      } else {
-        float sn, cs;
-        sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
-        e1[r] = mk(cs, sn);
-        z[r] = mk(1.f, 0.f);
       }
     }
   }

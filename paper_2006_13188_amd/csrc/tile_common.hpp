@@ -169,9 +169,15 @@ __device__ __forceinline__ void rdft8(const float* x, cx<float>* X) {
 // S[N - k][l] = conj(S[k][(N - l) mod N]), so only rows k <= N/2 are transformed along
 // the rows (window_spectrum supplies the others). Ends with a barrier.
 // (rows and columns of H outside [ylo, ny) x [xlo, nx) are taken as zero)
-template <int N, int NT>
+// `during` runs once, after the window loads of the first group are issued and before
+// their values are used, so that its work overlaps their latency (it must not touch A).
+struct NoHook {
+  __device__ void operator()() const {}
+};
+template <int N, int NT, typename Hook = NoHook>
 __device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, int ldH, int ny, int nx, int y0,
-                                               int x0, int R, int t, int ylo = 0, int xlo = 0) {
+                                               int x0, int R, int t, int ylo = 0, int xlo = 0,
+                                               Hook during = Hook()) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8, NI = (N + LS - 1) / LS, H2 = N / 2 + 1;
   constexpr int NQ = (N * M + NT - 1) / NT;   // column pass-0 items of a thread
   constexpr int G = NQ < 4 ? NQ : 4;          // items whose loads are in flight together
@@ -192,6 +198,7 @@ __device__ __forceinline__ void forward_window(cx<float>* A, const float* Hb, in
         h[g][r] = (colok && gy >= ylo && gy < ny) ? Hb[(long long)gy * ldH + gx] : 0.f;
       }
     }
+    if (s0 == 0) during();
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int q = t + (s0 + g) * NT;
