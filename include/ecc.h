@@ -58,13 +58,13 @@ typedef enum {
 
 /* How extended correlations are evaluated (both reach the same result up to rounding).
  * TWO_PASS: the paper's form (Sec. 4): one zero-padded FFT correlation per component over
- * the whole image, P >= n + R, with the per-pixel combination fused into the last
- * inverse pass. TILED: overlap-save blocks: each T x T block of outputs is computed from
+ * the whole image, P >= n + R (ecc_fft_size), with the per-pixel combination fused into
+ * the last inverse pass. TILED: overlap-save blocks: each T x T block of outputs is computed from
  * an N x N window (N - 2R >= T) entirely on chip, per component, then combined per
  * pixel (block shapes exist for R <= 56). AUTO takes TILED when a block shape with side
  * T >= 2R exists, choosing among those by a cost model (measured when the autotuner is
- * on). Correlation, convolution, scale smoothing and matching have both forms; the
- * adjoint always uses TWO_PASS. */
+ * on). Correlation, convolution, scale smoothing, matching and the adjoint have both
+ * forms (ecc_extended_save writes the two-pass stack and so always runs TWO_PASS). */
 typedef enum {
   ECC_STRATEGY_AUTO = 0,
   ECC_STRATEGY_TWO_PASS = 1,
@@ -212,8 +212,11 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
  *                     (summed over the batch in a fixed order; complex64 (K+1) x S x S)
  * Any of grad_signal, grad_field, grad_comps may be NULL (not computed). `saved` is NULL
  * (recompute the modulated-signal stack) or device memory of
- * ecc_backward_saved_size() bytes filled by ecc_extended_save(). Only ECC_CONVOLUTION
- * is implemented (ECC_CORRELATION returns UNSUPPORTED). */
+ * ecc_backward_saved_size() bytes filled by ecc_extended_save(). With the block strategy
+ * (a block shape exists for the radius) grad_signal and grad_field come from one on-chip
+ * correlation of grad_out with two outputs, and grad_comps from per-block lag sums
+ * (context workspace) added in a fixed order; `saved` is then not read. Only
+ * ECC_CONVOLUTION is implemented (ECC_CORRELATION returns UNSUPPORTED). */
 ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch,
                                  int ny, int nx, const float* signal, const float* field,
                                  const float* grad_out, float* grad_signal, float* grad_comps,
