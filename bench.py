@@ -192,14 +192,12 @@ def matching_precisions(E, ctx, stream, timeit):
     res["speedup_fp16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["fp16_hilo"]["ms"], 3)
     res["speedup_bf16_hilo_vs_fp32"] = round(res["fp32"]["ms"] / res["bf16_hilo"]["ms"], 3)
     res["angle_search_speedup_fp16_hilo"] = round(res["fp32"]["angle_search_ms"] / res["fp16_hilo"]["angle_search_ms"], 3)
-    # angle search. Float32: 64 angles x 2 (K + 1) fused multiply-adds per pixel on the
-    # vector units (ALU-bound). Matrix cores: the products take a few microseconds at the
-    # float16/bfloat16 rate, so the bound is HBM: the stack read (K + 1 complex planes) and
-    # the score and index written.
-    res["fp32"]["angle_search_roofline"] = alu_roofline(N * N * 2.0 * 64 * 2 * (K + 1),
-                                                        res["fp32"]["angle_search_ms"])
+    # angle search, bound by HBM in every form: the stack read (K + 1 complex planes) and
+    # the score and index written. (Float32 evaluates the 64 angles as a length-64 inverse
+    # DFT, about 1.1 kflop per pixel; the matrix-core products take a few microseconds at
+    # the float16/bfloat16 rate.)
     ab = N * N * (8 * (K + 1) + 8)
-    for name in ("fp16_hilo", "bf16_hilo"):
+    for name in ("fp32", "fp16_hilo", "bf16_hilo"):
         gbs = ab / (res[name]["angle_search_ms"] * 1e-3) / 1e9
         res[name]["angle_search_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                               "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "alg_bytes": ab}

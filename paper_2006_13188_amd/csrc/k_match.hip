@@ -5,7 +5,9 @@
 //   D[m][2c] = w_c cos(2 pi c m / A),  D[m][2c+1] = -w_c sin(2 pi c m / A),
 // a dense [A x 2U] by [2U x pixels] product, then the maximum over m and the first m
 // attaining it. Three forms:
-//   * float32 fused multiply-adds, one thread per pixel;
+//   * float32, one thread per pixel: for A = 64 (the usual angle count) as a length-64
+//     inverse DFT of the U nonzero inputs w_c G_c (four 16-point DFTs, below), else as
+//     fused multiply-adds with the table;
 //   * matrix cores (16x16x16 MFMA) with float16 operands split into hi + lo parts:
 //     D g = D_hi g_hi + D_hi g_lo + D_lo g_hi (the lo*lo term, ~2^-22 relative, dropped),
 //     accumulated in float32; g is scaled per group of 16 pixels by a power of two so
@@ -58,6 +60,51 @@ __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restri
   const long long y = p / nx, x = p - y * nx;
   score[y * ldOut + x] = best;
   index[y * ldOut + x] = bi;
+}
+
+// A = 64, U <= UMAX <= 32: C(m) = Re sum_c X_c e^{2 pi i c m / 64}, X_c = w_c G_c. With
+// m = 4 a + b (a < 16, b < 4) and c = 16 q + r (r < 16),
+//   C(4 a + b) = Re sum_r [sum_q X_{16 q + r} e^{2 pi i (16 q + r) b / 64}] e^{2 pi i r a / 16},
+// so each b is one 16-point DFT of the twiddled inputs folded modulo 16: about a quarter of
+// the arithmetic of the 64 x 2U product. The weights w_c are row m = 0 of the table.
+template <int UMAX>
+__global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __restrict__ stack, int U,
+                                                                long long npix, const float* __restrict__ dtab,
+                                                                float* __restrict__ score, int* __restrict__ index,
+                                                                int ldOut, int nx) {
+  static_assert(UMAX <= 32, "inputs fold at most twice onto 16 bins");
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= npix) return;
+  cx<float> X[UMAX];
+#pragma unroll
+  for (int c = 0; c < UMAX; ++c) {
+    const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
+    const float w = (c < U) ? dtab[2 * c] : 0.f;
+    X[c] = mk(w * v.x, w * v.y);
+  }
+  float best = -INFINITY;
+  int bi = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    cx<float> y[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) y[r] = mk(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < UMAX; ++c) y[c % 16] = y[c % 16] + twiddle_const<64, +1, float>(X[c], c * b);
+    dft<16, +1, float>(y);
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int m = 4 * a + b;
+      const float v = y[a].re;
+      if (v > best || (v == best && m < bi)) {
+        best = v;
+        bi = m;
+      }
+    }
+  }
+  const long long yy = p / nx, xx = p - yy * nx;
+  score[yy * ldOut + xx] = best;
+  index[yy * ldOut + xx] = bi;
 }
 
 __device__ __forceinline__ short bf16_bits(float x) {   // round to nearest even
@@ -201,6 +248,18 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int
   const float2* stack = reinterpret_cast<const float2*>(stackf);
   if (prec == 0) {
     const unsigned grid = (unsigned)((npix + 255) / 256);
+    if (A == 64) {
+#define ECC_MD(UM)                                                                                         \
+  hipLaunchKernelGGL((k_match_angles_f32_dft64<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, dtab,    \
+                     score, index, ldOut, nx)
+      if (U <= 8) ECC_MD(8);
+      else if (U <= 16) ECC_MD(16);
+      else if (U <= 20) ECC_MD(20);
+      else if (U <= 24) ECC_MD(24);
+      else ECC_MD(32);
+#undef ECC_MD
+      return last();
+    }
 #define ECC_MF(UM)                                                                                         \
   hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, A, dtab,      \
                      score, index, ldOut, nx)

@@ -66,7 +66,8 @@ def check(score, index, ref, C, tol):
 
 @pytest.mark.parametrize("prec", [FP32, FP16_HILO, BF16_HILO], ids=["fp32", "fp16_hilo", "bf16_hilo"])
 @pytest.mark.parametrize("shape,S,K,A", [((96, 80), 15, 7, 64), ((70, 131), 9, 4, 17), ((64, 64), 21, 10, 32),
-                                         ((150, 140), 63, 16, 64), ((40, 200), 7, 31, 63)])
+                                         ((150, 140), 63, 16, 64), ((40, 200), 7, 31, 63), ((60, 90), 11, 23, 64),
+                                         ((48, 72), 9, 31, 64)])
 def test_matching_parity(E, sctx, prec, shape, S, K, A):
     ctx, strat = sctx
     img = blurred_noise(shape, 3)
