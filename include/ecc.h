@@ -215,8 +215,14 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
  * ecc_backward_saved_size() bytes filled by ecc_extended_save(). With the block strategy
  * (a block shape exists for the radius) grad_signal and grad_field come from one on-chip
  * correlation of grad_out with two outputs, and grad_comps from per-block lag sums
- * (context workspace) added in a fixed order; `saved` is then not read. Only
- * ECC_CONVOLUTION is implemented (ECC_CORRELATION returns UNSUPPORTED). */
+ * (context workspace) added in a fixed order; `saved` is then not read.
+ * ECC_CORRELATION (y = Re sum_k w_k e^{ik theta} (H star F_k), G_k = H star F_k; `saved`
+ * must be NULL):
+ *   grad_signal = Re sum_k w_k (gbar e^{-ik theta}) * F_k (the forward convolution of gbar)
+ *   grad_field  = -gbar sum_k w_k k Im(e^{ik theta} G_k)
+ *   grad_comps_k(x) = w_k sum_b sum_p gbar_b(p) e^{ik theta_b(p)} H_b(p + x)
+ * (the forward correlation's second output, and the convolution adjoint's filter part with
+ * the signal and grad_out exchanged). */
 ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch,
                                  int ny, int nx, const float* signal, const float* field,
                                  const float* grad_out, float* grad_signal, float* grad_comps,

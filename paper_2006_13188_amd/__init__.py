@@ -17,7 +17,7 @@ from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, G
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
-    "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv",
+    "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
     "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
     "PREC_MFMA_FP16_HILO", "PREC_MFMA_BF16_HILO",
@@ -232,8 +232,9 @@ def ecc_extended_save(ctx: Context, plan: FilterPlan, signal, field, saved, out=
 
 
 def ecc_extended_backward(ctx: Context, plan: FilterPlan, signal, field, grad_out, need_signal=True,
-                          need_comps=True, need_field=True, saved=None, stream=None):
-    """Adjoint of the extended convolution: returns (grad_signal, grad_comps, grad_field)."""
+                          need_comps=True, need_field=True, saved=None, stream=None, op=CONVOLUTION):
+    """Adjoint of the extended convolution (op=CONVOLUTION) or correlation
+    (op=CORRELATION, saved must be None): returns (grad_signal, grad_comps, grad_field)."""
     import torch
     signal = signal.contiguous()
     field = field.contiguous()
@@ -244,7 +245,7 @@ def ecc_extended_backward(ctx: Context, plan: FilterPlan, signal, field, grad_ou
     gs = torch.empty(signal.shape, dtype=torch.float32, device=dev) if need_signal else None
     gf = torch.empty(signal.shape, dtype=torch.float32, device=dev) if need_field else None
     gc = torch.empty((plan.K + 1, plan.S, plan.S), dtype=torch.complex64, device=dev) if need_comps else None
-    _check(lib().ecc_extended_backward(ctx.h, CONVOLUTION, plan.h, batch, ny, nx, _ptr(signal),
+    _check(lib().ecc_extended_backward(ctx.h, op, plan.h, batch, ny, nx, _ptr(signal),
                                        _ptr(field), _ptr(grad_out), _ptr(gs), _ptr(gc), _ptr(gf),
                                        _ptr(saved), _stream(stream)))
     return gs, gc, gf
@@ -288,17 +289,49 @@ def _ext_conv_function():
     return ExtConv
 
 
+def _ext_corr_function():
+    import torch
+
+    class ExtCorr(torch.autograd.Function):
+        """y = extended correlation of `signal` with components `comps` ((K+1, S, S)
+        complex64) steered by the angle field `theta`; backward uses the hand-written
+        adjoint (recomputing what it needs)."""
+
+        @staticmethod
+        def forward(ctx_, signal, theta, comps, ectx):
+            plan = FilterPlan.from_components(ectx, comps.detach())
+            sig = signal.detach().contiguous()
+            th = theta.detach().contiguous()
+            y = ecc_extended(ectx, CORRELATION, plan, sig, th)
+            ctx_.plan, ctx_.ectx = plan, ectx
+            ctx_.save_for_backward(sig, th)
+            return y
+
+        @staticmethod
+        def backward(ctx_, gy):
+            sig, th = ctx_.saved_tensors
+            gs, gc, gf = ecc_extended_backward(
+                ctx_.ectx, ctx_.plan, sig, th, gy, need_signal=ctx_.needs_input_grad[0],
+                need_comps=ctx_.needs_input_grad[2], need_field=ctx_.needs_input_grad[1],
+                op=CORRELATION)
+            return gs, gf, gc, None
+
+    return ExtCorr
+
+
 class _Lazy:
-    def __init__(self):
+    def __init__(self, make):
+        self._make = make
         self._f = None
 
     def apply(self, *args, **kw):
         if self._f is None:
-            self._f = _ext_conv_function()
+            self._f = self._make()
         return self._f.apply(*args, **kw)
 
 
-ExtConv = _Lazy()
+ExtConv = _Lazy(_ext_conv_function)
+ExtCorr = _Lazy(_ext_corr_function)
 
 
 class BatchPlan:

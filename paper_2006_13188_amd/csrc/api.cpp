@@ -962,16 +962,73 @@ ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, i
                       S(stream), saved);
 }
 
+// Adjoint of the extended correlation (derived from eq. Def-ECorr), with G_k = H star F_k:
+//   grad_signal = Re sum_k w_k (gbar e^{-ik theta}) * F_k: the scatter of gbar e^{ik theta}
+//                 with conj F_k has the same real part as its conjugate, which is the forward
+//                 extended convolution of gbar;
+//   grad_field  = -gbar sum_k w_k k Im(e^{ik theta} G_k): the second output of the forward
+//                 correlation of H (weighted by gbar), negated;
+//   grad_comps  = w_k sum_p gbar(p) e^{ik theta(p)} H(p + x): the convolution adjoint's filter
+//                 part with the signal and the output gradient exchanged.
+static ecc_status corr_backward(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                                const float* signal, const float* field, const float* grad_out,
+                                float* grad_signal, float* grad_comps, float* grad_field, void* stream) {
+  hipStream_t st = S(stream);
+  const long long pI = (long long)ny * nx;
+  if (grad_field) {
+    DevBuf tmp;
+    float* ybuf = grad_signal;   // the forward output lands here and is overwritten below
+    if (!ybuf) {
+      ECC_HIP(tmp.ensure((size_t)batch * pI * sizeof(float)));
+      ybuf = tmp.as<float>();
+    }
+    ecc_strategy cstrat = ECC_STRATEGY_TWO_PASS;
+    TileChoice ctc;
+    ECC_TRY(resolve_strategy(ctx, ECC_CORRELATION, plan, ny, nx, batch, &cstrat, &ctc));
+    Field fl = make_field(plan, field, pI, nx, 1.0);
+    if (cstrat == ECC_STRATEGY_TILED && tile_has_y2(ctc.N, ctc.TV)) {
+      const bool sym = tile_symmetric(ctc.N, ctc.TV) && rotation_parity(plan);
+      const Spectrum* sp = nullptr;
+      ECC_TRY(get_tile_spectrum(plan, ctc.N, st, &sp, sym ? SPEC_CENTRED : SPEC_CORR));
+      ECC_HIP(launch_tile_corr(st, ctc.N, ctc.TV, batch, signal, pI, nx, fl, ybuf, pI, nx, ny, nx, plan->R, ctc.T,
+                               plan->U, 0, plan->d_weights.as<float>(), 1.0f / ((float)ctc.N * (float)ctc.N),
+                               sp->buf.as<cx<float>>(), sym, grad_field, grad_out, pI, nx));
+    } else {
+      Geometry g{};
+      ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+      cx<float>* T;
+      long long pTk, pTi;
+      ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pI, nx, 0, st, &T, &pTk, &pTi));
+      ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, ybuf, pI, nx, 1.0f / ((float)g.Py * (float)g.Px),
+                        grad_field, grad_out, pI, nx, st));
+    }
+    ECC_HIP(launch_scale_f(st, grad_field, (long long)batch * pI, -1.0f));
+    if (tmp.p) ECC_HIP(hipStreamSynchronize(st));   // tmp is freed on return
+  }
+  if (grad_signal)
+    ECC_TRY(forward_impl(ctx, ECC_CONVOLUTION, plan, batch, ny, nx, grad_out, nx, field, nx, grad_signal, nx, st,
+                         nullptr));
+  if (grad_comps)
+    return ecc_extended_backward(ctx, ECC_CONVOLUTION, plan, batch, ny, nx, grad_out, field, signal, nullptr,
+                                 grad_comps, nullptr, nullptr, stream);
+  return ECC_OK;
+}
+
 ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny,
                                  int nx, const float* signal, const float* field,
                                  const float* grad_out, float* grad_signal, float* grad_comps,
                                  float* grad_field, void* saved, void* stream) {
   ECC_REQ(ctx && plan && signal && field && grad_out, "NULL argument");
   ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
-  if (op != ECC_CONVOLUTION) return fail(ECC_ERR_UNSUPPORTED, "only the convolution adjoint is implemented");
+  ECC_REQ(op == ECC_CONVOLUTION || op == ECC_CORRELATION, "unknown op");
   ECC_REQ(plan->group == ECC_GROUP_ROTATION, "the adjoint needs a rotation plan");
   ECC_TRY(validate_images(plan, batch, ny, nx));
   DeviceGuard dg(ctx->device);
+  if (op == ECC_CORRELATION) {
+    ECC_REQ(!saved, "the correlation adjoint takes no saved stack");
+    return corr_backward(ctx, plan, batch, ny, nx, signal, field, grad_out, grad_signal, grad_comps, grad_field,
+                         stream);
+  }
   hipStream_t st = S(stream);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));

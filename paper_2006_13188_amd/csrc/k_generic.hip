@@ -238,6 +238,10 @@ __global__ void k_conj_d(const cx<double>* __restrict__ in, cx<double>* __restri
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = conj(in[i]);
 }
+__global__ void k_scale_f(float* __restrict__ y, long long n, float a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= a;
+}
 __global__ void k_f2d(const cx<float>* __restrict__ in, cx<double>* __restrict__ out, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -341,6 +345,11 @@ hipError_t launch_d2f(hipStream_t s, const cx<double>* in, cx<float>* out, long 
 }
 hipError_t launch_conj_d(hipStream_t s, const cx<double>* in, cx<double>* out, long long n) {
   hipLaunchKernelGGL(k_conj_d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+  return last();
+}
+hipError_t launch_scale_f(hipStream_t s, float* y, long long n, float a) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, n, a);
   return last();
 }
 hipError_t launch_f2d(hipStream_t s, const cx<float>* in, cx<double>* out, long long n) {

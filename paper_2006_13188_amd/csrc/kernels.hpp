@@ -86,6 +86,7 @@ hipError_t launch_scale_components(hipStream_t s, double sigma0, double u_lo, do
 hipError_t launch_d2f(hipStream_t s, const cx<double>* in, cx<float>* out, long long n);
 hipError_t launch_conj_d(hipStream_t s, const cx<double>* in, cx<double>* out, long long n);   // out = conj(in)
 hipError_t launch_f2d(hipStream_t s, const cx<float>* in, cx<double>* out, long long n);
+hipError_t launch_scale_f(hipStream_t s, float* y, long long n, float a);                      // y *= a
 
 // ---- adjoint helpers
 hipError_t launch_grad_filter_cols(hipStream_t s, const ColCfg& c, int batch,

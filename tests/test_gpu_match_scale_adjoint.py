@@ -216,3 +216,93 @@ def test_autograd_function(E, ctx):
         assert rel2(gi.cpu().numpy().astype(np.float64), rh) <= TOL
         assert rel2(gt.cpu().numpy().astype(np.float64), rt) <= TOL
         assert rel2(gc.cpu().numpy().astype(np.complex128), rc) <= TOL
+
+
+@pytest.mark.parametrize("strategy", ["auto", "two_pass"])
+@pytest.mark.parametrize("from_components", [False, True])
+def test_correlation_adjoint_parity(E, from_components, strategy):
+    """Adjoint of the extended correlation (signal, angle field and components) against
+    the oracle's gradients, with the block strategy (N = 64 blocks) and the two-pass one."""
+    import torch
+    B, n, S, K = 2, 64, 11, 5
+    imgs = np.stack([blurred_noise((n, n), 160 + i) for i in range(B)])
+    ths = np.stack([theta_field((n, n), 170 + i) for i in range(B)])
+    filt = random_filter(S, 180, 3.0)
+    g = np.random.default_rng(181).standard_normal((B, n, n)).astype(np.float32)
+    comps, _ = O.angular_components(filt, K)
+    half = O.half_components(comps)
+    c = E.Context(0)
+    try:
+        if strategy == "two_pass":
+            c.set_strategy(E.STRATEGY_TWO_PASS)
+        if from_components:
+            plan = E.FilterPlan.from_components(c, torch.from_numpy(half.astype(np.complex64)).cuda())
+            half = half.astype(np.complex64).astype(np.complex128)
+        else:
+            plan = E.FilterPlan.rotation(c, dev(filt), K)
+        gs, gc, gf = E.ecc_extended_backward(c, plan, dev(imgs), dev(ths), dev(g), op=E.CORRELATION)
+        gs, gc, gf = host(gs).astype(np.float64), host(gc).astype(np.complex128), host(gf).astype(np.float64)
+        plan.close()
+    finally:
+        c.close()
+    rgc = np.zeros_like(half)
+    for b in range(B):
+        rh, rt, rc = O.corr_backward(imgs[b].astype(np.float64), ths[b].astype(np.float64), half,
+                                     g[b].astype(np.float64))
+        assert rel2(gs[b], rh) <= TOL and relinf(gs[b], rh) <= 2 * TOL
+        assert rel2(gf[b], rt) <= TOL and relinf(gf[b], rt) <= 2 * TOL
+        rgc += rc
+    assert rel2(gc, rgc) <= TOL
+
+
+def test_correlation_adjoint_symmetric_pair_form(E):
+    """The field part through the symmetric N = 96 pair form (a large image, radius 10)."""
+    shape, S, K = (520, 491), 21, 8
+    img = blurred_noise(shape, 190)
+    th = theta_field(shape, 191)
+    filt = random_filter(S, 192, 4.0 * S / 15)
+    g = np.random.default_rng(193).standard_normal(shape).astype(np.float32)
+    c = E.Context(0)
+    try:
+        plan = E.FilterPlan.rotation(c, dev(filt), K)
+        strat, n, _ = c.describe(E.CORRELATION, plan, *shape)
+        assert strat == E.STRATEGY_TILED and n == 96
+        gs, gc, gf = E.ecc_extended_backward(c, plan, dev(img), dev(th), dev(g), op=E.CORRELATION)
+        gs, gc, gf = host(gs).astype(np.float64), host(gc).astype(np.complex128), host(gf).astype(np.float64)
+        plan.close()
+    finally:
+        c.close()
+    comps, _ = O.angular_components(filt, K)
+    rh, rt, rc = O.corr_backward(img.astype(np.float64), th.astype(np.float64), O.half_components(comps),
+                                 g.astype(np.float64))
+    assert rel2(gs, rh) <= TOL and relinf(gs, rh) <= 2 * TOL
+    assert rel2(gf, rt) <= TOL and relinf(gf, rt) <= 2 * TOL
+    assert rel2(gc, rc) <= TOL
+
+
+def test_correlation_adjoint_rejects_saved_stack(E, ctx):
+    import torch
+    plan = E.FilterPlan.rotation(ctx, dev(random_filter(9, 194, 2.5)), 3)
+    x = dev(blurred_noise((32, 32), 195))
+    saved = torch.empty(16, dtype=torch.float32, device="cuda")
+    with pytest.raises(E.EccError):
+        E.ecc_extended_backward(ctx, plan, x, x.clone(), x.clone(), saved=saved, op=E.CORRELATION)
+
+
+def test_autograd_correlation_function(E, ctx):
+    import torch
+    n, S, K = 40, 9, 4
+    img = torch.from_numpy(blurred_noise((n, n), 17)).cuda().requires_grad_(True)
+    th = torch.from_numpy(theta_field((n, n), 18)).cuda().requires_grad_(True)
+    comps, _ = O.angular_components(random_filter(S, 19, 2.5), K)
+    half = torch.from_numpy(O.half_components(comps).astype(np.complex64)).cuda().requires_grad_(True)
+    y = E.ExtCorr.apply(img, th, half, ctx)
+    gy = torch.randn_like(y)
+    gi, gt, gc = torch.autograd.grad(y, (img, th, half), gy)
+    rh, rt, rc = O.corr_backward(img.detach().cpu().numpy().astype(np.float64),
+                                 th.detach().cpu().numpy().astype(np.float64),
+                                 half.detach().cpu().numpy().astype(np.complex128),
+                                 gy.cpu().numpy().astype(np.float64))
+    assert rel2(gi.cpu().numpy().astype(np.float64), rh) <= TOL
+    assert rel2(gt.cpu().numpy().astype(np.float64), rt) <= TOL
+    assert rel2(gc.cpu().numpy().astype(np.complex128), rc) <= TOL
