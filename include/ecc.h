@@ -193,10 +193,12 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
  * (int32): device ny x nx with stride ld_out.
  * With a block shape (TILED / AUTO strategy) the components are computed block by block
  * into a stack in the context's workspace (K+1 planes of ny nx complex64) and the
- * angle search is a dense product done by `prec`: ECC_PREC_FP32 (float32 multiply-adds),
- * ECC_PREC_MFMA_FP16_HILO (matrix cores, float16 hi + lo operands, float32 accumulation;
- * ~1e-6 relative), ECC_PREC_MFMA_BF16_HILO (bfloat16 hi + lo; ~1e-5 relative). The
- * two-pass strategy supports ECC_PREC_FP32 only (else UNSUPPORTED). */
+ * angle search runs in the precision `prec`: ECC_PREC_FP32 (float32; for n_angles = 64
+ * and K <= 31 a length-64 inverse DFT over k per pixel, else the dense product of the
+ * angle table with the components), ECC_PREC_MFMA_FP16_HILO (the dense product on matrix
+ * cores, float16 hi + lo operands, float32 accumulation; ~1e-6 relative),
+ * ECC_PREC_MFMA_BF16_HILO (bfloat16 hi + lo; ~1e-5 relative). The two-pass strategy
+ * supports ECC_PREC_FP32 only (else UNSUPPORTED). */
 ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
                                const float* signal, int ld, int n_angles, float* best_score,
                                int* best_index, int ld_out, ecc_precision prec, void* stream);
