@@ -500,19 +500,19 @@ def main():
     cpu = None
     if not args.no_cpu:
         # float64 oracle (numpy FFT route, single-threaded pocketfft) on the same image,
-        # median of 3 full-image runs (about 5-15 s of CPU work)
+        # median of 7 full-image runs (about 10 s of CPU work)
         import oracle as O
         comps, _ = O.angular_components(filt, K)
         half = O.half_components(comps)
         times = []
-        for _ in range(3):
+        for _ in range(7):
             t0 = time.perf_counter()
             O.ext_corr_half(img.astype(np.float64), theta.astype(np.float64), half)
             times.append(time.perf_counter() - t0)
-        tcpu = sorted(times)[1]
+        tcpu = sorted(times)[3]
         cpu = {"value": round(N * N * (2 * K + 1) / tcpu / 1e6, 3), "unit": "Mpix*comp/s",
                "cores": 1, "kind": "oracle",
-               "sample": f"full 1024x1024 image, 31x31 filter, K=16, float64 FFT route, median of 3 "
+               "sample": f"full 1024x1024 image, 31x31 filter, K=16, float64 FFT route, median of 7 "
                          f"runs ({tcpu:.2f} s each) on {cpu_model()}"}
 
     rec = {
