@@ -27,7 +27,7 @@ from .decompose import (
 )
 from .extended import (
     ext_corr_brute, ext_conv_brute, ext_corr_fft, ext_conv_fft,
-    ext_conv_half, ext_corr_half, match_rotations, min_fft_size,
+    ext_conv_half, ext_corr_half, match_rotations, min_fft_size, fft_workers,
 )
 from .adjoint import conv_backward, corr_backward
 from .scale import (
@@ -39,7 +39,7 @@ __all__ = [
     "default_angular_samples", "bilinear", "grid_radii", "angular_components",
     "rotated_filter", "half_components",
     "ext_corr_brute", "ext_conv_brute", "ext_corr_fft", "ext_conv_fft",
-    "ext_conv_half", "ext_corr_half", "match_rotations", "min_fft_size",
+    "ext_conv_half", "ext_corr_half", "match_rotations", "min_fft_size", "fft_workers",
     "conv_backward", "corr_backward",
     "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
     "scale_smooth_fft",

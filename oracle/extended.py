@@ -17,10 +17,43 @@ the filter is real.
 """
 from __future__ import annotations
 
+import contextlib
+
 import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view
 
 from .decompose import rotated_filter
+
+# FFT library of the FFT routes: numpy.fft (single-threaded pocketfft) by default; inside
+# fft_workers(n) scipy.fft with n threads (the same algorithm, its 1D transforms spread
+# over n threads). The arithmetic of the routes does not change.
+_FFT_WORKERS = None
+
+
+@contextlib.contextmanager
+def fft_workers(n: int):
+    """Runs the FFT routes on scipy.fft with `n` worker threads within the block."""
+    global _FFT_WORKERS
+    old = _FFT_WORKERS
+    _FFT_WORKERS = int(n)
+    try:
+        yield
+    finally:
+        _FFT_WORKERS = old
+
+
+def _fft2(a, s=None):
+    if _FFT_WORKERS is None:
+        return np.fft.fft2(a, s=s)
+    import scipy.fft
+    return scipy.fft.fft2(a, s=s, workers=_FFT_WORKERS)
+
+
+def _ifft2(a):
+    if _FFT_WORKERS is None:
+        return np.fft.ifft2(a)
+    import scipy.fft
+    return scipy.fft.ifft2(a, workers=_FFT_WORKERS)
 
 
 def min_fft_size(n: int, R: int) -> int:
@@ -103,11 +136,11 @@ def standard_correlations(H, comps, P=None):
     R = (S - 1) // 2
     ny, nx = H.shape
     Py, Px = _sizes(H.shape, R, P)
-    Hh = np.fft.fft2(H, s=(Py, Px))
+    Hh = _fft2(H, s=(Py, Px))
     G = np.empty((comps.shape[0], ny, nx), dtype=np.complex128)
     for i, Fk in enumerate(comps):
-        Fh = np.fft.fft2(_place(Fk, Py, Px))
-        G[i] = np.fft.ifft2(Hh * np.conj(Fh))[:ny, :nx]
+        Fh = _fft2(_place(Fk, Py, Px))
+        G[i] = _ifft2(Hh * np.conj(Fh))[:ny, :nx]
     return G
 
 
@@ -134,8 +167,8 @@ def ext_conv_fft(H, theta, comps, P=None):
     acc = np.zeros((Py, Px), dtype=np.complex128)
     for i, Fk in enumerate(comps):
         Mk = H * ph[..., i]
-        acc += np.fft.fft2(Mk, s=(Py, Px)) * np.fft.fft2(_place(Fk, Py, Px))
-    return np.fft.ifft2(acc)[:ny, :nx]
+        acc += _fft2(Mk, s=(Py, Px)) * _fft2(_place(Fk, Py, Px))
+    return _ifft2(acc)[:ny, :nx]
 
 
 def _half_weights(n_half, weights):
@@ -172,8 +205,8 @@ def ext_conv_half(H, alpha, comps_half, weights=None, P=None):
     acc = np.zeros((Py, Px), dtype=np.complex128)
     for k, Fk in enumerate(comps_half):
         Mk = H * np.exp(-1j * k * alpha)
-        acc += w[k] * np.fft.fft2(Mk, s=(Py, Px)) * np.fft.fft2(_place(Fk, Py, Px))
-    return np.real(np.fft.ifft2(acc)[:ny, :nx])
+        acc += w[k] * _fft2(Mk, s=(Py, Px)) * _fft2(_place(Fk, Py, Px))
+    return np.real(_ifft2(acc)[:ny, :nx])
 
 
 def match_rotations(H, comps, n_angles=64, P=None):
