@@ -89,16 +89,17 @@ def two_pass_min_bytes(ny, nx, Py, Px, U):
     return 12 * ny * nx + (U + 1) * (8 * Py * Px + 16 * ny * Px)
 
 
-def stored_traffic(kernel_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel,
-    or None when there is none or the kernel source changed since it was taken."""
+def stored_figure(profile, key):
+    """A number recorded in a committed rocprofv3 summary under profiles/ ("<key>: value"),
+    or None when the summary is missing or the kernel source (and the headers it is
+    built from, listed with their sha256 in the summary) changed since it was taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"bytes per launch: ([0-9.eE+]+)", text)
+    m = re.search(re.escape(key) + r": ([0-9.eE+]+)", text)
     h = re.search(r"source sha256: ([0-9a-f]{64}) \(([^)]+)\)", text)
     if not m or not h:
         return None
@@ -237,11 +238,14 @@ def scale_workload(E, timeit):
 def adjoint_workload(E, ctx, timeit):
     """Forward + hand-written adjoint of the extended convolution through the autograd
     function: 16 images of 512^2, a shared 21x21 filter (K = 12, 13 complex components),
-    gradients for the signal, the components and the angle field; with the modulated
-    stack kept from the forward pass and with it recomputed (checkpointing); peak memory
-    of each."""
+    gradients for the signal, the components and the angle field; the default (the stack
+    is kept only when the backward reads it) and checkpointed forms; peak memory of each;
+    errors against the float64 oracle: output and every gradient of images 0 and 15, and
+    the component gradient of the same two images run as a batch of 2."""
+    import numpy as np
     import torch
 
+    import oracle as O
     from synthetic import adjoint_config
 
     imgs, thetas, filt, g = adjoint_config()
@@ -254,10 +258,11 @@ def adjoint_workload(E, ctx, timeit):
     Cc = half.clone().requires_grad_(True)
     G = torch.from_numpy(g).cuda()
     res = {"workload": "extended convolution forward + adjoint, 16 x 512^2, 21x21 filter, K=12"}
-    for name, ckpt in (("saved_stack", False), ("checkpointed", True)):
+    last = {}
+    for name, ckpt in (("default", False), ("checkpointed", True)):
         def step():
             y = E.ExtConv.apply(H, T, Cc, ctx, ckpt)
-            torch.autograd.grad(y, (H, T, Cc), G)
+            last[name] = (y,) + torch.autograd.grad(y, (H, T, Cc), G)
         step()
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
@@ -267,6 +272,30 @@ def adjoint_workload(E, ctx, timeit):
         peak = torch.cuda.max_memory_allocated() - base
         ms = timeit(step, reps=10)
         res[name] = {"fwd_bwd_ms": round(ms, 3), "peak_extra_MiB": round(peak / 2 ** 20, 1)}
+    torch.cuda.synchronize()
+    y, gi, gt, _ = (t.detach().cpu().numpy() for t in last["default"])
+    half64 = half.cpu().numpy().astype(np.complex128)
+    errs = {"output": 0.0, "grad_signal": 0.0, "grad_field": 0.0}
+    rgc = np.zeros_like(half64)
+
+    def rel2(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    for b in (0, 15):
+        im, th, gb = (a[b].astype(np.float64) for a in (imgs, thetas, g))
+        rh, rt, rc = O.conv_backward(im, th, half64, gb)
+        rgc += rc
+        errs["output"] = max(errs["output"], rel2(y[b].astype(np.float64), O.ext_conv_half(im, th, half64)))
+        errs["grad_signal"] = max(errs["grad_signal"], rel2(gi[b].astype(np.float64), rh))
+        errs["grad_field"] = max(errs["grad_field"], rel2(gt[b].astype(np.float64), rt))
+    cplan = E.FilterPlan.from_components(ctx, half)
+    sel = torch.tensor([0, 15], device="cuda")
+    _, gc2, _ = E.ecc_extended_backward(ctx, cplan, H.detach()[sel], T.detach()[sel], G[sel],
+                                        need_signal=False, need_field=False)
+    torch.cuda.synchronize()
+    errs["grad_comps"] = rel2(gc2.cpu().numpy().astype(np.complex128), rgc)
+    cplan.close()
+    res["rel_l2_err_vs_float64_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
     return res
 
 
@@ -322,6 +351,52 @@ def batch_workload(E, timeit):
         p.close()
     ctx.close()
     return res
+
+
+def cpu_baseline(img, filt, theta):
+    """The float64 oracle on the host cores, on the same inputs (about 20 s in all):
+      * FFT route, all the cores this process may use (up to 16): scipy.fft with that
+        many workers, median of 3 full-image runs -> `value`;
+      * FFT route, one core: numpy.fft, median of 5 full-image runs;
+      * brute force (the definition, pixel by pixel) on the small 128^2 / 15x15 / K = 8
+        case, median of 3 runs."""
+    import numpy as np
+
+    import oracle as O
+    from synthetic import rotation_config
+
+    half = O.half_components(O.angular_components(filt, K)[0])
+    H64, T64 = img.astype(np.float64), theta.astype(np.float64)
+
+    def median_time(fn, n):
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[n // 2]
+
+    work = N * N * (2 * K + 1)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with O.fft_workers(workers):
+        t_all = median_time(lambda: O.ext_corr_half(H64, T64, half), 3)
+    t_one = median_time(lambda: O.ext_corr_half(H64, T64, half), 5)
+    img0, filt0, th0, K0 = rotation_config(128, 15, 8)
+    comps0 = O.angular_components(filt0, K0)[0]
+    t_bf = median_time(lambda: O.ext_corr_brute(img0, th0, comps0), 3)
+    legs = {
+        "fft_all_cores": {"value": round(work / t_all / 1e6, 3), "cores": workers, "s_per_image": round(t_all, 3),
+                          "sample": "full 1024x1024 image, 31x31 filter, K=16, scipy.fft workers, median of 3"},
+        "fft_one_core": {"value": round(work / t_one / 1e6, 3), "cores": 1, "s_per_image": round(t_one, 3),
+                         "sample": "full 1024x1024 image, 31x31 filter, K=16, numpy.fft, median of 5"},
+        "brute_force_128": {"value": round(128 * 128 * (2 * K0 + 1) / t_bf / 1e6, 3), "cores": 1,
+                            "s_per_image": round(t_bf, 4),
+                            "sample": "128x128 image, 15x15 filter, K=8, definition evaluated per pixel, median of 3"},
+    }
+    return {"value": legs["fft_all_cores"]["value"], "unit": "Mpix*comp/s", "cores": workers, "kind": "oracle",
+            "sample": f"float64 oracle, FFT route, full 1024x1024 image, 31x31 filter, K=16, {workers} threads "
+                      f"(scipy.fft workers), median of 3 runs of {t_all:.2f} s on {cpu_model()}",
+            "legs": legs}
 
 
 def main():
@@ -415,23 +490,39 @@ def main():
 
     value = N * N * (2 * K + 1) / (ms * 1e-3) / 1e6
     dom = max(stage_ms, key=stage_ms.get)
+    R = (S - 1) // 2
+    # algorithmic HBM bytes of one correlation (the paper's structure at the minimum
+    # padding P = n + R): 12 B per pixel plus, per computed component and for the signal,
+    # one filter-spectrum read and one write + read of the cropped inter-pass plane
+    sb = two_pass_min_bytes(N, N, N + R, N + R, U)
     if strat == TILED:
-        fl = alg_flops_tiled(N, N, tn, tblk, U)
-        achieved = fl / (stage_ms[dom] * 1e-3) / 1e12
-        traffic = stored_traffic("tile_corr_1024sq_S31_K16")
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "alg_flops": fl, "avg_ms": round(stage_ms[dom], 5),
-                "frac_of_nonpacked_fp32": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
-                "block": {"transform": tn, "side": tblk}}
+        # one launch is the whole correlation: the algorithmic bytes over its average
+        # duration, against the HBM peak
+        t_k = stage_ms[dom]
+        achieved = sb / (t_k * 1e-3) / 1e9
+        executed = stored_figure("tile_corr_1024sq_S31_K16_sq_counters.md", "executed flops per launch")
+        nominal = alg_flops_tiled(N, N, tn, tblk, U)
+        alu = {"basis": "FP32 arithmetic the counters executed per launch (ADD + MUL + 2 FMA, x 64 lanes)",
+               "executed_flops": executed, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+               "nominal_flops_5nlog2n": nominal,
+               "nominal_achieved": round(nominal / (t_k * 1e-3) / 1e12, 2)}
+        if executed is not None:
+            tf = executed / (t_k * 1e-3) / 1e12
+            alu.update(achieved=round(tf, 2), frac=round(tf / PEAK_FP32_TFLOPS, 4),
+                       frac_of_nonpacked_fp32=round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4))
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": stored_figure("tile_corr_1024sq_S31_K16_hbm_traffic.md", "bytes per launch"),
+                "alg_bytes": sb,
+                "alg_bytes_formula": "12*ny*nx + (U+1)*(8*Py*Px + 16*ny*Px), P = n + R = 1039, U = K + 1 = 17",
+                "avg_ms": round(t_k, 5), "block": {"transform": tn, "side": tblk}, "alu": alu}
     else:
-        Py = ctx.fft_size(N, (S - 1) // 2)
+        Py = ctx.fft_size(N, R)
         ab = alg_bytes_corr(N, N, Py, Py, U)
         achieved = ab[dom] / (stage_ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                 "alg_bytes": ab[dom], "avg_ms": round(stage_ms[dom], 5)}
-    sb = two_pass_min_bytes(N, N, N + (S - 1) // 2, N + (S - 1) // 2, U)
 
     # ---- spot check of this exact launch configuration (sampled pixels, summed directly
     # from the plan's components)
@@ -445,7 +536,7 @@ def main():
         "strategy": "tiled" if strat == TILED else "two_pass",
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "plan_build_ms": round(plan_ms, 3),
-        "hbm_roofline_frac_of_two_pass_alg_bytes": round(sb / (PEAK_HBM_GBS * 1e9) / (ms * 1e-3), 4),
+        "hbm_roofline_frac_per_step": round(sb / (PEAK_HBM_GBS * 1e9) / (ms * 1e-3), 4),
         "sampled_max_abs_err_over_max": spot,
     }
 
@@ -499,21 +590,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        # float64 oracle (numpy FFT route, single-threaded pocketfft) on the same image,
-        # median of 7 full-image runs (about 10 s of CPU work)
-        import oracle as O
-        comps, _ = O.angular_components(filt, K)
-        half = O.half_components(comps)
-        times = []
-        for _ in range(7):
-            t0 = time.perf_counter()
-            O.ext_corr_half(img.astype(np.float64), theta.astype(np.float64), half)
-            times.append(time.perf_counter() - t0)
-        tcpu = sorted(times)[3]
-        cpu = {"value": round(N * N * (2 * K + 1) / tcpu / 1e6, 3), "unit": "Mpix*comp/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"full 1024x1024 image, 31x31 filter, K=16, float64 FFT route, median of 7 "
-                         f"runs ({tcpu:.2f} s each) on {cpu_model()}"}
+        cpu = cpu_baseline(img, filt, theta)
 
     rec = {
         "metric": "Mpix\u00b7K/s, 1024\u00b2 rotation ext. correlation; mixed vs FP32 speedup at stated err",

@@ -26,7 +26,7 @@
  *    hipStream_t (NULL = the null stream). Calls enqueue work and return without
  *    waiting, except plan creation, which may wait for its own set-up.
  *  - Every call returns an ecc_status. Arguments are validated before anything is
- *    enqueued, so a failed call leaves outputs untouched; ecc_last_error() gives the
+ *    enqueued, so a failed call leaves outputs untouched; ecc_last_error gives the
  *    message (thread-local). No call aborts, throws or prints.
  */
 #ifndef ECC_H
@@ -91,16 +91,21 @@ typedef struct {
 
 /* Creates a context bound to HIP device `hip_device` (made current for the call).
  * The context owns twiddle tables, scratch workspace and size choices. One context
- * must not be used by two host threads at once. Errors: INVALID_ARGUMENT (bad device
- * or NULL out), HIP. */
+ * must not be used by two host threads at once. One host thread may use it on several
+ * streams: a call that uses the workspace on a stream other than the previous such
+ * call's first waits (on the device) for that call's last kernel. Errors:
+ * INVALID_ARGUMENT (bad device or NULL out), HIP. */
 ecc_status ecc_create(int hip_device, ecc_context* out);
 /* Waits for the device, then frees everything the context owns, including filter plans
  * made from it that are still alive (their handles must not be used afterwards). NULL
  * is accepted. */
 ecc_status ecc_destroy(ecc_context ctx);
 const char* ecc_status_string(ecc_status s);
-/* Message of the last failed call on this host thread ("" if none). */
-const char* ecc_last_error(void);
+/* Message of the last failed call on this host thread ("" if none). The text is kept
+ * per host thread, not per context: `ctx` may be NULL (as after a failed ecc_create) and
+ * does not select among contexts; the pointer stays valid until the thread's next failed
+ * call. */
+const char* ecc_last_error(ecc_context ctx);
 
 /* FFT size of the two-pass path for an image side n and filter radius R: the smallest
  * 7-smooth integer >= max(n + R, 16) (zero-boundary linear correlation needs >= n + R;
@@ -130,6 +135,38 @@ ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny
  * transforms + component sum, row transforms; matching as correlation with the angle
  * search in the last kernel. */
 ecc_status ecc_set_stage_events(ecc_context ctx, void* const* events, int n);
+
+/* ---------------------------------------------------------------- workspace */
+
+/* The calls whose device workspace ecc_workspace_size reports. The first two values are
+ * those of ecc_op (ecc_extended with that op). */
+typedef enum {
+  ECC_WS_EXTENDED_CORRELATION = 0, /* ecc_extended(ECC_CORRELATION, ...)                 */
+  ECC_WS_EXTENDED_CONVOLUTION = 1, /* ecc_extended(ECC_CONVOLUTION, ...)                 */
+  ECC_WS_SCALE_SMOOTH = 2,         /* ecc_scale_smooth (batch = 1)                       */
+  ECC_WS_MATCH_ROTATIONS = 3,      /* ecc_match_rotations (batch = 1)                    */
+  ECC_WS_BACKWARD_CONVOLUTION = 4, /* ecc_extended_backward(ECC_CONVOLUTION), no saved stack */
+  ECC_WS_BACKWARD_CORRELATION = 5  /* ecc_extended_backward(ECC_CORRELATION)             */
+} ecc_ws_call;
+
+/* Every context owns one device workspace, shared by its calls and grown on demand (a
+ * call that needs more than is allocated waits for the device, frees it and allocates
+ * the larger size). ecc_workspace_size reports, without enqueueing or allocating
+ * anything, the bytes that `call` (an ecc_ws_call; ECC_CORRELATION and ECC_CONVOLUTION
+ * mean ecc_extended with that op) needs for `batch` images of ny x nx with `plan` under
+ * the context's current strategy: 0 for the on-chip block paths of the correlation,
+ * convolution and smoothing; the component stack of matching; the two-pass stacks
+ * otherwise. (The adjoints also allocate a temporary image when grad_signal is NULL.)
+ * When the autotuner is enabled and has not run, this call runs it first (the choice of
+ * block shape depends on it). Errors: INVALID_ARGUMENT, HIP. */
+ecc_status ecc_workspace_size(ecc_context ctx, int call, ecc_filter_plan plan, int batch, int ny,
+                              int nx, size_t* bytes);
+/* Grows the context's workspace to at least `bytes` now (waiting for the device first if
+ * a smaller workspace exists), so that later calls needing at most that much allocate
+ * nothing. Errors: OUT_OF_MEMORY, HIP. */
+ecc_status ecc_workspace_reserve(ecc_context ctx, size_t bytes);
+/* Bytes of workspace the context currently holds. */
+ecc_status ecc_workspace_allocated(ecc_context ctx, size_t* bytes);
 
 /* ---------------------------------------------------------------- filter plans */
 
@@ -229,7 +266,11 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
                                  int ny, int nx, const float* signal, const float* field,
                                  const float* grad_out, float* grad_signal, float* grad_comps,
                                  float* grad_field, void* saved, void* stream);
-/* Bytes of the stack saved by the forward pass for ecc_extended_backward. */
+/* Bytes of the stack saved by the forward pass for ecc_extended_backward: 0 when the
+ * backward would not read one, i.e. when its filter gradient runs on chip (a block shape
+ * exists for the radius under the context's strategy; then the backward recomputes what
+ * it needs per block and a saving forward would only cost time and memory). Otherwise
+ * batch * (K+1) * ny * P_x complex64 values (P_x = ecc_fft_size(nx, R)). */
 ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int batch, int ny,
                                    int nx, size_t* bytes);
 /* Forward extended convolution that also writes the per-component row spectra of the
@@ -271,8 +312,9 @@ typedef struct {
 ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,
                                  ecc_batch_plan* out);
 /* Replaces the instances' pointers and strides (same count, ops, plans and sizes as at
- * creation; checked). Synchronous: returns after the new descriptors are on the device;
- * must not overlap a running ecc_batch_execute of the same plan. */
+ * creation; checked). Synchronous: waits for the last ecc_batch_execute of this plan to
+ * finish (on whatever stream it was enqueued), then returns after the new descriptors
+ * are on the device. */
 ecc_status ecc_batch_update(ecc_batch_plan bp, const ecc_instance* inst, int n);
 /* Runs the whole batch on `stream`: one graph launch for the tiled instances, then the
  * remaining instances one call each. */

@@ -13,7 +13,9 @@ from typing import Optional
 from . import _lib
 from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, GROUP_ROTATION,
                    GROUP_SCALE, PREC_FP32, PREC_MFMA_BF16_HILO, PREC_MFMA_FP16_HILO, STRATEGY_AUTO,
-                   STRATEGY_TILED, STRATEGY_TWO_PASS, EccError, GroupParams, Instance)
+                   STRATEGY_TILED, STRATEGY_TWO_PASS, WS_BACKWARD_CONVOLUTION,
+                   WS_BACKWARD_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_EXTENDED_CORRELATION,
+                   WS_MATCH_ROTATIONS, WS_SCALE_SMOOTH, EccError, GroupParams, Instance)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
@@ -23,6 +25,8 @@ __all__ = [
     "PREC_MFMA_FP16_HILO", "PREC_MFMA_BF16_HILO",
     "BATCH_PERSISTENT",
     "GroupParams",
+    "WS_EXTENDED_CORRELATION", "WS_EXTENDED_CONVOLUTION", "WS_SCALE_SMOOTH", "WS_MATCH_ROTATIONS",
+    "WS_BACKWARD_CONVOLUTION", "WS_BACKWARD_CORRELATION",
 ]
 
 _LIB = None
@@ -37,7 +41,7 @@ def lib():
 
 def _check(status):
     if status != _lib.ECC_OK:
-        raise EccError(status, lib().ecc_last_error().decode())
+        raise EccError(status, lib().ecc_last_error(None).decode())
 
 
 def _stream(stream=None):
@@ -95,6 +99,20 @@ class Context:
 
     def set_strategy(self, strategy: int):
         _check(lib().ecc_set_strategy(self.h, strategy))
+
+    def workspace_size(self, call: int, plan: "FilterPlan", ny: int, nx: int, batch: int = 1) -> int:
+        """Bytes of context workspace that `call` (an ecc_ws_call value, WS_*) needs."""
+        n = C.c_size_t()
+        _check(lib().ecc_workspace_size(self.h, call, plan.h, batch, ny, nx, C.byref(n)))
+        return n.value
+
+    def workspace_reserve(self, nbytes: int):
+        _check(lib().ecc_workspace_reserve(self.h, nbytes))
+
+    def workspace_allocated(self) -> int:
+        n = C.c_size_t()
+        _check(lib().ecc_workspace_allocated(self.h, C.byref(n)))
+        return n.value
 
     def describe(self, op: int, plan: "FilterPlan", ny: int, nx: int):
         """(strategy, transform length, block side) that ecc_extended would use."""
@@ -257,8 +275,9 @@ def _ext_conv_function():
     class ExtConv(torch.autograd.Function):
         """y = extended convolution of `signal` with components `comps` ((K+1, S, S)
         complex64) steered by the angle field `theta`; backward uses the hand-written
-        adjoint. checkpoint=True recomputes the modulated-signal stack in backward
-        instead of keeping it."""
+        adjoint. The modulated-signal stack is kept from the forward pass only when the
+        backward reads it (ecc_backward_saved_size > 0: the two-pass filter gradient) and
+        checkpoint is False; checkpoint=True always recomputes it in backward."""
 
         @staticmethod
         def forward(ctx_, signal, theta, comps, ectx, checkpoint=False):
@@ -266,11 +285,12 @@ def _ext_conv_function():
             sig = signal.detach().contiguous()
             th = theta.detach().contiguous()
             batch = sig.shape[0] if sig.dim() == 3 else 1
-            if checkpoint:
+            nbytes = 0 if checkpoint else ecc_backward_saved_size(ectx, plan, batch, sig.shape[-2],
+                                                                  sig.shape[-1])
+            if nbytes == 0:
                 y = ecc_extended(ectx, CONVOLUTION, plan, sig, th)
                 saved = None
             else:
-                nbytes = ecc_backward_saved_size(ectx, plan, batch, sig.shape[-2], sig.shape[-1])
                 saved = torch.empty(nbytes // 4, dtype=torch.float32, device=sig.device)
                 y = ecc_extended_save(ectx, plan, sig, th, saved)
             ctx_.plan, ctx_.ectx, ctx_.saved_stack = plan, ectx, saved

@@ -14,6 +14,9 @@ GROUP_ROTATION, GROUP_SCALE = 0, 1
 CORRELATION, CONVOLUTION = 0, 1
 PREC_FP32, PREC_MFMA_FP16_HILO, PREC_MFMA_BF16_HILO = 0, 1, 2
 STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED = 0, 1, 2
+# ecc_ws_call: the calls whose workspace ecc_workspace_size reports
+(WS_EXTENDED_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_SCALE_SMOOTH, WS_MATCH_ROTATIONS,
+ WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION) = range(6)
 
 
 class GroupParams(C.Structure):
@@ -81,10 +84,13 @@ PROTOS = {
     "ecc_extended_backward": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "ecc_backward_saved_size": [_P, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_extended_save": [_P, _P, _I, _I, _I, _P, _P, _P, _P, _P],
+    "ecc_workspace_size": [_P, _I, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
+    "ecc_workspace_reserve": [_P, C.c_size_t],
+    "ecc_workspace_allocated": [_P, C.POINTER(C.c_size_t)],
 }
 EXTRA = {
     "ecc_status_string": ([_I], C.c_char_p),
-    "ecc_last_error": ([], C.c_char_p),
+    "ecc_last_error": ([_P], C.c_char_p),
 }
 
 

@@ -46,17 +46,34 @@ namespace {
 // complex row pitch rounded up to 16 elements (128 bytes)
 inline int pitch16(int n) { return (n + 15) & ~15; }
 
-// Launch-shape overrides for tuning experiments (environment, read once per process).
-int tune_int(const char* name, int dflt) {
-  static std::mutex mu;
-  static std::map<std::string, int> cache;
-  std::lock_guard<std::mutex> g(mu);
-  auto it = cache.find(name);
-  if (it != cache.end()) return it->second;
-  const char* v = std::getenv(name);
-  const int r = (v && *v) ? std::atoi(v) : dflt;
-  cache[name] = r;
-  return r;
+// ---- bytes of context workspace each path uses; the call sites and ecc_workspace_size
+// both take them from here
+// two-pass correlation stack: row spectra ny x W', signal spectrum Py x W', and two
+// (direct, mirror) planes per component, W' = pitch16(Px / 2 + 1)
+size_t ws_corr_stack(int batch, int ny, int Py, int Px, int U) {
+  const size_t ldW = (size_t)pitch16(Px / 2 + 1);
+  return (size_t)batch * ((size_t)ny * ldW + (size_t)Py * ldW + 2 * (size_t)ny * ldW * U) * sizeof(cx<float>);
+}
+// two-pass convolution: modulated row spectra (unless saved by the caller) and the
+// column-summed plane, per signal
+size_t ws_conv_two_pass(int batch, int ny, int Px, int U, int nsig, bool saved) {
+  const size_t plane = (size_t)ny * Px;
+  return ((saved ? 0 : (size_t)batch * nsig * U * plane) + (size_t)batch * nsig * plane) * sizeof(cx<float>);
+}
+// tiled matching: the component stack, U planes of ny x nx
+size_t ws_match_tiled(int ny, int nx, int U) { return (size_t)ny * nx * U * sizeof(cx<float>); }
+// on-chip filter gradient: per-block lag sums (256-byte aligned) + the reduction's scratch
+size_t ws_gradf_parts(long long nblk, int U, int Sz) {
+  return ((size_t)nblk * U * Sz * Sz * sizeof(cx<float>) + 255) / 256 * 256;
+}
+// two-pass filter gradient: row and full spectra of the output gradient, the product
+// planes, the column-transformed lags, the lag windows and (unless saved) the stack
+size_t ws_gradf_two_pass(int batch, int ny, int Py, int Px, int U, int Sz, bool saved) {
+  const size_t W = (size_t)(Px / 2 + 1);
+  size_t n = (size_t)batch * ((size_t)ny * W + (size_t)Py * W) + (size_t)U * Py * Px + (size_t)U * Sz * Px +
+             (size_t)U * Sz * Sz;
+  if (!saved) n += (size_t)batch * U * ny * Px;
+  return n * sizeof(cx<float>);
 }
 
 ecc_status check_cfg_row(const RowCfg& c, const Transform& t, size_t elem, const char* what) {
@@ -256,7 +273,7 @@ const char* ecc_status_string(ecc_status s) {
   return "unknown status";
 }
 
-const char* ecc_last_error(void) { return g_err.c_str(); }
+const char* ecc_last_error(ecc_context) { return g_err.c_str(); }
 
 ecc_status ecc_create(int hip_device, ecc_context* out) {
   ECC_REQ(out != nullptr, "out is NULL");
@@ -282,6 +299,7 @@ ecc_status ecc_destroy(ecc_context ctx) {
   (void)hipDeviceSynchronize();
   for (ecc_filter_plan p : ctx->plans) delete p;   // plans still alive go with the context
   ctx->plans.clear();
+  if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
   delete ctx;
   return ECC_OK;
 }
@@ -520,7 +538,7 @@ ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, 
   const int ldW = pitch16(W);
   const long long pA = (long long)ny * ldW, pH = (long long)Py * ldW, pTk = 2LL * ny * ldW,
                   pTi = pTk * U;
-  const size_t need = ((size_t)batch * (pA + pH + pTi)) * sizeof(cx<float>);
+  const size_t need = ws_corr_stack(batch, ny, Py, Px, U);
   if (fwd) ECC_HIP(ctx->ws.ensure(need));
   else if (ctx->ws.n < need) return fail(ECC_ERR_INTERNAL, "component chunk larger than the first");
   cx<float>* A = ctx->ws.as<cx<float>>();
@@ -528,8 +546,7 @@ ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, 
   cx<float>* T = Hh + batch * pH;
   RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
   ColCfg c2 = col_config(*g.Ty, 2, sizeof(cx<float>), 512);
-  ColCfg c3 = col_config(*g.Ty, tune_int("ECC_CORR_LGB", 2), sizeof(cx<float>),
-                         tune_int("ECC_CORR_NTHR", 1024));
+  ColCfg c3 = col_config(*g.Ty, 2, sizeof(cx<float>), 1024);
   {
     // the component kernel supports NB <= 2 and at most 16 rows per thread
     const int TF = c3.nthr >> c3.lgB;
@@ -547,24 +564,12 @@ ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, 
   }
   const cx<float>* Fspec = g.sp->buf.as<cx<float>>() + (long long)kb * Py * g.sp->ld;
   const int nblk = (W + (1 << c3.lgB) - 1) >> c3.lgB;
-  int kchunk = tune_int("ECC_CORR_KCHUNK", 0);
-  if (kchunk <= 0) kchunk = std::max(1, (U * nblk * batch + 2047) / 2048);
-  kchunk = std::min(kchunk, U);
+  // components per workgroup: enough workgroups for about 2048 in flight
+  const int kchunk = std::min(U, std::max(1, (U * nblk * batch + 2047) / 2048));
   const float* par = plan->symmetric ? plan->d_parity.as<float>() + kb : nullptr;
-  if (g.Ty->fR0 > 0 && tune_int("ECC_FIXED_COLS", 0)) {
-    const int Bc = tune_int("ECC_FCOLS_B", 8);
-    const int nxb = (W + Bc - 1) / Bc;
-    int kc = tune_int("ECC_FCOLS_KCHUNK", 0);
-    if (kc <= 0) kc = std::max(1, (U * nxb * batch + 511) / 512);
-    kc = std::min(kc, U);
-    ECC_HIP(launch_corr_cols_fixed(st, Bc, batch, kc, Hh, pH, ldW, Fspec,
-                                   (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi,
-                                   ldW, ny, Px, W, U, conj_mode, Py, g.Ty->fx()));
-  } else {
-    ECC_HIP(launch_corr_cols(st, c3, batch, kchunk, Hh, pH, ldW, Fspec,
-                             (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi, ldW,
-                             ny, Px, W, U, conj_mode, g.Ty->desc, g.Ty->f()));
-  }
+  ECC_HIP(launch_corr_cols(st, c3, batch, kchunk, Hh, pH, ldW, Fspec,
+                           (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par, T, pTk, pTi, ldW,
+                           ny, Px, W, U, conj_mode, g.Ty->desc, g.Ty->f()));
   if (fwd) mark(ctx, 3, st);
   *T_out = T;
   *planeTk = pTk;
@@ -616,8 +621,8 @@ ecc_status corr_rows(ecc_filter_plan plan, const Geometry& g, int batch, const c
   if (kn < 0) kn = plan->U - kb;
   const int U = kn;
   const float* wts = plan->d_weights.as<float>() + kb;
-  if (g.Tx->fR0 > 0 && tune_int("ECC_FIXED", 1)) {
-    const int NR = tune_int("ECC_FROWS_NR", 4);
+  if (g.Tx->fR0 > 0) {
+    const int NR = 4;   // image rows per workgroup
     ECC_HIP(launch_corr_rows_fixed(st, NR, batch, T, pTk, pTi, pitch16(g.W), fl, y, planeY, ldY, g.ny, g.nx, U,
                                    wts, scl, y2, mulsig, planeMul, ldMul, 1.0f, kb, accum, g.Px,
                                    g.Tx->fx()));
@@ -716,31 +721,22 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
     mark(ctx, 1, st);
     return ECC_OK;
   }
+  WsUse wu(ctx, st);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   if (op == ECC_CORRELATION) {
-    // components in chunks: the stack of one chunk is written and read back while it
-    // is still resident in the last-level cache
     const int U = plan->U;
-    int nck = tune_int("ECC_KCHUNKS", 1);
-    nck = std::max(1, std::min(nck, U));
-    const int per = (U + nck - 1) / nck;
     Field fl = make_field(plan, field, pF, ld_field, 1.0);
-    for (int kb = 0, j = 0; kb < U; kb += per, ++j) {
-      const int kn = std::min(per, U - kb);
-      cx<float>* T;
-      long long pTk, pTi;
-      ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pS, ld_signal, 0, st, &T, &pTk, &pTi, kb, kn, j == 0));
-      ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, out, pO, ld_out,
-                        1.0f / ((float)g.Py * (float)g.Px), nullptr, nullptr, 0, 0, st, kb, kn, j > 0));
-    }
+    cx<float>* T;
+    long long pTk, pTi;
+    ECC_TRY(corr_stack(ctx, plan, g, batch, signal, pS, ld_signal, 0, st, &T, &pTk, &pTi, 0, U, true));
+    ECC_TRY(corr_rows(plan, g, batch, T, pTk, pTi, fl, out, pO, ld_out,
+                      1.0f / ((float)g.Py * (float)g.Px), nullptr, nullptr, 0, 0, st, 0, U, 0));
     mark(ctx, 4, st);
     return ECC_OK;
   }
   const long long pB = (long long)batch * plan->U * ny * g.Px;
-  const long long pC = (long long)batch * ny * g.Px;
-  const size_t need = (size_t)((saved ? 0 : pB) + pC) * sizeof(cx<float>);
-  ECC_HIP(ctx->ws.ensure(need));
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, plan->U, 1, saved != nullptr)));
   cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : ctx->ws.as<cx<float>>();
   cx<float>* C = saved ? ctx->ws.as<cx<float>>() : ctx->ws.as<cx<float>>() + pB;
   Field fl = make_field(plan, field, pF, ld_field, 1.0);
@@ -840,10 +836,11 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
     mark(ctx, 1, st);
     return ECC_OK;
   }
+  WsUse wu(ctx, st);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
-  const long long pB = 2LL * plan->U * ny * g.Px, pC = 2LL * ny * g.Px;
-  ECC_HIP(ctx->ws.ensure((size_t)(pB + pC) * sizeof(cx<float>)));
+  const long long pB = 2LL * plan->U * ny * g.Px;
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(1, ny, g.Px, plan->U, 2, false)));
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + pB;
   Field fl = make_field(plan, scale_, 0, ld_scale, 1.0);
@@ -867,6 +864,7 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
   if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
+  WsUse wu(ctx, st);
   const int R = plan->R, U = plan->U;
   TileChoice tc;
   bool tiled = false;
@@ -892,7 +890,7 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
       plan->match_tab_A = n_angles;
     }
     const long long npix = (long long)ny * nx;
-    ECC_HIP(ctx->ws.ensure((size_t)npix * U * sizeof(cx<float>)));
+    ECC_HIP(ctx->ws.ensure(ws_match_tiled(ny, nx, U)));
     mark(ctx, 0, st);
     ECC_HIP(launch_tile_stack(st, tc.N, tc.TV, signal, ld, ny, nx, R, tc.T, U, 1.0f / ((float)tc.N * (float)tc.N),
                               sp->buf.as<cx<float>>(), ctx->ws.as<float>(), sym));
@@ -946,6 +944,19 @@ ecc_status ecc_backward_saved_size(ecc_context ctx, ecc_filter_plan plan, int ba
                                    size_t* bytes) {
   ECC_REQ(ctx && plan && bytes, "NULL argument");
   ECC_TRY(validate_images(plan, batch, ny, nx));
+  // the stack is read only by the two-pass filter gradient; with the on-chip one the
+  // backward recomputes everything per block and nothing is worth saving
+  if (ctx->autotune) {
+    DeviceGuard dg(ctx->device);
+    ECC_TRY(calibrate_tiles(ctx, nullptr));
+  }
+  ecc_strategy vstrat = ECC_STRATEGY_TWO_PASS;
+  TileChoice vtc;
+  ECC_TRY(resolve_strategy(ctx, ECC_CONVOLUTION, plan, ny, nx, batch, &vstrat, &vtc));
+  if (vstrat == ECC_STRATEGY_TILED && tgradf_supported(vtc.N, vtc.TV)) {
+    *bytes = 0;
+    return ECC_OK;
+  }
   const int Px = fft_size_for(ctx, nx, plan->R);
   *bytes = (size_t)batch * plan->U * ny * Px * sizeof(cx<float>);
   return ECC_OK;
@@ -957,6 +968,9 @@ ecc_status ecc_extended_save(ecc_context ctx, ecc_filter_plan plan, int batch, i
   ECC_REQ(ctx && plan && signal && field && out && saved, "NULL argument");
   ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
   ECC_TRY(validate_images(plan, batch, ny, nx));
+  ECC_REQ(!overlaps(out, (size_t)batch * ny * nx * sizeof(float), signal, (size_t)batch * ny * nx * sizeof(float)) &&
+              !overlaps(out, (size_t)batch * ny * nx * sizeof(float), field, (size_t)batch * ny * nx * sizeof(float)),
+          "out aliases an input");
   DeviceGuard dg(ctx->device);
   return forward_impl(ctx, ECC_CONVOLUTION, plan, batch, ny, nx, signal, nx, field, nx, out, nx,
                       S(stream), saved);
@@ -974,6 +988,7 @@ static ecc_status corr_backward(ecc_context ctx, ecc_filter_plan plan, int batch
                                 const float* signal, const float* field, const float* grad_out,
                                 float* grad_signal, float* grad_comps, float* grad_field, void* stream) {
   hipStream_t st = S(stream);
+  WsUse wu(ctx, st);
   const long long pI = (long long)ny * nx;
   if (grad_field) {
     DevBuf tmp;
@@ -1030,6 +1045,7 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
                          stream);
   }
   hipStream_t st = S(stream);
+  WsUse wu(ctx, st);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   const int Py = g.Py, Px = g.Px, W = g.W, U = plan->U, Sz = plan->S, R = plan->R;
@@ -1092,7 +1108,7 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     ga.U = U;
     const long long nblk = (long long)((ny + vtc.T - 1) / vtc.T) * ((nx + vtc.T - 1) / vtc.T) * batch;
     ECC_REQ(nblk <= 0x7fffffffLL, "too many blocks");
-    const size_t pbytes = ((size_t)nblk * U * Sz * Sz * sizeof(cx<float>) + 255) / 256 * 256;
+    const size_t pbytes = ws_gradf_parts(nblk, U, Sz);
     ECC_HIP(ctx->ws.ensure(pbytes + gradf_reduce_scratch(U, Sz)));
     ga.part = ctx->ws.as<cx<float>>();
     ECC_HIP(launch_tile_gradf(st, vtc.N, vtc.TV, batch, ga));
@@ -1104,9 +1120,7 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     const long long pBk = (long long)ny * Px, pBi = pBk * U;
     const long long pA = (long long)ny * W, pG = (long long)Py * W;
     const long long pD = (long long)Py * Px;
-    size_t need = (size_t)(batch * (pA + pG) + U * pD + (long long)U * Sz * Px + (long long)U * Sz * Sz) * sizeof(cx<float>);
-    if (!saved) need += (size_t)batch * pBi * sizeof(cx<float>);
-    ECC_HIP(ctx->ws.ensure(need));
+    ECC_HIP(ctx->ws.ensure(ws_gradf_two_pass(batch, ny, Py, Px, U, Sz, saved != nullptr)));
     cx<float>* A = ctx->ws.as<cx<float>>();
     cx<float>* Gh = A + batch * pA;
     cx<float>* D = Gh + batch * pG;
@@ -1138,6 +1152,112 @@ ecc_status ecc_extended_backward(ecc_context ctx, ecc_op op, ecc_filter_plan pla
     ECC_HIP(launch_grad_filter_finish(st, win, (long long)Sz * Sz, Sz, plan->d_weights.as<float>(), scl,
                                       reinterpret_cast<cx<float>*>(grad_comps), Sz, U));
   }
+  return ECC_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// Workspace sizing: the same strategy choice and size formulas as the calls themselves.
+namespace {
+
+ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int batch, int ny, int nx,
+                          size_t* bytes) {
+  const int R = plan->R, U = plan->U, Sz = plan->S;
+  const int Py = fft_size_for(ctx, ny, R), Px = fft_size_for(ctx, nx, R);
+  auto strat = [&](ecc_op op, int b, TileChoice& tc, bool* tiled) -> ecc_status {
+    ecc_strategy used = ECC_STRATEGY_TWO_PASS;
+    ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, b, &used, &tc));
+    *tiled = used == ECC_STRATEGY_TILED;
+    return ECC_OK;
+  };
+  // the signal/field part of the convolution adjoint, and the field part of the
+  // correlation adjoint: an on-chip correlation with a second output, or the stack
+  auto corr_y2 = [&](size_t* n) -> ecc_status {
+    TileChoice tc;
+    bool tiled = false;
+    ECC_TRY(strat(ECC_CORRELATION, batch, tc, &tiled));
+    *n = (tiled && tile_has_y2(tc.N, tc.TV)) ? 0 : ws_corr_stack(batch, ny, Py, Px, U);
+    return ECC_OK;
+  };
+  auto gradf = [&](size_t* n) -> ecc_status {
+    TileChoice tc;
+    bool tiled = false;
+    ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+    if (tiled && tgradf_supported(tc.N, tc.TV)) {
+      const long long nblk = (long long)((ny + tc.T - 1) / tc.T) * ((nx + tc.T - 1) / tc.T) * batch;
+      *n = ws_gradf_parts(nblk, U, Sz) + gradf_reduce_scratch(U, Sz);
+    } else {
+      *n = ws_gradf_two_pass(batch, ny, Py, Px, U, Sz, false);
+    }
+    return ECC_OK;
+  };
+  TileChoice tc;
+  bool tiled = false;
+  size_t a = 0, b = 0, c = 0;
+  switch (call) {
+    case ECC_WS_EXTENDED_CORRELATION:
+      ECC_TRY(strat(ECC_CORRELATION, batch, tc, &tiled));
+      *bytes = tiled ? 0 : ws_corr_stack(batch, ny, Py, Px, U);
+      return ECC_OK;
+    case ECC_WS_EXTENDED_CONVOLUTION:
+      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+      *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 1, false);
+      return ECC_OK;
+    case ECC_WS_SCALE_SMOOTH:
+      ECC_REQ(plan->group == ECC_GROUP_SCALE, "scale smoothing needs a scale plan");
+      ECC_REQ(batch == 1, "scale smoothing takes one image");
+      ECC_TRY(strat(ECC_CONVOLUTION, 1, tc, &tiled));
+      *bytes = tiled ? 0 : ws_conv_two_pass(1, ny, Px, U, 2, false);
+      return ECC_OK;
+    case ECC_WS_MATCH_ROTATIONS:
+      ECC_REQ(batch == 1, "matching takes one image");
+      ECC_TRY(strat(ECC_CORRELATION, 1, tc, &tiled));
+      *bytes = tiled ? ws_match_tiled(ny, nx, U) : ws_corr_stack(1, ny, Py, Px, U);
+      return ECC_OK;
+    case ECC_WS_BACKWARD_CONVOLUTION:
+      ECC_TRY(corr_y2(&a));
+      ECC_TRY(gradf(&b));
+      *bytes = std::max(a, b);
+      return ECC_OK;
+    case ECC_WS_BACKWARD_CORRELATION:
+      ECC_TRY(corr_y2(&a));
+      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+      b = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 1, false);
+      ECC_TRY(gradf(&c));
+      *bytes = std::max(a, std::max(b, c));
+      return ECC_OK;
+  }
+  return fail(ECC_ERR_INVALID_ARGUMENT, "unknown call for ecc_workspace_size");
+}
+
+}  // namespace
+
+extern "C" {
+
+ecc_status ecc_workspace_size(ecc_context ctx, int call, ecc_filter_plan plan, int batch, int ny, int nx,
+                              size_t* bytes) {
+  ECC_REQ(ctx && plan && bytes, "NULL argument");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  if (call == ECC_WS_BACKWARD_CONVOLUTION || call == ECC_WS_BACKWARD_CORRELATION)
+    ECC_REQ(plan->group == ECC_GROUP_ROTATION, "the adjoint needs a rotation plan");
+  if (call == ECC_WS_MATCH_ROTATIONS) ECC_REQ(plan->group == ECC_GROUP_ROTATION, "matching needs a rotation plan");
+  DeviceGuard dg(ctx->device);
+  if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, nullptr));
+  return workspace_need(ctx, call, plan, batch, ny, nx, bytes);
+}
+
+ecc_status ecc_workspace_reserve(ecc_context ctx, size_t bytes) {
+  ECC_REQ(ctx, "NULL context");
+  DeviceGuard dg(ctx->device);
+  ECC_HIP(ctx->ws.ensure(bytes));
+  return ECC_OK;
+}
+
+ecc_status ecc_workspace_allocated(ecc_context ctx, size_t* bytes) {
+  ECC_REQ(ctx && bytes, "NULL argument");
+  *bytes = ctx->ws.n;
   return ECC_OK;
 }
 

@@ -48,6 +48,25 @@ struct DeviceGuard {
 
 inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
+// Scope of one call's use of the context workspace on stream `st`: if the previous user
+// ran on another stream, `st` first waits for its last kernel; on exit an event marks
+// this call's last kernel. Calls from one host thread on several streams therefore never
+// overwrite a workspace that queued work still reads.
+struct WsUse {
+  ecc_context ctx;
+  hipStream_t st;
+  WsUse(ecc_context c, hipStream_t s) : ctx(c), st(s) {
+    if (ctx->ws_event && ctx->ws_stream != st) (void)hipStreamWaitEvent(st, ctx->ws_event, 0);
+  }
+  ~WsUse() {
+    if (!ctx->ws_event && hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming) != hipSuccess)
+      ctx->ws_event = nullptr;
+    if (ctx->ws_event && hipEventRecord(ctx->ws_event, st) == hipSuccess) ctx->ws_stream = st;
+  }
+  WsUse(const WsUse&) = delete;
+  WsUse& operator=(const WsUse&) = delete;
+};
+
 constexpr size_t kMaxLds = 160 * 1024;
 
 // ---- tiled path

@@ -179,8 +179,10 @@ struct ecc_batch_plan_s {
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;         // recorded after every execution's last launch
   int nblocks = 0;
   ~ecc_batch_plan_s() {
+    if (done) (void)hipEventDestroy(done);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cs) (void)hipStreamDestroy(cs);
@@ -259,6 +261,7 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
   bp->flags = flags;
   bp->inst.assign(inst, inst + n);
   ECC_HIP(hipStreamCreateWithFlags(&bp->cs, hipStreamNonBlocking));
+  ECC_HIP(hipEventCreateWithFlags(&bp->done, hipEventDisableTiming));
   if (flags & ECC_BATCH_AUTOTUNE) ECC_TRY(calibrate_tiles(ctx, bp->cs));
 
   // ---- block shape per instance
@@ -369,6 +372,9 @@ ecc_status ecc_batch_update(ecc_batch_plan bp, const ecc_instance* inst, int n) 
     ECC_TRY(check_instance(bp->ctx, a));
   }
   DeviceGuard dg(bp->ctx->device);
+  // the descriptors are rewritten in place: wait for the last execution (on whatever
+  // stream it ran) and for the upload stream
+  ECC_HIP(hipEventSynchronize(bp->done));
   ECC_HIP(hipStreamSynchronize(bp->cs));
   bp->inst.assign(inst, inst + n);
   ECC_TRY(upload_descs(bp, bp->cs));
@@ -385,6 +391,7 @@ ecc_status ecc_batch_execute(ecc_batch_plan bp, void* stream) {
     ECC_TRY(forward_impl(bp->ctx, in.op, in.plan, 1, in.ny, in.nx, in.signal, in.ld_signal, in.field,
                          in.ld_field, in.out, in.ld_out, st, nullptr));
   }
+  ECC_HIP(hipEventRecord(bp->done, st));
   return ECC_OK;
 }
 

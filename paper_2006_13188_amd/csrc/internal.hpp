@@ -71,6 +71,8 @@ struct ecc_context_s {
   std::mutex mu;
   std::map<int, std::unique_ptr<ecc::Transform>> transforms;
   ecc::DevBuf ws;           // per-call workspace (grown on demand)
+  hipStream_t ws_stream = nullptr;   // stream of the last call that used ws
+  hipEvent_t ws_event = nullptr;     // recorded on it after that call's last kernel
   ecc::DevBuf angle_tab;    // cos/sin tables for matching
   int angle_tab_n = 0;
   int autotune = 0;

@@ -98,13 +98,8 @@ hipError_t launch_grad_filter_finish(hipStream_t s, const cx<float>* win, long l
                                      int ldWin, const float* w, float scale, cx<float>* out, int S,
                                      int U);
 
-// ---- correlation kernels for transform lengths with a compiled schedule P = R0 R1 R2
+// ---- correlation row kernel for transform lengths with a compiled schedule P = R0 R1 R2
 bool fixed_split(int P, int* R0, int* R1, int* R2);
-hipError_t launch_corr_cols_fixed(hipStream_t s, int Bc, int batch, int kchunk, const cx<float>* Hh,
-                                  long long planeHh, int ldHh, const cx<float>* Fh, long long planeFk,
-                                  int ldF, int fullplane, const float* parity, cx<float>* T,
-                                  long long planeTk, long long planeTimg, int ldT, int ny, int Px, int W,
-                                  int U, int conj_mode, int Py, const cx<float>* tw);
 hipError_t launch_corr_rows_fixed(hipStream_t s, int NR, int batch, const cx<float>* T, long long planeTk,
                                   long long planeTimg, int ldT, const Field& fld, float* y,
                                   long long planeY, int ldY, int ny, int nx, int U, const float* w,

@@ -179,23 +179,82 @@ def test_convolution_adjoint_parity(E, ctx, from_components):
     assert rel2(gc, rgc) <= TOL
 
 
-def test_saved_stack_matches_recompute(E, ctx):
+@pytest.mark.parametrize("case", ["two_pass_strategy", "radius_without_block"])
+def test_saved_stack_branch_matches_oracle(E, case):
+    """The backward branch that reads a saved stack: the filter gradient of the two-pass
+    form, reached with the two-pass strategy forced and, under the default strategy, with
+    a radius no block shape covers (R = 57 > 56). Saved and recomputed stacks both match
+    the float64 oracle gradient."""
     import torch
-    B, n, S, K = 2, 48, 9, 4
+    if case == "two_pass_strategy":
+        B, n, S, K = 2, 48, 9, 4
+    else:
+        B, n, S, K = 1, 120, 115, 3
     imgs = np.stack([blurred_noise((n, n), 90 + i) for i in range(B)])
     ths = np.stack([theta_field((n, n), 95 + i) for i in range(B)])
     g = np.random.default_rng(99).standard_normal((B, n, n)).astype(np.float32)
-    plan = E.FilterPlan.rotation(ctx, dev(random_filter(S, 98, 2.5)), K)
-    nbytes = E.ecc_backward_saved_size(ctx, plan, B, n, n)
-    saved = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    y1 = host(E.ecc_extended_save(ctx, plan, dev(imgs), dev(ths), saved))
-    y2 = host(E.ecc_extended(ctx, E.CONVOLUTION, plan, dev(imgs), dev(ths)))
-    # the saving forward runs the two-pass form; the default call may take the tiled one
-    assert np.max(np.abs(y1 - y2)) <= 1e-6 * np.max(np.abs(y2))
-    a = E.ecc_extended_backward(ctx, plan, dev(imgs), dev(ths), dev(g), saved=saved)
-    b = E.ecc_extended_backward(ctx, plan, dev(imgs), dev(ths), dev(g), saved=None)
-    for x, y in zip(a, b):
-        assert np.array_equal(host(x), host(y))
+    filt = random_filter(S, 98, 2.5 * S / 9)
+    c = E.Context(0)
+    try:
+        if case == "two_pass_strategy":
+            c.set_strategy(E.STRATEGY_TWO_PASS)
+        plan = E.FilterPlan.rotation(c, dev(filt), K)
+        nbytes = E.ecc_backward_saved_size(c, plan, B, n, n)
+        assert nbytes == B * (K + 1) * n * c.fft_size(n, (S - 1) // 2) * 8
+        saved = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        y1 = host(E.ecc_extended_save(c, plan, dev(imgs), dev(ths), saved)).astype(np.float64)
+        half = O.half_components(O.angular_components(filt, K)[0])
+        grads = [E.ecc_extended_backward(c, plan, dev(imgs), dev(ths), dev(g), saved=sv)
+                 for sv in (saved, None)]
+        grads = [tuple(host(x) for x in gr) for gr in grads]
+        plan.close()
+    finally:
+        c.close()
+    rgc = np.zeros_like(half)
+    for b in range(B):
+        ref_y = O.ext_conv_half(imgs[b].astype(np.float64), ths[b].astype(np.float64), half)
+        assert rel2(y1[b], ref_y) <= TOL
+        rh, rt, rc = O.conv_backward(imgs[b].astype(np.float64), ths[b].astype(np.float64), half,
+                                     g[b].astype(np.float64))
+        for gs, gc, gf in grads:
+            assert rel2(gs[b].astype(np.float64), rh) <= TOL
+            assert rel2(gf[b].astype(np.float64), rt) <= TOL
+        rgc += rc
+    for gs, gc, gf in grads:
+        assert rel2(gc.astype(np.complex128), rgc) <= TOL, rel2(gc.astype(np.complex128), rgc)
+
+
+@pytest.mark.parametrize("checkpoint", [False, True])
+def test_adjoint_full_size_through_autograd(E, ctx, checkpoint):
+    """The differentiation workload at its real shape: 16 images of 512^2, a shared 21x21
+    filter, K = 12, through the autograd function with a plan built from components (the
+    general, non-symmetric block forms of the forward convolution, the signal/field
+    correlation and the per-block filter lags). Every gradient against the float64
+    oracle's at rel-L2 <= 1e-5: signal and field on four images, the components summed
+    over all sixteen."""
+    import torch
+    from synthetic import adjoint_config
+    imgs, thetas, filt, gbar = adjoint_config()
+    B, K = imgs.shape[0], 12
+    half = O.half_components(O.angular_components(filt, K)[0]).astype(np.complex64)
+    H = dev(imgs).requires_grad_(True)
+    T = dev(thetas).requires_grad_(True)
+    Cc = torch.from_numpy(half).cuda().requires_grad_(True)
+    y = E.ExtConv.apply(H, T, Cc, ctx, checkpoint)
+    gi, gt, gc = torch.autograd.grad(y, (H, T, Cc), dev(gbar))
+    y, gi, gt, gc = host(y), host(gi), host(gt), host(gc).astype(np.complex128)
+    half64 = half.astype(np.complex128)
+    rgc = np.zeros_like(half64)
+    for b in range(B):
+        img, th, gb = (a[b].astype(np.float64) for a in (imgs, thetas, gbar))
+        rh, rt, rc = O.conv_backward(img, th, half64, gb)
+        rgc += rc
+        if b in (0, 5, 10, 15):
+            ref_y = O.ext_conv_half(img, th, half64)
+            assert rel2(y[b].astype(np.float64), ref_y) <= TOL
+            assert rel2(gi[b].astype(np.float64), rh) <= TOL, (b, rel2(gi[b].astype(np.float64), rh))
+            assert rel2(gt[b].astype(np.float64), rt) <= TOL, (b, rel2(gt[b].astype(np.float64), rt))
+    assert rel2(gc, rgc) <= TOL, rel2(gc, rgc)
 
 
 def test_autograd_function(E, ctx):

@@ -232,11 +232,13 @@ def test_tiled_symmetric_and_general_pair_forms(E):
         ctx.close()
 
 
-def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
-    """The signal and field parts of the convolution adjoint run as a tiled correlation
-    with a second output (symmetric pair form at N = 96 for a rotation plan) and the
-    filter part as per-block lag sums; all three agree with the two-pass adjoint, itself
-    checked against the float64 oracle on small images."""
+@pytest.mark.parametrize("source", ["rotation_plan", "from_components"])
+def test_adjoint_at_n96_blocks_both_strategies(E, source):
+    """The convolution adjoint where the block strategy runs N = 96 transforms (radius
+    15): the signal and field parts as a tiled correlation with a second output (the
+    symmetric pair form for a rotation plan, the general form for a plan built from
+    components) and the filter part as per-block lag sums, and the two-pass adjoint on
+    the same input; every gradient against the float64 oracle."""
     import torch
     cts = [E.Context(0), E.Context(0)]
     cts[0].set_strategy(TILED)
@@ -244,28 +246,35 @@ def test_adjoint_signal_and_field_parts_tiled_vs_two_pass(E):
     try:
         S, K = 31, 6
         filt = random_filter(S, 41, 4.0 * S / 15)
-        plans = [E.FilterPlan.rotation(c, dev(filt), K) for c in cts]
+        half = O.half_components(O.angular_components(filt, K)[0])
+        if source == "rotation_plan":
+            plans = [E.FilterPlan.rotation(c, dev(filt), K) for c in cts]
+        else:
+            half = half.astype(np.complex64).astype(np.complex128)
+            plans = [E.FilterPlan.from_components(c, torch.from_numpy(half.astype(np.complex64)).cuda())
+                     for c in cts]
         shapes = [sh for sh in ((520, 491), (700, 653), (1024, 1000))
                   if cts[0].describe(0, plans[0], *sh)[1] == 96]
         assert shapes, "no candidate shape runs N = 96 blocks"
         shape = shapes[0]
-        img = blurred_noise(shape, 42)[None]
-        th = theta_field(shape, 43)[None]
-        g = np.random.default_rng(44).standard_normal((1,) + shape).astype(np.float32)
+        img = blurred_noise(shape, 42)
+        th = theta_field(shape, 43)
+        g = np.random.default_rng(44).standard_normal(shape).astype(np.float32)
         outs = []
         for c, p in zip(cts, plans):
-            gs, gc, gf = E.ecc_extended_backward(c, p, dev(img), dev(th), dev(g))
-            outs.append((host(gs).astype(np.float64), host(gf).astype(np.float64),
+            gs, gc, gf = E.ecc_extended_backward(c, p, dev(img[None]), dev(th[None]), dev(g[None]))
+            outs.append((host(gs)[0].astype(np.float64), host(gf)[0].astype(np.float64),
                          host(gc).astype(np.complex128)))
-        for a, b in zip(outs[0][:2], outs[1][:2]):
-            assert rel2(a, b) <= TOL and relinf(a, b) <= 2 * TOL, (rel2(a, b), relinf(a, b))
-        # the filter part: per-block lags summed on chip against the two-pass column form
-        assert rel2(outs[0][2], outs[1][2]) <= TOL, rel2(outs[0][2], outs[1][2])
         for p in plans:
             p.close()
     finally:
         for c in cts:
             c.close()
+    rh, rt, rc = O.conv_backward(img.astype(np.float64), th.astype(np.float64), half, g.astype(np.float64))
+    for gs, gf, gc in outs:
+        assert rel2(gs, rh) <= TOL and relinf(gs, rh) <= 2 * TOL, (rel2(gs, rh), relinf(gs, rh))
+        assert rel2(gf, rt) <= TOL and relinf(gf, rt) <= 2 * TOL, (rel2(gf, rt), relinf(gf, rt))
+        assert rel2(gc, rc) <= TOL, rel2(gc, rc)
 
 
 @pytest.mark.parametrize("K", [0, 1, 2])

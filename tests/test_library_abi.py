@@ -19,7 +19,8 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for s in ("ecc_create", "ecc_destroy", "ecc_filter_plan_create", "ecc_extended",
-              "ecc_match_rotations", "ecc_scale_smooth", "ecc_extended_backward"):
+              "ecc_match_rotations", "ecc_scale_smooth", "ecc_extended_backward",
+              "ecc_workspace_size", "ecc_last_error"):
         assert s in syms
 
 
@@ -39,4 +40,4 @@ def test_status_strings_without_device():
     lib = _lib.load()
     assert lib.ecc_status_string(0) == b"ok"
     assert lib.ecc_status_string(1) == b"invalid argument"
-    assert lib.ecc_last_error() == b""
+    assert lib.ecc_last_error(None) == b""
