@@ -41,7 +41,7 @@ def dev(a):
 def host(t):
     import torch
     torch.cuda.synchronize()
-    return t.cpu().numpy()
+    return t.detach().cpu().numpy()
 
 
 # ---------------------------------------------------------------- matching
