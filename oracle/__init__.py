@@ -12,7 +12,8 @@ Everything here follows "Efficient Spatially Adaptive Convolution and Correlatio
   * the rotation algorithm: Sec. 4.1 (filter decomposition, standard correlations,
     linear combination, and the pre-multiplied convolution);
   * band-limiting: Sec. 4.3;
-  * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal.
+  * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal;
+  * normalised filtering with a rotation field (line-integral convolution): Sec. 8.
 
 Readings where the paper is silent are listed per function (boundary = zero outside
 the image, bilinear polar resampling at the exact grid radii, k = -K..K, etc.).
@@ -30,6 +31,7 @@ from .extended import (
     ext_conv_half, ext_corr_half, match_rotations, min_fft_size, fft_workers,
 )
 from .adjoint import conv_backward, corr_backward
+from .normalized import normalized_conv_brute, normalized_conv_fft, normalized_conv_half
 from .scale import (
     ScaleParams, scale_components, scale_filter_at, scale_smooth_brute,
     scale_smooth_fft,
@@ -41,6 +43,7 @@ __all__ = [
     "ext_corr_brute", "ext_conv_brute", "ext_corr_fft", "ext_conv_fft",
     "ext_conv_half", "ext_corr_half", "match_rotations", "min_fft_size", "fft_workers",
     "conv_backward", "corr_backward",
+    "normalized_conv_brute", "normalized_conv_fft", "normalized_conv_half",
     "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
     "scale_smooth_fft",
 ]

@@ -9,6 +9,9 @@ consumes); the oracle upcasts the same float32 values to float64, so both sides
 see bit-identical inputs.
 
 Recipes (the paper has no datasets for this path; these stand in for its images):
+  * line-integral convolution: white U[0,1] noise, a long narrow anisotropic Gaussian
+            (elongated along x), and the angle of a vortex vector field plus a smooth
+            seeded perturbation (stands in for the paper's vector-field figure)
   * image:  U[0,1] noise blurred by a Gaussian (sigma 2, reflect, truncate 4)
   * filter: N(0,1) entries times a Gaussian window
   * theta:  orientation atan2(d/drow, d/dcol) of an independent noise field
@@ -23,7 +26,7 @@ from scipy import ndimage
 __all__ = [
     "blurred_noise", "random_filter", "theta_field", "scale_field", "block_image",
     "rotation_config", "matching_scene", "scale_config", "batch_shapes",
-    "batch_instance", "adjoint_config",
+    "batch_instance", "adjoint_config", "anisotropic_gaussian", "vortex_field", "lic_config",
 ]
 
 
@@ -161,3 +164,30 @@ def adjoint_config(batch=16, n=512, S=21, seed_theta=40, seed_filter=41, seed_gr
     filt = random_filter(S, seed_filter, 4.0 * S / 15.0)
     g = np.random.default_rng(seed_grad).standard_normal((batch, n, n)).astype(np.float32)
     return imgs, thetas, filt, g
+
+
+def anisotropic_gaussian(S, sigma_along, sigma_across):
+    """exp(-(x^2 / 2 sa^2 + y^2 / 2 sc^2)) on the S x S grid, x = column offset (the long
+    axis), y = row offset; peak 1 at the centre."""
+    R = (S - 1) // 2
+    yy, xx = np.mgrid[-R:R + 1, -R:R + 1].astype(np.float64)
+    g = np.exp(-(xx * xx) / (2.0 * sigma_along ** 2) - (yy * yy) / (2.0 * sigma_across ** 2))
+    return g.astype(np.float32)
+
+
+def vortex_field(shape, seed, wobble=0.6, sigma=24.0):
+    """Angle (radians, mod 2 pi) of a circular flow around the image centre, perturbed by
+    `wobble` times blurred zero-mean noise (unit standard deviation before scaling)."""
+    ny, nx = shape
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    base = np.arctan2(yy - (ny - 1) / 2.0, xx - (nx - 1) / 2.0) + np.pi / 2.0
+    n = ndimage.gaussian_filter(np.random.default_rng(seed).standard_normal(shape), sigma,
+                                mode="reflect", truncate=4.0)
+    n = n / max(float(np.std(n)), 1e-300)
+    return np.mod(base + wobble * n, 2.0 * np.pi).astype(np.float32)
+
+
+def lic_config(n=1024, S=31, seeds=(50, 51), sigma_along=8.0, sigma_across=1.5):
+    """White noise image, anisotropic Gaussian filter and vortex angle field."""
+    img = np.random.default_rng(seeds[0]).random((n, n)).astype(np.float32)
+    return img, anisotropic_gaussian(S, sigma_along, sigma_across), vortex_field((n, n), seeds[1])
