@@ -240,6 +240,27 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
                                const float* signal, int ld, int n_angles, float* best_score,
                                int* best_index, int ld_out, ecc_precision prec, void* stream);
 
+/* Variant of ecc_match_rotations for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, same results, and it calls no hipMalloc, hipFree or allocating routine.
+ * The component stack goes through a fixed 64 MiB device array of the library (one per
+ * GPU, held until the process ends) instead of the context workspace, one band of block
+ * rows at a time: for each band the stack kernel writes the band's K+1 planes and the
+ * angle search reads them back. Every call on one GPU shares that array, whatever the
+ * context: calls that overlap on one GPU (two host threads, or two streams without an
+ * ordering between them) race and give wrong results. Nothing in the array needs to
+ * start at zero (every band is fully written before it is read).
+ * Preconditions (else ECC_ERR_UNSUPPORTED, nothing enqueued): a block shape exists for
+ * the filter radius under the context's strategy; the plan's block spectra and angle
+ * table for this image size and n_angles exist, i.e. ecc_match_rotations has run once
+ * with the same plan, size and n_angles; if the autotuner is on, it has calibrated.
+ * One block row of the stack, (K+1) * T * nx complex64 values (T = the block side, 64
+ * for the 63 x 63 pattern), must fit in 64 MiB, else ECC_ERR_INVALID_ARGUMENT. */
+ecc_status ecc_match_rotations_noalloc(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
+                                       const float* signal, int ld, int n_angles, float* best_score,
+                                       int* best_index, int ld_out, ecc_precision prec,
+                                       void* stream);
+
 /* ---------------------------------------------------------------- adjoint */
 
 /* Gradients of the rotation-plan extended convolution y = Re sum_k w_k (H e^{-ik theta}) * F_k

@@ -19,6 +19,7 @@ from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, G
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
+    "ecc_match_rotations_noalloc",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
     "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
@@ -227,6 +228,22 @@ def ecc_match_rotations(ctx: Context, plan: FilterPlan, signal, n_angles=64, pre
     index = torch.empty((ny, nx), dtype=torch.int32, device=signal.device)
     _check(lib().ecc_match_rotations(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), n_angles,
                                      _ptr(score), _ptr(index), nx, precision, _stream(stream)))
+    return score, index
+
+
+def ecc_match_rotations_noalloc(ctx: Context, plan: FilterPlan, signal, score, index, n_angles=64,
+                                precision=PREC_FP32, stream=None):
+    """ecc_match_rotations into the caller's score (float32) and index (int32) tensors,
+    with the library allocating nothing (the plan must have run ecc_match_rotations with
+    the same size and n_angles once)."""
+    import torch
+    _img(signal, "signal")
+    ny, nx = signal.shape
+    if score.shape != (ny, nx) or index.shape != (ny, nx) or score.dtype != torch.float32 \
+            or index.dtype != torch.int32 or not score.is_contiguous() or not index.is_contiguous():
+        raise ValueError("score / index must be contiguous float32 / int32 tensors of the signal's shape")
+    _check(lib().ecc_match_rotations_noalloc(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), n_angles,
+                                             _ptr(score), _ptr(index), nx, precision, _stream(stream)))
     return score, index
 
 

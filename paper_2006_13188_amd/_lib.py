@@ -81,6 +81,7 @@ PROTOS = {
     "ecc_extended": [_P, _I, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_scale_smooth": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_match_rotations": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
+    "ecc_match_rotations_noalloc": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
     "ecc_extended_backward": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "ecc_backward_saved_size": [_P, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_extended_save": [_P, _P, _I, _I, _I, _P, _P, _P, _P, _P],

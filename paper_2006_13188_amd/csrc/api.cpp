@@ -150,6 +150,12 @@ bool rotation_parity(ecc_filter_plan plan) {
   return true;
 }
 
+const Spectrum* find_tile_spectrum(ecc_filter_plan plan, int N, int mode) {
+  std::lock_guard<std::mutex> g(plan->mu);
+  auto it = plan->tile_spectra.find(mode * 1000 + N);
+  return it == plan->tile_spectra.end() ? nullptr : it->second.get();
+}
+
 ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode) {
   std::lock_guard<std::mutex> g(plan->mu);
   const bool conv = mode == SPEC_CONV;

@@ -93,6 +93,9 @@ bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, in
 // modes are those of conj(F_k) (the adjoint correlates with F_k itself).
 enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2, SPEC_CORR_CONJ = 3, SPEC_CENTRED_CONJ = 4 };
 ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode = SPEC_CORR);
+// The cached block spectra of get_tile_spectrum, or NULL if they have not been built
+// (builds nothing and allocates nothing).
+const Spectrum* find_tile_spectrum(ecc_filter_plan plan, int N, int mode);
 // rotation plans: F_k(-x) = (-1)^k F_k(x), components k = 0 .. U - 1
 bool rotation_parity(ecc_filter_plan plan);
 // Per-pixel angle description of a plan's field argument.

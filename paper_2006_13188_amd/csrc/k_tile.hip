@@ -328,14 +328,15 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
     if constexpr (STACK) {
       // the T x T block of G_c, with consecutive lanes along rows
       __syncthreads();
-      float* dst = a.stack + 2 * (long long)c * a.ny * a.nx;
+      float* dst = a.stack + 2 * (long long)c * a.stack_plane;
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
         const int e = t + NT * k, row = e / TV, col = e % TV;
         const int gy = y0 + row, gx = x0 + col;
         if (e < TV * TV && row < T && col < T && gy < a.ny && gx < a.nx) {
           const cx<float> v = Bb[row * P + col];
-          *reinterpret_cast<float2*>(dst + 2 * ((long long)gy * a.nx + gx)) = make_float2(v.re * a.scale, v.im * a.scale);
+          *reinterpret_cast<float2*>(dst + 2 * ((long long)(gy - a.stack_y0) * a.nx + gx)) =
+              make_float2(v.re * a.scale, v.im * a.scale);
         }
       }
       lds_barrier();   // the image is rewritten next; the stores are not waited for
@@ -670,14 +671,14 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
       for (int cc = 0; cc < 2; ++cc) {
         if (cc == 0 || two) {
           const cx<float>* Ar = cc ? A1 : A0;
-          float* dst = a.stack + 2 * (long long)(c + cc) * a.ny * a.nx;
+          float* dst = a.stack + 2 * (long long)(c + cc) * a.stack_plane;
 #pragma unroll
           for (int i = 0; i < FPT; ++i) {
             const int e = t + 2 * kTileThreads * i, row = e / TV, col = e % TV;
             const int gy = y0 + row, gx = x0 + col;
             if (row < T && col < T && gy < a.ny && gx < a.nx) {
               const cx<float> v = Ar[row * P + col];
-              *reinterpret_cast<float2*>(dst + 2 * ((long long)gy * a.nx + gx)) =
+              *reinterpret_cast<float2*>(dst + 2 * ((long long)(gy - a.stack_y0) * a.nx + gx)) =
                   make_float2(v.re * a.scale, v.im * a.scale);
             }
           }
@@ -747,13 +748,13 @@ template <int N, int TV, bool SEPB, bool SYM = false>
 __global__ void __launch_bounds__((tile_nt<N, 1>())) k_tile_stack_one(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  corr_block_one<N, TV, SEPB, true, tile_nt<N, 1>(), SYM>(a, 0, lb, lds_t);
+  corr_block_one<N, TV, SEPB, true, tile_nt<N, 1>(), SYM>(a, 0, a.tile0 + lb, lds_t);
 }
 template <int N, bool SYM = false>
 __global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a) {
   extern __shared__ cx<float> lds_t[];
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  corr_block_pair<N, true, SYM>(a, 0, lb, lds_t);
+  corr_block_pair<N, true, SYM>(a, 0, a.tile0 + lb, lds_t);
 }
 
 // Batches of independent instances (every instance one image); item = (descriptor
@@ -976,8 +977,12 @@ bool tile_has_y2(int N, int TV) {
 }
 
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym) {
+                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym, int by0,
+                             int by1) {
   if (T < 1 || T > TV || T > N - 2 * R) return hipErrorInvalidValue;
+  const int nby = (ny + T - 1) / T;
+  if (by1 < 0) by1 = nby;
+  if (by0 < 0 || by1 > nby || by0 >= by1) return hipErrorInvalidValue;
   if (sym && !tile_symmetric(N, TV)) return hipErrorInvalidValue;
   TileArgs a{};
   a.H = H;
@@ -992,7 +997,10 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
   a.scale = scale;
   a.Fs = Fs;
   a.stack = stack;
-  const long long nblk = (long long)a.tx * a.ty;
+  a.stack_y0 = by0 * T;
+  a.stack_plane = (long long)((ny < by1 * T ? ny : by1 * T) - a.stack_y0) * nx;
+  a.tile0 = by0 * a.tx;
+  const long long nblk = (long long)a.tx * (by1 - by0);
 #define ECC_TSK(n, tv, sb, hv) \
   if (N == n && TV == tv) return launch_stack_kernel<n, tv, sb, hv>(s, (unsigned)nblk, a, sym);
   ECC_TILE_CONFIGS(ECC_TSK)

@@ -121,7 +121,10 @@ struct TileArgs {          // one correlation job (batch of images of one shape)
   const float* w;
   float scale;
   const cx<float>* Fs;     // U block spectra of N x N
-  float* stack;            // component stacks (matching): U planes of ny nx (re, im), or NULL
+  float* stack;            // component stacks (matching): U planes (re, im), or NULL
+  long long stack_plane;   // pixels per stack plane (rows [stack_y0, ...) of nx pixels)
+  int stack_y0;            // first image row held by the stack
+  int tile0;               // stack kernels: block index of the launch's first workgroup
   // second output (adjoint w.r.t. the field): y2 = scale * mulsig * sum_c w_c (kofs + c)
   // Im(e^{i (kofs + c) alpha} G_c), or NULL
   float* y2;
@@ -136,9 +139,12 @@ bool tile_supported(int N, int TV);
 bool tile_symmetric(int N, int TV);
 size_t tile_lds_bytes(int N, int TV);
 int tile_threads(int N, int TV);
-// component stack of one image: stack[2 (c ny nx + y nx + x) .. +1] = G_c(y, x) * scale
+// component stack of the block rows [by0, by1) of one image (by1 < 0: to the last):
+// with y0 = by0 T and rows = min(ny, by1 T) - y0,
+// stack[2 (c rows nx + (y - y0) nx + x) .. +1] = G_c(y, x) * scale for y0 <= y < y0 + rows
 hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int ldH, int ny, int nx, int R,
-                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym = false);
+                             int T, int U, float scale, const cx<float>* Fs, float* stack, bool sym = false,
+                             int by0 = 0, int by1 = -1);
 // angle search over a component stack: score = max_m sum_c Re(e^{2 pi i c m / A} w_c G_c),
 // index = first maximising m; prec 0 = float32 FMA, 1 = float16 hi/lo MFMA, 2 = bfloat16
 // hi/lo MFMA. dtab: float32 [64][64] (angle m, stack entry k) = w_{k/2} cos / -w_{k/2} sin.
