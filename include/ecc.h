@@ -146,7 +146,8 @@ typedef enum {
   ECC_WS_SCALE_SMOOTH = 2,         /* ecc_scale_smooth (batch = 1)                       */
   ECC_WS_MATCH_ROTATIONS = 3,      /* ecc_match_rotations (batch = 1)                    */
   ECC_WS_BACKWARD_CONVOLUTION = 4, /* ecc_extended_backward(ECC_CONVOLUTION), no saved stack */
-  ECC_WS_BACKWARD_CORRELATION = 5  /* ecc_extended_backward(ECC_CORRELATION)             */
+  ECC_WS_BACKWARD_CORRELATION = 5, /* ecc_extended_backward(ECC_CORRELATION)             */
+  ECC_WS_NORMALIZED_CONVOLUTION = 6 /* ecc_normalized_convolution                        */
 } ecc_ws_call;
 
 /* Every context owns one device workspace, shared by its calls and grown on demand (a
@@ -154,9 +155,9 @@ typedef enum {
  * the larger size). ecc_workspace_size reports, without enqueueing or allocating
  * anything, the bytes that `call` (an ecc_ws_call; ECC_CORRELATION and ECC_CONVOLUTION
  * mean ecc_extended with that op) needs for `batch` images of ny x nx with `plan` under
- * the context's current strategy: 0 for the on-chip block paths of the correlation,
- * convolution and smoothing; the component stack of matching; the two-pass stacks
- * otherwise. (The adjoints also allocate a temporary image when grad_signal is NULL.)
+ * the context's current strategy: 0 for the on-chip block paths of the correlation and
+ * convolution; the overlap-add regions of the normalised convolution and the scale
+ * smoothing; the component stack of matching; the two-pass stacks otherwise. (The adjoints also allocate a temporary image when grad_signal is NULL.)
  * When the autotuner is enabled and has not run, this call runs it first (the choice of
  * block shape depends on it). Errors: INVALID_ARGUMENT, HIP. */
 ecc_status ecc_workspace_size(ecc_context ctx, int call, ecc_filter_plan plan, int batch, int ny,
@@ -216,11 +217,38 @@ ecc_status ecc_extended(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
 
 /* Scale-adaptive smoothing (Sec. 8, eq. normalization with the normalised signal):
  * out = {H / s^2, s} * F divided by {1 / s^2, s} * F, for a scale plan.
- * signal, scale, out: device float32 ny x nx with the given row strides. */
+ * signal, scale, out: device float32 ny x nx with the given row strides. The same call as
+ * ecc_normalized_convolution with batch = 1 (see there for the strategies and workspace). */
 ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
                             const float* signal, int ld_signal, const float* scale,
                             int ld_scale, float* out, int ld_out, ecc_precision prec,
                             void* stream);
+
+/* Normalised adaptive filtering (Sec. 8, eq. normalization): the extended convolution of
+ * the signal divided, pixel by pixel, by the extended convolution of the constant signal
+ * 1 (1 inside the image, 0 outside) with the same field, so that every output is the
+ * weighted average of the contributions it receives. Rotation plans: the signal is used
+ * as it is (rotations keep the filter's integral); with a long, narrow anisotropic filter
+ * and the angle of a vector field on a noise image this is line-integral convolution.
+ * Scale plans: the signal is first divided by s(q)^2 and the constant signal is 1/s^2
+ * (the normalised signal of Sec. 8), which is ecc_scale_smooth.
+ * signal, field, out: device float32, batch x ny x nx with row strides ld_* and image
+ * stride ny * ld_*; out must not alias an input. Where the denominator is zero the
+ * output is not finite. Block strategy (TILED / AUTO with a block shape): where the block
+ * convolution would use 128-point transforms (filter radii above about 16), for plans
+ * whose components have parity (every plan made by ecc_filter_plan_create), one
+ * overlap-add launch transforms the (at most) 64 x 64 sources of each block for both
+ * signals at once and writes its 128 x 128 region of (numerator, denominator) to the
+ * context workspace; a second kernel adds the overlapping regions in a fixed order and
+ * divides. Otherwise two launches of the block convolution (numerator, then the
+ * denominator divided into it). Two-pass: both signals' transforms in one set of
+ * kernels. Workspace: ecc_workspace_size with ECC_WS_NORMALIZED_CONVOLUTION. Only
+ * ECC_PREC_FP32 is implemented. Errors as for
+ * ecc_extended. */
+ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny,
+                                      int nx, const float* signal, int ld_signal, const float* field,
+                                      int ld_field, float* out, int ld_out, ecc_precision prec,
+                                      void* stream);
 
 /* Rotation-independent matching (Sec. 5 in band-limited form): the correlation
  * response at n_angles equispaced angles 2 pi m / n_angles,

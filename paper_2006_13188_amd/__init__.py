@@ -15,10 +15,12 @@ from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, G
                    GROUP_SCALE, PREC_FP32, PREC_MFMA_BF16_HILO, PREC_MFMA_FP16_HILO, STRATEGY_AUTO,
                    STRATEGY_TILED, STRATEGY_TWO_PASS, WS_BACKWARD_CONVOLUTION,
                    WS_BACKWARD_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_EXTENDED_CORRELATION,
-                   WS_MATCH_ROTATIONS, WS_SCALE_SMOOTH, EccError, GroupParams, Instance)
+                   WS_MATCH_ROTATIONS, WS_NORMALIZED_CONVOLUTION, WS_SCALE_SMOOTH, EccError,
+                   GroupParams, Instance)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
+    "ecc_normalized_convolution", "WS_NORMALIZED_CONVOLUTION",
     "ecc_match_rotations_noalloc",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
@@ -202,6 +204,27 @@ def ecc_extended(ctx: Context, op: int, plan: FilterPlan, signal, field, out=Non
     _check(lib().ecc_extended(ctx.h, op, plan.h, batch, ny, nx, _ptr(signal), _ld(signal),
                               _ptr(field), _ld(field), _ptr(out), _ld(out), PREC_FP32,
                               _stream(stream)))
+    return out
+
+
+def ecc_normalized_convolution(ctx: Context, plan: FilterPlan, signal, field, out=None, stream=None):
+    """Extended convolution of the signal over that of the constant 1 (rotation plans:
+    line-integral convolution with an anisotropic filter; scale plans: the smoothing of
+    ecc_scale_smooth). signal, field: (ny, nx) or (batch, ny, nx) float32 device tensors."""
+    import torch
+    _img(signal, "signal")
+    _img(field, "field")
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    _img(out, "out")
+    ny, nx = signal.shape[-2], signal.shape[-1]
+    batch = signal.shape[0] if signal.dim() == 3 else 1
+    for t in (signal, field, out):
+        if t.dim() == 3 and t.stride(0) != t.shape[-2] * t.stride(-2):
+            raise ValueError("batched images must be stacked with image stride ny * ld")
+    _check(lib().ecc_normalized_convolution(ctx.h, plan.h, batch, ny, nx, _ptr(signal), _ld(signal),
+                                            _ptr(field), _ld(field), _ptr(out), _ld(out), PREC_FP32,
+                                            _stream(stream)))
     return out
 
 

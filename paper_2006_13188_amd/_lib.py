@@ -16,7 +16,7 @@ PREC_FP32, PREC_MFMA_FP16_HILO, PREC_MFMA_BF16_HILO = 0, 1, 2
 STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED = 0, 1, 2
 # ecc_ws_call: the calls whose workspace ecc_workspace_size reports
 (WS_EXTENDED_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_SCALE_SMOOTH, WS_MATCH_ROTATIONS,
- WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION) = range(6)
+ WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION, WS_NORMALIZED_CONVOLUTION) = range(7)
 
 
 class GroupParams(C.Structure):
@@ -80,6 +80,7 @@ PROTOS = {
     "ecc_filter_plan_destroy": [_P],
     "ecc_extended": [_P, _I, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_scale_smooth": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
+    "ecc_normalized_convolution": [_P, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_match_rotations": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
     "ecc_match_rotations_noalloc": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
     "ecc_extended_backward": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P],

@@ -173,7 +173,10 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
   const int U = plan->U, Sz = plan->S;
   // correlation: F_k with its window corner at (0, 0), planes of N x N; convolution:
   // offset x at x - R, planes of tconv_plane(N) values with row pitch N + 1
-  const bool centred = mode == SPEC_CENTRED || mode == SPEC_CENTRED_CONJ;
+  const bool ratio = mode == SPEC_RATIO;
+  if (ratio && (!plan->symmetric || (int)plan->parity.size() != U))
+    return fail(ECC_ERR_INTERNAL, "ratio spectra need components with parity");
+  const bool centred = mode == SPEC_CENTRED || mode == SPEC_CENTRED_CONJ || ratio;
   const bool cconj = mode == SPEC_CORR_CONJ || mode == SPEC_CENTRED_CONJ;
   const int shift = conv ? -2 * plan->R : centred ? -plan->R : 0;
   sp->ld = conv ? tconv_pitch(N) : N;
@@ -198,7 +201,11 @@ ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const 
                                    Tn->desc, Tn->d())));
   ECC_HIP((launch_fft_cols<double>(st, cc, U, -1, tmp.as<cx<double>>(), (long long)Sz * N, N, N, Sz, shift,
                                    spec64.as<cx<double>>(), plane, sp->ld, N, 0, Tn->desc, Tn->d())));
-  ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * plane));
+  if (ratio)
+    ECC_HIP(launch_ratio_spectra(st, spec64.as<cx<double>>(), U, N, plan->d_weights.as<float>(),
+                                 plan->d_parity.as<float>(), sp->buf.as<float2>()));
+  else
+    ECC_HIP(launch_d2f(st, spec64.as<cx<double>>(), sp->buf.as<cx<float>>(), (long long)U * plane));
   ECC_HIP(hipStreamSynchronize(st));
   *out = sp.get();
   plan->tile_spectra[key] = std::move(sp);
@@ -800,34 +807,75 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
                             int ld_signal, const float* scale_, int ld_scale, float* out, int ld_out,
                             ecc_precision prec, void* stream) {
   ECC_REQ(ctx && plan, "NULL context or plan");
-  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
   ECC_REQ(plan->group == ECC_GROUP_SCALE, "ecc_scale_smooth needs a scale plan");
-  ECC_REQ(signal && scale_ && out, "NULL image pointer");
+  return ecc_normalized_convolution(ctx, plan, 1, ny, nx, signal, ld_signal, scale_, ld_scale, out, ld_out, prec,
+                                    stream);
+}
+
+ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                                      const float* signal, int ld_signal, const float* field, int ld_field,
+                                      float* out, int ld_out, ecc_precision prec, void* stream) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_REQ(signal && field && out, "NULL image pointer");
   if (prec != ECC_PREC_FP32) return fail(ECC_ERR_UNSUPPORTED, "precision not implemented");
-  ECC_TRY(validate_images(plan, 1, ny, nx));
-  ECC_REQ(ld_signal >= nx && ld_scale >= nx && ld_out >= nx, "row strides must be >= nx");
-  const size_t bo = (size_t)ny * ld_out * sizeof(float);
-  ECC_REQ(!overlaps(out, bo, signal, (size_t)ny * ld_signal * sizeof(float)) &&
-              !overlaps(out, bo, scale_, (size_t)ny * ld_scale * sizeof(float)),
+  ECC_TRY(validate_images(plan, batch, ny, nx));
+  ECC_REQ(ld_signal >= nx && ld_field >= nx && ld_out >= nx, "row strides must be >= nx");
+  const size_t bo = (size_t)batch * ny * ld_out * sizeof(float);
+  ECC_REQ(!overlaps(out, bo, signal, (size_t)batch * ny * ld_signal * sizeof(float)) &&
+              !overlaps(out, bo, field, (size_t)batch * ny * ld_field * sizeof(float)),
           "out aliases an input");
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
+  const long long pS = (long long)ny * ld_signal, pF = (long long)ny * ld_field, pO = (long long)ny * ld_out;
+  // the scale group divides the signal by |T(q)|^2 = s(q)^2 (eq. normalization with the
+  // normalised signal); rotations keep the filter's integral and leave it as it is
+  const int sig_norm = plan->sig_norm;
+  if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
+  ecc_strategy strat;
   TileChoice tc;
-  bool tiled = false;
-  if (ctx->strategy != ECC_STRATEGY_TWO_PASS)
-    tiled = pick_tile_conv(ctx, plan->R, plan->U, ny, nx, 1, ctx->strategy == ECC_STRATEGY_AUTO ? 2 * plan->R : 16, tc);
-  if (ctx->strategy == ECC_STRATEGY_TILED && !tiled)
-    return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
-  if (tiled) {
+  ECC_TRY(resolve_strategy(ctx, ECC_CONVOLUTION, plan, ny, nx, batch, &strat, &tc));
+  TileChoice rc;
+  if (strat == ECC_STRATEGY_TILED && tc.N == 128 && pick_tile_ratio(plan, rc)) {
+    // overlap-add blocks: both signals in one launch, regions added by a second kernel
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, rc.N, st, &sp, SPEC_RATIO));
+    WsUse wu(ctx, st);
+    ECC_HIP(ctx->ws.ensure(tratio_scratch_bytes(rc.N, rc.T, batch, ny, nx)));
+    TileRatioArgs ra{};
+    ra.H = signal;
+    ra.planeH = pS;
+    ra.ldH = ld_signal;
+    ra.fld = make_field(plan, field, pF, ld_field, 1.0);
+    ra.sig_norm = sig_norm;
+    ra.y = out;
+    ra.planeY = pO;
+    ra.ldY = ld_out;
+    ra.ny = ny;
+    ra.nx = nx;
+    ra.R = plan->R;
+    ra.T = rc.T;
+    ra.U = plan->U;
+    ra.Fs = sp->buf.as<float2>();
+    ra.par = plan->d_parity.as<float>();
+    ra.part = ctx->ws.as<cx<float>>();
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_ratio(st, rc.N, rc.TV, batch, ra));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
+  if (strat == ECC_STRATEGY_TILED) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
     TileConvArgs ca{};
     ca.H = signal;
+    ca.planeH = pS;
     ca.ldH = ld_signal;
-    ca.fld = make_field(plan, scale_, 0, ld_scale, 1.0);
-    ca.sig_norm = 1;
+    ca.fld = make_field(plan, field, pF, ld_field, 1.0);
+    ca.sig_norm = sig_norm;
     ca.nsig = 2;
     ca.y = out;
+    ca.planeY = pO;
     ca.ldY = ld_out;
     ca.ny = ny;
     ca.nx = nx;
@@ -838,20 +886,20 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
     ca.scale = 1.0f;
     ca.Fs = sp->buf.as<cx<float>>();
     mark(ctx, 0, st);
-    ECC_HIP(launch_tile_conv(st, tc.N, tc.TV, 1, ca));
+    ECC_HIP(launch_tile_conv(st, tc.N, tc.TV, batch, ca));
     mark(ctx, 1, st);
     return ECC_OK;
   }
   WsUse wu(ctx, st);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
-  const long long pB = 2LL * plan->U * ny * g.Px;
-  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(1, ny, g.Px, plan->U, 2, false)));
+  const long long pB = (long long)batch * 2 * plan->U * ny * g.Px;
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, plan->U, 2, false)));
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + pB;
-  Field fl = make_field(plan, scale_, 0, ld_scale, 1.0);
-  ECC_TRY(conv_stack_rows(ctx, plan, g, 1, signal, 0, ld_signal, fl, 1, 2, Bk, st));
-  ECC_TRY(conv_finish(ctx, plan, g, 1, Bk, 2, C, out, 0, ld_out, st));
+  Field fl = make_field(plan, field, pF, ld_field, 1.0);
+  ECC_TRY(conv_stack_rows(ctx, plan, g, batch, signal, pS, ld_signal, fl, sig_norm, 2, Bk, st));
+  ECC_TRY(conv_finish(ctx, plan, g, batch, Bk, 2, C, out, pO, ld_out, st));
   return ECC_OK;
 }
 
@@ -1211,11 +1259,18 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 1, false);
       return ECC_OK;
     case ECC_WS_SCALE_SMOOTH:
-      ECC_REQ(plan->group == ECC_GROUP_SCALE, "scale smoothing needs a scale plan");
-      ECC_REQ(batch == 1, "scale smoothing takes one image");
-      ECC_TRY(strat(ECC_CONVOLUTION, 1, tc, &tiled));
-      *bytes = tiled ? 0 : ws_conv_two_pass(1, ny, Px, U, 2, false);
+    case ECC_WS_NORMALIZED_CONVOLUTION: {
+      if (call == ECC_WS_SCALE_SMOOTH) {
+        ECC_REQ(plan->group == ECC_GROUP_SCALE, "scale smoothing needs a scale plan");
+        ECC_REQ(batch == 1, "scale smoothing takes one image");
+      }
+      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+      TileChoice rc;
+      if (tiled && tc.N == 128 && pick_tile_ratio(plan, rc))
+        *bytes = tratio_scratch_bytes(rc.N, rc.T, batch, ny, nx);
+      else *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 2, false);
       return ECC_OK;
+    }
     case ECC_WS_MATCH_ROTATIONS:
       ECC_REQ(batch == 1, "matching takes one image");
       ECC_TRY(strat(ECC_CORRELATION, 1, tc, &tiled));

@@ -87,11 +87,17 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
 ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
 // Same choice for the tiled convolution (static operation count).
 bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best);
+// Block shape of the overlap-add ratio kernel for the plan's filter radius R (plans with
+// component parity only): among the compiled shapes, the smallest transform work per
+// output pixel, N^2 log2 N / T^2 with T = min(TV, N - 2R) >= 16. The normalised
+// convolution takes it where the block convolution would use N = 128.
+bool pick_tile_ratio(ecc_filter_plan plan, TileChoice& best);
 // Block spectra of a plan for transform length N (cached in the plan): for correlation
 // (F_k with its window corner at (0, 0)), convolution (offset x at (x - R) mod N, padded
 // planes) or the symmetric correlation form (centred: offset x at x mod N); the _CONJ
 // modes are those of conj(F_k) (the adjoint correlates with F_k itself).
-enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2, SPEC_CORR_CONJ = 3, SPEC_CENTRED_CONJ = 4 };
+// SPEC_RATIO: the float2 planes of the overlap-add ratio kernel (launch_ratio_spectra).
+enum { SPEC_CORR = 0, SPEC_CONV = 1, SPEC_CENTRED = 2, SPEC_CORR_CONJ = 3, SPEC_CENTRED_CONJ = 4, SPEC_RATIO = 5 };
 ecc_status get_tile_spectrum(ecc_filter_plan plan, int N, hipStream_t st, const Spectrum** out, int mode = SPEC_CORR);
 // The cached block spectra of get_tile_spectrum, or NULL if they have not been built
 // (builds nothing and allocates nothing).

@@ -100,6 +100,26 @@ bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, in
   return found;
 }
 
+bool pick_tile_ratio(ecc_filter_plan plan, TileChoice& best) {
+  if (!plan->symmetric || (int)plan->parity.size() != plan->U) return false;
+  bool found = false;
+  for (const auto& c : kShapes) {
+    const int N = c[0], TV = c[1];
+    if (!tratio_supported(N, TV)) continue;
+    const int T = std::min(TV, N - 2 * plan->R);
+    if (T < 16) continue;
+    const double cost = (double)N * N * std::log2((double)N) / ((double)T * T);
+    if (!found || cost < best.cost) {
+      best.N = N;
+      best.TV = TV;
+      best.T = T;
+      best.cost = cost;
+      found = true;
+    }
+  }
+  return found;
+}
+
 ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st) {
   if (ctx->tile_calibrated) return ECC_OK;
   DeviceGuard dg(ctx->device);

@@ -211,6 +211,32 @@ hipError_t launch_tile_gradf(hipStream_t s, int N, int TV, int batch, const Tile
 size_t gradf_reduce_scratch(int U, int S);
 hipError_t launch_gradf_reduce(hipStream_t s, const cx<float>* part, int nblk, int U, int S, const float* w,
                                float scale, cx<float>* out, void* scratch);
+// ---- normalised convolution by overlap-add blocks: num + i den of two signals sharing
+// the field in one launch (sources T x T per block, regions of N x N, N >= T + 2R, added
+// in a fixed order by a second kernel that also divides)
+struct TileRatioArgs {
+  const float* H;
+  long long planeH;
+  int ldH;
+  Field fld;               // phase e^{-i c alpha}
+  int sig_norm;            // 1: s1 = H / f^2, s2 = 1 / f^2; 0: s1 = H, s2 = 1
+  float* y;
+  long long planeY;
+  int ldY;
+  int ny, nx, R, T, tx, ty, U;   // tx, ty set by the launcher
+  const float2* Fs;        // U planes of N x N (w_c rho_a, w_c rho_b), [column freq][row freq]
+  const float* par;        // parity p_c of each component (+1: real spectra, -1: imaginary)
+  cx<float>* part;         // partial sums: blocks x N x N (tratio_scratch_bytes)
+};
+bool tratio_supported(int N, int TV);
+size_t tratio_scratch_bytes(int N, int T, int batch, int ny, int nx);
+hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a);
+// spectra of the overlap-add ratio kernel from the centred float64 spectra of the
+// components (U planes of N x N, [row freq][column freq]): per component the real parts of
+// the spectra of Re F_c and Im F_c (parity +1) or their imaginary parts (parity -1), times
+// w_c, as float2 planes [column freq][row freq]
+hipError_t launch_ratio_spectra(hipStream_t s, const cx<double>* spec, int U, int N, const float* w,
+                                const float* par, float2* out);
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);
 hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);

@@ -124,17 +124,25 @@ def test_reported_size_is_what_the_call_uses(E, what, strategy, shape_s_k, reser
     assert rel2(y.astype(np.float64), ref) <= TOL
 
 
-@pytest.mark.parametrize("strategy", ["tiled", "two_pass"])
+@pytest.mark.parametrize("strategy", ["auto", "tiled", "two_pass"])
 def test_scale_smoothing_workspace(E, strategy):
     shape = (150, 170)
     img = blurred_noise(shape, 320)
     s = scale_field(shape, 321)
     c = E.Context(0)
     try:
-        c.set_strategy(E.STRATEGY_TILED if strategy == "tiled" else E.STRATEGY_TWO_PASS)
+        c.set_strategy({"auto": E.STRATEGY_AUTO, "tiled": E.STRATEGY_TILED, "two_pass": E.STRATEGY_TWO_PASS}[strategy])
         plan = E.FilterPlan.scale(c)
         need = c.workspace_size(E.WS_SCALE_SMOOTH, plan, *shape)
-        assert (need == 0) == (strategy == "tiled")
+        assert need == c.workspace_size(E.WS_NORMALIZED_CONVOLUTION, plan, *shape)
+        if strategy == "auto":
+            # radius 32: 128-point blocks, the overlap-add ratio kernel: 3 x 3 blocks of
+            # 64 x 64 sources, a 128 x 128 complex64 region each
+            assert need == 9 * 128 * 128 * 8
+        elif strategy == "tiled":
+            # any block side >= 16 allowed: 96-point blocks of 32 x 32 (two launches, no
+            # workspace) cost less for so small an image
+            assert need == 0
         y = host(E.ecc_scale_smooth(c, plan, dev(img), dev(s)))
         assert c.workspace_allocated() == need
         plan.close()
