@@ -53,6 +53,12 @@ __device__ __forceinline__ void dft8_pruned(cx<float>* x) {
 
 template <int N>
 __shared__ cx<float> ratio_img_lds[N * (N + 1)];
+// the sources' signal values, [pixel of the item][thread], and the phase step of each
+// thread's first source pixel (kept out of the registers)
+template <int NT, int NV>
+__shared__ float ratio_h_lds[NV * NT];
+template <int NT>
+__shared__ cx<float> ratio_e1_lds[NT];
 
 template <int N, int TV, int NT>
 __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int tile, int blk, cx<float>* A) {
@@ -75,7 +81,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
   // ---- sources of this thread's column pass-0 items: h = H (0 outside), z = wn e^{i c alpha}
   // for the current component c (from c = 0), advanced by e1 = e^{i alpha}
   const float* Hb = a.H + (long long)img * a.planeH;
-  float hs[NQ0][RMAX];
+  float* hs = ratio_h_lds<NT, NQ0 * RMAX>;   // hs[(s RMAX + r) NT + t]
   cx<float> z[NQ0][RMAX], e1[NQ0][RMAX];
 #pragma unroll
   for (int s = 0; s < NQ0; ++s) {
@@ -85,7 +91,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
     for (int r = 0; r < RMAX; ++r) {
       const int i = b + M * r;
       const int gy = y0 + i, gx = x0 + v;
-      hs[s][r] = 0.f;
+      float hv = 0.f;
       z[s][r] = mk(0.f, 0.f);
       e1[s][r] = mk(0.f, 0.f);
       if (b < M && v < T && i < T && gy < a.ny && gx < a.nx) {
@@ -100,9 +106,11 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
           sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
         }
         e1[s][r] = mk(cs, sn);
+        if (s == 0 && r == 0) ratio_e1_lds<NT>[t] = e1[0][0];   // read back only by this thread
         z[s][r] = mk(a.sig_norm ? 1.f / (fv * fv) : 1.f, 0.f);
-        hs[s][r] = Hb[(long long)gy * a.ldH + gx];
+        hv = Hb[(long long)gy * a.ldH + gx];
       }
+      hs[(s * RMAX + r) * NT + t] = hv;   // read back only by this thread
     }
   }
   cx<float> Z[NI][M];
@@ -120,6 +128,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
     const bool odd = a.par[c] < 0.f;   // spectra imaginary
 #pragma unroll 1
     for (int part = 0; part < 2; ++part) {   // P (cosine, with a_c), then Q (sine, with b_c)
+
       // ---- column pass 0 (radix 8, inputs below T only), straight from the sources
 #pragma unroll
       for (int s = 0; s < NQ0; ++s) {
@@ -131,7 +140,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
           for (int r = 0; r < 8; ++r) {
             if (r < RMAX) {
               const float f = part ? z[s][r].im : z[s][r].re;
-              x[r] = mk(hs[s][r] * f, f);
+              x[r] = mk(hs[(s * RMAX + r) * NT + t] * f, f);
             } else {
               x[r] = mk(0.f, 0.f);
             }
@@ -145,30 +154,36 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
       // ---- column pass 1 over the T source columns
       pass1_inplace<N, -1, false, NIT, NT>(A, tw, bq, l, T, N);
       __syncthreads();
-      // ---- row pass 0 (radix 8, columns below T only)
+      // ---- row pass 0 (radix 8, columns below T only), in NG groups of rows: a group's
+      // outputs overwrite only its own rows, so the next group's inputs can be read right
+      // after them, and only one group's values are held at a time
       {
-        cx<float> xv[NQR][8];
+        constexpr int NG = NQR % 2 == 0 ? 2 : 1, RG = N / NG, NQG = (RG * M + NT - 1) / NT;
 #pragma unroll
-        for (int s = 0; s < NQR; ++s) {
-          const int q = t + s * NT;
-          const int row = q % N, b = q / N;
-          if (b < M) {
+        for (int g = 0; g < NG; ++g) {
+          cx<float> xv[NQG][8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-              const int col = b + M * r;
-              xv[s][r] = (r < RMAX && col < T) ? A[row * P + col] : mk(0.f, 0.f);
+          for (int s = 0; s < NQG; ++s) {
+            const int q = t + s * NT;
+            const int row = g * RG + q % RG, b = q / RG;
+            if (b < M) {
+#pragma unroll
+              for (int r = 0; r < 8; ++r) {
+                const int col = b + M * r;
+                xv[s][r] = (r < RMAX && col < T) ? A[row * P + col] : mk(0.f, 0.f);
+              }
             }
           }
-        }
-        __syncthreads();
+          __syncthreads();
 #pragma unroll
-        for (int s = 0; s < NQR; ++s) {
-          const int q = t + s * NT;
-          const int row = q % N, b = q / N;
-          if (b < M) {
-            dft8_pruned<RMAX, -1>(xv[s]);
+          for (int s = 0; s < NQG; ++s) {
+            const int q = t + s * NT;
+            const int row = g * RG + q % RG, b = q / RG;
+            if (b < M) {
+              dft8_pruned<RMAX, -1>(xv[s]);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) A[row * P + 8 * b + r] = xv[s][r];
+              for (int r = 0; r < 8; ++r) A[row * P + 8 * b + r] = xv[s][r];
+            }
           }
         }
       }
@@ -186,10 +201,11 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
           dft<M, -1, float>(x);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
-            const float2 f = __builtin_bit_cast(
-                float2, __builtin_amdgcn_raw_buffer_load_b64(fsrc, u * (int)sizeof(float2),
-                                                             ((c * N + bq + 8 * r) * N) * (int)sizeof(float2), 0));
-            const float rho = part ? f.y : f.x;
+            // w_c rho_a (P) or w_c rho_b (Q): one word of the element's float2
+            const float rho = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(
+                           fsrc, u * (int)sizeof(float2),
+                           ((c * N + bq + 8 * r) * N) * (int)sizeof(float2) + part * (int)sizeof(float), 0));
             if (odd) {   // times i rho
               Z[i][r].re -= x[r].im * rho;
               Z[i][r].im += x[r].re * rho;
@@ -205,7 +221,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
 #pragma unroll
     for (int s = 0; s < NQ0; ++s)
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) z[s][r] = cmul(z[s][r], e1[s][r]);
+      for (int r = 0; r < RMAX; ++r) z[s][r] = cmul(z[s][r], (s == 0 && r == 0) ? ratio_e1_lds<NT>[t] : e1[s][r]);
   }
 
   // ---- inverse transform of the accumulated spectrum: num + i den on the whole window
@@ -243,7 +259,11 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
 }
 
 // 1024 threads: four waves per SIMD at 128 registers (with 512, 212 registers and two
-// waves per SIMD measured 1.09 against 0.83 ms for the 2048^2 smoothing)
+// waves per SIMD measured 1.09 against 0.83 ms for the 2048^2 smoothing). The registers
+// hold the accumulator (32), the phases of the thread's four sources (16) and one pass's
+// values; the sources' signal values and one phase step per thread sit in the LDS left
+// beside the image (16 + 8 KB), which took the spills inside the component loop from 25
+// registers to none (0.83 -> 0.69 ms).
 template <int N>
 constexpr int tratio_threads() {
   return 1024;
