@@ -13,7 +13,8 @@ Everything here follows "Efficient Spatially Adaptive Convolution and Correlatio
     linear combination, and the pre-multiplied convolution);
   * band-limiting: Sec. 4.3;
   * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal;
-  * normalised filtering with a rotation field (line-integral convolution): Sec. 8.
+  * normalised filtering with a rotation field (line-integral convolution): Sec. 8;
+  * pattern detection (gradient signal and field, consensus filter by voting, peaks): Sec. 5.
 
 Readings where the paper is silent are listed per function (boundary = zero outside
 the image, bilinear polar resampling at the exact grid radii, k = -K..K, etc.).
@@ -32,6 +33,7 @@ from .extended import (
 )
 from .adjoint import conv_backward, corr_backward
 from .normalized import normalized_conv_brute, normalized_conv_fft, normalized_conv_half
+from .detection import gradient_field, voting_filter, find_peaks, detection_response
 from .scale import (
     ScaleParams, scale_components, scale_filter_at, scale_smooth_brute,
     scale_smooth_fft,
@@ -44,6 +46,7 @@ __all__ = [
     "ext_conv_half", "ext_corr_half", "match_rotations", "min_fft_size", "fft_workers",
     "conv_backward", "corr_backward",
     "normalized_conv_brute", "normalized_conv_fft", "normalized_conv_half",
+    "gradient_field", "voting_filter", "find_peaks", "detection_response",
     "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
     "scale_smooth_fft",
 ]
