@@ -335,6 +335,60 @@ def adjoint_workload(E, ctx, timeit):
     return res
 
 
+def detection_workload(E, timeit):
+    """Pattern detection (Sec. 5) on the 1024^2 matching scene with its 63 x 63 pattern:
+    the consensus filter by voting and its plan (once per pattern), then per image the
+    gradient signal and field, the extended convolution (K = 16) and the peaks."""
+    import torch
+
+    from synthetic import matching_scene
+
+    img, pat, truth = matching_scene(1024, 63)
+    Hd, Pd = torch.from_numpy(img).cuda(), torch.from_numpy(pat).cuda()
+    c = E.Context(0)
+    res = {"workload": "pattern detection, 1024x1024 scene, 63x63 pattern, K=16, peaks radius 8"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = E.ecc_voting_filter(c, Pd)
+    plan = E.FilterPlan.rotation(c, F, 16)
+    torch.cuda.synchronize()
+    res["filter_and_plan_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    mag, ang = torch.empty_like(Hd), torch.empty_like(Hd)
+    D = torch.empty_like(Hd)
+    rows = torch.empty(16, dtype=torch.int32, device="cuda")
+    cols, cnt = torch.empty_like(rows), torch.empty(1, dtype=torch.int32, device="cuda")
+    vals = torch.empty(16, dtype=torch.float32, device="cuda")
+    lib = E.lib()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def grad():
+        E.ecc_gradient_field(c, Hd, mag, ang)
+
+    def conv():
+        E.ecc_extended(c, E.CONVOLUTION, plan, mag, ang, out=D)
+
+    def peaks():
+        lib.ecc_find_peaks(c.h, 1024, 1024, C.c_void_p(D.data_ptr()), 1024, 8, C.c_float(0.3), 1, 16,
+                           C.c_void_p(rows.data_ptr()), C.c_void_p(cols.data_ptr()), C.c_void_p(vals.data_ptr()),
+                           C.c_void_p(cnt.data_ptr()), st)
+
+    def whole():
+        grad()
+        conv()
+        peaks()
+
+    res["gradient_ms"] = round(timeit(grad), 4)
+    res["convolution_ms"] = round(timeit(conv), 4)
+    res["peaks_ms"] = round(timeit(peaks), 4)
+    res["per_image_ms"] = round(timeit(whole), 4)
+    n = int(cnt.item())
+    found = sorted(zip(rows[:3].cpu().tolist(), cols[:3].cpu().tolist())) if n >= 3 else []
+    res["top3_are_the_planted_centres"] = found == sorted((r, c_) for r, c_, _ in truth)
+    plan.close()
+    c.close()
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -443,7 +497,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of side workloads: two_pass,conv,matching,scale,lic,adjoint,batch")
+                    help="comma list of side workloads: two_pass,conv,matching,scale,lic,detection,adjoint,batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
@@ -495,7 +549,7 @@ def main():
 
     side = {}
     want = set() if args.no_extras else (
-        {"two_pass", "conv", "matching", "scale", "lic", "adjoint", "batch"} if args.extras == "all"
+        {"two_pass", "conv", "matching", "scale", "lic", "detection", "adjoint", "batch"} if args.extras == "all"
         else set(args.extras.split(",")))
     if "two_pass" in want:
         # the paper's two-pass form on the same workload
@@ -526,6 +580,8 @@ def main():
         side["scale_smoothing_2048"] = scale_workload(E, timeit)
     if "lic" in want:
         side["lic_1024"] = lic_workload(E, timeit)
+    if "detection" in want:
+        side["detection_1024"] = detection_workload(E, timeit)
     if "adjoint" in want:
         side["adjoint_16x512"] = adjoint_workload(E, ctx, timeit)
     if "batch" in want:

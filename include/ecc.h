@@ -289,6 +289,46 @@ ecc_status ecc_match_rotations_noalloc(ecc_context ctx, ecc_filter_plan plan, in
                                        int* best_index, int ld_out, ecc_precision prec,
                                        void* stream);
 
+/* ---------------------------------------------------------------- pattern detection */
+/* The steps of pattern detection by extended convolution (Sec. 5): the target image gives
+ * the signal and the field, the pattern gives the filter by voting, the extended
+ * convolution (ecc_extended, ECC_CONVOLUTION, with a plan of that filter) makes every
+ * pixel vote for the centres of rotated copies of the pattern, and the peaks of the
+ * response are the detections. */
+
+/* Signal and field of an image (eq. signal, eq. theta): magnitude = |grad I| and
+ * angle = atan2(dI/dy, dI/dx) (radians, y = row, x = column), with central differences
+ * inside and one-sided differences on the first and last row and column. image,
+ * magnitude, angle: device float32, batch x ny x nx (row strides ld_image / ld_out, image
+ * strides ny * ld). ny, nx >= 2. Outputs must not alias each other or the image.
+ * Errors: INVALID_ARGUMENT, HIP. */
+ecc_status ecc_gradient_field(ecc_context ctx, int batch, int ny, int nx, const float* image,
+                              int ld_image, float* magnitude, float* angle, int ld_out,
+                              void* stream);
+/* Consensus filter of a pattern (eq. opt_filt; appendix "Defining Optimal Filters"): every
+ * pixel x of the S x S pattern P (device float32, S odd, 3 <= S <= 255) within the disk
+ * |x - c| <= R = (S-1)/2 around its centre c votes with weight |grad P(x)| (gradients as in
+ * ecc_gradient_field) for the position of c seen from the frame at x whose first axis is
+ * the gradient direction, R_{-theta_P(x)} (c - x); a vote is split bilinearly over the four
+ * surrounding bins and dropped outside the window. `filter`: device float32 S x S, centre
+ * at (R, R), ready for ecc_filter_plan_create. Computed in float64 (each bin sums its votes
+ * in raster order: the same result on every run) and rounded once. Uses the context
+ * workspace (24 S^2 bytes). Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, HIP. */
+ecc_status ecc_voting_filter(ecc_context ctx, int S, const float* pattern, float* filter,
+                             void* stream);
+/* Peaks of a response (device float32 ny x nx, stride ld): pixels whose value is >= the
+ * threshold (`threshold` itself, or `threshold` times the largest value when `relative`
+ * is nonzero; then 0 < threshold <= 1) and is not exceeded within the (2 radius + 1)^2
+ * window around them, ties going to the first pixel in raster order. The strongest
+ * min(max_peaks, number of peaks) are written to rows, cols (device int32) and values
+ * (device float32) by decreasing value (ties by raster index); `count` (device int32)
+ * receives their number. Deterministic. Uses the context workspace (16 bytes per
+ * (radius+1)^2 cell of the image plus the sort's temporary storage).
+ * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, HIP. */
+ecc_status ecc_find_peaks(ecc_context ctx, int ny, int nx, const float* response, int ld,
+                          int radius, float threshold, int relative, int max_peaks, int* rows,
+                          int* cols, float* values, int* count, void* stream);
+
 /* ---------------------------------------------------------------- adjoint */
 
 /* Gradients of the rotation-plan extended convolution y = Re sum_k w_k (H e^{-ik theta}) * F_k

@@ -21,6 +21,7 @@ from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, G
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
     "ecc_normalized_convolution", "WS_NORMALIZED_CONVOLUTION",
+    "ecc_gradient_field", "ecc_voting_filter", "ecc_find_peaks", "detect_pattern",
     "ecc_match_rotations_noalloc",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
@@ -268,6 +269,73 @@ def ecc_match_rotations_noalloc(ctx: Context, plan: FilterPlan, signal, score, i
     _check(lib().ecc_match_rotations_noalloc(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), n_angles,
                                              _ptr(score), _ptr(index), nx, precision, _stream(stream)))
     return score, index
+
+
+def ecc_gradient_field(ctx: Context, image, magnitude=None, angle=None, stream=None):
+    """(|grad I|, atan2(I_y, I_x)) of (ny, nx) or (batch, ny, nx) float32 device images."""
+    import torch
+    _img(image, "image")
+    if magnitude is None:
+        magnitude = torch.empty(image.shape, dtype=torch.float32, device=image.device)
+    if angle is None:
+        angle = torch.empty(image.shape, dtype=torch.float32, device=image.device)
+    _img(magnitude, "magnitude")
+    _img(angle, "angle")
+    if _ld(magnitude) != _ld(angle):
+        raise ValueError("magnitude and angle must share their row stride")
+    ny, nx = image.shape[-2], image.shape[-1]
+    batch = image.shape[0] if image.dim() == 3 else 1
+    for t in (image, magnitude, angle):
+        if t.dim() == 3 and t.stride(0) != t.shape[-2] * t.stride(-2):
+            raise ValueError("batched images must be stacked with image stride ny * ld")
+    _check(lib().ecc_gradient_field(ctx.h, batch, ny, nx, _ptr(image), _ld(image), _ptr(magnitude), _ptr(angle),
+                                    _ld(magnitude), _stream(stream)))
+    return magnitude, angle
+
+
+def ecc_voting_filter(ctx: Context, pattern, stream=None):
+    """Consensus filter (S x S float32) of an S x S float32 device pattern, S odd."""
+    import torch
+    _img(pattern, "pattern")
+    if pattern.dim() != 2 or pattern.shape[0] != pattern.shape[1] or not pattern.is_contiguous():
+        raise ValueError("pattern must be a contiguous S x S tensor")
+    F = torch.empty_like(pattern)
+    _check(lib().ecc_voting_filter(ctx.h, pattern.shape[0], _ptr(pattern), _ptr(F), _stream(stream)))
+    return F
+
+
+def ecc_find_peaks(ctx: Context, response, radius, threshold, relative=False, max_peaks=64, stream=None):
+    """Peaks of a (ny, nx) float32 device response: (rows, cols, values) device tensors of the
+    strongest ones, by decreasing value (waits for the stream to read their number)."""
+    import torch
+    _img(response, "response")
+    ny, nx = response.shape
+    dev = response.device
+    rows = torch.empty(max_peaks, dtype=torch.int32, device=dev)
+    cols = torch.empty(max_peaks, dtype=torch.int32, device=dev)
+    vals = torch.empty(max_peaks, dtype=torch.float32, device=dev)
+    count = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().ecc_find_peaks(ctx.h, ny, nx, _ptr(response), _ld(response), radius, C.c_float(threshold),
+                                1 if relative else 0, max_peaks, _ptr(rows), _ptr(cols), _ptr(vals), _ptr(count),
+                                _stream(stream)))
+    n = int(count.item())
+    return rows[:n], cols[:n], vals[:n]
+
+
+def detect_pattern(ctx: Context, image, pattern, K, radius=8, threshold=0.3, relative=True, max_peaks=64,
+                   stream=None):
+    """Pattern detection by extended convolution (Sec. 5), as a sequence of library calls:
+    signal and field of the image, the pattern's consensus filter, its plan (band limit K),
+    the extended convolution, the peaks. Returns (rows, cols, values, response)."""
+    H, theta = ecc_gradient_field(ctx, image, stream=stream)
+    F = ecc_voting_filter(ctx, pattern, stream=stream)
+    plan = FilterPlan.rotation(ctx, F, K, stream=stream)
+    try:
+        D = ecc_extended(ctx, CONVOLUTION, plan, H, theta, stream=stream)
+    finally:
+        plan.close()
+    rows, cols, vals = ecc_find_peaks(ctx, D, radius, threshold, relative, max_peaks, stream=stream)
+    return rows, cols, vals, D
 
 
 def ecc_backward_saved_size(ctx: Context, plan: FilterPlan, batch, ny, nx) -> int:

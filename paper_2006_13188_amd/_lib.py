@@ -86,6 +86,9 @@ PROTOS = {
     "ecc_extended_backward": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "ecc_backward_saved_size": [_P, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_extended_save": [_P, _P, _I, _I, _I, _P, _P, _P, _P, _P],
+    "ecc_gradient_field": [_P, _I, _I, _I, _P, _I, _P, _P, _I, _P],
+    "ecc_voting_filter": [_P, _I, _P, _P, _P],
+    "ecc_find_peaks": [_P, _I, _I, _P, _I, _I, C.c_float, _I, _I, _P, _P, _P, _P, _P],
     "ecc_workspace_size": [_P, _I, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_workspace_reserve": [_P, C.c_size_t],
     "ecc_workspace_allocated": [_P, C.POINTER(C.c_size_t)],
