@@ -213,9 +213,20 @@ def scale_workload(E, timeit):
 
     from synthetic import scale_config
 
+    import numpy as np
+
+    import oracle as O
+
     img, s = scale_config(2048)
     Hs, Ss = torch.from_numpy(img).cuda(), torch.from_numpy(s).cuda()
     res = {"workload": "scale-adaptive smoothing, 2048x2048, 24 components (13 computed), ratio form"}
+    # the float64 oracle of the same smoothing, for the error of every precision
+    ref = O.scale_smooth_fft(img.astype(np.float64), s.astype(np.float64), O.ScaleParams())[0]
+
+    def errs(out):
+        g = out.cpu().numpy().astype(np.float64)
+        return {"rel_l2": float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
+                "rel_inf": float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))}
     for name, strat in (("tiled", TILED), ("two_pass", TWO_PASS)):
         c = E.Context(0)
         c.set_strategy(strat)
@@ -224,6 +235,16 @@ def scale_workload(E, timeit):
         E.ecc_scale_smooth(c, plan, Hs, Ss, out=out)
         ms = timeit(lambda: E.ecc_scale_smooth(c, plan, Hs, Ss, out=out), reps=10)
         res[name + "_ms"] = round(ms, 4)
+        res[name + "_err_vs_float64_oracle"] = errs(out)
+        if strat == TILED:
+            # the matrix-core forms of the overlap-add kernel's radix-16 passes
+            mixed = {}
+            for pname, prec in (("fp16_hilo", E.PREC_MFMA_FP16_HILO), ("bf16_hilo", E.PREC_MFMA_BF16_HILO)):
+                E.ecc_scale_smooth(c, plan, Hs, Ss, out=out, precision=prec)
+                pms = timeit(lambda: E.ecc_scale_smooth(c, plan, Hs, Ss, out=out, precision=prec), reps=10)
+                mixed[pname] = {"ms": round(pms, 4), "speedup_vs_fp32": round(ms / pms, 3),
+                                "err_vs_float64_oracle": errs(out)}
+            res["matrix_core_precisions"] = mixed
         res[name + "_Mpix_comp_s"] = round(2048 * 2048 * 24 / (ms * 1e-3) / 1e6, 1)
         # algorithmic HBM bytes of the numerator and the denominator convolutions at the
         # minimum padding P = n + R = 2080 with U = 13 computed components

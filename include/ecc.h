@@ -242,9 +242,12 @@ ecc_status ecc_scale_smooth(ecc_context ctx, ecc_filter_plan plan, int ny, int n
  * context workspace; a second kernel adds the overlapping regions in a fixed order and
  * divides. Otherwise two launches of the block convolution (numerator, then the
  * denominator divided into it). Two-pass: both signals' transforms in one set of
- * kernels. Workspace: ecc_workspace_size with ECC_WS_NORMALIZED_CONVOLUTION. Only
- * ECC_PREC_FP32 is implemented. Errors as for
- * ecc_extended. */
+ * kernels. Workspace: ecc_workspace_size with ECC_WS_NORMALIZED_CONVOLUTION.
+ * Precision: ECC_PREC_FP32 everywhere; ECC_PREC_MFMA_FP16_HILO / ECC_PREC_MFMA_BF16_HILO
+ * in the overlap-add kernel only (else UNSUPPORTED): the radix-16 passes of its forward
+ * transforms (16-point DFTs of 16 lines at a time) run on the matrix cores with float16
+ * (scaled per tile) or bfloat16 operands split into hi + lo parts, float32 accumulation;
+ * everything else stays float32. Errors as for ecc_extended. */
 ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny,
                                       int nx, const float* signal, int ld_signal, const float* field,
                                       int ld_field, float* out, int ld_out, ecc_precision prec,

@@ -208,7 +208,8 @@ def ecc_extended(ctx: Context, op: int, plan: FilterPlan, signal, field, out=Non
     return out
 
 
-def ecc_normalized_convolution(ctx: Context, plan: FilterPlan, signal, field, out=None, stream=None):
+def ecc_normalized_convolution(ctx: Context, plan: FilterPlan, signal, field, out=None, stream=None,
+                               precision=PREC_FP32):
     """Extended convolution of the signal over that of the constant 1 (rotation plans:
     line-integral convolution with an anisotropic filter; scale plans: the smoothing of
     ecc_scale_smooth). signal, field: (ny, nx) or (batch, ny, nx) float32 device tensors."""
@@ -224,12 +225,12 @@ def ecc_normalized_convolution(ctx: Context, plan: FilterPlan, signal, field, ou
         if t.dim() == 3 and t.stride(0) != t.shape[-2] * t.stride(-2):
             raise ValueError("batched images must be stacked with image stride ny * ld")
     _check(lib().ecc_normalized_convolution(ctx.h, plan.h, batch, ny, nx, _ptr(signal), _ld(signal),
-                                            _ptr(field), _ld(field), _ptr(out), _ld(out), PREC_FP32,
+                                            _ptr(field), _ld(field), _ptr(out), _ld(out), precision,
                                             _stream(stream)))
     return out
 
 
-def ecc_scale_smooth(ctx: Context, plan: FilterPlan, signal, scale, out=None, stream=None):
+def ecc_scale_smooth(ctx: Context, plan: FilterPlan, signal, scale, out=None, stream=None, precision=PREC_FP32):
     import torch
     _img(signal, "signal")
     _img(scale, "scale")
@@ -237,7 +238,7 @@ def ecc_scale_smooth(ctx: Context, plan: FilterPlan, signal, scale, out=None, st
         out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
     ny, nx = signal.shape
     _check(lib().ecc_scale_smooth(ctx.h, plan.h, ny, nx, _ptr(signal), _ld(signal), _ptr(scale),
-                                  _ld(scale), _ptr(out), _ld(out), PREC_FP32, _stream(stream)))
+                                  _ld(scale), _ptr(out), _ld(out), precision, _stream(stream)))
     return out
 
 

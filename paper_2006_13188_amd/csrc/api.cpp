@@ -818,7 +818,8 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
   ECC_REQ(ctx && plan, "NULL context or plan");
   ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
   ECC_REQ(signal && field && out, "NULL image pointer");
-  if (prec != ECC_PREC_FP32) return fail(ECC_ERR_UNSUPPORTED, "precision not implemented");
+  ECC_REQ(prec == ECC_PREC_FP32 || prec == ECC_PREC_MFMA_FP16_HILO || prec == ECC_PREC_MFMA_BF16_HILO,
+          "unknown precision");
   ECC_TRY(validate_images(plan, batch, ny, nx));
   ECC_REQ(ld_signal >= nx && ld_field >= nx && ld_out >= nx, "row strides must be >= nx");
   const size_t bo = (size_t)batch * ny * ld_out * sizeof(float);
@@ -860,10 +861,15 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
     ra.par = plan->d_parity.as<float>();
     ra.part = ctx->ws.as<cx<float>>();
     mark(ctx, 0, st);
-    ECC_HIP(launch_tile_ratio(st, rc.N, rc.TV, batch, ra));
+    ECC_HIP(launch_tile_ratio(st, rc.N, rc.TV, batch, ra,
+                              prec == ECC_PREC_FP32 ? 0 : (prec == ECC_PREC_MFMA_FP16_HILO ? 1 : 2)));
     mark(ctx, 1, st);
     return ECC_OK;
   }
+  if (prec != ECC_PREC_FP32)
+    return fail(ECC_ERR_UNSUPPORTED,
+                "the matrix-core precisions run in the overlap-add block kernel only (128-point blocks: filter "
+                "radius above 24 under the default strategy, components with parity)");
   if (strat == ECC_STRATEGY_TILED) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));

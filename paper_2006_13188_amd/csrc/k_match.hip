@@ -14,14 +14,11 @@
 //     that its largest magnitude lies in [2^10, 2^11) (lo parts stay normal numbers);
 //   * the same with bfloat16 hi + lo parts (about 2^-16 relative per product).
 #include "kcommon.hpp"
+#include "mfma_split.hpp"
 
 namespace ecc {
 
 namespace {
-
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef short bf4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
 
 // The stack holds U planes of npix complex values (component-major). UMAX >= U (the
 // components beyond U are zero and their products are not formed past UMAX); the table
@@ -106,45 +103,6 @@ __global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __
   score[yy * ldOut + xx] = best;
   index[yy * ldOut + xx] = bi;
 }
-
-__device__ __forceinline__ short bf16_bits(float x) {   // round to nearest even
-  const unsigned u = __float_as_uint(x);
-  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ __forceinline__ float bf16_value(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
-
-template <bool BF16>
-struct Split;
-template <>
-struct Split<false> {
-  typedef half4_t T;
-  static __device__ __forceinline__ void split(const float* v, T& hi, T& lo) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const _Float16 h = (_Float16)v[j];
-      hi[j] = h;
-      lo[j] = (_Float16)(v[j] - (float)h);
-    }
-  }
-  static __device__ __forceinline__ f4_t mma(T a, T b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Split<true> {
-  typedef bf4_t T;
-  static __device__ __forceinline__ void split(const float* v, T& hi, T& lo) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const short h = bf16_bits(v[j]);
-      hi[j] = h;
-      lo[j] = bf16_bits(v[j] - bf16_value(h));
-    }
-  }
-  static __device__ __forceinline__ f4_t mma(T a, T b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-  }
-};
 
 // One wave per group of 16 pixels (grid-stride over groups). C^T = D (A_mat, M = angles)
 // times g (B_mat, N = pixels): lane l holds D rows 16 mt + l%16, columns 16 s + 4 (l/16)

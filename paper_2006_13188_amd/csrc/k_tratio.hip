@@ -24,6 +24,7 @@
 // Pruning: the sources fill rows and columns [0, T) of the window; column transforms run
 // only over those T columns, and every radix-8 butterfly of the first pass of a line reads
 // only its inputs below T (at most ceil(T / M) of the eight).
+#include "mfma_split.hpp"
 #include "tile_common.hpp"
 
 namespace ecc {
@@ -51,6 +52,92 @@ __device__ __forceinline__ void dft8_pruned(cx<float>* x) {
   else dft<8, DIR, float>(x);
 }
 
+// ---- 16-point DFTs on the matrix cores (float16 or bfloat16 hi + lo operands). For 16
+// lines of one pass-1 butterfly at a time (a "tile", one wave): Y = X D with
+// D[r][k] = exp(-2 pi i r k / 16), computed as Y^T = D^T X^T, so that lane l holds line
+// l % 16 with elements r = 4 (l / 16) + j as its operand and gets back the same line with
+// frequencies k = 4 (l / 16) + j. Complex products as real ones:
+// Re Y = Re D Re X - Im D Im X, Im Y = Re D Im X + Im D Re X, each with hi/lo operands.
+struct Cos16 {
+  float c[16], s[16];
+};
+constexpr Cos16 make_cos16() {
+  Cos16 t{};
+  for (int m = 0; m < 16; ++m) {
+    t.c[m] = (float)cos_turn(m, 16);
+    t.s[m] = (float)sin_turn(m, 16);
+  }
+  return t;
+}
+__constant__ Cos16 kCos16 = make_cos16();
+
+template <bool BF16>
+struct D16Ops {
+  typename Split<BF16>::T rh, rl, ih, il, nih, nil;   // Re D, Im D, -Im D (A operands, D^T)
+};
+template <bool BF16>
+__device__ __forceinline__ D16Ops<BF16> make_d16(int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+  float re[4], im[4], nim[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int m = ((4 * lq + j) * lr) & 15;   // A[k = lr][r = 4 lq + j] = D[r][k]
+    re[j] = kCos16.c[m];
+    im[j] = -kCos16.s[m];
+    nim[j] = kCos16.s[m];
+  }
+  D16Ops<BF16> d;
+  Split<BF16>::split(re, d.rh, d.rl);
+  Split<BF16>::split(im, d.ih, d.il);
+  Split<BF16>::split(nim, d.nih, d.nil);
+  return d;
+}
+// x: this lane's four (twiddled) elements of its line; y: its four outputs. float16
+// operands are scaled per tile by a power of two so that the largest magnitude lies in
+// [2^10, 2^11) (every lane of the wave takes part in the reduction).
+template <bool BF16>
+__device__ __forceinline__ void dft16_tile(const cx<float>* x, cx<float>* y, const D16Ops<BF16>& d) {
+  using SP = Split<BF16>;
+  float f = 1.f, inv = 1.f;
+  if constexpr (!BF16) {
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mx = fmaxf(mx, fmaxf(fabsf(x[j].re), fabsf(x[j].im)));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    int ex = 0;
+    (void)frexpf(mx, &ex);
+    if (mx > 0.f) {
+      f = ldexpf(1.f, 11 - ex);
+      inv = ldexpf(1.f, ex - 11);
+    }
+  }
+  float xr[4], xi[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    xr[j] = x[j].re * f;
+    xi[j] = x[j].im * f;
+  }
+  typename SP::T xrh, xrl, xih, xil;
+  SP::split(xr, xrh, xrl);
+  SP::split(xi, xih, xil);
+  f4_t yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+  yr = SP::mma(d.rh, xrh, yr);
+  yr = SP::mma(d.rh, xrl, yr);
+  yr = SP::mma(d.rl, xrh, yr);
+  yr = SP::mma(d.nih, xih, yr);
+  yr = SP::mma(d.nih, xil, yr);
+  yr = SP::mma(d.nil, xih, yr);
+  yi = SP::mma(d.rh, xih, yi);
+  yi = SP::mma(d.rh, xil, yi);
+  yi = SP::mma(d.rl, xih, yi);
+  yi = SP::mma(d.ih, xrh, yi);
+  yi = SP::mma(d.ih, xrl, yi);
+  yi = SP::mma(d.il, xrh, yi);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) y[j] = mk(yr[j] * inv, yi[j] * inv);
+}
+
 template <int N>
 __shared__ cx<float> ratio_img_lds[N * (N + 1)];
 // the sources' signal values, [pixel of the item][thread], and the phase step of each
@@ -60,7 +147,7 @@ __shared__ float ratio_h_lds[NV * NT];
 template <int NT>
 __shared__ cx<float> ratio_e1_lds[NT];
 
-template <int N, int TV, int NT>
+template <int N, int TV, int NT, int PREC>
 __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int tile, int blk, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr int RMAX = (TV + M - 1) / M;        // pass-0 inputs that can lie below T
@@ -69,14 +156,32 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
   constexpr int NI = (N + LS - 1) / LS;         // pass-1 lines over N lines
   constexpr int NIT = (TV + LS - 1) / LS;       // pass-1 lines over the source columns
   static_assert(RMAX <= 8, "source block wider than the window");
+  // PREC 0: float32 radix-16 passes on the vector units; 1 / 2: the radix-16 passes of the
+  // forward transforms (column pass 1, row pass 1 with the product) on the matrix cores,
+  // float16 / bfloat16 hi + lo operands (tiles: 16 lines of one butterfly per wave)
+  constexpr bool MF = PREC != 0;
+  static_assert(!MF || (N == 128 && NT == 1024), "matrix-core passes: 128-point blocks, 16 waves");
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int mlr = lane & 15, mlq = lane >> 4;
+  const int mbq = wv & 7;   // the pass-1 butterfly of every tile of this wave
   const int t = threadIdx.x, l = t % LS;
   const int bq = (NT % 64 == 0 && LS % 64 == 0) ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
   const int T = a.T;
   const int y0 = (tile / a.tx) * T, x0 = (tile % a.tx) * T;
   const TileTwiddles<N>& tt = tile_twiddles<N>();
   cx<float> tw[M];
+  if constexpr (!MF) {
 #pragma unroll
-  for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+    for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
+  }
+  // matrix-core tiles: the pass-1 twiddles of this lane's elements r = 4 mlq + j, and D
+  cx<float> twm[4];
+  D16Ops<PREC == 2> d16;
+  if constexpr (MF) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) twm[j] = mk(tt.re[mbq][4 * mlq + j], tt.im[mbq][4 * mlq + j]);
+    d16 = make_d16<PREC == 2>(lane);
+  }
 
   // ---- sources of this thread's column pass-0 items: h = H (0 outside), z = wn e^{i c alpha}
   // for the current component c (from c = 0), advanced by e1 = e^{i alpha}
@@ -113,11 +218,14 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
       hs[(s * RMAX + r) * NT + t] = hv;   // read back only by this thread
     }
   }
-  cx<float> Z[NI][M];
+  // accumulated spectrum bins of this thread: [line item][element] (vector units) or
+  // [tile][j] (matrix cores: tile i is row group 2 i + wv / 8, bins (u, mbq + 8 (4 mlq + j)))
+  constexpr int ZA = MF ? 4 : NI, ZB = MF ? 4 : M;
+  cx<float> Z[ZA][ZB];
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+  for (int i = 0; i < ZA; ++i)
 #pragma unroll
-    for (int r = 0; r < M; ++r) Z[i][r] = mk(0.f, 0.f);
+    for (int r = 0; r < ZB; ++r) Z[i][r] = mk(0.f, 0.f);
 
   // filter spectra through buffer loads: the lane offset u (consecutive lanes, one
   // register) plus a wave-uniform offset per element, so the addresses take no registers
@@ -152,7 +260,29 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
       }
       __syncthreads();
       // ---- column pass 1 over the T source columns
-      pass1_inplace<N, -1, false, NIT, NT>(A, tw, bq, l, T, N);
+      if constexpr (MF) {
+        // tiles (column group cg, butterfly mbq), in place: a lane reads elements
+        // 4 mlq + j of its column and writes frequencies 4 mlq + j of the same column
+        const int ncg = (T + 15) >> 4;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int cg = (wv >> 3) + 2 * i;
+          if (cg < ncg) {
+            const int v = 16 * cg + mlr;
+            cx<float> x[4], y[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              x[j] = v < T ? cmulc(A[(mbq + 8 * (4 * mlq + j)) * P + v], twm[j]) : mk(0.f, 0.f);
+            dft16_tile<PREC == 2>(x, y, d16);
+            if (v < T) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) A[(mbq + 8 * (4 * mlq + j)) * P + v] = y[j];
+            }
+          }
+        }
+      } else {
+        pass1_inplace<N, -1, false, NIT, NT>(A, tw, bq, l, T, N);
+      }
       __syncthreads();
       // ---- row pass 0 (radix 8, columns below T only), in NG groups of rows: a group's
       // outputs overwrite only its own rows, so the next group's inputs can be read right
@@ -189,6 +319,31 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
       }
       __syncthreads();
       // ---- row pass 1 and the product with the (real or imaginary) filter spectrum
+      if constexpr (MF) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u = 16 * ((wv >> 3) + 2 * i) + mlr;
+          cx<float> x[4], y[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = cmulc(A[u * P + mbq + 8 * (4 * mlq + j)], twm[j]);
+          dft16_tile<PREC == 2>(x, y, d16);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int vv = mbq + 8 * (4 * mlq + j);
+            const float rho = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(
+                           fsrc, (vv * N + u) * (int)sizeof(float2),
+                           (c * N * N) * (int)sizeof(float2) + part * (int)sizeof(float), 0));
+            if (odd) {
+              Z[i][j].re -= y[j].im * rho;
+              Z[i][j].im += y[j].re * rho;
+            } else {
+              Z[i][j].re += y[j].re * rho;
+              Z[i][j].im += y[j].im * rho;
+            }
+          }
+        }
+      } else {
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         const int u = l + LS * i;
@@ -216,6 +371,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
           }
         }
       }
+      }
       __syncthreads();   // the image is rewritten next
     }
 #pragma unroll
@@ -225,11 +381,20 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
   }
 
   // ---- inverse transform of the accumulated spectrum: num + i den on the whole window
+  if constexpr (MF) {
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+    for (int r = 0; r < M; ++r) tw[r] = mk(tt.re[bq][r], tt.im[bq][r]);
 #pragma unroll
-    for (int r = 0; r < M; ++r)
-      if (N % LS == 0 || l + LS * i < N) A[(l + LS * i) * P + bq + 8 * r] = Z[i][r];
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[(16 * ((wv >> 3) + 2 * i) + mlr) * P + mbq + 8 * (4 * mlq + j)] = Z[i][j];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int r = 0; r < M; ++r)
+        if (N % LS == 0 || l + LS * i < N) A[(l + LS * i) * P + bq + 8 * r] = Z[i][r];
+  }
   __syncthreads();
   pass0_inplace<N, +1, false, N, NT>(A, t, N, true);
   __syncthreads();
@@ -269,11 +434,11 @@ constexpr int tratio_threads() {
   return 1024;
 }
 
-template <int N, int TV>
+template <int N, int TV, int PREC>
 __global__ void __launch_bounds__(tratio_threads<N>()) k_tile_ratio(TileRatioArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  ratio_block<N, TV, tratio_threads<N>()>(a, lb / ntile, lb % ntile, lb, ratio_img_lds<N>);
+  ratio_block<N, TV, tratio_threads<N>(), PREC>(a, lb / ntile, lb % ntile, lb, ratio_img_lds<N>);
 }
 
 // out(p) = sum of the real parts over the regions that cover p / the same sum of the
@@ -342,16 +507,21 @@ size_t tratio_scratch_bytes(int N, int T, int batch, int ny, int nx) {
   return (size_t)nblk * N * N * sizeof(cx<float>);
 }
 
-hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a0) {
+hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a0, int prec) {
   TileRatioArgs a = a0;
-  if (a.T < 1 || a.T > TV || a.T + 2 * a.R > N || a.R < 0) return hipErrorInvalidValue;
+  if (a.T < 1 || a.T > TV || a.T + 2 * a.R > N || a.R < 0 || prec < 0 || prec > 2) return hipErrorInvalidValue;
   a.tx = (a.nx + a.T - 1) / a.T;
   a.ty = (a.ny + a.T - 1) / a.T;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL || a.ny > 65535 || batch > 65535) return hipErrorInvalidValue;
 #define ECC_RL(n, tv)                                                                                 \
   if (N == n && TV == tv) {                                                                          \
-    hipLaunchKernelGGL((k_tile_ratio<n, tv>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, a); \
+    if (prec == 0)                                                                                   \
+      hipLaunchKernelGGL((k_tile_ratio<n, tv, 0>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, a); \
+    else if (prec == 1)                                                                              \
+      hipLaunchKernelGGL((k_tile_ratio<n, tv, 1>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, a); \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_tile_ratio<n, tv, 2>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, a); \
     hipError_t e = last();                                                                           \
     if (e != hipSuccess) return e;                                                                   \
     hipLaunchKernelGGL(k_ratio_sum, dim3((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)batch), \

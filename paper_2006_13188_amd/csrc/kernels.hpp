@@ -230,7 +230,9 @@ struct TileRatioArgs {
 };
 bool tratio_supported(int N, int TV);
 size_t tratio_scratch_bytes(int N, int T, int batch, int ny, int nx);
-hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a);
+// prec 0: float32; 1 / 2: the radix-16 passes of the forward transforms on the matrix
+// cores with float16 / bfloat16 hi + lo operands (float32 accumulation)
+hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a, int prec = 0);
 // spectra of the overlap-add ratio kernel from the centred float64 spectra of the
 // components (U planes of N x N, [row freq][column freq]): per component the real parts of
 // the spectra of Re F_c and Im F_c (parity +1) or their imaginary parts (parity -1), times

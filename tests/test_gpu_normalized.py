@@ -164,3 +164,48 @@ def test_scale_plan_is_the_scale_smoothing(E, sctx):
     b = host(E.ecc_scale_smooth(ctx, plan, dev(img), dev(s)))
     assert np.array_equal(a, b)
     plan.close()
+
+
+# ---------------------------------------------------------------- matrix-core precisions
+
+PREC_TOL = {1: (1e-5, 1e-5), 2: (1e-4, 1e-4)}   # (rel-L2, rel-inf): float16 hi/lo, bfloat16 hi/lo (2^-16 operands)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16_hilo", "bf16_hilo"])
+def test_lic_matrix_core_precisions(E, actx, prec):
+    """The overlap-add kernel's radix-16 passes on the matrix cores (hi/lo operands): LIC
+    with a 65 x 65 filter against the float64 oracle."""
+    shape, S, K = (300, 280), 65, 12
+    img = np.random.default_rng(1).random(shape).astype(np.float32)
+    th = vortex_field(shape, 2, sigma=6.0)
+    filt = anisotropic_gaussian(S, 14.0, 2.0)
+    plan = E.FilterPlan.rotation(actx, dev(filt), K)
+    got = host(E.ecc_normalized_convolution(actx, plan, dev(img), dev(th), precision=prec)).astype(np.float64)
+    ref = oracle_lic(img, th, filt, K)
+    t2, ti = PREC_TOL[prec]
+    assert rel2(got, ref) <= t2 and relinf(got, ref) <= ti, (rel2(got, ref), relinf(got, ref))
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16_hilo", "bf16_hilo"])
+def test_scale_smoothing_matrix_core_full_size(E, actx, prec):
+    """The scale-group workload (2048 x 2048, 24 components, 65 x 65 support) with the
+    matrix-core passes, against the float64 oracle."""
+    from synthetic import scale_config
+    img, s = scale_config(2048)
+    print(f"scale smoothing 2048^2 precision={prec}", flush=True)
+    plan = E.FilterPlan.scale(actx)
+    got = host(E.ecc_scale_smooth(actx, plan, dev(img), dev(s), precision=prec)).astype(np.float64)
+    ref = O.scale_smooth_fft(img.astype(np.float64), s.astype(np.float64), O.ScaleParams())[0]
+    t2, ti = PREC_TOL[prec]
+    assert rel2(got, ref) <= t2 and relinf(got, ref) <= ti, (rel2(got, ref), relinf(got, ref))
+    plan.close()
+
+
+def test_matrix_core_precisions_need_the_overlap_add_kernel(E, actx):
+    plan = E.FilterPlan.rotation(actx, dev(anisotropic_gaussian(31, 8.0, 1.5)), 16)
+    img = dev(np.ones((128, 128), np.float32))
+    with pytest.raises(E.EccError) as ei:
+        E.ecc_normalized_convolution(actx, plan, img, img, precision=1)
+    assert ei.value.status == 2
+    plan.close()
