@@ -14,14 +14,16 @@ Everything here follows "Efficient Spatially Adaptive Convolution and Correlatio
   * band-limiting: Sec. 4.3;
   * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal;
   * normalised filtering with a rotation field (line-integral convolution): Sec. 8;
-  * pattern detection (gradient signal and field, consensus filter by voting, peaks): Sec. 5.
+  * pattern detection (gradient signal and field, consensus filter by voting, peaks): Sec. 5;
+  * joint rotation and scale fields (the Conclusion's future work): joint.py.
 
 Readings where the paper is silent are listed per function (boundary = zero outside
 the image, bilinear polar resampling at the exact grid radii, k = -K..K, etc.).
 
 Parity status: every function below is pinned by tests in tests/test_oracle_*.py
-except the scale-group coefficients c_k, whose values are fixed only by the reading
-of the scale decomposition (parity unpinned; see scale.py).
+except the scale-group coefficients c_k and the joint coefficients c_{k,l}, whose values
+are fixed only by the readings of those decompositions (parity unpinned; see scale.py and
+joint.py).
 """
 from .decompose import (
     default_angular_samples, bilinear, grid_radii, angular_components,
@@ -34,6 +36,7 @@ from .extended import (
 from .adjoint import conv_backward, corr_backward
 from .normalized import normalized_conv_brute, normalized_conv_fft, normalized_conv_half
 from .detection import gradient_field, voting_filter, find_peaks, detection_response
+from .joint import JointParams, joint_components, joint_filter_at, joint_conv_brute, joint_conv_fft, joint_smooth
 from .scale import (
     ScaleParams, scale_components, scale_filter_at, scale_smooth_brute,
     scale_smooth_fft,
@@ -47,6 +50,7 @@ __all__ = [
     "conv_backward", "corr_backward",
     "normalized_conv_brute", "normalized_conv_fft", "normalized_conv_half",
     "gradient_field", "voting_filter", "find_peaks", "detection_response",
+    "JointParams", "joint_components", "joint_filter_at", "joint_conv_brute", "joint_conv_fft", "joint_smooth",
     "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
     "scale_smooth_fft",
 ]
