@@ -410,6 +410,37 @@ def detection_workload(E, timeit):
     return res
 
 
+def joint_workload(E, timeit):
+    """Joint rotation and scale fields: 1024^2 block image, 31 x 31 anisotropic Gaussian
+    (sigma 1.8 along, 0.7 across), K = 8 and 9 log-radial modes (77 components of the real
+    half set), vortex angle field, scale field in [1, 2]; normalised smoothing and the plain
+    extended convolution (two-pass form)."""
+    import torch
+
+    from synthetic import joint_config
+
+    img, filt, th, sc = joint_config()
+    Hd, Td, Sd = (torch.from_numpy(a).cuda() for a in (img, th, sc))
+    c = E.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = E.FilterPlan.joint(c, torch.from_numpy(filt).cuda(), 8, n_log=9, scale_min=1.0, scale_max=2.0)
+    out = torch.empty_like(Hd)
+    E.ecc_joint_convolution(c, plan, Hd, Td, Sd, True, out=out)   # builds the spectra
+    torch.cuda.synchronize()
+    U = plan.components().shape[0]
+    res = {"workload": "joint rotation + scale normalised smoothing, 1024x1024, 31x31 anisotropic Gaussian, "
+                       "K=8, 9 log-radial modes", "components": int(U),
+           "plan_ms": round((time.perf_counter() - t0) * 1e3, 3)}
+    ms = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, True, out=out), reps=10)
+    ms1 = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, False, out=out), reps=10)
+    res.update(normalised_ms=round(ms, 4), plain_ms=round(ms1, 4),
+               plain_Mpix_comp_s=round(1024 * 1024 * (2 * U - 1) / (ms1 * 1e-3) / 1e6, 1))
+    plan.close()
+    c.close()
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -518,7 +549,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of side workloads: two_pass,conv,matching,scale,lic,detection,adjoint,batch")
+                    help="comma list of side workloads: two_pass,conv,matching,scale,lic,detection,joint,adjoint,batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
@@ -570,7 +601,7 @@ def main():
 
     side = {}
     want = set() if args.no_extras else (
-        {"two_pass", "conv", "matching", "scale", "lic", "detection", "adjoint", "batch"} if args.extras == "all"
+        {"two_pass", "conv", "matching", "scale", "lic", "detection", "joint", "adjoint", "batch"} if args.extras == "all"
         else set(args.extras.split(",")))
     if "two_pass" in want:
         # the paper's two-pass form on the same workload
@@ -603,6 +634,8 @@ def main():
         side["lic_1024"] = lic_workload(E, timeit)
     if "detection" in want:
         side["detection_1024"] = detection_workload(E, timeit)
+    if "joint" in want:
+        side["joint_1024"] = joint_workload(E, timeit)
     if "adjoint" in want:
         side["adjoint_16x512"] = adjoint_workload(E, ctx, timeit)
     if "batch" in want:

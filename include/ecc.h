@@ -48,7 +48,11 @@ typedef enum {
   ECC_ERR_INTERNAL = 6
 } ecc_status;
 
-typedef enum { ECC_GROUP_ROTATION = 0, ECC_GROUP_SCALE = 1 } ecc_group;
+typedef enum {
+  ECC_GROUP_ROTATION = 0,
+  ECC_GROUP_SCALE = 1,
+  ECC_GROUP_ROTATION_SCALE = 2   /* joint rotation and scale fields: ecc_joint_convolution */
+} ecc_group;
 typedef enum { ECC_CORRELATION = 0, ECC_CONVOLUTION = 1 } ecc_op;
 typedef enum {
   ECC_PREC_FP32 = 0,
@@ -147,7 +151,8 @@ typedef enum {
   ECC_WS_MATCH_ROTATIONS = 3,      /* ecc_match_rotations (batch = 1)                    */
   ECC_WS_BACKWARD_CONVOLUTION = 4, /* ecc_extended_backward(ECC_CONVOLUTION), no saved stack */
   ECC_WS_BACKWARD_CORRELATION = 5, /* ecc_extended_backward(ECC_CORRELATION)             */
-  ECC_WS_NORMALIZED_CONVOLUTION = 6 /* ecc_normalized_convolution                        */
+  ECC_WS_NORMALIZED_CONVOLUTION = 6, /* ecc_normalized_convolution                       */
+  ECC_WS_JOINT_CONVOLUTION = 7      /* ecc_joint_convolution (the normalised form's size) */
 } ecc_ws_call;
 
 /* Every context owns one device workspace, shared by its calls and grown on demand (a
@@ -182,6 +187,17 @@ ecc_status ecc_workspace_allocated(ecc_context ctx, size_t* bytes);
  * the log-radial components of a Gaussian from `gp` (see ecc_group_params): F_k(x) =
  * c_k e^{i omega_k (ln|x| - u_lo)}, k = 0..n/2, on the disk of radius
  * R = ceil(4 sigma0 scale_max).
+ * Rotation and scale (the Conclusion's product group): `filter` as for rotation; the plan
+ * decomposes it into modes F_{k,l}(x) = c_{k,l} e^{i k phi(x)} e^{i omega_l (ln|x| - u_lo)},
+ * k = -K..K, l = -(n-1)/2..(n-1)/2 with n = gp->scale_components (odd; default 9),
+ * omega_l = 2 pi l / L: the filter is sampled bilinearly (zero outside the disk |x| <= R)
+ * at M angles on the log-radii e^{u_lo + j L / n}, u_lo = -ln scale_max, the angular DFT
+ * gives f_k, and the n-point DFT over j of f_k(e^u) gives c_{k,l}, where
+ * L = scale_period_factor (u_hi - u_lo), u_hi = ln R - ln scale_min, and on (u_hi, u_lo + L)
+ * f_k(e^u) is replaced by a raised-cosine blend from its value at u_hi back to that at
+ * u_lo (defaults: scale range [1, 2], factor 1.5). F_{k,l}(0) = F(0) for (0, 0), else 0.
+ * The plan keeps the real filter's half set, k = 0 with l = 0..(n-1)/2 and k = 1..K with
+ * every l: (K+1) n - (n-1)/2 components; only ecc_joint_convolution takes such plans.
  * `gp` may be NULL (defaults). Waits for `stream`. Errors: INVALID_ARGUMENT, UNSUPPORTED
  * (complex filters are not accepted by this signature), OUT_OF_MEMORY, HIP. */
 ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float* filter,
@@ -189,11 +205,16 @@ ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float*
                                   ecc_filter_plan* out);
 /* Plan from explicit components: `comps` is device complex64 (interleaved), (K+1) x S x S,
  * k = 0..K, as described above. For ECC_GROUP_SCALE the field angle and weights come
- * from `gp` as for ecc_filter_plan_create. Waits for `stream`. */
+ * from `gp` as for ecc_filter_plan_create; ECC_GROUP_ROTATION_SCALE is not accepted
+ * (INVALID_ARGUMENT). Waits for `stream`. */
 ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, const float* comps,
                                            int S, int K, const ecc_group_params* gp,
                                            void* stream, ecc_filter_plan* out);
-/* Copies the plan's complex64 components ((K+1) x S x S, interleaved) to device `out`. */
+/* Number of components U a plan stores: K + 1 for rotation plans, n/2 + 1 for scale plans,
+ * (K+1) n - (n-1)/2 for rotation-and-scale plans. */
+ecc_status ecc_filter_plan_component_count(ecc_filter_plan plan, int* U);
+/* Copies the plan's complex64 components (U x S x S, interleaved; U as
+ * ecc_filter_plan_component_count reports) to device `out`. */
 ecc_status ecc_filter_plan_get_components(ecc_filter_plan plan, float* out, void* stream);
 /* Window size S, band limit K (components k = 0..K) and angular samples M of a plan. */
 ecc_status ecc_filter_plan_info(ecc_filter_plan plan, int* S, int* K, int* M);
@@ -252,6 +273,22 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
                                       int nx, const float* signal, int ld_signal, const float* field,
                                       int ld_field, float* out, int ld_out, ecc_precision prec,
                                       void* stream);
+
+/* Extended convolution with joint rotation and scale fields (a rotation-and-scale plan):
+ *   y = Re sum_c w_c (Hn e^{-i (k_c theta + omega_{l_c} ln s)}) * F_c,
+ * i.e. every pixel q scatters Hn(q) times the filter rotated by theta(q) and scaled by s(q)
+ * (band-limited as the plan's modes), with w = 1 for (0, 0) and 2 otherwise; Hn = H when
+ * `normalized` is 0. With `normalized` nonzero the output is the normalised smoothing of
+ * Sec. 8 for this group: Hn = H / s^2, divided by the same convolution of 1 / s^2.
+ * signal, angle (radians), scale (> 0), out: device float32, batch x ny x nx with row
+ * strides ld_* and image stride ny * ld_*; out must not alias an input. Runs the two-pass
+ * form (one zero-padded transform per component and signal; context workspace as
+ * ECC_WS_JOINT_CONVOLUTION reports). Errors: INVALID_ARGUMENT (sizes, strides, NULL,
+ * aliasing, a plan of another group), OUT_OF_MEMORY, HIP. */
+ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                                 const float* signal, int ld_signal, const float* angle, int ld_angle,
+                                 const float* scale, int ld_scale, float* out, int ld_out,
+                                 int normalized, void* stream);
 
 /* Rotation-independent matching (Sec. 5 in band-limited form): the correlation
  * response at n_angles equispaced angles 2 pi m / n_angles,

@@ -21,7 +21,9 @@ paper gives only the idea):
   J4  period: the range of ln|x| - ln s met on the grid, [u_lo, u_hi] =
       [-ln s_max, ln R - ln s_min], times period_factor; on (u_hi, u_lo + L) h_k blends
       from h_k(u_hi) back to h_k(u_lo) with a raised cosine (the scale group's S4 for
-      every angular frequency);
+      every angular frequency); radii up to R + 1e-9 count as inside the disk and samples
+      up to u_hi + 1e-12 as inside the range (so that e^{ln R} rounding above R changes
+      nothing);
   J5  real filters: F_{-k,-l} = conj F_{k,l}; the half set {(0, l >= 0)} and {(k >= 1, all l)}
       with weights 1 for (0, 0) and 2 otherwise;
   J6  normalised smoothing: as the scale group, {H / s^2} over {1 / s^2}.
@@ -83,7 +85,7 @@ def joint_coefficients(F, p: JointParams):
     def f_k(u):
         """angular Fourier coefficients of F on the circle of radius e^u (zero beyond R)."""
         r = np.exp(u)
-        if r > R:
+        if r > R + 1e-9:          # outside the disk (the tolerance absorbs e^{ln R} != R)
             return np.zeros(2 * K + 1, dtype=np.complex128)
         v = bilinear(F, r * np.cos(phi), r * np.sin(phi))
         return np.array([np.sum(v * np.exp(-1j * k * phi)) / M for k in ks])
@@ -91,7 +93,7 @@ def joint_coefficients(F, p: JointParams):
     f_hi, f_lo = f_k(u_hi), f_k(u_lo)
     H = np.zeros((n, 2 * K + 1), dtype=np.complex128)
     for j, u in enumerate(uj):
-        if u <= u_hi:
+        if u <= u_hi + 1e-12:     # (at u_hi both branches give f_k(e^{u_hi}))
             H[j] = f_k(u)
         else:
             t = (u - u_hi) / (u_lo + L - u_hi)

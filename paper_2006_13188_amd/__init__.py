@@ -15,13 +15,15 @@ from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, G
                    GROUP_SCALE, PREC_FP32, PREC_MFMA_BF16_HILO, PREC_MFMA_FP16_HILO, STRATEGY_AUTO,
                    STRATEGY_TILED, STRATEGY_TWO_PASS, WS_BACKWARD_CONVOLUTION,
                    WS_BACKWARD_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_EXTENDED_CORRELATION,
-                   WS_MATCH_ROTATIONS, WS_NORMALIZED_CONVOLUTION, WS_SCALE_SMOOTH, EccError,
+                   WS_MATCH_ROTATIONS, WS_NORMALIZED_CONVOLUTION, WS_SCALE_SMOOTH, WS_JOINT_CONVOLUTION,
+                   GROUP_ROTATION_SCALE, EccError,
                    GroupParams, Instance)
 
 __all__ = [
     "lib", "Context", "FilterPlan", "ecc_extended", "ecc_scale_smooth", "ecc_match_rotations",
     "ecc_normalized_convolution", "WS_NORMALIZED_CONVOLUTION",
     "ecc_gradient_field", "ecc_voting_filter", "ecc_find_peaks", "detect_pattern",
+    "ecc_joint_convolution", "GROUP_ROTATION_SCALE", "WS_JOINT_CONVOLUTION",
     "ecc_match_rotations_noalloc",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
@@ -146,6 +148,19 @@ class FilterPlan:
         return cls(ctx, h)
 
     @classmethod
+    def joint(cls, ctx: Context, filt, K: int, n_log: int = 9, scale_min: float = 1.0, scale_max: float = 2.0,
+              period_factor: float = 1.5, angular_samples: int = 0, stream=None):
+        """Rotation-and-scale plan of an S x S float32 device filter: modes (k, l), k = -K..K,
+        n_log (odd) log-radial modes over the scale range [scale_min, scale_max]."""
+        filt = _img(filt, "filter").contiguous()
+        gp = GroupParams(angular_samples=angular_samples, sigma0=0.0, scale_min=scale_min, scale_max=scale_max,
+                         scale_components=n_log, scale_period_factor=period_factor)
+        h = C.c_void_p()
+        _check(lib().ecc_filter_plan_create(ctx.h, GROUP_ROTATION_SCALE, _ptr(filt), filt.shape[-1], K,
+                                            C.byref(gp), _stream(stream), C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
     def scale(cls, ctx: Context, sigma0=1.0, scale_min=1.0, scale_max=8.0, components=24,
               period_factor=1.5, stream=None):
         gp = GroupParams(0, sigma0, scale_min, scale_max, components, period_factor)
@@ -171,8 +186,9 @@ class FilterPlan:
 
     def components(self, stream=None):
         import torch
-        out = torch.empty((self.K + 1, self.S, self.S), dtype=torch.complex64,
-                          device=f"cuda:{self.ctx.device}")
+        U = C.c_int()
+        _check(lib().ecc_filter_plan_component_count(self.h, C.byref(U)))
+        out = torch.empty((U.value, self.S, self.S), dtype=torch.complex64, device=f"cuda:{self.ctx.device}")
         _check(lib().ecc_filter_plan_get_components(self.h, _ptr(out), _stream(stream)))
         return out
 
@@ -227,6 +243,27 @@ def ecc_normalized_convolution(ctx: Context, plan: FilterPlan, signal, field, ou
     _check(lib().ecc_normalized_convolution(ctx.h, plan.h, batch, ny, nx, _ptr(signal), _ld(signal),
                                             _ptr(field), _ld(field), _ptr(out), _ld(out), precision,
                                             _stream(stream)))
+    return out
+
+
+def ecc_joint_convolution(ctx: Context, plan: FilterPlan, signal, angle, scale, normalized=False, out=None,
+                          stream=None):
+    """Extended convolution with joint rotation (angle) and scale fields, or the normalised
+    smoothing (normalized=True); (ny, nx) or (batch, ny, nx) float32 device tensors."""
+    import torch
+    for t, n in ((signal, "signal"), (angle, "angle"), (scale, "scale")):
+        _img(t, n)
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    _img(out, "out")
+    ny, nx = signal.shape[-2], signal.shape[-1]
+    batch = signal.shape[0] if signal.dim() == 3 else 1
+    for t in (signal, angle, scale, out):
+        if t.dim() == 3 and t.stride(0) != t.shape[-2] * t.stride(-2):
+            raise ValueError("batched images must be stacked with image stride ny * ld")
+    _check(lib().ecc_joint_convolution(ctx.h, plan.h, batch, ny, nx, _ptr(signal), _ld(signal), _ptr(angle),
+                                       _ld(angle), _ptr(scale), _ld(scale), _ptr(out), _ld(out),
+                                       1 if normalized else 0, _stream(stream)))
     return out
 
 

@@ -10,13 +10,13 @@ LIB_PATH = os.path.join(HERE, "libecc.so")
 ECC_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory", 4: "HIP error",
           5: "plan mismatch", 6: "internal error"}
-GROUP_ROTATION, GROUP_SCALE = 0, 1
+GROUP_ROTATION, GROUP_SCALE, GROUP_ROTATION_SCALE = 0, 1, 2
 CORRELATION, CONVOLUTION = 0, 1
 PREC_FP32, PREC_MFMA_FP16_HILO, PREC_MFMA_BF16_HILO = 0, 1, 2
 STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED = 0, 1, 2
 # ecc_ws_call: the calls whose workspace ecc_workspace_size reports
 (WS_EXTENDED_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_SCALE_SMOOTH, WS_MATCH_ROTATIONS,
- WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION, WS_NORMALIZED_CONVOLUTION) = range(7)
+ WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION, WS_NORMALIZED_CONVOLUTION, WS_JOINT_CONVOLUTION) = range(8)
 
 
 class GroupParams(C.Structure):
@@ -77,10 +77,12 @@ PROTOS = {
     "ecc_filter_plan_from_components": [_P, _I, _P, _I, _I, C.POINTER(GroupParams), _P, C.POINTER(_P)],
     "ecc_filter_plan_get_components": [_P, _P, _P],
     "ecc_filter_plan_info": [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],
+    "ecc_filter_plan_component_count": [_P, C.POINTER(_I)],
     "ecc_filter_plan_destroy": [_P],
     "ecc_extended": [_P, _I, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_scale_smooth": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_normalized_convolution": [_P, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _I, _P],
+    "ecc_joint_convolution": [_P, _P, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _I, _I, _P],
     "ecc_match_rotations": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
     "ecc_match_rotations_noalloc": [_P, _P, _I, _I, _P, _I, _I, _P, _P, _I, _I, _P],
     "ecc_extended_backward": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P],

@@ -422,6 +422,53 @@ ecc_status ecc_filter_plan_create(ecc_context ctx, ecc_group group, const float*
                                     plan->comps64.as<cx<double>>()));
     plan->parity.assign(plan->U, 1.f);   // radial components: F_k(-x) = F_k(x)
     plan->symmetric = 1;
+  } else if (group == ECC_GROUP_ROTATION_SCALE) {
+    ECC_REQ(filter != nullptr, "filter is NULL");
+    ECC_REQ(Sz >= 3 && Sz <= 255 && Sz % 2 == 1, "S must be odd, 3 <= S <= 255");
+    const int R = (Sz - 1) / 2;
+    const int n = (gp && gp->scale_components > 0) ? gp->scale_components : 9;
+    const double smin = (gp && gp->scale_min > 0) ? gp->scale_min : 1.0;
+    const double smax = (gp && gp->scale_max > 0) ? gp->scale_max : 2.0;
+    const double fac = (gp && gp->scale_period_factor > 0) ? gp->scale_period_factor : 1.5;
+    ECC_REQ(n % 2 == 1 && n <= 255, "scale_components must be odd and <= 255 for joint plans");
+    ECC_REQ(smin <= smax && fac >= 1.0, "need scale_min <= scale_max and scale_period_factor >= 1");
+    int M = (gp && gp->angular_samples > 0) ? gp->angular_samples : 0;
+    if (M == 0) {
+      const int need = std::max(8 * (2 * K + 1), 4 * (int)std::ceil(2.0 * 3.14159265358979323846 * R));
+      M = 1;
+      while (M < need) M *= 2;
+    }
+    ECC_REQ(K >= 0 && 2 * K + 2 <= M && M <= 2048, "need 0 <= K <= M/2 - 1 and angular_samples <= 2048");
+    const double u_lo = -std::log(smax), u_hi = std::log((double)R) - std::log(smin);
+    const double L = fac * (u_hi - u_lo);
+    ECC_REQ(L > 0.0, "empty log-radial range (R = 1 with scale_min = scale_max = 1)");
+    const int U = (K + 1) * n - (n - 1) / 2;
+    ECC_REQ(U <= 4096, "too many components");
+    plan->S = Sz;
+    plan->R = R;
+    plan->K = K;
+    plan->U = U;
+    plan->M = M;
+    plan->joint_n = n;
+    plan->joint_om1 = 2.0 * 3.14159265358979323846 / L;
+    DevBuf ftmp, ctmp;
+    ECC_HIP(ftmp.ensure((size_t)(n + 2) * (2 * K + 1) * sizeof(cx<double>)));
+    ECC_HIP(ctmp.ensure((size_t)(2 * K + 1) * n * sizeof(cx<double>)));
+    ECC_HIP(plan->comps64.ensure((size_t)U * Sz * Sz * sizeof(cx<double>)));
+    ECC_HIP(launch_joint_components(st, filter, Sz, K, M, n, u_lo, u_hi, L, ftmp.as<cx<double>>(),
+                                    ctmp.as<cx<double>>(), plan->comps64.as<cx<double>>()));
+    plan->weights.assign(U, 2.f);
+    plan->weights[0] = 1.f;
+    plan->parity.resize(U);
+    {
+      const int h = (n - 1) / 2;
+      for (int c = 0; c < U; ++c) {
+        const int k = c <= h ? 0 : 1 + (c - (h + 1)) / n;
+        plan->parity[c] = (k % 2) ? -1.f : 1.f;   // F_{k,l}(-x) = (-1)^k F_{k,l}(x)
+      }
+    }
+    plan->symmetric = 1;
+    ECC_HIP(hipStreamSynchronize(st));   // temporaries above are freed on return
   } else {
     return fail(ECC_ERR_INVALID_ARGUMENT, "unknown group");
   }
@@ -455,7 +502,7 @@ ecc_status ecc_filter_plan_from_components(ecc_context ctx, ecc_group group, con
     plan->weights.assign(K + 1, 2.f);
     plan->weights[0] = 1.f;
   } else {
-    return fail(ECC_ERR_INVALID_ARGUMENT, "unknown group");
+    return fail(ECC_ERR_INVALID_ARGUMENT, "unknown group (rotation-and-scale plans are built from a filter only)");
   }
   plan->S = Sz;
   plan->R = (Sz - 1) / 2;
@@ -486,6 +533,12 @@ ecc_status ecc_filter_plan_info(ecc_filter_plan plan, int* Sz, int* K, int* M) {
   if (Sz) *Sz = plan->S;
   if (K) *K = plan->K;
   if (M) *M = plan->M;
+  return ECC_OK;
+}
+
+ecc_status ecc_filter_plan_component_count(ecc_filter_plan plan, int* U) {
+  ECC_REQ(plan && U, "NULL argument");
+  *U = plan->U;
   return ECC_OK;
 }
 
@@ -526,7 +579,10 @@ ecc_status geometry(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, hipSt
 
 }  // namespace
 namespace ecc {
-ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx) {
+ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx, bool joint) {
+  ECC_REQ(joint == (plan->group == ECC_GROUP_ROTATION_SCALE),
+          joint ? "ecc_joint_convolution needs a rotation-and-scale plan"
+                : "rotation-and-scale plans need both fields: use ecc_joint_convolution");
   ECC_REQ(batch >= 1 && batch <= 65535, "batch must be in [1, 65535]");
   ECC_REQ(ny >= 1 && nx >= 1 && ny <= 4096 && nx <= 4096, "image sides must be in [1, 4096]");
   ECC_REQ(plan->S <= std::min(ny, nx) || plan->group == ECC_GROUP_SCALE,
@@ -909,6 +965,49 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
   return ECC_OK;
 }
 
+ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
+                                 const float* signal, int ld_signal, const float* angle, int ld_angle,
+                                 const float* scale_, int ld_scale, float* out, int ld_out, int normalized,
+                                 void* stream) {
+  ECC_REQ(ctx && plan, "NULL context or plan");
+  ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
+  ECC_REQ(signal && angle && scale_ && out, "NULL image pointer");
+  ECC_TRY(validate_images(plan, batch, ny, nx, true));
+  ECC_REQ(ld_signal >= nx && ld_angle >= nx && ld_scale >= nx && ld_out >= nx, "row strides must be >= nx");
+  const size_t bo = (size_t)batch * ny * ld_out * sizeof(float);
+  ECC_REQ(!overlaps(out, bo, signal, (size_t)batch * ny * ld_signal * sizeof(float)) &&
+              !overlaps(out, bo, angle, (size_t)batch * ny * ld_angle * sizeof(float)) &&
+              !overlaps(out, bo, scale_, (size_t)batch * ny * ld_scale * sizeof(float)),
+          "out aliases an input");
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = S(stream);
+  WsUse wu(ctx, st);
+  Geometry g{};
+  ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
+  const int nsig = normalized ? 2 : 1, U = plan->U;
+  const long long pS = (long long)ny * ld_signal, pO = (long long)ny * ld_out;
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, U, nsig, false)));
+  cx<float>* Bk = ctx->ws.as<cx<float>>();
+  cx<float>* C = Bk + (long long)batch * nsig * U * ny * g.Px;
+  JointField jf{};
+  jf.theta = angle;
+  jf.plane_t = (long long)ny * ld_angle;
+  jf.ld_t = ld_angle;
+  jf.scale = scale_;
+  jf.plane_s = (long long)ny * ld_scale;
+  jf.ld_s = ld_scale;
+  jf.om1 = plan->joint_om1;
+  const long long pBk = (long long)ny * g.Px, pBs = pBk * U, pBi = pBs * nsig;
+  RowCfg r1 = row_config(*g.Tx, nx, sizeof(cx<float>));
+  ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+  mark(ctx, 0, st);
+  ECC_HIP(launch_conv_rows_fwd_joint(st, r1, batch, signal, pS, ld_signal, jf, normalized ? 1 : 0, nsig, Bk, pBk,
+                                     pBs, pBi, g.Px, ny, nx, U, plan->joint_n, g.Tx->desc, g.Tx->f()));
+  mark(ctx, 1, st);
+  ECC_TRY(conv_finish(ctx, plan, g, batch, Bk, nsig, C, out, pO, ld_out, st));
+  return ECC_OK;
+}
+
 ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, int nx, const float* signal,
                                int ld, int n_angles, float* best_score, int* best_index, int ld_out,
                                ecc_precision prec, void* stream) {
@@ -1277,6 +1376,9 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       else *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 2, false);
       return ECC_OK;
     }
+    case ECC_WS_JOINT_CONVOLUTION:
+      *bytes = ws_conv_two_pass(batch, ny, Px, U, 2, false);
+      return ECC_OK;
     case ECC_WS_MATCH_ROTATIONS:
       ECC_REQ(batch == 1, "matching takes one image");
       ECC_TRY(strat(ECC_CORRELATION, 1, tc, &tiled));
@@ -1306,7 +1408,7 @@ ecc_status ecc_workspace_size(ecc_context ctx, int call, ecc_filter_plan plan, i
                               size_t* bytes) {
   ECC_REQ(ctx && plan && bytes, "NULL argument");
   ECC_REQ(plan->ctx == ctx, "plan belongs to another context");
-  ECC_TRY(validate_images(plan, batch, ny, nx));
+  ECC_TRY(validate_images(plan, batch, ny, nx, call == ECC_WS_JOINT_CONVOLUTION));
   if (call == ECC_WS_BACKWARD_CONVOLUTION || call == ECC_WS_BACKWARD_CORRELATION)
     ECC_REQ(plan->group == ECC_GROUP_ROTATION, "the adjoint needs a rotation plan");
   if (call == ECC_WS_MATCH_ROTATIONS) ECC_REQ(plan->group == ECC_GROUP_ROTATION, "matching needs a rotation plan");

@@ -110,7 +110,9 @@ Field make_field(ecc_filter_plan plan, const float* f, long long plane, int ld, 
 ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int batch, int ny, int nx,
                         const float* signal, int ld_signal, const float* field, int ld_field,
                         float* out, int ld_out, hipStream_t st, void* saved);
-ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx);
+// Common checks of a call's images; `joint`: the call takes rotation-and-scale plans (and
+// only those), else it refuses them.
+ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx, bool joint = false);
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 
 }  // namespace ecc

@@ -110,6 +110,8 @@ struct ecc_filter_plan_s {
   double field_mul = 1.0;
   int log_mode = 0;
   int sig_norm = 0;   // divide the signal by field^2 (scale group)
+  int joint_n = 0;    // joint rotation and scale plans: log-radial modes n (odd), else 0
+  double joint_om1 = 0.0;   // omega_1 = 2 pi / L
   std::mutex mu;
   std::map<std::pair<int, int>, std::unique_ptr<Spectrum>> spectra;
   std::map<int, std::unique_ptr<Spectrum>> tile_spectra;   // N -> U planes of N x N

@@ -47,12 +47,32 @@ hipError_t launch_match_rows(hipStream_t s, const RowCfg& c, const cx<float>* T,
                              const float* w, float scale, int n_angles, const float* angle_tab,
                              const FftDesc& d, const cx<float>* tw);
 
+// joint rotation and scale fields: angle theta(q) and scale s(q) of every pixel
+struct JointField {
+  const float* theta;
+  long long plane_t;
+  int ld_t;
+  const float* scale;
+  long long plane_s;
+  int ld_s;
+  double om1;   // omega_1 = 2 pi / L of the log-radial modes
+};
+
 // ---- convolution path
 hipError_t launch_conv_rows_fwd(hipStream_t s, const RowCfg& c, int batch, const float* H,
                                 long long planeH, int ldH, const Field& fld, int sig_norm,
                                 int nsig, cx<float>* Bk, long long planeBk, long long planeBsig,
                                 long long planeBimg, int ldB, int ny, int nx, int U,
                                 const FftDesc& d, const cx<float>* tw);
+// the same for joint plans (components in the half-set order k = 0: l = 0..h; k = 1..K:
+// l = -h..h; n = 2h + 1 log-radial modes)
+hipError_t launch_conv_rows_fwd_joint(hipStream_t s, const RowCfg& c, int batch, const float* H, long long planeH,
+                                      int ldH, const JointField& jf, int sig_norm, int nsig, cx<float>* Bk,
+                                      long long planeBk, long long planeBsig, long long planeBimg, int ldB, int ny,
+                                      int nx, int U, int n, const FftDesc& d, const cx<float>* tw);
+// joint plan components (float64): f_tmp (n + 2) x (2K + 1), c_tmp (2K + 1) x n, comps U x S x S
+hipError_t launch_joint_components(hipStream_t s, const float* F, int S, int K, int M, int n, double u_lo,
+                                   double u_hi, double L, cx<double>* f_tmp, cx<double>* c_tmp, cx<double>* comps);
 hipError_t launch_conv_cols(hipStream_t s, const ColCfg& c, int batch, const cx<float>* Bk,
                             long long planeBk, long long planeBsig, long long planeBimg, int ldB,
                             const cx<float>* Fh, long long planeFk, int ldF, int fullplane,

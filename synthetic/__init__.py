@@ -9,6 +9,8 @@ consumes); the oracle upcasts the same float32 values to float64, so both sides
 see bit-identical inputs.
 
 Recipes (the paper has no datasets for this path; these stand in for its images):
+  * joint rotation and scale smoothing: the block image, an anisotropic Gaussian, the vortex
+            angle field and a smooth scale field in [1, 2]
   * line-integral convolution: white U[0,1] noise, a long narrow anisotropic Gaussian
             (elongated along x), and the angle of a vortex vector field plus a smooth
             seeded perturbation (stands in for the paper's vector-field figure)
@@ -27,6 +29,7 @@ __all__ = [
     "blurred_noise", "random_filter", "theta_field", "scale_field", "block_image",
     "rotation_config", "matching_scene", "scale_config", "batch_shapes",
     "batch_instance", "adjoint_config", "anisotropic_gaussian", "vortex_field", "lic_config",
+    "joint_config",
 ]
 
 
@@ -191,3 +194,13 @@ def lic_config(n=1024, S=31, seeds=(50, 51), sigma_along=8.0, sigma_across=1.5):
     """White noise image, anisotropic Gaussian filter and vortex angle field."""
     img = np.random.default_rng(seeds[0]).random((n, n)).astype(np.float32)
     return img, anisotropic_gaussian(S, sigma_along, sigma_across), vortex_field((n, n), seeds[1])
+
+
+def joint_config(n=1024, S=31, seeds=(60, 61, 62, 63), sigma_along=1.8, sigma_across=0.7, s_max=2.0):
+    """Image (blurred noise plus blocks), anisotropic Gaussian filter, angle field and scale
+    field in [1, s_max] (log-uniform, spatially smooth)."""
+    img = block_image((n, n), seeds[0], seeds[1])
+    filt = anisotropic_gaussian(S, sigma_along, sigma_across)
+    theta = vortex_field((n, n), seeds[2])
+    s = scale_field((n, n), seeds[3], 1.0, s_max)
+    return img, filt, theta, s

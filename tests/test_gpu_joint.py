@@ -1,0 +1,124 @@
+"""Joint rotation and scale fields on the GPU against the float64 oracle: the plan's
+components (k, l), the extended convolution with both fields and the normalised smoothing
+on ragged shapes, batches and the 1024 x 1024 workload. Tolerance rel-L2 and rel-inf 1e-5."""
+import numpy as np
+import pytest
+
+from oracle.joint import JointParams, joint_components, joint_conv_fft, joint_smooth
+from synthetic import anisotropic_gaussian, blurred_noise, joint_config, scale_field, vortex_field
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def relinf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    import paper_2006_13188_amd as E_
+    assert torch.cuda.is_available()
+    E_.lib()
+    return E_
+
+
+@pytest.fixture(scope="module")
+def ctx(E):
+    c = E.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def plan_for(E, ctx, F, p):
+    return E.FilterPlan.joint(ctx, dev(F), p.K, n_log=p.n_log, scale_min=p.s_min, scale_max=p.s_max,
+                              period_factor=p.period_factor)
+
+
+@pytest.mark.parametrize("S,K,n", [(15, 4, 7), (9, 2, 5), (31, 8, 9)])
+def test_components_match_the_oracle(E, ctx, S, K, n):
+    p = JointParams(K=K, n_log=n, s_min=1.0, s_max=2.0)
+    F = anisotropic_gaussian(S, S / 8.0, S / 20.0)
+    plan = plan_for(E, ctx, F, p)
+    got = host(plan.components()).astype(np.complex128)
+    ks, ls, ws, ref = joint_components(F.astype(np.float64), p)
+    assert got.shape == ref.shape
+    assert rel2(got, ref) <= 1e-6, rel2(got, ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("normalized", [False, True])
+@pytest.mark.parametrize("shape,S,K,n", [((97, 130), 15, 4, 7), ((64, 64), 9, 3, 5), ((130, 111), 21, 6, 9)])
+def test_joint_convolution_parity(E, ctx, shape, S, K, n, normalized):
+    p = JointParams(K=K, n_log=n, s_min=1.0, s_max=2.0)
+    F = anisotropic_gaussian(S, S / 8.0, S / 20.0)
+    img = blurred_noise(shape, 70 + S)
+    th = vortex_field(shape, 71 + S, sigma=6.0)
+    s = scale_field(shape, 72 + S, 1.0, 2.0, sigma=5.0)
+    print(f"joint shape={shape} S={S} K={K} n={n} normalized={normalized}", flush=True)
+    plan = plan_for(E, ctx, F, p)
+    got = host(E.ecc_joint_convolution(ctx, plan, dev(img), dev(th), dev(s), normalized)).astype(np.float64)
+    args = (img.astype(np.float64), th.astype(np.float64), s.astype(np.float64), F.astype(np.float64), p)
+    ref = joint_smooth(*args)[0] if normalized else joint_conv_fft(*args)
+    assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    plan.close()
+
+
+def test_joint_batch(E, ctx):
+    p = JointParams(K=3, n_log=5, s_min=1.0, s_max=2.0)
+    F = anisotropic_gaussian(11, 1.5, 0.7)
+    B, shape = 3, (70, 90)
+    imgs = np.stack([blurred_noise(shape, 80 + b) for b in range(B)])
+    ths = np.stack([vortex_field(shape, 85 + b, sigma=5.0) for b in range(B)])
+    ss = np.stack([scale_field(shape, 90 + b, 1.0, 2.0, sigma=5.0) for b in range(B)])
+    plan = plan_for(E, ctx, F, p)
+    got = host(E.ecc_joint_convolution(ctx, plan, dev(imgs), dev(ths), dev(ss), True)).astype(np.float64)
+    for b in range(B):
+        ref = joint_smooth(imgs[b].astype(np.float64), ths[b].astype(np.float64), ss[b].astype(np.float64),
+                           F.astype(np.float64), p)[0]
+        assert rel2(got[b], ref) <= TOL and relinf(got[b], ref) <= TOL
+    plan.close()
+
+
+def test_joint_plans_need_the_joint_call(E, ctx):
+    p = JointParams(K=2, n_log=5)
+    plan = plan_for(E, ctx, anisotropic_gaussian(9, 1.5, 0.7), p)
+    img = dev(np.ones((32, 32), np.float32))
+    with pytest.raises(E.EccError):
+        E.ecc_extended(ctx, E.CONVOLUTION, plan, img, img)
+    rplan = E.FilterPlan.rotation(ctx, dev(anisotropic_gaussian(9, 1.5, 0.7)), 2)
+    with pytest.raises(E.EccError):
+        E.ecc_joint_convolution(ctx, rplan, img, img, img)
+    rplan.close()
+    plan.close()
+
+
+def test_full_size_joint_smoothing(E, ctx):
+    """The joint workload: 1024 x 1024 block image, 31 x 31 anisotropic Gaussian
+    (sigma 1.8 along, 0.7 across), K = 8, 9 log-radial modes (77 components), vortex angle
+    field, scale field in [1, 2]; normalised smoothing."""
+    img, F, th, s = joint_config()
+    p = JointParams(K=8, n_log=9, s_min=1.0, s_max=2.0)
+    print("joint full size 1024^2, 77 components", flush=True)
+    plan = plan_for(E, ctx, F, p)
+    got = host(E.ecc_joint_convolution(ctx, plan, dev(img), dev(th), dev(s), True)).astype(np.float64)
+    ref = joint_smooth(img.astype(np.float64), th.astype(np.float64), s.astype(np.float64), F.astype(np.float64),
+                       p)[0]
+    assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    plan.close()
