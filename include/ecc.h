@@ -429,13 +429,15 @@ typedef struct {
 /* Flags of ecc_batch_plan_create. */
 #define ECC_BATCH_AUTOTUNE 1     /* time every block shape on this device first (once per
                                     context) and choose shapes from the measured costs */
-#define ECC_BATCH_PERSISTENT 2   /* persistent workgroups that loop over host-dealt block
-                                    lists instead of one workgroup per block */
+#define ECC_BATCH_PERSISTENT 2   /* as many workgroups as fit on the device, each taking
+                                    blocks from a device counter, instead of one workgroup
+                                    per block; executions of one such plan must not
+                                    overlap (they share the counter) */
 
 /* Builds a batch plan: every correlation instance that has a block shape (tiled path,
- * the filter's radius R <= 56) is split into blocks; blocks of the same shape go into one
- * kernel launch (at most four shapes), ordered longest first, and the launches are
- * captured once into a HIP graph. Instances without a block shape, and convolutions,
+ * the filter's radius R <= 56) is split into blocks; blocks of the same shape and form go
+ * into one kernel launch, ordered longest first, and the launches are captured once
+ * into a HIP graph as parallel branches. Instances without a block shape, and convolutions,
  * are kept for the per-call path. Plans must outlive the batch plan. Errors:
  * INVALID_ARGUMENT (as ecc_extended for any instance), HIP. */
 ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,

@@ -4,9 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
-#include <functional>
 #include <numeric>
-#include <queue>
+#include <tuple>
 #include <vector>
 
 #include "api_common.hpp"
@@ -190,9 +189,10 @@ struct ecc_batch_plan_s {
   std::vector<ecc_instance> inst;
   struct Shape {
     int N = 0, TV = 0, nwg = 0, nitems = 0;
+    bool sym = false;                // symmetric form (centred spectra)
     std::vector<int> members;        // instance indices, in descriptor order
     std::vector<int> T;              // block side per member
-    DevBuf descs, items, off;
+    DevBuf descs, items, ctr;        // ctr: the persistent form's counter pair
   };
   std::deque<Shape> shapes;         // deque: elements own device buffers and never move
   std::vector<int> rest;             // instances for the per-call path
@@ -200,8 +200,16 @@ struct ecc_batch_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;         // recorded after every execution's last launch
+  // capture-time fork/join: one stream and one event per block shape, so that the
+  // graph holds the shapes' launches as parallel branches and their tails overlap
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> joined;
+  hipEvent_t fork = nullptr;
   int nblocks = 0;
   ~ecc_batch_plan_s() {
+    for (hipEvent_t e : joined) (void)hipEventDestroy(e);
+    for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+    if (fork) (void)hipEventDestroy(fork);
     if (done) (void)hipEventDestroy(done);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -253,10 +261,9 @@ ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
     for (size_t m = 0; m < sh.members.size(); ++m) {
       const ecc_instance& in = bp->inst[sh.members[m]];
       const Spectrum* sp = nullptr;
-      const bool sym = tile_symmetric(sh.N, sh.TV) && rotation_parity(in.plan);
-      ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp, sym ? SPEC_CENTRED : SPEC_CORR));
+      ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp, sh.sym ? SPEC_CENTRED : SPEC_CORR));
       d.push_back(make_desc(in, sh.N, sh.T[m], sp));
-      d.back().sym = sym ? 1 : 0;
+      d.back().sym = sh.sym ? 1 : 0;
     }
     ECC_HIP(sh.descs.ensure(d.size() * sizeof(TileArgs)));
     ECC_HIP(hipMemcpy(sh.descs.p, d.data(), d.size() * sizeof(TileArgs), hipMemcpyHostToDevice));
@@ -284,8 +291,8 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
   ECC_HIP(hipEventCreateWithFlags(&bp->done, hipEventDisableTiming));
   if (flags & ECC_BATCH_AUTOTUNE) ECC_TRY(calibrate_tiles(ctx, bp->cs));
 
-  // ---- block shape per instance
-  std::map<std::pair<int, int>, int> shape_of;
+  // ---- block shape and form per instance
+  std::map<std::tuple<int, int, bool>, int> shape_of;
   for (int i = 0; i < n; ++i) {
     const ecc_instance& in = inst[i];
     TileChoice tc;
@@ -297,13 +304,15 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       bp->rest.push_back(i);
       continue;
     }
-    auto key = std::make_pair(tc.N, tc.TV);
+    const bool sym = tile_symmetric(tc.N, tc.TV) && rotation_parity(in.plan);
+    auto key = std::make_tuple(tc.N, tc.TV, sym);
     auto it = shape_of.find(key);
     if (it == shape_of.end()) {
       it = shape_of.emplace(key, (int)bp->shapes.size()).first;
       bp->shapes.emplace_back();
       bp->shapes.back().N = tc.N;
       bp->shapes.back().TV = tc.TV;
+      bp->shapes.back().sym = sym;
     }
     bp->shapes[it->second].members.push_back(i);
     bp->shapes[it->second].T.push_back(tc.T);
@@ -327,48 +336,44 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
     sh.nitems = (int)items.size();
     bp->nblocks += sh.nitems;
     std::vector<int2> list;
-    std::vector<int> off;
+    for (const Item& it : items) list.push_back(make_int2(it.desc, it.block));
+    sh.nwg = sh.nitems;
     if (flags & ECC_BATCH_PERSISTENT) {
-      // deal the blocks to the least-loaded resident workgroup (greedy, longest first)
-      const int nwg = std::max(1, std::min<int>(sh.nitems, cus * blocks_per_cu(ctx, sh.N, sh.TV)));
-      std::vector<std::vector<int2>> per(nwg);
-      using Load = std::pair<long long, int>;
-      std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-      for (int w = 0; w < nwg; ++w) pq.push({0, w});
-      for (const Item& it : items) {
-        Load l = pq.top();
-        pq.pop();
-        per[l.second].push_back(make_int2(it.desc, it.block));
-        pq.push({l.first + it.cost + 1, l.second});
-      }
-      off.push_back(0);
-      for (auto& v : per) {
-        list.insert(list.end(), v.begin(), v.end());
-        off.push_back((int)list.size());
-      }
-      sh.nwg = nwg;
-    } else {
-      for (const Item& it : items) list.push_back(make_int2(it.desc, it.block));
-      sh.nwg = sh.nitems;
+      // as many workgroups as fit at once; they draw the items, longest first, from the
+      // counter pair (zero now, and zero again after every launch)
+      sh.nwg = std::max(1, std::min<int>(sh.nitems, cus * blocks_per_cu(ctx, sh.N, sh.TV)));
+      ECC_HIP(sh.ctr.ensure(2 * sizeof(int)));
+      ECC_HIP(hipMemset(sh.ctr.p, 0, 2 * sizeof(int)));
     }
     ECC_HIP(sh.items.ensure(std::max<size_t>(1, list.size()) * sizeof(int2)));
     if (!list.empty()) ECC_HIP(hipMemcpy(sh.items.p, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice));
-    if (!off.empty()) {
-      ECC_HIP(sh.off.ensure(off.size() * sizeof(int)));
-      ECC_HIP(hipMemcpy(sh.off.p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
-    }
   }
 
   // ---- capture the launches once
   bool any = false;
   for (auto& sh : bp->shapes) any = any || sh.nitems > 0;
   if (any) {
+    ECC_HIP(hipEventCreateWithFlags(&bp->fork, hipEventDisableTiming));
+    for (auto& sh : bp->shapes) {
+      if (sh.nitems == 0) continue;
+      bp->branch.push_back(nullptr);
+      ECC_HIP(hipStreamCreateWithFlags(&bp->branch.back(), hipStreamNonBlocking));
+      bp->joined.push_back(nullptr);
+      ECC_HIP(hipEventCreateWithFlags(&bp->joined.back(), hipEventDisableTiming));
+    }
     ECC_HIP(hipStreamBeginCapture(bp->cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
+    hipError_t e = hipEventRecord(bp->fork, bp->cs);
+    size_t b = 0;
     for (auto& sh : bp->shapes) {
       if (sh.nitems == 0 || e != hipSuccess) continue;
-      e = launch_tile_batch(bp->cs, sh.N, sh.TV, sh.nwg, sh.descs.as<TileArgs>(),
-                            (flags & ECC_BATCH_PERSISTENT) ? sh.off.as<int>() : nullptr, sh.items.as<int2>());
+      hipStream_t st = bp->branch[b];
+      e = hipStreamWaitEvent(st, bp->fork, 0);
+      if (e == hipSuccess)
+        e = launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(), sh.items.as<int2>(),
+                              sh.nitems, (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);
+      if (e == hipSuccess) e = hipEventRecord(bp->joined[b], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(bp->cs, bp->joined[b], 0);
+      ++b;
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(bp->cs, &g);

@@ -37,14 +37,15 @@ namespace {
 // is the item itself, so the second transform rewrites the same values), and the other two
 // are single units of lanes in waves 0 and 1.
 template <int N, int TV, bool SEPB, bool STACK = false, int NT = kTileThreads, bool SYM = false>
-__device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
+__device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int tile, cx<float>* lds_t,
+                                               int tid = -1) {
   static_assert(!SYM || (N == 128 && NT == 512 && !SEPB), "symmetric one-group form: N = 128, 512 threads");
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr int NQ0 = (N * M + NT - 1) / NT;   // column pass-0 items
   constexpr int NQ2 = (TV * M + NT - 1) / NT;  // row pass-0 items
   constexpr int TR = (TV + LS - 1) / LS, RV = TV / 8;
   constexpr bool PREFETCH = NT == kTileThreads && N <= 96;
-  const int t = threadIdx.x, l = t % LS;
+  const int t = tid >= 0 ? tid : (int)threadIdx.x, l = t % LS;
   const int bq = NT == 512 ? __builtin_amdgcn_readfirstlane(t / LS) : t / LS;
   cx<float>* A = lds_t;
   cx<float>* Bb = SEPB ? A + N * P : A;
@@ -393,7 +394,8 @@ __device__ __forceinline__ void corr_block_one(const TileArgs& a, int img, int t
 // Y2: also accumulate sum_c w_c (kofs + c) Im(z_c G_c) and write it times mulsig as the
 // second output y2 (the field part of the adjoint).
 template <int N, bool STACK = false, bool SYM = false, bool Y2 = false>
-__device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t) {
+__device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int tile, cx<float>* lds_t,
+                                                int tid = -1) {
   constexpr int M = N / 8, P = N + 1, TV = 64, NL = N * M;
   constexpr int NF = NL / (2 * kTileThreads), REM = NL - NF * 2 * kTileThreads;
   constexpr int NH = SYM ? 2 : NF + (REM ? 1 : 0);
@@ -404,7 +406,7 @@ __device__ __forceinline__ void corr_block_pair(const TileArgs& a, int img, int 
   static_assert(!SYM || (N == 96 && NPAIR >= 2 * kTileThreads && NX <= 2 * kTileThreads),
                 "symmetric pair form: N = 96");
   static_assert(REM * 2 <= 2 * kTileThreads, "remainder items exceed one round");
-  const int t = threadIdx.x;
+  const int t = tid >= 0 ? tid : (int)threadIdx.x;
   const int g = t / kTileThreads, tg = t - g * kTileThreads;
   const int bq1 = tg >> 5, l1 = tg & 31;                       // column pass 1 mapping
   const int u4 = t & 63;
@@ -758,52 +760,59 @@ __global__ void __launch_bounds__(2 * kTileThreads) k_tile_stack_pair(TileArgs a
 }
 
 // Batches of independent instances (every instance one image); item = (descriptor
-// index, block index).
+// index, block index). Every launch holds the instances of one block shape and one form
+// (plain or symmetric), so each kernel inlines a single block routine.
+template <int N, int TV>
+constexpr bool tile_sym_form() {
+  return (N == 96 && TV == 64) || N == 128;
+}
+
+// tid >= 0: the thread index, passed in (see the persistent form)
+template <int N, int TV, bool SEPB, int HV, bool SYM>
+__device__ __forceinline__ void batch_block(const TileArgs& a, int blk, cx<float>* lds, int tid = -1) {
+  if constexpr (HV == 2) corr_block_pair<N, false, SYM>(a, 0, blk, lds, tid);
+  else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), SYM>(a, 0, blk, lds, tid);
+}
+
 // Item-table form: workgroup b runs item b. The host orders the items by decreasing
 // cost, so the hardware dispatcher, which starts workgroups in order as CUs free up,
 // schedules them longest first.
-template <int N, int TV, bool SEPB, int HV>
+template <int N, int TV, bool SEPB, int HV, bool SYM>
 __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_items(const TileArgs* __restrict__ descs,
                                                                  const int2* __restrict__ items) {
   extern __shared__ cx<float> lds_t[];
   const int2 it = items[blockIdx.x];
-  const TileArgs& a = descs[it.x];
-  if constexpr (HV == 2 && N == 96) {
-    if (a.sym) corr_block_pair<N, false, true>(a, 0, it.y, lds_t);
-    else corr_block_pair<N>(a, 0, it.y, lds_t);
-  } else if constexpr (HV == 2) {
-    corr_block_pair<N>(a, 0, it.y, lds_t);
-  } else if constexpr (N == 128 && !SEPB) {
-    if (a.sym) corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), true>(a, 0, it.y, lds_t);
-    else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
-  } else {
-    corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
-  }
+  batch_block<N, TV, SEPB, HV, SYM>(descs[it.x], it.y, lds_t);
 }
 
-// Persistent form: workgroup w runs the blocks items[off[w] .. off[w+1]) one after
-// another (the host deals the items over the workgroups, longest first).
-template <int N, int TV, bool SEPB, int HV>
+// Persistent form: a grid of resident workgroups takes the items (ordered by decreasing
+// cost) one at a time from the counter ctr[0]. A workgroup that draws past the end counts
+// itself out in ctr[1]; the last one to do so sets both counters back to zero, so the next
+// launch (stream order) starts from a clean state without a separate clearing step.
+template <int N, int TV, bool SEPB, int HV, bool SYM>
 __global__ void __launch_bounds__((tile_nt<N, HV>())) k_tile_batch(const TileArgs* __restrict__ descs,
-                                                                 const int* __restrict__ off,
-                                                                 const int2* __restrict__ items) {
+                                                                 const int2* __restrict__ items,
+                                                                 int nitems, int* __restrict__ ctr) {
   extern __shared__ cx<float> lds_t[];
-  const int w = blockIdx.x;
-  const int i0 = off[w], i1 = off[w + 1];
-  for (int i = i0; i < i1; ++i) {
+  int* slot = reinterpret_cast<int*>(lds_t);
+  for (;;) {
+    __syncthreads();   // the previous block has finished with the LDS
+    if (threadIdx.x == 0) *slot = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int i = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();   // every thread has read the slot before the block reuses the LDS
+    if (i >= nitems) break;
     const int2 it = items[i];
-    const TileArgs& a = descs[it.x];
-    if constexpr (HV == 2 && N == 96) {
-      if (a.sym) corr_block_pair<N, false, true>(a, 0, it.y, lds_t);
-      else corr_block_pair<N>(a, 0, it.y, lds_t);
-    } else if constexpr (HV == 2) {
-      corr_block_pair<N>(a, 0, it.y, lds_t);
-    } else if constexpr (N == 128 && !SEPB) {
-      if (a.sym) corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>(), true>(a, 0, it.y, lds_t);
-      else corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
-    } else {
-      corr_block_one<N, TV, SEPB, false, tile_nt<N, 1>()>(a, 0, it.y, lds_t);
-    }
+    // the thread index through an empty asm statement: what the block routine derives
+    // from it (twiddles in registers, addresses) is then recomputed for every block
+    // instead of being hoisted out of the loop and held live across it
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    batch_block<N, TV, SEPB, HV, SYM>(descs[it.x], it.y, lds_t, tid);
+  }
+  if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+    atomicExch(&ctr[0], 0);
+    atomicExch(&ctr[1], 0);
   }
 }
 
@@ -875,7 +884,12 @@ hipError_t launch_stack_kernel(hipStream_t s, unsigned nblk, const TileArgs& a, 
 
 template <int N, int TV, bool SEPB, int HV>
 hipError_t prepare_tile_kernel() {
-  hipError_t e = allow_lds(k_tile_batch<N, TV, SEPB, HV>);
+  hipError_t e = allow_lds(k_tile_batch<N, TV, SEPB, HV, false>);
+  if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV, false>);
+  if constexpr (tile_sym_form<N, TV>()) {
+    if (e == hipSuccess) e = allow_lds(k_tile_batch<N, TV, SEPB, HV, true>);
+    if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV, true>);
+  }
   if (e == hipSuccess) {
     if constexpr (HV == 2) {
       e = allow_lds(k_tile_stack_pair<N>);
@@ -889,7 +903,6 @@ hipError_t prepare_tile_kernel() {
       }
     }
   }
-  if (e == hipSuccess) e = allow_lds(k_tile_items<N, TV, SEPB, HV>);
   if (e != hipSuccess) return e;
   if constexpr (HV == 2) {
     e = allow_lds(k_tile_corr_pair<N>);
@@ -968,7 +981,12 @@ hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float
   return hipErrorInvalidValue;
 }
 
-bool tile_symmetric(int N, int TV) { return (N == 96 && TV == 64) || N == 128; }
+bool tile_symmetric(int N, int TV) {
+#define ECC_TSY(n, tv, sb, hv) if (N == n && TV == tv) return tile_sym_form<n, tv>();
+  ECC_TILE_CONFIGS(ECC_TSY)
+#undef ECC_TSY
+  return false;
+}
 bool tile_has_y2(int N, int TV) {
 #define ECC_TY(n, tv, sb, hv) if (N == n && TV == tv) return hv == 2;
   ECC_TILE_CONFIGS(ECC_TY)
@@ -1019,7 +1037,7 @@ int tile_blocks_per_cu(int N, int TV) {
   int nb = 0;
 #define ECC_TO(n, tv, sb, hv)                                                                   \
   if (N == n && TV == tv) {                                                                     \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_items<n, tv, sb, hv>,          \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_items<n, tv, sb, hv, false>,   \
                                                      tile_nt<n, hv>(),                         \
                                                      tile_lds<n, tv, sb, hv>()) != hipSuccess)  \
       nb = 1;                                                                                   \
@@ -1030,26 +1048,34 @@ int tile_blocks_per_cu(int N, int TV) {
   return 1;
 }
 
-hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileArgs* descs, const int* off,
-                             const int2* items) {
-  if (nwg < 1) return hipErrorInvalidValue;
-  if (off == nullptr) {   // item-table form: one workgroup per item
-#define ECC_TIT(n, tv, sb, hv)                                                                   \
-  if (N == n && TV == tv) {                                                                     \
-    hipLaunchKernelGGL((k_tile_items<n, tv, sb, hv>), dim3(nwg), dim3(tile_nt<n, hv>()),         \
-                       (tile_lds<n, tv, sb, hv>()), s, descs, items);                            \
-    return last();                                                                               \
+template <int N, int TV, bool SEPB, int HV, bool SYM>
+hipError_t launch_batch_kernel(hipStream_t s, int nwg, const TileArgs* descs, const int2* items, int nitems,
+                               int* ctr) {
+  constexpr size_t lds = tile_lds<N, TV, SEPB, HV>();
+  if (ctr == nullptr)
+    hipLaunchKernelGGL((k_tile_items<N, TV, SEPB, HV, SYM>), dim3(nwg), dim3(tile_nt<N, HV>()), lds, s, descs,
+                       items);
+  else
+    hipLaunchKernelGGL((k_tile_batch<N, TV, SEPB, HV, SYM>), dim3(nwg), dim3(tile_nt<N, HV>()), lds, s, descs,
+                       items, nitems, ctr);
+  return last();
+}
+
+template <int N, int TV, bool SEPB, int HV>
+hipError_t launch_batch_form(hipStream_t s, bool sym, int nwg, const TileArgs* descs, const int2* items,
+                             int nitems, int* ctr) {
+  if constexpr (tile_sym_form<N, TV>()) {
+    if (sym) return launch_batch_kernel<N, TV, SEPB, HV, true>(s, nwg, descs, items, nitems, ctr);
   }
-    ECC_TILE_CONFIGS(ECC_TIT)
-#undef ECC_TIT
-    return hipErrorInvalidValue;
-  }
-#define ECC_TBL(n, tv, sb, hv)                                                                   \
-  if (N == n && TV == tv) {                                                                     \
-    hipLaunchKernelGGL((k_tile_batch<n, tv, sb, hv>), dim3(nwg), dim3(tile_nt<n, hv>()),         \
-                       (tile_lds<n, tv, sb, hv>()), s, descs, off, items);                       \
-    return last();                                                                               \
-  }
+  if (sym) return hipErrorInvalidValue;
+  return launch_batch_kernel<N, TV, SEPB, HV, false>(s, nwg, descs, items, nitems, ctr);
+}
+
+hipError_t launch_tile_batch(hipStream_t s, int N, int TV, bool sym, int nwg, const TileArgs* descs,
+                             const int2* items, int nitems, int* ctr) {
+  if (nwg < 1 || nitems < 1 || (ctr == nullptr && nwg != nitems)) return hipErrorInvalidValue;
+#define ECC_TBL(n, tv, sb, hv) \
+  if (N == n && TV == tv) return launch_batch_form<n, tv, sb, hv>(s, sym, nwg, descs, items, nitems, ctr);
   ECC_TILE_CONFIGS(ECC_TBL)
 #undef ECC_TBL
   return hipErrorInvalidValue;

@@ -171,11 +171,13 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
 hipError_t launch_match_angles(hipStream_t s, int prec, const float* stack, int U, long long npix, int A,
                                const float* dtab, float* score, int* index, int ldOut, int nx);
 int tile_blocks_per_cu(int N, int TV);   // resident workgroups per CU (occupancy query)
-// batches: item = (descriptor index, block index). Persistent form (off != NULL): nwg
-// workgroups, workgroup w runs items[off[w] .. off[w+1]). Item-table form (off == NULL):
-// nwg = number of items, workgroup b runs item b.
-hipError_t launch_tile_batch(hipStream_t s, int N, int TV, int nwg, const TileArgs* descs, const int* off,
-                             const int2* items);
+// batches: item = (descriptor index, block index), all of one block shape and one form
+// (sym: the symmetric form, centred spectra). Item-table form (ctr == NULL): nwg = nitems
+// workgroups, workgroup b runs item b. Persistent form: nwg workgroups take the items in
+// order from the counter pair ctr[0..1], which must be zero at launch and is zero again
+// when the launch ends; launches sharing one counter pair must not overlap.
+hipError_t launch_tile_batch(hipStream_t s, int N, int TV, bool sym, int nwg, const TileArgs* descs,
+                             const int2* items, int nitems, int* ctr);
 hipError_t launch_tile_corr(hipStream_t s, int N, int TV, int batch, const float* H, long long planeH,
                             int ldH, const Field& fld, float* y, long long planeY, int ldY, int ny,
                             int nx, int R, int T, int U, int kofs, const float* w, float scale,
