@@ -15,7 +15,9 @@ Everything here follows "Efficient Spatially Adaptive Convolution and Correlatio
   * scale group and normalisation: Sec. 8, eq. (normalization), normalised signal;
   * normalised filtering with a rotation field (line-integral convolution): Sec. 8;
   * pattern detection (gradient signal and field, consensus filter by voting, peaks): Sec. 5;
-  * joint rotation and scale fields (the Conclusion's future work): joint.py.
+  * joint rotation and scale fields (the Conclusion's future work): joint.py;
+  * steering in 3D (spherical harmonics per radius, Wigner-D combination): Sec. 9,
+    steer3d.py.
 
 Readings where the paper is silent are listed per function (boundary = zero outside
 the image, bilinear polar resampling at the exact grid radii, k = -K..K, etc.).
@@ -37,6 +39,10 @@ from .adjoint import conv_backward, corr_backward
 from .normalized import normalized_conv_brute, normalized_conv_fft, normalized_conv_half
 from .detection import gradient_field, voting_filter, find_peaks, detection_response
 from .joint import JointParams, joint_components, joint_filter_at, joint_conv_brute, joint_conv_fft, joint_smooth
+from .steer3d import (
+    sh_coefficients, half_set, components3d, euler_matrix, wigner_small_d, wigner_D,
+    ext_corr3d_brute, ext_conv3d_brute, ext_corr3d_fft, ext_conv3d_fft,
+)
 from .scale import (
     ScaleParams, scale_components, scale_filter_at, scale_smooth_brute,
     scale_smooth_fft,
@@ -53,4 +59,6 @@ __all__ = [
     "JointParams", "joint_components", "joint_filter_at", "joint_conv_brute", "joint_conv_fft", "joint_smooth",
     "ScaleParams", "scale_components", "scale_filter_at", "scale_smooth_brute",
     "scale_smooth_fft",
+    "sh_coefficients", "half_set", "components3d", "euler_matrix", "wigner_small_d", "wigner_D",
+    "ext_corr3d_brute", "ext_conv3d_brute", "ext_corr3d_fft", "ext_conv3d_fft",
 ]
