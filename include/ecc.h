@@ -455,6 +455,58 @@ ecc_status ecc_batch_execute(ecc_batch_plan bp, void* stream);
 ecc_status ecc_batch_info(ecc_batch_plan bp, int* graph_instances, int* launches, int* blocks);
 ecc_status ecc_batch_plan_destroy(ecc_batch_plan bp);
 
+/* ---------------------------------------------------------------- steering in 3D (Sec. 9)
+ *
+ * Volumes are device float32 arrays [nz][ny][nx], contiguous. A volume plan holds the
+ * spherical-harmonic components of a real filter (Sec. 9, "Filter Decomposition"): the
+ * filter F (S x S x S, centre (R, R, R), R = (S - 1) / 2, voxel offset q = (x, y, z) =
+ * (column, row, slice)) restricted to the ball |q| <= R, with
+ * f_l^m(r) = integral over the unit sphere of F(r w) conj(Y_l^m(w)) at every grid radius,
+ * by Gauss-Legendre quadrature in cos(theta) (M / 2 nodes) times M azimuths, M the
+ * smallest power of two >= max(8 (2K + 1), 4 ceil(2 pi R)), F(r w) trilinear (zero
+ * outside the array); Y_l^m orthonormal with the Condon-Shortley phase, polar angle from
+ * +z, azimuth atan2(y, x). The plan's components are C_{l,m',m}(q) = f_l^m(|q|)
+ * Y_l^{m'}(q / |q|) on the ball (the centre keeps F(0) in l = 0) for the half set of a
+ * real filter, in the order l = 0..K; m' = 0 with m = 0..l; m' = 1..l with m = -l..l,
+ * weights w = 1 for (l, 0, 0) and 2 otherwise: U = sum_l (2 l^2 + 2 l + 1) components. */
+typedef struct ecc_volume_plan_s* ecc_volume_plan;
+
+/* Builds a volume plan from device `filter` (float32 S^3, S odd, 3..63) for band limit
+ * K (0..8). Computed on the device in float64; waits for `stream`. The plan belongs to the
+ * context (freed with it if still alive). Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, HIP. */
+ecc_status ecc_volume_plan_create(ecc_context ctx, const float* filter, int S, int K, void* stream,
+                                  ecc_volume_plan* out);
+ecc_status ecc_volume_plan_destroy(ecc_volume_plan plan);
+/* U (components) and M (azimuth samples of the decomposition); either may be NULL. */
+ecc_status ecc_volume_plan_info(ecc_volume_plan plan, int* U, int* M);
+/* Copies the components (device complex64, U x S^3 interleaved) to `comps`, the host
+ * table (l, m', m) of every component to `table` (3 U ints) and the host weights to
+ * `weights` (U floats); NULL skips an output. Waits for `stream`. */
+ecc_status ecc_volume_plan_components(ecc_volume_plan plan, float* comps, int* table, float* weights,
+                                      void* stream);
+/* Extended correlation / convolution of a volume with a rotation field (Sec. 9; the
+ * definitions of Sec. 2 on Z^3). The rotation at voxel p is R_p = Rz(alpha) Ry(beta)
+ * Rz(gamma) (ZYZ Euler angles in radians, active, acting on (x, y, z)); a rotated filter
+ * is (R F)(q) = F(R^{-1} q), so that Y_l^m(R^{-1} x) = sum_m' D^l_{m'm}(R) Y_l^{m'}(x) with
+ * D^l_{m'm} = e^{-i m' alpha} d^l_{m'm}(beta) e^{-i m gamma} (Wigner's explicit sum).
+ *   correlation: y(p) = sum_q H(p + q) (R_p F)(q) = sum_c w_c Re(D_c(R_p) (H star C_c)(p));
+ *   convolution: y(p) = sum_q H(q) (R_q F)(p - q) = sum_c w_c Re(((H D_c(R_.)) * C_c)(p));
+ * zero outside the volume. Correlation: one forward 3D transform of H, U products and U
+ * inverse transforms, then the per-voxel Wigner-D combination; convolution: U modulated
+ * signals and forward transforms, one weighted sum of products, one inverse. Transform
+ * sizes P = smallest 7-smooth >= max(n + R, 8) per axis; float32 arithmetic with float64
+ * spectra (rounded once) and float64 Wigner-D. Context workspace: (2 U + 1) Pz Py Px
+ * complex64 (ecc_volume_workspace_size); the plan caches its spectra per (op, P) (U Pz Py Px
+ * complex64). signal, alpha, beta, gamma, out: device float32 nz x ny x nx; out must not
+ * alias an input. Errors: INVALID_ARGUMENT, UNSUPPORTED (a transform too long), OUT_OF_MEMORY,
+ * HIP. */
+ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int nz, int ny, int nx,
+                           const float* signal, const float* alpha, const float* beta, const float* gamma,
+                           float* out, void* stream);
+/* Bytes of context workspace ecc_extended_3d takes for these sizes. */
+ecc_status ecc_volume_workspace_size(ecc_context ctx, ecc_volume_plan plan, int nz, int ny, int nx,
+                                     size_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

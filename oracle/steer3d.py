@@ -307,15 +307,15 @@ def fft_size3(n: int, R: int) -> int:
     return n + R
 
 
-def ext_corr3d_fft(H, alpha, beta, gamma, F, K: int, M: int = 0):
+def ext_corr3d_fft(H, alpha, beta, gamma, F, K: int, M: int = 0, parts=None):
     """The FFT route of Sec. 9 (V7, V8): G_c = H correlated with C_c by zero-padded 3D FFTs
-    of n + R per axis, y = sum_c w_c Re(D_c G_c)."""
+    of n + R per axis, y = sum_c w_c Re(D_c G_c). parts: components3d(F, K, M) if known."""
     H = np.asarray(H, dtype=np.float64)
     S = np.asarray(F).shape[0]
     R = (S - 1) // 2
     nz, ny, nx = H.shape
     P = (nz + R, ny + R, nx + R)
-    hs, comps = components3d(F, K, M)
+    hs, comps = parts if parts is not None else components3d(F, K, M)
     D = _D_half(hs, alpha, beta, gamma)
     Hf = np.fft.fftn(H, s=P, axes=(0, 1, 2))
     idx = np.arange(-R, R + 1)
@@ -329,14 +329,15 @@ def ext_corr3d_fft(H, alpha, beta, gamma, F, K: int, M: int = 0):
     return y
 
 
-def ext_conv3d_fft(H, alpha, beta, gamma, F, K: int, M: int = 0):
-    """Convolution by the FFT route (V7, V8): y = Re sum_c w_c ((H D_c) convolved with C_c)."""
+def ext_conv3d_fft(H, alpha, beta, gamma, F, K: int, M: int = 0, parts=None):
+    """Convolution by the FFT route (V7, V8): y = Re sum_c w_c ((H D_c) convolved with C_c).
+    parts: components3d(F, K, M) if known."""
     H = np.asarray(H, dtype=np.float64)
     S = np.asarray(F).shape[0]
     R = (S - 1) // 2
     nz, ny, nx = H.shape
     P = (nz + R, ny + R, nx + R)
-    hs, comps = components3d(F, K, M)
+    hs, comps = parts if parts is not None else components3d(F, K, M)
     D = _D_half(hs, alpha, beta, gamma)
     idx = np.arange(-R, R + 1)
     acc = np.zeros(P, dtype=np.complex128)

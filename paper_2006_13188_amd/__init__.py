@@ -24,7 +24,7 @@ __all__ = [
     "ecc_normalized_convolution", "WS_NORMALIZED_CONVOLUTION",
     "ecc_gradient_field", "ecc_voting_filter", "ecc_find_peaks", "detect_pattern",
     "ecc_joint_convolution", "GROUP_ROTATION_SCALE", "WS_JOINT_CONVOLUTION",
-    "ecc_match_rotations_noalloc",
+    "ecc_match_rotations_noalloc", "VolumePlan", "ecc_extended_3d",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
     "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
@@ -120,6 +120,12 @@ class Context:
         _check(lib().ecc_workspace_allocated(self.h, C.byref(n)))
         return n.value
 
+    def volume_workspace_size(self, plan: "VolumePlan", nz: int, ny: int, nx: int) -> int:
+        """Bytes of context workspace ecc_extended_3d needs for this volume size."""
+        n = C.c_size_t()
+        _check(lib().ecc_volume_workspace_size(self.h, plan.h, nz, ny, nx, C.byref(n)))
+        return n.value
+
     def describe(self, op: int, plan: "FilterPlan", ny: int, nx: int):
         """(strategy, transform length, block side) that ecc_extended would use."""
         s, n, b = C.c_int(), C.c_int(), C.c_int()
@@ -202,6 +208,69 @@ class FilterPlan:
             self.close()
         except Exception:
             pass
+
+
+class VolumePlan:
+    """Spherical-harmonic components of an S x S x S filter up to band limit K (steering
+    in 3D; see ecc_volume_plan_create)."""
+
+    def __init__(self, ctx: Context, filt, K: int, stream=None):
+        import torch
+        if not (isinstance(filt, torch.Tensor) and filt.is_cuda and filt.dtype == torch.float32 and filt.dim() == 3):
+            raise TypeError("filter must be an (S, S, S) float32 tensor on a HIP device")
+        filt = filt.contiguous()
+        h = C.c_void_p()
+        _check(lib().ecc_volume_plan_create(ctx.h, _ptr(filt), filt.shape[-1], K, _stream(stream), C.byref(h)))
+        self.ctx, self.h, self.S, self.K = ctx, h, filt.shape[-1], K
+        ctx._plans.add(self)
+        U, M = C.c_int(), C.c_int()
+        _check(lib().ecc_volume_plan_info(h, C.byref(U), C.byref(M)))
+        self.U, self.M = U.value, M.value
+
+    def components(self, stream=None):
+        """(comps complex64 (U, S, S, S) on the device, table int32 (U, 3) of (l, m', m),
+        weights float32 (U,))."""
+        import numpy as np
+        import torch
+        comps = torch.empty((self.U, self.S, self.S, self.S), dtype=torch.complex64,
+                            device=f"cuda:{self.ctx.device}")
+        table = np.zeros((self.U, 3), dtype=np.int32)
+        w = np.zeros(self.U, dtype=np.float32)
+        _check(lib().ecc_volume_plan_components(self.h, _ptr(comps), table.ctypes.data_as(C.c_void_p),
+                                                w.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return comps, table, w
+
+    def close(self):
+        if self.h:
+            lib().ecc_volume_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ecc_extended_3d(ctx: Context, op: int, plan: VolumePlan, signal, alpha, beta, gamma, out=None, stream=None):
+    """Extended correlation / convolution of an (nz, ny, nx) float32 device volume with the
+    rotation field given by ZYZ Euler angles alpha, beta, gamma (same shape)."""
+    import torch
+    vols = (signal, alpha, beta, gamma)
+    for t, n in zip(vols, ("signal", "alpha", "beta", "gamma")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == 3
+                and t.is_contiguous()):
+            raise TypeError(f"{n} must be a contiguous (nz, ny, nx) float32 tensor on a HIP device")
+        if t.shape != signal.shape:
+            raise ValueError("signal and angle volumes differ in shape")
+    if out is None:
+        out = torch.empty(signal.shape, dtype=torch.float32, device=signal.device)
+    if not (out.is_contiguous() and out.shape == signal.shape and out.dtype == torch.float32):
+        raise ValueError("out must be a contiguous float32 volume of the signal's shape")
+    nz, ny, nx = signal.shape
+    _check(lib().ecc_extended_3d(ctx.h, op, plan.h, nz, ny, nx, _ptr(signal), _ptr(alpha), _ptr(beta), _ptr(gamma),
+                                 _ptr(out), _stream(stream)))
+    return out
 
 
 def ecc_extended(ctx: Context, op: int, plan: FilterPlan, signal, field, out=None, stream=None):

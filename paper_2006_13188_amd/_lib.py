@@ -91,6 +91,12 @@ PROTOS = {
     "ecc_gradient_field": [_P, _I, _I, _I, _P, _I, _P, _P, _I, _P],
     "ecc_voting_filter": [_P, _I, _P, _P, _P],
     "ecc_find_peaks": [_P, _I, _I, _P, _I, _I, C.c_float, _I, _I, _P, _P, _P, _P, _P],
+    "ecc_volume_plan_create": [_P, _P, _I, _I, _P, C.POINTER(_P)],
+    "ecc_volume_plan_destroy": [_P],
+    "ecc_volume_plan_info": [_P, C.POINTER(_I), C.POINTER(_I)],
+    "ecc_volume_plan_components": [_P, _P, _P, _P, _P],
+    "ecc_extended_3d": [_P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P],
+    "ecc_volume_workspace_size": [_P, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_workspace_size": [_P, _I, _P, _I, _I, _I, C.POINTER(C.c_size_t)],
     "ecc_workspace_reserve": [_P, C.c_size_t],
     "ecc_workspace_allocated": [_P, C.POINTER(C.c_size_t)],

@@ -312,6 +312,7 @@ ecc_status ecc_destroy(ecc_context ctx) {
   (void)hipDeviceSynchronize();
   for (ecc_filter_plan p : ctx->plans) delete p;   // plans still alive go with the context
   ctx->plans.clear();
+  destroy_volume_plans(ctx);
   if (ctx->ws_event) (void)hipEventDestroy(ctx->ws_event);
   delete ctx;
   return ECC_OK;

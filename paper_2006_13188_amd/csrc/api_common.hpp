@@ -114,5 +114,7 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
 // only those), else it refuses them.
 ecc_status validate_images(ecc_filter_plan plan, int batch, int ny, int nx, bool joint = false);
 bool overlaps(const void* a, size_t na, const void* b, size_t nb);
+// Frees the volume plans still alive in a context that is being destroyed.
+void destroy_volume_plans(ecc_context ctx);
 
 }  // namespace ecc

@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 
 struct ecc_context_s;
+struct ecc_volume_plan_s;
 
 namespace ecc {
 
@@ -80,6 +81,7 @@ struct ecc_context_s {
   std::map<std::string, int> tuned;   // shape key -> chosen FFT size
   std::vector<hipEvent_t> stage_events;   // measurement hook (see ecc_set_stage_events)
   std::set<ecc_filter_plan_s*> plans;     // live plans made from this context
+  std::set<ecc_volume_plan_s*> vplans;    // live volume plans made from this context
   // measured cost of one full wave of blocks of each tiled shape (N, TV): t = a + b U (ms)
   struct TileCost {
     double a = 0, b = 0;

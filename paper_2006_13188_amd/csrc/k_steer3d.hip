@@ -1,0 +1,366 @@
+// Steering in 3D (Sec. 9): spherical-harmonic components of a filter (float64), and the
+// per-voxel kernels of the volume path (spectral products, Wigner-D combination and
+// modulation).
+//
+// Conventions: volumes are [z][y][x]; the filter's S^3 array has its centre at (R, R, R)
+// and voxel offset q = (x, y, z); polar angle from +z, azimuth atan2(y, x). Spherical
+// harmonics are orthonormal with the Condon-Shortley phase, Y_l^m = lam_l^m(cos t) e^{i m p}.
+// A rotation R = Rz(alpha) Ry(beta) Rz(gamma) acts on filters by (R F)(x) = F(R^{-1} x), so
+// that Y_l^m(R^{-1} x) = sum_m' D^l_{m'm}(R) Y_l^m'(x) with
+// D^l_{m'm} = e^{-i m' alpha} d^l_{m'm}(beta) e^{-i m gamma} (Wigner's explicit sum for d).
+#include <type_traits>
+
+#include "kcommon.hpp"
+
+namespace ecc {
+
+namespace {
+
+// lam_l^m(t) for one m >= 0 (fully normalised, Condon-Shortley phase): lam_m^m from the
+// product formula, then the three-term recurrence in l.
+__device__ double sh_lambda(int l, int m, double t) {
+  const double s = sqrt(fmax(0.0, 1.0 - t * t));
+  double pmm = 0.28209479177387814347;   // 1 / sqrt(4 pi)
+  for (int j = 1; j <= m; ++j) pmm = -sqrt((2.0 * j + 1.0) / (2.0 * j)) * s * pmm;
+  if (l == m) return pmm;
+  double p1 = t * sqrt(2.0 * m + 3.0) * pmm;   // l = m + 1
+  double p0 = pmm;
+  for (int j = m + 2; j <= l; ++j) {
+    const double a = sqrt((4.0 * j * j - 1.0) / ((double)j * j - (double)m * m));
+    const double b = sqrt(((double)(j - 1) * (j - 1) - (double)m * m) / (4.0 * (j - 1) * (j - 1) - 1.0));
+    const double p2 = a * (t * p1 - b * p0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+__device__ double trilinear64(const float* __restrict__ F, int S, double x, double y, double z) {
+  const int R = (S - 1) / 2;
+  const double cx_ = x + R, cy = y + R, cz = z + R;
+  const double fx0 = floor(cx_), fy0 = floor(cy), fz0 = floor(cz);
+  const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+  const double fx = cx_ - fx0, fy = cy - fy0, fz = cz - fz0;
+  double acc = 0.0;
+  for (int dz = 0; dz < 2; ++dz) {
+    const int zz = iz + dz;
+    if (zz < 0 || zz >= S) continue;
+    const double wz = dz ? fz : 1.0 - fz;
+    for (int dy = 0; dy < 2; ++dy) {
+      const int yy = iy + dy;
+      if (yy < 0 || yy >= S) continue;
+      const double wy = dy ? fy : 1.0 - fy;
+      for (int dx = 0; dx < 2; ++dx) {
+        const int xx = ix + dx;
+        if (xx < 0 || xx >= S) continue;
+        const double wx = dx ? fx : 1.0 - fx;
+        acc += wz * wy * wx * (double)F[((long long)zz * S + yy) * S + xx];
+      }
+    }
+  }
+  return acc;
+}
+
+// A[ri][i][m] = sum_j F(r_ri w_ij) e^{-i m phi_j}, m = 0..K (negative m: conjugates), on
+// the sphere of radius r_ri = sqrt(d2[ri]) at polar node t_i = cos(theta_i) and
+// azimuths phi_j = 2 pi j / M.
+__global__ void __launch_bounds__(256) k_sh_azimuth(const float* __restrict__ F, int S, int K, int M, int nt,
+                                                   const double* __restrict__ gl_t, int nr,
+                                                   const int* __restrict__ d2, cx<double>* __restrict__ A) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nr * nt) return;
+  const int ri = id / nt, i = id - ri * nt;
+  const double r = sqrt((double)d2[ri]);
+  const double t = gl_t[i], st = sqrt(fmax(0.0, 1.0 - t * t));
+  double are[kMaxSteerK + 1], aim[kMaxSteerK + 1];
+#pragma unroll
+  for (int m = 0; m <= kMaxSteerK; ++m) are[m] = aim[m] = 0.0;
+  for (int j = 0; j < M; ++j) {
+    double sp, cp;
+    sincospi(2.0 * j / M, &sp, &cp);
+    const double v = trilinear64(F, S, r * st * cp, r * st * sp, r * t);
+    // e^{-i m phi} by repeated multiplication with e^{-i phi}
+    double er = 1.0, ei = 0.0;
+#pragma unroll
+    for (int m = 0; m <= kMaxSteerK; ++m) {
+      if (m <= K) {
+        are[m] += v * er;
+        aim[m] += v * ei;
+      }
+      const double nr_ = er * cp + ei * sp, ni = ei * cp - er * sp;
+      er = nr_;
+      ei = ni;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m <= kMaxSteerK; ++m)
+    if (m <= K) A[((long long)ri * nt + i) * (K + 1) + m] = mk(are[m], aim[m]);
+}
+
+// f[ri][l][m + K] = (2 pi / M) sum_i w_i lam_l^m(t_i) A_m[ri][i] (conj(Y) = lam e^{-i m phi}),
+// A_{-m} = conj(A_m) and lam_l^{-m} = (-1)^m lam_l^m.
+__global__ void __launch_bounds__(256) k_sh_polar(const cx<double>* __restrict__ A, int nr, int nt, int K, int M,
+                                                 const double* __restrict__ gl_t, const double* __restrict__ gl_w,
+                                                 cx<double>* __restrict__ f) {
+  const int W = 2 * K + 1;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nr * (K + 1) * W) return;
+  const int ri = id / ((K + 1) * W), rem = id - ri * (K + 1) * W;
+  const int l = rem / W, m = rem % W - K;
+  cx<double> out = mk(0.0, 0.0);
+  if (m >= -l && m <= l) {
+    const int am = m < 0 ? -m : m;
+    const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+    double sr = 0.0, si = 0.0;
+    for (int i = 0; i < nt; ++i) {
+      const cx<double> a = A[((long long)ri * nt + i) * (K + 1) + am];
+      const double c = gl_w[i] * sh_lambda(l, am, gl_t[i]);
+      sr += c * a.re;
+      si += c * (m < 0 ? -a.im : a.im);
+    }
+    const double q = sg * 2.0 * 3.14159265358979323846 / M;
+    out = mk(q * sr, q * si);
+  }
+  f[id] = out;
+}
+
+// comps[c][z][y][x] = f_l^m(|q|) Y_l^{m'}(q / |q|) on the ball, the centre F(0) for l = 0.
+__global__ void __launch_bounds__(256) k_sh_components(const float* __restrict__ F, int S, int K, int U,
+                                                      const int4* __restrict__ hs, const int* __restrict__ rindex,
+                                                      const cx<double>* __restrict__ f,
+                                                      cx<double>* __restrict__ comps) {
+  const long long S3 = (long long)S * S * S;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)U * S3) return;
+  const int c = (int)(id / S3);
+  const int v = (int)(id - (long long)c * S3);
+  const int R = (S - 1) / 2;
+  const int iz = v / (S * S), iy = (v / S) % S, ix = v % S;
+  const int qx = ix - R, qy = iy - R, qz = iz - R;
+  const int d2 = qx * qx + qy * qy + qz * qz;
+  const int4 h = hs[c];   // (l, m', m, -)
+  cx<double> val = mk(0.0, 0.0);
+  if (d2 == 0) {
+    if (h.x == 0) val = mk((double)F[v], 0.0);
+  } else if (d2 <= R * R) {
+    const double r = sqrt((double)d2);
+    const double t = qz / r;
+    const double ph = atan2((double)qy, (double)qx);
+    const double lam = sh_lambda(h.x, h.y, t);
+    double sp, cp;
+    sincos(h.y * ph, &sp, &cp);
+    const cx<double> fc = f[((long long)rindex[d2] * (K + 1) + h.x) * (2 * K + 1) + h.z + K];
+    const cx<double> y = mk(lam * cp, lam * sp);
+    val = cmul(fc, y);
+  }
+  comps[id] = val;
+}
+
+__global__ void k_real_to_cx(const float* __restrict__ in, cx<float>* __restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = mk(in[i], 0.0f);
+}
+
+// Z[c][v] = A[v] Sp[c][v], c < U
+__global__ void __launch_bounds__(256) k_spec_products(const cx<float>* __restrict__ A,
+                                                      const cx<float>* __restrict__ Sp, long long V, int U,
+                                                      cx<float>* __restrict__ Z) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
+    const cx<float> a = A[v];
+    for (int c = 0; c < U; ++c) Z[(long long)c * V + v] = cmul(a, Sp[(long long)c * V + v]);
+  }
+}
+
+// A[v] = sum_c w_c X[c][v] Sp[c][v]
+__global__ void __launch_bounds__(256) k_spec_accumulate(const cx<float>* __restrict__ X,
+                                                        const cx<float>* __restrict__ Sp, const float* __restrict__ w,
+                                                        long long V, int U, cx<float>* __restrict__ A) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
+    float re = 0.f, im = 0.f;
+    for (int c = 0; c < U; ++c) {
+      const cx<float> p = cmul(X[(long long)c * V + v], Sp[(long long)c * V + v]);
+      re = fmaf(w[c], p.re, re);
+      im = fmaf(w[c], p.im, im);
+    }
+    A[v] = mk(re, im);
+  }
+}
+
+// y[v] = scale Re(in[v])
+__global__ void k_real_part(const cx<float>* __restrict__ in, float* __restrict__ y, long long n, float scale) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = in[i].re * scale;
+}
+
+// ---- Wigner-D per voxel, with the half-set loops unrolled at compile time
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+// terms of Wigner's sum for d^l_{m'm}: k = max(0, m - m') .. min(l + m, l - m')
+constexpr int wig_terms(int l, int mp, int m) { return cmin(l + m, l - mp) - cmax(0, m - mp) + 1; }
+// half-set order: l = 0..K; m' = 0 with m = 0..l; m' = 1..l with m = -l..l
+constexpr int hs_first_m(int mp, int l) { return mp == 0 ? 0 : -l; }
+constexpr int hs_index(int l, int mp, int m) {
+  int c = 0;
+  for (int a = 0; a < l; ++a) c += 2 * a * a + 2 * a + 1;
+  for (int b = 0; b < mp; ++b) c += b == 0 ? l + 1 : 2 * l + 1;
+  return c + m - hs_first_m(mp, l);
+}
+constexpr int term_index(int l, int mp, int m) {
+  int t = 0;
+  for (int a = 0; a <= l; ++a)
+    for (int b = 0; b <= a; ++b)
+      for (int c = hs_first_m(b, a); c <= a; ++c) {
+        if (a == l && b == mp && c == m) return t;
+        t += wig_terms(a, b, c);
+      }
+  return t;
+}
+
+// MODE 0 (correlation): y[v] = scale sum_c w_c Re(D_c G_c[v]); MODE 1 (convolution):
+// M[c][v] = H[v] D_c. coef: Wigner's coefficients in the order of term_index.
+template <int K, int MODE>
+__global__ void __launch_bounds__(256) k_wigner_voxels(const float* __restrict__ alpha, const float* __restrict__ beta,
+                                                      const float* __restrict__ gamma, long long nvox,
+                                                      const double* __restrict__ coef, const float* __restrict__ w,
+                                                      const cx<float>* __restrict__ G, const float* __restrict__ H,
+                                                      float* __restrict__ y, cx<float>* __restrict__ Mout,
+                                                      float scale) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  double sb, cb, sa, ca, sg, cg;
+  sincos(0.5 * (double)beta[v], &sb, &cb);
+  sincos((double)alpha[v], &sa, &ca);
+  sincos((double)gamma[v], &sg, &cg);
+  double cpw[2 * K + 1], spw[2 * K + 1];
+  cpw[0] = spw[0] = 1.0;
+#pragma unroll
+  for (int j = 1; j <= 2 * K; ++j) {
+    cpw[j] = cpw[j - 1] * cb;
+    spw[j] = spw[j - 1] * sb;
+  }
+  // e^{-i m alpha}, e^{-i m gamma} for m = 0..K
+  double ear[K + 1], eai[K + 1], egr[K + 1], egi[K + 1];
+  ear[0] = egr[0] = 1.0;
+  eai[0] = egi[0] = 0.0;
+#pragma unroll
+  for (int j = 1; j <= K; ++j) {
+    ear[j] = ear[j - 1] * ca + eai[j - 1] * sa;
+    eai[j] = eai[j - 1] * ca - ear[j - 1] * sa;
+    egr[j] = egr[j - 1] * cg + egi[j - 1] * sg;
+    egi[j] = egi[j - 1] * cg - egr[j - 1] * sg;
+  }
+  const float h = MODE == 1 ? H[v] : 0.f;
+  float acc = 0.f;
+  static_for<0, K + 1>([&](auto L_) {
+    constexpr int l = decltype(L_)::value;
+    static_for<0, l + 1>([&](auto MP_) {
+      constexpr int mp = decltype(MP_)::value;
+      static_for<hs_first_m(mp, l), l + 1>([&](auto M_) {
+        constexpr int m = decltype(M_)::value;
+        constexpr int t0 = term_index(l, mp, m), k0 = cmax(0, m - mp), nk = wig_terms(l, mp, m);
+        double d = 0.0;
+        static_for<0, nk>([&](auto J_) {
+          constexpr int k = k0 + decltype(J_)::value;
+          d = fma(coef[t0 + decltype(J_)::value], cpw[2 * l + m - mp - 2 * k] * spw[mp - m + 2 * k], d);
+        });
+        // D = e^{-i m' alpha} d e^{-i m gamma}; for m < 0, e^{-i m gamma} = conj(e^{-i |m| gamma})
+        constexpr int am = m < 0 ? -m : m;
+        const double gr = egr[am], gi = m < 0 ? -egi[am] : egi[am];
+        const double pr = ear[mp] * gr - eai[mp] * gi, pi = ear[mp] * gi + eai[mp] * gr;
+        constexpr int c = hs_index(l, mp, m);
+        if constexpr (MODE == 0) {
+          const cx<float> g = G[(long long)c * nvox + v];
+          // Re(D G) = d (pr g.re - pi g.im)
+          acc = fmaf(w[c] * (float)d, (float)pr * g.re - (float)pi * g.im, acc);
+        } else {
+          Mout[(long long)c * nvox + v] = mk((float)(d * pr) * h, (float)(d * pi) * h);
+        }
+      });
+    });
+  });
+  if constexpr (MODE == 0) y[v] = acc * scale;
+}
+
+}  // namespace
+
+hipError_t launch_sh_azimuth(hipStream_t s, const float* F, int S, int K, int M, int nt, const double* gl_t, int nr,
+                             const int* d2, cx<double>* A) {
+  if (K < 0 || K > kMaxSteerK) return hipErrorInvalidValue;
+  const int n = nr * nt;
+  hipLaunchKernelGGL(k_sh_azimuth, dim3((n + 255) / 256), dim3(256), 0, s, F, S, K, M, nt, gl_t, nr, d2, A);
+  return last();
+}
+
+hipError_t launch_sh_polar(hipStream_t s, const cx<double>* A, int nr, int nt, int K, int M, const double* gl_t,
+                           const double* gl_w, cx<double>* f) {
+  const int n = nr * (K + 1) * (2 * K + 1);
+  hipLaunchKernelGGL(k_sh_polar, dim3((n + 255) / 256), dim3(256), 0, s, A, nr, nt, K, M, gl_t, gl_w, f);
+  return last();
+}
+
+hipError_t launch_sh_components(hipStream_t s, const float* F, int S, int K, int U, const int4* hs,
+                                const int* rindex, const cx<double>* f, cx<double>* comps) {
+  const long long n = (long long)U * S * S * S;
+  hipLaunchKernelGGL(k_sh_components, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, F, S, K, U, hs, rindex,
+                     f, comps);
+  return last();
+}
+
+static unsigned grid_for(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+
+hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, long long n) {
+  hipLaunchKernelGGL(k_real_to_cx, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  return last();
+}
+
+hipError_t launch_spec_products(hipStream_t s, const cx<float>* A, const cx<float>* Sp, long long V, int U,
+                                cx<float>* Z) {
+  hipLaunchKernelGGL(k_spec_products, dim3(grid_for(V)), dim3(256), 0, s, A, Sp, V, U, Z);
+  return last();
+}
+
+hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,
+                                  int U, cx<float>* A) {
+  hipLaunchKernelGGL(k_spec_accumulate, dim3(grid_for(V)), dim3(256), 0, s, X, Sp, w, V, U, A);
+  return last();
+}
+
+hipError_t launch_real_part(hipStream_t s, const cx<float>* in, float* y, long long n, float scale) {
+  hipLaunchKernelGGL(k_real_part, dim3(grid_for(n)), dim3(256), 0, s, in, y, n, scale);
+  return last();
+}
+
+hipError_t launch_wigner_voxels(hipStream_t s, int K, int mode, const float* alpha, const float* beta,
+                                const float* gamma, long long nvox, const double* coef, const float* w,
+                                const cx<float>* G, const float* H, float* y, cx<float>* M, float scale) {
+  const dim3 g((unsigned)((nvox + 255) / 256)), b(256);
+#define ECC_WV(KK)                                                                                        \
+  case KK:                                                                                                \
+    if (mode == 0)                                                                                        \
+      hipLaunchKernelGGL((k_wigner_voxels<KK, 0>), g, b, 0, s, alpha, beta, gamma, nvox, coef, w, G, H, y, M, \
+                         scale);                                                                          \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_wigner_voxels<KK, 1>), g, b, 0, s, alpha, beta, gamma, nvox, coef, w, G, H, y, M, \
+                         scale);                                                                          \
+    break;
+  switch (K) {
+    ECC_WV(0) ECC_WV(1) ECC_WV(2) ECC_WV(3) ECC_WV(4) ECC_WV(5) ECC_WV(6) ECC_WV(7) ECC_WV(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef ECC_WV
+  return last();
+}
+
+}  // namespace ecc

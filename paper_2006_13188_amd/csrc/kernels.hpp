@@ -270,4 +270,31 @@ size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);
 size_t lds_cols(const ColCfg& c, const FftDesc& d, size_t elem);
 hipError_t prepare_kernels();   // raises per-kernel dynamic LDS limits once
 
+// ---- steering in 3D (volumes [z][y][x]; spherical-harmonic components, Wigner-D)
+constexpr int kMaxSteerK = 8;
+// A[ri][i][m] = sum_j F(r w_ij) e^{-i m phi_j}, m = 0..K, r = sqrt(d2[ri]), polar nodes
+// gl_t (cos theta), M azimuths; float64, F trilinear (zero outside the S^3 array)
+hipError_t launch_sh_azimuth(hipStream_t s, const float* F, int S, int K, int M, int nt, const double* gl_t, int nr,
+                             const int* d2, cx<double>* A);
+// f[ri][l][m + K] = f_l^m(r) by the polar quadrature (weights gl_w)
+hipError_t launch_sh_polar(hipStream_t s, const cx<double>* A, int nr, int nt, int K, int M, const double* gl_t,
+                           const double* gl_w, cx<double>* f);
+// comps[c][S^3] = f_l^m(|q|) Y_l^{m'}(q/|q|) for hs[c] = (l, m', m), rindex[d2] = ri
+hipError_t launch_sh_components(hipStream_t s, const float* F, int S, int K, int U, const int4* hs,
+                                const int* rindex, const cx<double>* f, cx<double>* comps);
+hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, long long n);
+// Z[c][v] = A[v] Sp[c][v]
+hipError_t launch_spec_products(hipStream_t s, const cx<float>* A, const cx<float>* Sp, long long V, int U,
+                                cx<float>* Z);
+// A[v] = sum_c w_c X[c][v] Sp[c][v]
+hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,
+                                  int U, cx<float>* A);
+hipError_t launch_real_part(hipStream_t s, const cx<float>* in, float* y, long long n, float scale);
+// mode 0: y[v] = scale sum_c w_c Re(D_c(v) G[c][v]); mode 1: M[c][v] = H[v] D_c(v); D_c the
+// Wigner-D entry of half-set component c at the voxel's Euler angles; coef: Wigner's
+// coefficients, one per term of d^l_{m'm}, in half-set order
+hipError_t launch_wigner_voxels(hipStream_t s, int K, int mode, const float* alpha, const float* beta,
+                                const float* gamma, long long nvox, const double* coef, const float* w,
+                                const cx<float>* G, const float* H, float* y, cx<float>* M, float scale);
+
 }  // namespace ecc

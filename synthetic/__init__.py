@@ -9,6 +9,11 @@ consumes); the oracle upcasts the same float32 values to float64, so both sides
 see bit-identical inputs.
 
 Recipes (the paper has no datasets for this path; these stand in for its images):
+  * steering in 3D: a volume of U[0,1] noise blurred at sigma 2, a random S^3 filter
+            (N(0,1) entries times a Gaussian window) and the rotation field that turns +z
+            onto the local gradient of an independent noise volume blurred at sigma 6
+            (alpha = its azimuth, beta = its polar angle) with a smooth third Euler angle
+            gamma in [-pi, pi) (the orientation field of a volumetric feature detector)
   * joint rotation and scale smoothing: the block image, an anisotropic Gaussian, the vortex
             angle field and a smooth scale field in [1, 2]
   * line-integral convolution: white U[0,1] noise, a long narrow anisotropic Gaussian
@@ -29,7 +34,7 @@ __all__ = [
     "blurred_noise", "random_filter", "theta_field", "scale_field", "block_image",
     "rotation_config", "matching_scene", "scale_config", "batch_shapes",
     "batch_instance", "adjoint_config", "anisotropic_gaussian", "vortex_field", "lic_config",
-    "joint_config",
+    "joint_config", "random_filter3", "orientation_rotation_field", "steer3d_config",
 ]
 
 
@@ -204,3 +209,35 @@ def joint_config(n=1024, S=31, seeds=(60, 61, 62, 63), sigma_along=1.8, sigma_ac
     theta = vortex_field((n, n), seeds[2])
     s = scale_field((n, n), seeds[3], 1.0, s_max)
     return img, filt, theta, s
+
+
+def random_filter3(S, seed, window_sigma):
+    """S x S x S filter [z][y][x]: N(0,1) entries times a Gaussian window."""
+    rng = np.random.default_rng(seed)
+    R = (S - 1) // 2
+    zz, yy, xx = np.mgrid[-R:R + 1, -R:R + 1, -R:R + 1]
+    w = np.exp(-(xx * xx + yy * yy + zz * zz) / (2.0 * window_sigma ** 2))
+    return (rng.standard_normal((S, S, S)) * w).astype(np.float32)
+
+
+def orientation_rotation_field(shape, seed, sigma=6.0):
+    """ZYZ Euler angles (alpha, beta, gamma) of the rotation that takes +z to the gradient
+    direction of a blurred noise volume, with a smooth third angle gamma."""
+    rng = np.random.default_rng(seed)
+    n = ndimage.gaussian_filter(rng.random(shape), sigma, mode="reflect", truncate=4.0)
+    gz, gy, gx = (np.gradient(n, axis=i) if n.shape[i] > 1 else np.zeros_like(n) for i in range(3))
+    alpha = np.arctan2(gy, gx)
+    beta = np.arctan2(np.hypot(gx, gy), gz)
+    u = ndimage.gaussian_filter(rng.random(shape), sigma, mode="reflect", truncate=4.0)
+    u = (u - u.min()) / max(u.max() - u.min(), 1e-300)
+    gamma = 2.0 * np.pi * u - np.pi
+    return alpha.astype(np.float32), beta.astype(np.float32), gamma.astype(np.float32)
+
+
+def steer3d_config(n=128, S=15, seeds=(70, 71, 72)):
+    """Volume (nz = ny = nx = n or a shape tuple), filter and rotation field."""
+    shape = (n, n, n) if np.isscalar(n) else tuple(n)
+    vol = ndimage.gaussian_filter(np.random.default_rng(seeds[0]).random(shape), 2.0, mode="reflect",
+                                  truncate=4.0).astype(np.float32)
+    filt = random_filter3(S, seeds[1], S / 4.0)
+    return (vol, filt) + orientation_rotation_field(shape, seeds[2])
