@@ -441,6 +441,59 @@ def joint_workload(E, timeit):
     return res
 
 
+def steer3d_workload(E, timeit):
+    """Steering in 3D: 128^3 volume, 15^3 random filter, K = 4 (85 half-set components, 165
+    spherical-harmonic correlations of the full set), rotation field from the gradient
+    orientation of a noise volume; correlation and convolution, plans and spectra built
+    beforehand; two sampled voxels per op against the oracle on the crop they depend on."""
+    import numpy as np
+    import torch
+
+    from synthetic import steer3d_config
+
+    n, S, K = 128, 15, 4
+    vol, filt, a, b, g = steer3d_config(n, S)
+    dv = [torch.from_numpy(x).cuda() for x in (vol, a, b, g)]
+    c = E.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = E.VolumePlan(c, torch.from_numpy(filt).cuda(), K)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    full = (K + 1) * (2 * K + 1) * (2 * K + 3) // 3
+    res = {"workload": f"3D steering, {n}^3 volume, {S}^3 filter, K={K}, gradient-orientation ZYZ field",
+           "components": plan.U, "full_set_correlations": full, "plan_ms": round(plan_ms, 3)}
+    outs = {}
+    for name, op in (("correlation", E.CORRELATION), ("convolution", E.CONVOLUTION)):
+        out = torch.empty_like(dv[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E.ecc_extended_3d(c, op, plan, *dv, out=out)        # builds this op's spectra
+        torch.cuda.synchronize()
+        res[name + "_first_call_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        ms = timeit(lambda: E.ecc_extended_3d(c, op, plan, *dv, out=out), reps=10)
+        res[name + "_ms"] = round(ms, 4)
+        res[name + "_Mvox_comp_s"] = round(n ** 3 * full / (ms * 1e-3) / 1e6, 1)
+        outs[name] = (op, out.cpu().numpy().astype(np.float64))
+    res["workspace_bytes"] = c.volume_workspace_size(plan, n, n, n)
+    # sampled voxels against the oracle on the crop each depends on
+    import oracle.steer3d as O3
+    parts = O3.components3d(filt.astype(np.float64), K)
+    R = (S - 1) // 2
+    worst = 0.0
+    for name, (op, y) in outs.items():
+        for p in ((0, n - 1, 7), (61, 33, 90)):
+            sl = tuple(slice(max(0, q - R), min(n, q + R + 1)) for q in p)
+            f = O3.ext_corr3d_fft if op == E.CORRELATION else O3.ext_conv3d_fft
+            ref = f(*(x[sl].astype(np.float64) for x in (vol, a, b, g)), filt.astype(np.float64), K, parts=parts)
+            r = ref[tuple(q - s_.start for q, s_ in zip(p, sl))]
+            worst = max(worst, abs(y[p] - r) / float(np.max(np.abs(y))))
+    res["sampled_max_abs_err_over_max"] = worst
+    plan.close()
+    c.close()
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -549,7 +602,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of side workloads: two_pass,conv,matching,scale,lic,detection,joint,adjoint,batch")
+                    help="comma list of side workloads: "
+                         "two_pass,conv,matching,scale,lic,detection,joint,steer3d,adjoint,batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
@@ -601,7 +655,8 @@ def main():
 
     side = {}
     want = set() if args.no_extras else (
-        {"two_pass", "conv", "matching", "scale", "lic", "detection", "joint", "adjoint", "batch"} if args.extras == "all"
+        {"two_pass", "conv", "matching", "scale", "lic", "detection", "joint", "steer3d", "adjoint", "batch"}
+        if args.extras == "all"
         else set(args.extras.split(",")))
     if "two_pass" in want:
         # the paper's two-pass form on the same workload
@@ -636,6 +691,8 @@ def main():
         side["detection_1024"] = detection_workload(E, timeit)
     if "joint" in want:
         side["joint_1024"] = joint_workload(E, timeit)
+    if "steer3d" in want:
+        side["steer3d_128"] = steer3d_workload(E, timeit)
     if "adjoint" in want:
         side["adjoint_16x512"] = adjoint_workload(E, ctx, timeit)
     if "batch" in want:

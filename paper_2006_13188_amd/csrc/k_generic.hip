@@ -9,6 +9,8 @@ namespace ecc {
 // generic complex transforms with circular placement:
 //   rows: buf[(j + shift_in) mod P] = in[r][j] for j < nvalid; out[r][i] = buf[(i + shift_out) mod P]
 //   cols: the same along columns of B adjacent columns.
+constexpr int kLoadGroup = 8;
+
 template <typename T, int NB, int DIR>
 __global__ void __launch_bounds__(256) k_fft_rows(const cx<T>* __restrict__ in, long long planeIn,
                                                  int ldIn, int nrows, int nvalid, int shift_in,
@@ -26,15 +28,22 @@ __global__ void __launch_bounds__(256) k_fft_rows(const cx<T>* __restrict__ in, 
   Layout L{B, 0, P};
   if (active) {
     const cx<T>* src = in + (long long)blockIdx.y * planeIn + (long long)row * ldIn;
-    for (int pos = f; pos < P; pos += TF) {
-      int j = pos - shift_in;
-      j %= P;
-      if (j < 0) j += P;
-      cx<T> val;
-      val.re = T(0);
-      val.im = T(0);
-      if (j < nvalid) val = src[j];
-      buf[c * P + pos] = val;
+    // loads in groups of kLoadGroup per thread, all issued before their LDS stores, so that
+    // several loads per thread are in flight at once
+    for (int pos0 = f; pos0 < P; pos0 += kLoadGroup * TF) {
+      cx<T> v[kLoadGroup];
+#pragma unroll
+      for (int u = 0; u < kLoadGroup; ++u) {
+        const int pos = pos0 + u * TF;
+        int j = (pos - shift_in) % P;
+        if (j < 0) j += P;
+        v[u].re = T(0);
+        v[u].im = T(0);
+        if (pos < P && j < nvalid) v[u] = src[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadGroup; ++u)
+        if (pos0 + u * TF < P) buf[c * P + pos0 + u * TF] = v[u];
     }
   }
   __syncthreads();
@@ -54,7 +63,8 @@ __global__ void __launch_bounds__(512) k_fft_cols(const cx<T>* __restrict__ in, 
                                                  int ldIn, int ncols, int nvalid, int shift_in,
                                                  cx<T>* __restrict__ out, long long planeOut,
                                                  int ldOut, int nstore, int shift_out, FftDesc d,
-                                                 const cx<T>* __restrict__ tw, int lgB) {
+                                                 const cx<T>* __restrict__ tw, int lgB,
+                                                 const cx<T>* __restrict__ mul) {
   extern __shared__ char smem_raw[];
   cx<T>* twl = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = twl + lds_tw_pad(d.twsize);
@@ -63,15 +73,25 @@ __global__ void __launch_bounds__(512) k_fft_cols(const cx<T>* __restrict__ in, 
   const int c = threadIdx.x & (B - 1), f = threadIdx.x >> lgB;
   const int v0 = blockIdx.x * B;
   const cx<T>* src = in + (long long)blockIdx.y * planeIn;
-  for (int e = threadIdx.x; e < P * B; e += nthr) {
-    const int pos = e >> lgB, v = v0 + (e & (B - 1));
-    int j = (pos - shift_in) % P;
-    if (j < 0) j += P;
-    cx<T> val;
-    val.re = T(0);
-    val.im = T(0);
-    if (j < nvalid && v < ncols) val = src[(long long)j * ldIn + v];
-    buf[e] = val;
+  // loads in groups of kLoadGroup per thread (see k_fft_rows)
+  for (int e0 = threadIdx.x; e0 < P * B; e0 += kLoadGroup * nthr) {
+    cx<T> val[kLoadGroup];
+#pragma unroll
+    for (int u = 0; u < kLoadGroup; ++u) {
+      const int e = e0 + u * nthr;
+      const int pos = e >> lgB, v = v0 + (e & (B - 1));
+      int j = (pos - shift_in) % P;
+      if (j < 0) j += P;
+      val[u].re = T(0);
+      val[u].im = T(0);
+      if (e < P * B && j < nvalid && v < ncols) {
+        val[u] = src[(long long)j * ldIn + v];
+        if (mul) val[u] = cmul(val[u], mul[(long long)j * ldIn + v]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadGroup; ++u)
+      if (e0 + u * nthr < P * B) buf[e0 + u * nthr] = val[u];
   }
   __syncthreads();
   Layout L{B, lgB, 0};
@@ -288,18 +308,18 @@ template <typename T>
 hipError_t launch_fft_cols(hipStream_t s, const ColCfg& c, int nplanes, int dir, const cx<T>* in,
                            long long planeIn, int ldIn, int ncols, int nvalid, int shift_in,
                            cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
-                           const FftDesc& d, const cx<T>* tw) {
+                           const FftDesc& d, const cx<T>* tw, const cx<T>* mul) {
   const int B = 1 << c.lgB;
   dim3 grid((ncols + B - 1) / B, nplanes), block(c.nthr);
   const size_t lds = lds_cols(c, d, sizeof(cx<T>));
   if (dir < 0) {
     ECC_NB_SWITCH(c.NB, hipLaunchKernelGGL((k_fft_cols<T, NB, -1>), grid, block, lds, s, in, planeIn,
                                            ldIn, ncols, nvalid, shift_in, out, planeOut, ldOut,
-                                           nstore, shift_out, d, tw, c.lgB));
+                                           nstore, shift_out, d, tw, c.lgB, mul));
   } else {
     ECC_NB_SWITCH(c.NB, hipLaunchKernelGGL((k_fft_cols<T, NB, +1>), grid, block, lds, s, in, planeIn,
                                            ldIn, ncols, nvalid, shift_in, out, planeOut, ldOut,
-                                           nstore, shift_out, d, tw, c.lgB));
+                                           nstore, shift_out, d, tw, c.lgB, mul));
   }
   return last();
 }
@@ -312,10 +332,10 @@ template hipError_t launch_fft_rows<double>(hipStream_t, const RowCfg&, int, int
                                             int, int, int, const FftDesc&, const cx<double>*);
 template hipError_t launch_fft_cols<float>(hipStream_t, const ColCfg&, int, int, const cx<float>*,
                                            long long, int, int, int, int, cx<float>*, long long, int,
-                                           int, int, const FftDesc&, const cx<float>*);
+                                           int, int, const FftDesc&, const cx<float>*, const cx<float>*);
 template hipError_t launch_fft_cols<double>(hipStream_t, const ColCfg&, int, int, const cx<double>*,
                                             long long, int, int, int, int, cx<double>*, long long,
-                                            int, int, int, const FftDesc&, const cx<double>*);
+                                            int, int, int, const FftDesc&, const cx<double>*, const cx<double>*);
 
 hipError_t launch_polar_dft(hipStream_t s, const float* F, int S, int K, int M, const int* d2list,
                             int nrad, cx<double>* fk) {

@@ -161,16 +161,6 @@ __global__ void k_real_to_cx(const float* __restrict__ in, cx<float>* __restrict
     out[i] = mk(in[i], 0.0f);
 }
 
-// Z[c][v] = A[v] Sp[c][v], c < U
-__global__ void __launch_bounds__(256) k_spec_products(const cx<float>* __restrict__ A,
-                                                      const cx<float>* __restrict__ Sp, long long V, int U,
-                                                      cx<float>* __restrict__ Z) {
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
-    const cx<float> a = A[v];
-    for (int c = 0; c < U; ++c) Z[(long long)c * V + v] = cmul(a, Sp[(long long)c * V + v]);
-  }
-}
-
 // A[v] = sum_c w_c X[c][v] Sp[c][v]
 __global__ void __launch_bounds__(256) k_spec_accumulate(const cx<float>* __restrict__ X,
                                                         const cx<float>* __restrict__ Sp, const float* __restrict__ w,
@@ -321,12 +311,6 @@ static unsigned grid_for(long long n) {
 
 hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, long long n) {
   hipLaunchKernelGGL(k_real_to_cx, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
-  return last();
-}
-
-hipError_t launch_spec_products(hipStream_t s, const cx<float>* A, const cx<float>* Sp, long long V, int U,
-                                cx<float>* Z) {
-  hipLaunchKernelGGL(k_spec_products, dim3(grid_for(V)), dim3(256), 0, s, A, Sp, V, U, Z);
   return last();
 }
 

@@ -90,11 +90,13 @@ hipError_t launch_fft_rows(hipStream_t s, const RowCfg& c, int nplanes, int dir,
                            long long planeIn, int ldIn, int nrows, int nvalid, int shift_in,
                            cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
                            const FftDesc& d, const cx<T>* tw);
+// mul != NULL: every input element is multiplied on load by mul[j ldIn + v] (the same
+// multiplier plane for every input plane)
 template <typename T>
 hipError_t launch_fft_cols(hipStream_t s, const ColCfg& c, int nplanes, int dir, const cx<T>* in,
                            long long planeIn, int ldIn, int ncols, int nvalid, int shift_in,
                            cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
-                           const FftDesc& d, const cx<T>* tw);
+                           const FftDesc& d, const cx<T>* tw, const cx<T>* mul = nullptr);
 
 // ---- filter plans (float64)
 hipError_t launch_polar_dft(hipStream_t s, const float* F, int S, int K, int M, const int* d2list,
@@ -283,9 +285,6 @@ hipError_t launch_sh_polar(hipStream_t s, const cx<double>* A, int nr, int nt, i
 hipError_t launch_sh_components(hipStream_t s, const float* F, int S, int K, int U, const int4* hs,
                                 const int* rindex, const cx<double>* f, cx<double>* comps);
 hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, long long n);
-// Z[c][v] = A[v] Sp[c][v]
-hipError_t launch_spec_products(hipStream_t s, const cx<float>* A, const cx<float>* Sp, long long V, int U,
-                                cx<float>* Z);
 // A[v] = sum_c w_c X[c][v] Sp[c][v]
 hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,
                                   int U, cx<float>* A);

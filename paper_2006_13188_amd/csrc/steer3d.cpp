@@ -39,6 +39,8 @@ inline hipStream_t S_(void* s) { return static_cast<hipStream_t>(s); }
 
 constexpr int kMaxSteerS = 63;
 constexpr int kMaxPlanes = 65535;   // grid.y limit of the generic transforms
+// column passes: 2^kColLgB adjacent columns per workgroup of kColThreads threads
+constexpr int kColLgB = 4, kColThreads = 512;
 
 // Gauss-Legendre nodes and weights on [-1, 1] (Newton's iteration on P_n, long double).
 void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
@@ -119,13 +121,15 @@ ecc_status rows_pass(hipStream_t st, const Transform& tr, int nplanes, int dir, 
 // Columns: transform along the rows of planes of `ncols` columns with row pitch ld.
 template <typename T>
 ecc_status cols_pass(hipStream_t st, const Transform& tr, int nplanes, int dir, const cx<T>* in, long long pIn,
-                     int ldIn, int ncols, int nvalid, int shift, cx<T>* out, long long pOut, int ldOut, int nstore) {
-  const ColCfg cc = col_config(tr, 4, sizeof(cx<T>), 256);
+                     int ldIn, int ncols, int nvalid, int shift, cx<T>* out, long long pOut, int ldOut, int nstore,
+                     const cx<T>* mul = nullptr) {
+  const ColCfg cc = col_config(tr, kColLgB, sizeof(cx<T>), kColThreads);
   ECC_TRY(check_col(cc, tr, sizeof(cx<T>)));
   for (int p0 = 0; p0 < nplanes; p0 += kMaxPlanes) {
     const int np = std::min(kMaxPlanes, nplanes - p0);
     ECC_HIP((launch_fft_cols<T>(st, cc, np, dir, in + p0 * pIn, pIn, ldIn, ncols, nvalid, shift, out + p0 * pOut,
-                                pOut, ldOut, nstore, 0, tr.desc, sizeof(T) == 8 ? (const cx<T>*)tr.d() : (const cx<T>*)tr.f())));
+                                pOut, ldOut, nstore, 0, tr.desc, sizeof(T) == 8 ? (const cx<T>*)tr.d() : (const cx<T>*)tr.f(),
+                                mul)));
   }
   return ECC_OK;
 }
@@ -375,9 +379,10 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
     ECC_TRY((rows_pass<float>(st, *g.Tx, nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, g.Px, g.Px)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, nz, -1, W, plane, g.Px, g.Px, ny, 0, Z, plane, g.Px, g.Py)));
     ECC_TRY((cols_pass<float>(st, *g.Tz, 1, -1, Z, 0, PyPx, PyPx, nz, 0, A, 0, PyPx, g.Pz)));
-    ECC_HIP(launch_spec_products(st, A, Sp, g.V, U, Z));
-    // inverse transforms of every product, only the output voxels kept
-    ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Z, g.V, PyPx, PyPx, g.Pz, 0, W, (long long)nz * PyPx, PyPx, nz)));
+    // inverse transforms of the products A Sp_c (formed as the first pass loads them), only
+    // the output voxels kept
+    ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyPx, PyPx, g.Pz, 0, W, (long long)nz * PyPx, PyPx, nz,
+                              A)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, +1, W, plane, g.Px, g.Px, g.Py, 0, Z, (long long)ny * g.Px, g.Px,
                               ny)));
     ECC_TRY((rows_pass<float>(st, *g.Tx, U, +1, Z, (long long)nz * ny * g.Px, g.Px, nz * ny, g.Px, 0, W, nv, nx,
