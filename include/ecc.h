@@ -112,8 +112,9 @@ const char* ecc_status_string(ecc_status s);
 const char* ecc_last_error(ecc_context ctx);
 
 /* FFT size of the two-pass path for an image side n and filter radius R: the smallest
- * 7-smooth integer >= max(n + R, 16) (zero-boundary linear correlation needs >= n + R;
- * the floor of 16 keeps every transform at two passes or more). */
+ * 7-smooth integer >= max(n + R, 2R + 1, 16) (zero-boundary linear correlation needs
+ * >= n + R; the filter window of 2R + 1 taps is placed without wrapping onto itself; the
+ * floor of 16 keeps every transform at two passes or more). */
 ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
 /* Enables (1) or disables (0) the autotuner. When enabled, the next forward call (or
  * ecc_describe) first times every compiled block shape of the tiled path on this device
@@ -494,10 +495,10 @@ ecc_status ecc_volume_plan_components(ecc_volume_plan plan, float* comps, int* t
  * zero outside the volume. Correlation: one forward 3D transform of H, U products and U
  * inverse transforms, then the per-voxel Wigner-D combination; convolution: U modulated
  * signals and forward transforms, one weighted sum of products, one inverse. Transform
- * sizes P = smallest 7-smooth >= max(n + R, 8) per axis; float32 arithmetic with float64
- * spectra (rounded once) and float64 Wigner-D. Context workspace: (2 U + 1) Pz Py Px
- * complex64 (ecc_volume_workspace_size); the plan caches its spectra per (op, P) (U Pz Py Px
- * complex64). signal, alpha, beta, gamma, out: device float32 nz x ny x nx; out must not
+ * sizes P = smallest 7-smooth >= max(n + R, 2R + 1, 8) per axis; float32 arithmetic with float64
+ * spectra (rounded once) and float64 Wigner-D. Context workspace: (2 U + 1) Pz Py Lx
+ * complex64, Lx = Px rounded up to a multiple of 16 (ecc_volume_workspace_size); the plan
+ * caches its spectra per (op, P) (U Pz Py Lx complex64). signal, alpha, beta, gamma, out: device float32 nz x ny x nx; out must not
  * alias an input. Errors: INVALID_ARGUMENT, UNSUPPORTED (a transform too long), OUT_OF_MEMORY,
  * HIP. */
 ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int nz, int ny, int nx,

@@ -28,8 +28,9 @@ int fft_size_for(ecc_context ctx, int n, int R) {
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) return it->second;
   // at least 16: every transform then has two or more passes (zero padding beyond n + R
-  // changes nothing in the result)
-  return next_smooth7(std::max(n + R, 16));
+  // changes nothing in the result); at least 2R + 1: the filter window is placed without
+  // wrapping onto itself
+  return next_smooth7(std::max(std::max(n + R, 2 * R + 1), 16));
 }
 
 }  // namespace

@@ -9,6 +9,9 @@ namespace ecc {
 // generic complex transforms with circular placement:
 //   rows: buf[(j + shift_in) mod P] = in[r][j] for j < nvalid; out[r][i] = buf[(i + shift_out) mod P]
 //   cols: the same along columns of B adjacent columns.
+// The kernels take both shifts reduced to [0, P) by their launchers, so that the index of
+// every element is one conditional add or subtract (an integer modulo by the runtime
+// length would dominate the instruction count of these memory-bound passes).
 constexpr int kLoadGroup = 8;
 
 template <typename T, int NB, int DIR>
@@ -35,7 +38,7 @@ __global__ void __launch_bounds__(256) k_fft_rows(const cx<T>* __restrict__ in, 
 #pragma unroll
       for (int u = 0; u < kLoadGroup; ++u) {
         const int pos = pos0 + u * TF;
-        int j = (pos - shift_in) % P;
+        int j = pos - shift_in;
         if (j < 0) j += P;
         v[u].re = T(0);
         v[u].im = T(0);
@@ -51,8 +54,8 @@ __global__ void __launch_bounds__(256) k_fft_rows(const cx<T>* __restrict__ in, 
   if (active) {
     cx<T>* dst = out + (long long)blockIdx.y * planeOut + (long long)row * ldOut;
     for (int i = f; i < nstore; i += TF) {
-      int pos = (i + shift_out) % P;
-      if (pos < 0) pos += P;
+      int pos = i + shift_out;
+      if (pos >= P) pos -= P;
       dst[i] = buf[c * P + pos];
     }
   }
@@ -80,7 +83,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(const cx<T>* __restrict__ in, 
     for (int u = 0; u < kLoadGroup; ++u) {
       const int e = e0 + u * nthr;
       const int pos = e >> lgB, v = v0 + (e & (B - 1));
-      int j = (pos - shift_in) % P;
+      int j = pos - shift_in;
       if (j < 0) j += P;
       val[u].re = T(0);
       val[u].im = T(0);
@@ -100,8 +103,8 @@ __global__ void __launch_bounds__(512) k_fft_cols(const cx<T>* __restrict__ in, 
   for (int e = threadIdx.x; e < nstore * B; e += nthr) {
     const int i = e >> lgB, v = v0 + (e & (B - 1));
     if (v >= ncols) continue;
-    int pos = (i + shift_out) % P;
-    if (pos < 0) pos += P;
+    int pos = i + shift_out;
+    if (pos >= P) pos -= P;
     dst[(long long)i * ldOut + v] = buf[(pos << lgB) + (e & (B - 1))];
   }
 }
@@ -290,6 +293,9 @@ hipError_t launch_fft_rows(hipStream_t s, const RowCfg& c, int nplanes, int dir,
                            long long planeIn, int ldIn, int nrows, int nvalid, int shift_in,
                            cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
                            const FftDesc& d, const cx<T>* tw) {
+  if (nstore > d.P || nvalid > d.P) return hipErrorInvalidValue;
+  shift_in = ((shift_in % d.P) + d.P) % d.P;
+  shift_out = ((shift_out % d.P) + d.P) % d.P;
   dim3 grid((nrows + c.B - 1) / c.B, nplanes), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<T>));
   if (dir < 0) {
@@ -309,6 +315,9 @@ hipError_t launch_fft_cols(hipStream_t s, const ColCfg& c, int nplanes, int dir,
                            long long planeIn, int ldIn, int ncols, int nvalid, int shift_in,
                            cx<T>* out, long long planeOut, int ldOut, int nstore, int shift_out,
                            const FftDesc& d, const cx<T>* tw, const cx<T>* mul) {
+  if (nstore > d.P || nvalid > d.P) return hipErrorInvalidValue;
+  shift_in = ((shift_in % d.P) + d.P) % d.P;
+  shift_out = ((shift_out % d.P) + d.P) % d.P;
   const int B = 1 << c.lgB;
   dim3 grid((ncols + B - 1) / B, nplanes), block(c.nthr);
   const size_t lds = lds_cols(c, d, sizeof(cx<T>));
@@ -391,6 +400,7 @@ hipError_t prepare_kernels() {
   if (e == hipSuccess) e = prepare_fixed_kernels();
   if (e == hipSuccess) e = prepare_tile_kernels();
   if (e == hipSuccess) e = prepare_tconv_kernels();
+  if (e == hipSuccess) e = prepare_fx_kernels();
 #define ECC_ALLOW(...) if (e == hipSuccess) e = allow_lds(__VA_ARGS__)
 #define ECC_ALLOW_NB(KN) ECC_ALLOW(KN<1>); ECC_ALLOW(KN<2>); ECC_ALLOW(KN<4>)
 #define ECC_ALLOW_NB_E(KN, E) ECC_ALLOW(KN<1, E>); ECC_ALLOW(KN<2, E>); ECC_ALLOW(KN<4, E>)

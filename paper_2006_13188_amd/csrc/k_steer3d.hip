@@ -10,6 +10,7 @@
 // D^l_{m'm} = e^{-i m' alpha} d^l_{m'm}(beta) e^{-i m gamma} (Wigner's explicit sum for d).
 #include <type_traits>
 
+#include "fft_fixed.hpp"
 #include "kcommon.hpp"
 
 namespace ecc {
@@ -160,6 +161,149 @@ __global__ void k_real_to_cx(const float* __restrict__ in, cx<float>* __restrict
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = mk(in[i], 0.0f);
 }
+
+// ---- transforms of the volume passes with a compiled schedule (P = R0 R1 R2 with R2 > 1,
+// compile-time indexing, the radices and twiddles of fft_fixed.hpp)
+//
+// These passes are bound by HBM traffic, so the workgroups are small and hold one LDS
+// buffer: a transform has NL = P / R2 threads (the last pass is one butterfly per thread,
+// whose outputs go straight to memory), which take the earlier passes' butterflies in
+// turn; every pass reads all its inputs before a barrier and writes after it.
+//
+// Columns: kFxB adjacent columns per workgroup, thread (b, c) = (t / kFxB, t % kFxB), so
+// every load and store instruction of a wave covers rows of kFxB consecutive complex
+// values. in / out: planes (blockIdx.y) of rows with pitch ld; rows j >= nvalid read as
+// zero; rows i < nstore are written; mul != NULL multiplies each loaded element by
+// mul[j ldIn + v] (the same plane for every input plane).
+constexpr int kFxB = 16;
+
+template <class F>
+constexpr int fx_rmax() {
+  return F::R0 > F::R1 ? (F::R0 > F::R2 ? F::R0 : F::R2) : (F::R1 > F::R2 ? F::R1 : F::R2);
+}
+template <int N, int T>
+constexpr int fx_per_thread() { return (N + T - 1) / T; }
+
+// The three passes on one transform held in LDS at X[pos * ES] (ES = element stride; the
+// caller offsets X), driven by thread b < NL. The first pass's inputs come from `load(j)`;
+// the outputs X[b + r NL], r < R2, are handed to `store(i, value)`.
+template <class F, int DIR, int ES, class Load, class Store>
+__device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, int b, Load load, Store store) {
+  static_assert(F::R2 > 1, "three-pass schedules");
+  constexpr int NL = F::N2;
+  constexpr int K0 = fx_per_thread<F::N0, NL>(), K1 = fx_per_thread<F::N1, NL>();
+  // pass 0: X[b0 R0 + r] = DFT_R0(in[b0 + r N0])
+  cx<float> v0[K0][F::R0];
+#pragma unroll
+  for (int k = 0; k < K0; ++k) {
+    const int b0 = b + k * NL;
+    if (b0 < F::N0) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) v0[k][r] = load(b0 + r * F::N0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K0; ++k) {
+    const int b0 = b + k * NL;
+    if (b0 < F::N0) {
+      dft<F::R0, DIR, float>(v0[k]);
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) X[(b0 * F::R0 + r) * ES] = v0[k][r];
+    }
+  }
+  __syncthreads();
+  // pass 1 (Ls = R0)
+  cx<float> v1[K1][F::R1];
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int b1 = b + k * NL;
+    if (b1 < F::N1) {
+#pragma unroll
+      for (int r = 0; r < F::R1; ++r) v1[k][r] = X[(b1 + r * F::N1) * ES];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    const int b1 = b + k * NL;
+    if (b1 < F::N1) {
+      const int j = b1 % F::R0;
+      if (j != 0) fixed_twiddle<F::R1, DIR, float>(v1[k], tw + j * (F::R1 - 1));
+      dft<F::R1, DIR, float>(v1[k]);
+      const int base = (b1 - j) * F::R1 + j;
+#pragma unroll
+      for (int r = 0; r < F::R1; ++r) X[(base + r * F::R0) * ES] = v1[k][r];
+    }
+  }
+  __syncthreads();
+  // pass 2 (Ls = R0 R1, last): one butterfly per thread, natural order out
+  cx<float> v2[F::R2];
+#pragma unroll
+  for (int r = 0; r < F::R2; ++r) v2[r] = X[(b + r * NL) * ES];
+  if (b != 0) fixed_twiddle<F::R2, DIR, float>(v2, tw + F::TW1 + b * (F::R2 - 1));
+  dft<F::R2, DIR, float>(v2);
+#pragma unroll
+  for (int r = 0; r < F::R2; ++r) store(b + r * NL, v2[r]);
+}
+
+template <class F, int DIR>
+__global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols(const cx<float>* __restrict__ in, long long planeIn, int ldIn,
+                                                        int ncols, int nvalid, cx<float>* __restrict__ out,
+                                                        long long planeOut, int ldOut, int nstore,
+                                                        const cx<float>* __restrict__ twg,
+                                                        const cx<float>* __restrict__ mul) {
+  __shared__ cx<float> tw[(F::TW + 1) & ~1];
+  __shared__ cx<float> X[F::P * kFxB];
+  for (int i = threadIdx.x; i < F::TW; i += blockDim.x) tw[i] = twg[i];
+  const int c = threadIdx.x % kFxB, b = threadIdx.x / kFxB;
+  const int col = blockIdx.x * kFxB + c;
+  const bool cin = col < ncols;
+  const cx<float>* src = in + (long long)blockIdx.y * planeIn;
+  cx<float>* dst = out + (long long)blockIdx.y * planeOut;
+  fx_transform<F, DIR, kFxB>(
+      X + c, tw, b,
+      [&](int j) {
+        cx<float> v = mk(0.f, 0.f);
+        if (cin && j < nvalid) {
+          const long long o = (long long)j * ldIn + col;
+          v = src[o];
+          if (mul) v = cmul(v, mul[o]);
+        }
+        return v;
+      },
+      [&](int i, cx<float> v) {
+        if (cin && i < nstore) dst[(long long)i * ldOut + col] = v;
+      });
+}
+
+// Rows: kFxRows rows per workgroup, thread (row, b) = (t / NL, t % NL), each row in its
+// own LDS range; consecutive threads read consecutive elements of a row. in / out: planes
+// of nrows rows with pitch ld; elements j >= nvalid read as zero, i < nstore written.
+constexpr int kFxRows = 8;
+
+template <class F, int DIR>
+__global__ void __launch_bounds__(F::N2 * kFxRows) k_fx_rows(const cx<float>* __restrict__ in, long long planeIn,
+                                                           int ldIn, int nrows, int nvalid,
+                                                           cx<float>* __restrict__ out, long long planeOut,
+                                                           int ldOut, int nstore, const cx<float>* __restrict__ twg) {
+  __shared__ cx<float> tw[(F::TW + 1) & ~1];
+  __shared__ cx<float> X[F::P * kFxRows];
+  for (int i = threadIdx.x; i < F::TW; i += blockDim.x) tw[i] = twg[i];
+  const int rl = threadIdx.x / F::N2, b = threadIdx.x % F::N2;
+  const int row = blockIdx.x * kFxRows + rl;
+  const bool act = row < nrows;
+  const cx<float>* src = in + (long long)blockIdx.y * planeIn + (long long)(act ? row : 0) * ldIn;
+  cx<float>* dst = out + (long long)blockIdx.y * planeOut + (long long)(act ? row : 0) * ldOut;
+  fx_transform<F, DIR, 1>(
+      X + rl * F::P, tw, b,
+      [&](int j) { return act && j < nvalid ? src[j] : mk(0.f, 0.f); },
+      [&](int i, cx<float> v) {
+        if (act && i < nstore) dst[i] = v;
+      });
+}
+
+// the compiled schedules with a volume-pass form (R2 > 1 and NL kFxB <= 1024 threads)
+#define ECC_FX3_SIZES(X) X(5, 3, 9)
 
 // A[v] = sum_c w_c X[c][v] Sp[c][v]
 __global__ void __launch_bounds__(256) k_spec_accumulate(const cx<float>* __restrict__ X,
@@ -313,6 +457,58 @@ hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, lon
   hipLaunchKernelGGL(k_real_to_cx, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
   return last();
 }
+
+bool fx3_supported(int P) {
+#define ECC_FXS(a, b_, c_) \
+  if (P == (a) * (b_) * (c_)) return true;
+  ECC_FX3_SIZES(ECC_FXS)
+#undef ECC_FXS
+  return false;
+}
+
+hipError_t launch_fx_cols(hipStream_t s, int P, int dir, int nplanes, const cx<float>* in, long long planeIn,
+                          int ldIn, int ncols, int nvalid, cx<float>* out, long long planeOut, int ldOut,
+                          int nstore, const cx<float>* tw, const cx<float>* mul) {
+#define ECC_FXC(a, b_, c_)                                                                         \
+  if (P == (a) * (b_) * (c_)) {                                                                    \
+    using F = Fixed3<a, b_, c_>;                                                                   \
+    if (nvalid > P || nstore > P) return hipErrorInvalidValue;                                     \
+    const dim3 g((ncols + kFxB - 1) / kFxB, nplanes), blk(F::N2 * kFxB);                           \
+    if (dir < 0)                                                                                   \
+      hipLaunchKernelGGL((k_fx_cols<F, -1>), g, blk, 0, s, in, planeIn, ldIn, ncols, nvalid, out,  \
+                         planeOut, ldOut, nstore, tw, mul);                                        \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_fx_cols<F, +1>), g, blk, 0, s, in, planeIn, ldIn, ncols, nvalid, out,  \
+                         planeOut, ldOut, nstore, tw, mul);                                        \
+    return last();                                                                                 \
+  }
+  ECC_FX3_SIZES(ECC_FXC)
+#undef ECC_FXC
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<float>* in, long long planeIn,
+                          int ldIn, int nrows, int nvalid, cx<float>* out, long long planeOut, int ldOut,
+                          int nstore, const cx<float>* tw) {
+#define ECC_FXR(a, b_, c_)                                                                          \
+  if (P == (a) * (b_) * (c_)) {                                                                     \
+    using F = Fixed3<a, b_, c_>;                                                                    \
+    if (nvalid > P || nstore > P) return hipErrorInvalidValue;                                      \
+    const dim3 g((nrows + kFxRows - 1) / kFxRows, nplanes), blk(F::N2 * kFxRows);                    \
+    if (dir < 0)                                                                                    \
+      hipLaunchKernelGGL((k_fx_rows<F, -1>), g, blk, 0, s, in, planeIn, ldIn, nrows, nvalid, out,   \
+                         planeOut, ldOut, nstore, tw);                                              \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_fx_rows<F, +1>), g, blk, 0, s, in, planeIn, ldIn, nrows, nvalid, out,   \
+                         planeOut, ldOut, nstore, tw);                                              \
+    return last();                                                                                  \
+  }
+  ECC_FX3_SIZES(ECC_FXR)
+#undef ECC_FXR
+  return hipErrorInvalidValue;
+}
+
+hipError_t prepare_fx_kernels() { return hipSuccess; }   // static LDS only
 
 hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,
                                   int U, cx<float>* A) {

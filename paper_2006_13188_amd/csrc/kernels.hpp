@@ -285,6 +285,17 @@ hipError_t launch_sh_polar(hipStream_t s, const cx<double>* A, int nr, int nt, i
 hipError_t launch_sh_components(hipStream_t s, const float* F, int S, int K, int U, const int4* hs,
                                 const int* rindex, const cx<double>* f, cx<double>* comps);
 hipError_t launch_real_to_cx(hipStream_t s, const float* in, cx<float>* out, long long n);
+// Batched float32 transforms of length P with a compiled schedule (fx3_supported(P)), no
+// circular shift: columns (16 adjacent per workgroup; mul as launch_fft_cols) and rows.
+// tw: the transform's pass-1/pass-2 twiddle table (Transform::fx()).
+bool fx3_supported(int P);
+hipError_t launch_fx_cols(hipStream_t s, int P, int dir, int nplanes, const cx<float>* in, long long planeIn,
+                          int ldIn, int ncols, int nvalid, cx<float>* out, long long planeOut, int ldOut,
+                          int nstore, const cx<float>* tw, const cx<float>* mul);
+hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<float>* in, long long planeIn,
+                          int ldIn, int nrows, int nvalid, cx<float>* out, long long planeOut, int ldOut,
+                          int nstore, const cx<float>* tw);
+hipError_t prepare_fx_kernels();
 // A[v] = sum_c w_c X[c][v] Sp[c][v]
 hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,
                                   int U, cx<float>* A);

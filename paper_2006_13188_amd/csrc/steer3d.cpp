@@ -106,9 +106,20 @@ ecc_status check_col(const ColCfg& c, const Transform& t, size_t elem) {
 
 // Transforms along the three axes of a batch of volumes, planes split to respect the
 // grid limit. Rows (x): every plane holds `nrows` rows.
+// (float32 passes of a length with a compiled schedule take the fixed-schedule kernels)
 template <typename T>
 ecc_status rows_pass(hipStream_t st, const Transform& tr, int nplanes, int dir, const cx<T>* in, long long pIn,
                      int ldIn, int nrows, int nvalid, int shift, cx<T>* out, long long pOut, int ldOut, int nstore) {
+  if constexpr (sizeof(T) == 4) {
+    if (shift == 0 && tr.fR0 && fx3_supported(tr.desc.P)) {
+      for (int p0 = 0; p0 < nplanes; p0 += kMaxPlanes) {
+        const int np = std::min(kMaxPlanes, nplanes - p0);
+        ECC_HIP(launch_fx_rows(st, tr.desc.P, dir, np, in + p0 * pIn, pIn, ldIn, nrows, nvalid, out + p0 * pOut,
+                               pOut, ldOut, nstore, tr.fx()));
+      }
+      return ECC_OK;
+    }
+  }
   const RowCfg rc = row_config(tr, tr.desc.P, sizeof(cx<T>));
   ECC_TRY(check_row(rc, tr, sizeof(cx<T>)));
   for (int p0 = 0; p0 < nplanes; p0 += kMaxPlanes) {
@@ -123,6 +134,16 @@ template <typename T>
 ecc_status cols_pass(hipStream_t st, const Transform& tr, int nplanes, int dir, const cx<T>* in, long long pIn,
                      int ldIn, int ncols, int nvalid, int shift, cx<T>* out, long long pOut, int ldOut, int nstore,
                      const cx<T>* mul = nullptr) {
+  if constexpr (sizeof(T) == 4) {
+    if (shift == 0 && tr.fR0 && fx3_supported(tr.desc.P)) {
+      for (int p0 = 0; p0 < nplanes; p0 += kMaxPlanes) {
+        const int np = std::min(kMaxPlanes, nplanes - p0);
+        ECC_HIP(launch_fx_cols(st, tr.desc.P, dir, np, in + p0 * pIn, pIn, ldIn, ncols, nvalid, out + p0 * pOut,
+                               pOut, ldOut, nstore, tr.fx(), mul));
+      }
+      return ECC_OK;
+    }
+  }
   const ColCfg cc = col_config(tr, kColLgB, sizeof(cx<T>), kColThreads);
   ECC_TRY(check_col(cc, tr, sizeof(cx<T>)));
   for (int p0 = 0; p0 < nplanes; p0 += kMaxPlanes) {
@@ -134,8 +155,11 @@ ecc_status cols_pass(hipStream_t st, const Transform& tr, int nplanes, int dir, 
   return ECC_OK;
 }
 
+// Full-size buffers are [..][Pz][Py][Lx]: rows padded to Lx = Px rounded up to 16
+// complex values (128 bytes), so that every 16-column block of the column passes starts
+// on a cache line in every row; V = Pz Py Lx is the stored size, Pz Py Px the transform's.
 struct Geo3 {
-  int nz, ny, nx, Pz, Py, Px;
+  int nz, ny, nx, Pz, Py, Px, Lx;
   long long V;
   const Transform *Tz, *Ty, *Tx;
 };
@@ -144,10 +168,12 @@ ecc_status geometry3(ecc_context ctx, int R, int nz, int ny, int nx, Geo3& g) {
   g.nz = nz;
   g.ny = ny;
   g.nx = nx;
-  g.Pz = next_smooth7(std::max(nz + R, 8));
-  g.Py = next_smooth7(std::max(ny + R, 8));
-  g.Px = next_smooth7(std::max(nx + R, 8));
-  g.V = (long long)g.Pz * g.Py * g.Px;
+  // >= n + R (zero boundary), >= 2R + 1 (the filter window does not wrap onto itself)
+  g.Pz = next_smooth7(std::max({nz + R, 2 * R + 1, 8}));
+  g.Py = next_smooth7(std::max({ny + R, 2 * R + 1, 8}));
+  g.Px = next_smooth7(std::max({nx + R, 2 * R + 1, 8}));
+  g.Lx = (g.Px + 15) & ~15;
+  g.V = (long long)g.Pz * g.Py * g.Lx;
   ECC_HIP(get_transform(ctx, g.Pz, &g.Tz));
   ECC_HIP(get_transform(ctx, g.Py, &g.Ty));
   ECC_HIP(get_transform(ctx, g.Px, &g.Tx));
@@ -171,19 +197,20 @@ ecc_status volume_spectra(ecc_volume_plan plan, int op, const Geo3& g, hipStream
   ECC_HIP(buf->ensure((size_t)U * g.V * sizeof(cx<float>)));
   const int chunk = (int)std::max<long long>(1, std::min<long long>(U, (512LL << 20) / (g.V * 16)));
   DevBuf t1, t2, s64;
-  ECC_HIP(t1.ensure((size_t)chunk * S * S * g.Px * sizeof(cx<double>)));
-  ECC_HIP(t2.ensure((size_t)chunk * S * g.Py * g.Px * sizeof(cx<double>)));
+  ECC_HIP(t1.ensure((size_t)chunk * S * S * g.Lx * sizeof(cx<double>)));
+  ECC_HIP(t2.ensure((size_t)chunk * S * g.Py * g.Lx * sizeof(cx<double>)));
+  const int PyLx = g.Py * g.Lx;
   ECC_HIP(s64.ensure((size_t)chunk * g.V * sizeof(cx<double>)));
   const long long S3 = (long long)S * S * S;
   for (int c0 = 0; c0 < U; c0 += chunk) {
     const int nc = std::min(chunk, U - c0);
     const cx<double>* src = plan->comps64.as<cx<double>>() + c0 * S3;
     ECC_TRY((rows_pass<double>(st, *g.Tx, nc * S, dir, src, (long long)S * S, S, S, S, -R, t1.as<cx<double>>(),
-                               (long long)S * g.Px, g.Px, g.Px)));
-    ECC_TRY((cols_pass<double>(st, *g.Ty, nc * S, dir, t1.as<cx<double>>(), (long long)S * g.Px, g.Px, g.Px, S, -R,
-                               t2.as<cx<double>>(), (long long)g.Py * g.Px, g.Px, g.Py)));
-    ECC_TRY((cols_pass<double>(st, *g.Tz, nc, dir, t2.as<cx<double>>(), (long long)S * g.Py * g.Px, g.Py * g.Px,
-                               g.Py * g.Px, S, -R, s64.as<cx<double>>(), g.V, g.Py * g.Px, g.Pz)));
+                               (long long)S * g.Lx, g.Lx, g.Px)));
+    ECC_TRY((cols_pass<double>(st, *g.Ty, nc * S, dir, t1.as<cx<double>>(), (long long)S * g.Lx, g.Lx, g.Px, S, -R,
+                               t2.as<cx<double>>(), (long long)PyLx, g.Lx, g.Py)));
+    ECC_TRY((cols_pass<double>(st, *g.Tz, nc, dir, t2.as<cx<double>>(), (long long)S * PyLx, PyLx, PyLx, S, -R,
+                               s64.as<cx<double>>(), g.V, PyLx, g.Pz)));
     ECC_HIP(launch_d2f(st, s64.as<cx<double>>(), buf->as<cx<float>>() + (long long)c0 * g.V, (long long)nc * g.V));
   }
   ECC_HIP(hipStreamSynchronize(st));   // temporaries are freed on return
@@ -361,7 +388,7 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
   hipStream_t st = S_(stream);
   Geo3 g{};
   ECC_TRY(geometry3(ctx, plan->R, nz, ny, nx, g));
-  ECC_REQ((long long)g.Py * g.Px <= (1LL << 31) - 1, "volume too large");
+  ECC_REQ((long long)g.Pz * g.Py * g.Lx <= (1LL << 31) - 1, "volume too large");
   const cx<float>* Sp = nullptr;
   ECC_TRY(volume_spectra(plan, op, g, st, &Sp));
   WsUse wu(ctx, st);
@@ -370,23 +397,21 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
   cx<float>* A = ctx->ws.as<cx<float>>();
   cx<float>* Z = A + g.V;
   cx<float>* W = Z + (long long)U * g.V;
-  const int PyPx = g.Py * g.Px;
-  const long long plane = (long long)PyPx;
-  const float scale = (float)(1.0 / (double)g.V);
+  const int PyLx = g.Py * g.Lx, Lx = g.Lx;
+  const long long plane = (long long)PyLx;
+  const float scale = (float)(1.0 / ((double)g.Pz * g.Py * g.Px));
   if (op == ECC_CORRELATION) {
     // H -> spectrum A (x, y, z passes), products with every component's spectrum
     ECC_HIP(launch_real_to_cx(st, signal, Z, nv));
-    ECC_TRY((rows_pass<float>(st, *g.Tx, nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, g.Px, g.Px)));
-    ECC_TRY((cols_pass<float>(st, *g.Ty, nz, -1, W, plane, g.Px, g.Px, ny, 0, Z, plane, g.Px, g.Py)));
-    ECC_TRY((cols_pass<float>(st, *g.Tz, 1, -1, Z, 0, PyPx, PyPx, nz, 0, A, 0, PyPx, g.Pz)));
+    ECC_TRY((rows_pass<float>(st, *g.Tx, nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, Lx, g.Px)));
+    ECC_TRY((cols_pass<float>(st, *g.Ty, nz, -1, W, plane, Lx, g.Px, ny, 0, Z, plane, Lx, g.Py)));
+    ECC_TRY((cols_pass<float>(st, *g.Tz, 1, -1, Z, 0, PyLx, PyLx, nz, 0, A, 0, PyLx, g.Pz)));
     // inverse transforms of the products A Sp_c (formed as the first pass loads them), only
     // the output voxels kept
-    ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyPx, PyPx, g.Pz, 0, W, (long long)nz * PyPx, PyPx, nz,
+    ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyLx, PyLx, g.Pz, 0, W, (long long)nz * PyLx, PyLx, nz,
                               A)));
-    ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, +1, W, plane, g.Px, g.Px, g.Py, 0, Z, (long long)ny * g.Px, g.Px,
-                              ny)));
-    ECC_TRY((rows_pass<float>(st, *g.Tx, U, +1, Z, (long long)nz * ny * g.Px, g.Px, nz * ny, g.Px, 0, W, nv, nx,
-                              nx)));
+    ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, +1, W, plane, Lx, g.Px, g.Py, 0, Z, (long long)ny * Lx, Lx, ny)));
+    ECC_TRY((rows_pass<float>(st, *g.Tx, U, +1, Z, (long long)nz * ny * Lx, Lx, nz * ny, g.Px, 0, W, nv, nx, nx)));
     // Wigner-D combination per voxel
     ECC_HIP(launch_wigner_voxels(st, plan->K, 0, alpha, beta, gamma, nv, plan->coef.as<double>(),
                                  plan->d_w.as<float>(), W, nullptr, out, nullptr, scale));
@@ -394,13 +419,13 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
     // modulated signals H D_c, their spectra, the weighted sum of products, one inverse
     ECC_HIP(launch_wigner_voxels(st, plan->K, 1, alpha, beta, gamma, nv, plan->coef.as<double>(),
                                  plan->d_w.as<float>(), nullptr, signal, nullptr, Z, 1.0f));
-    ECC_TRY((rows_pass<float>(st, *g.Tx, U * nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, g.Px, g.Px)));
-    ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, -1, W, plane, g.Px, g.Px, ny, 0, Z, plane, g.Px, g.Py)));
-    ECC_TRY((cols_pass<float>(st, *g.Tz, U, -1, Z, (long long)nz * PyPx, PyPx, PyPx, nz, 0, W, g.V, PyPx, g.Pz)));
+    ECC_TRY((rows_pass<float>(st, *g.Tx, U * nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, Lx, g.Px)));
+    ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, -1, W, plane, Lx, g.Px, ny, 0, Z, plane, Lx, g.Py)));
+    ECC_TRY((cols_pass<float>(st, *g.Tz, U, -1, Z, (long long)nz * PyLx, PyLx, PyLx, nz, 0, W, g.V, PyLx, g.Pz)));
     ECC_HIP(launch_spec_accumulate(st, W, Sp, plan->d_w.as<float>(), g.V, U, A));
-    ECC_TRY((cols_pass<float>(st, *g.Tz, 1, +1, A, 0, PyPx, PyPx, g.Pz, 0, Z, 0, PyPx, nz)));
-    ECC_TRY((cols_pass<float>(st, *g.Ty, nz, +1, Z, plane, g.Px, g.Px, g.Py, 0, W, (long long)ny * g.Px, g.Px, ny)));
-    ECC_TRY((rows_pass<float>(st, *g.Tx, 1, +1, W, 0, g.Px, nz * ny, g.Px, 0, Z, 0, nx, nx)));
+    ECC_TRY((cols_pass<float>(st, *g.Tz, 1, +1, A, 0, PyLx, PyLx, g.Pz, 0, Z, 0, PyLx, nz)));
+    ECC_TRY((cols_pass<float>(st, *g.Ty, nz, +1, Z, plane, Lx, g.Px, g.Py, 0, W, (long long)ny * Lx, Lx, ny)));
+    ECC_TRY((rows_pass<float>(st, *g.Tx, 1, +1, W, 0, Lx, nz * ny, g.Px, 0, Z, 0, nx, nx)));
     ECC_HIP(launch_real_part(st, Z, out, nv, scale));
   }
   return ECC_OK;

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synthetic import blurred_noise, random_filter, theta_field
+from synthetic import scale_field, blurred_noise, random_filter, theta_field
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -114,6 +114,31 @@ def test_smallest_images(E, op, shape):
             plan = E.FilterPlan.rotation(ctx, dev(filt), K)
             y = host(E.ecc_extended(ctx, op, plan, dev(img), dev(theta))).astype(np.float64)
             plan.close()
+        finally:
+            ctx.close()
+        assert relinf(y, ref) <= TOL, (name, relinf(y, ref))
+
+
+@pytest.mark.parametrize("shape", [(4, 40), (9, 6), (1, 1)])
+def test_images_smaller_than_the_filter_radius(E, shape):
+    """Scale smoothing (65 x 65 support, R = 32) of images with a side <= R: the two-pass
+    transform size must hold the whole filter window (2R + 1 taps) as well as n + R; every
+    strategy against the oracle."""
+    img = blurred_noise(shape, 47, sigma=0.8) if min(shape) > 1 else np.array([[0.7]], np.float32)
+    s = scale_field(shape, 48, 1.0, 8.0, sigma=1.0) if min(shape) > 1 else np.array([[3.0]], np.float32)
+    ref, _, _ = O.scale_smooth_fft(img.astype(np.float64), s.astype(np.float64), O.ScaleParams())
+    for name, strat in strategies(E) + [("auto", E.STRATEGY_AUTO)]:
+        ctx = E.Context(0)
+        try:
+            ctx.set_strategy(strat)
+            plan = E.FilterPlan.scale(ctx)
+            try:
+                y = host(E.ecc_scale_smooth(ctx, plan, dev(img), dev(s))).astype(np.float64)
+            except E.EccError as err:       # a strategy without a block shape for R = 32 says so
+                assert strat == E.STRATEGY_TILED and err.status == 2, (name, err)
+                continue
+            finally:
+                plan.close()
         finally:
             ctx.close()
         assert relinf(y, ref) <= TOL, (name, relinf(y, ref))
