@@ -476,6 +476,31 @@ def steer3d_workload(E, timeit):
         res[name + "_Mvox_comp_s"] = round(n ** 3 * full / (ms * 1e-3) / 1e6, 1)
         outs[name] = (op, out.cpu().numpy().astype(np.float64))
     res["workspace_bytes"] = c.volume_workspace_size(plan, n, n, n)
+    # HBM bytes the passes of one call move (transform size P per axis, rows padded to
+    # Lx = P rounded up to 16 complex values; U component volumes; complex64 = 8 B)
+    R = (S - 1) // 2
+    P = max(n + R, 2 * R + 1, 8)
+    while True:                       # the library's size rule: the next 7-smooth integer
+        m = P
+        for f in (2, 3, 5, 7):
+            while m % f == 0:
+                m //= f
+        if m == 1:
+            break
+        P += 1
+    U, Lx, nv = plan.U, (P + 15) // 16 * 16, n ** 3
+    V = P * P * Lx
+    zy, yy = U * n * P * Lx * 8, U * n * n * Lx * 8      # U volumes of n x P / n x n rows of Lx
+    # correlation: z pass (spectra in, products formed on load), y pass, x pass, combination
+    corr = (U * V * 8 + zy) + (zy + yy) + (yy + U * nv * 8) + (U * nv * 8 + 16 * nv)
+    # convolution: modulation, x, y and z passes, product sum (the single-volume inverse
+    # transforms are left out: 6 V x 8 B)
+    conv = (16 * nv + U * nv * 8) + (U * nv * 8 + yy) + (yy + zy) + (zy + U * V * 8) + (2 * U * V * 8 + V * 8)
+    for name, nbytes in (("correlation", corr), ("convolution", conv)):
+        tbs = nbytes / (res[name + "_ms"] * 1e-3) / 1e12
+        res[name + "_pass_traffic_GB"] = round(nbytes / 1e9, 3)
+        res[name + "_achieved_TBs"] = round(tbs, 3)
+        res[name + "_frac_of_hbm_peak"] = round(tbs / (PEAK_HBM_GBS / 1e3), 3)
     # sampled voxels against the oracle on the crop each depends on
     import oracle.steer3d as O3
     parts = O3.components3d(filt.astype(np.float64), K)
