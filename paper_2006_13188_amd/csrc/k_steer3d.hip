@@ -8,6 +8,7 @@
 // A rotation R = Rz(alpha) Ry(beta) Rz(gamma) acts on filters by (R F)(x) = F(R^{-1} x), so
 // that Y_l^m(R^{-1} x) = sum_m' D^l_{m'm}(R) Y_l^m'(x) with
 // D^l_{m'm} = e^{-i m' alpha} d^l_{m'm}(beta) e^{-i m gamma} (Wigner's explicit sum for d).
+#include <algorithm>
 #include <type_traits>
 
 #include "fft_fixed.hpp"
@@ -186,9 +187,11 @@ constexpr int fx_per_thread() { return (N + T - 1) / T; }
 
 // The three passes on one transform held in LDS at X[pos * ES] (ES = element stride; the
 // caller offsets X), driven by thread b < NL. The first pass's inputs come from `load(j)`;
-// the outputs X[b + r NL], r < R2, are handed to `store(i, value)`.
+// the outputs X[b + r NL], r < R2, are handed to `store(r, i = b + r NL, value)`.
+// Threads with act == false take part in the barriers only (the caller's other threads).
 template <class F, int DIR, int ES, class Load, class Store>
-__device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, int b, Load load, Store store) {
+__device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, int b, bool act, Load load,
+                                             Store store) {
   static_assert(F::R2 > 1, "three-pass schedules");
   constexpr int NL = F::N2;
   constexpr int K0 = fx_per_thread<F::N0, NL>(), K1 = fx_per_thread<F::N1, NL>();
@@ -197,7 +200,7 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
 #pragma unroll
   for (int k = 0; k < K0; ++k) {
     const int b0 = b + k * NL;
-    if (b0 < F::N0) {
+    if (act && b0 < F::N0) {
 #pragma unroll
       for (int r = 0; r < F::R0; ++r) v0[k][r] = load(b0 + r * F::N0);
     }
@@ -205,7 +208,7 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
 #pragma unroll
   for (int k = 0; k < K0; ++k) {
     const int b0 = b + k * NL;
-    if (b0 < F::N0) {
+    if (act && b0 < F::N0) {
       dft<F::R0, DIR, float>(v0[k]);
 #pragma unroll
       for (int r = 0; r < F::R0; ++r) X[(b0 * F::R0 + r) * ES] = v0[k][r];
@@ -217,7 +220,7 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
 #pragma unroll
   for (int k = 0; k < K1; ++k) {
     const int b1 = b + k * NL;
-    if (b1 < F::N1) {
+    if (act && b1 < F::N1) {
 #pragma unroll
       for (int r = 0; r < F::R1; ++r) v1[k][r] = X[(b1 + r * F::N1) * ES];
     }
@@ -226,7 +229,7 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
 #pragma unroll
   for (int k = 0; k < K1; ++k) {
     const int b1 = b + k * NL;
-    if (b1 < F::N1) {
+    if (act && b1 < F::N1) {
       const int j = b1 % F::R0;
       if (j != 0) fixed_twiddle<F::R1, DIR, float>(v1[k], tw + j * (F::R1 - 1));
       dft<F::R1, DIR, float>(v1[k]);
@@ -237,13 +240,15 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
   }
   __syncthreads();
   // pass 2 (Ls = R0 R1, last): one butterfly per thread, natural order out
-  cx<float> v2[F::R2];
+  if (act) {
+    cx<float> v2[F::R2];
 #pragma unroll
-  for (int r = 0; r < F::R2; ++r) v2[r] = X[(b + r * NL) * ES];
-  if (b != 0) fixed_twiddle<F::R2, DIR, float>(v2, tw + F::TW1 + b * (F::R2 - 1));
-  dft<F::R2, DIR, float>(v2);
+    for (int r = 0; r < F::R2; ++r) v2[r] = X[(b + r * NL) * ES];
+    if (b != 0) fixed_twiddle<F::R2, DIR, float>(v2, tw + F::TW1 + b * (F::R2 - 1));
+    dft<F::R2, DIR, float>(v2);
 #pragma unroll
-  for (int r = 0; r < F::R2; ++r) store(b + r * NL, v2[r]);
+    for (int r = 0; r < F::R2; ++r) store(r, b + r * NL, v2[r]);
+  }
 }
 
 template <class F, int DIR>
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols(const cx<float>* __res
   const cx<float>* src = in + (long long)blockIdx.y * planeIn;
   cx<float>* dst = out + (long long)blockIdx.y * planeOut;
   fx_transform<F, DIR, kFxB>(
-      X + c, tw, b,
+      X + c, tw, b, true,
       [&](int j) {
         cx<float> v = mk(0.f, 0.f);
         if (cin && j < nvalid) {
@@ -271,9 +276,66 @@ __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols(const cx<float>* __res
         }
         return v;
       },
-      [&](int i, cx<float> v) {
+      [&](int, int i, cx<float> v) {
         if (cin && i < nstore) dst[(long long)i * ldOut + col] = v;
       });
+}
+
+// Forward column transforms of U planes with the weighted sum of their products with U
+// spectra (the convolution's last forward pass and its sum over the components):
+// out_g[i][v] = sum_{u in group g} w_u Sp_u[i][v] (DFT of in_u along the rows)[i][v] for
+// every i < P, Sp_u and out with row pitch ldOut, in_u rows j >= nvalid zero. Group g =
+// blockIdx.y takes components [g per, (g + 1) per) and writes plane g of out (planeOut
+// apart); the groups are added by k_sum_planes. Within a group the components are summed
+// in order, in registers, so the result does not depend on the launch.
+template <class F>
+__global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols_accum(const cx<float>* __restrict__ in, long long planeIn,
+                                                              int ldIn, int ncols, int nvalid, int U,
+                                                              const cx<float>* __restrict__ Sp, long long planeSp,
+                                                              const float* __restrict__ w, int per,
+                                                              cx<float>* __restrict__ out, long long planeOut,
+                                                              int ldOut, const cx<float>* __restrict__ twg) {
+  __shared__ cx<float> tw[(F::TW + 1) & ~1];
+  __shared__ cx<float> X[F::P * kFxB];
+  for (int i = threadIdx.x; i < F::TW; i += blockDim.x) tw[i] = twg[i];
+  const int c = threadIdx.x % kFxB, b = threadIdx.x / kFxB;
+  const int col = blockIdx.x * kFxB + c;
+  const bool cin = col < ncols;
+  cx<float> acc[F::R2];
+#pragma unroll
+  for (int r = 0; r < F::R2; ++r) acc[r] = mk(0.f, 0.f);
+  const int u0 = blockIdx.y * per, u1 = min(U, u0 + per);
+  for (int u = u0; u < u1; ++u) {
+    const cx<float>* src = in + (long long)u * planeIn;
+    const cx<float>* sp = Sp + (long long)u * planeSp;
+    const float wu = w[u];
+    fx_transform<F, -1, kFxB>(
+        X + c, tw, b, true,
+        [&](int j) { return cin && j < nvalid ? src[(long long)j * ldIn + col] : mk(0.f, 0.f); },
+        [&](int r, int i, cx<float> v) {
+          if (cin) {
+            const cx<float> p = cmul(v, sp[(long long)i * ldOut + col]);
+            acc[r].re = fmaf(wu, p.re, acc[r].re);
+            acc[r].im = fmaf(wu, p.im, acc[r].im);
+          }
+        });
+    __syncthreads();   // the next component rewrites X
+  }
+  if (cin) {
+    cx<float>* dst = out + (long long)blockIdx.y * planeOut;
+#pragma unroll
+    for (int r = 0; r < F::R2; ++r) dst[(long long)(b + r * F::N2) * ldOut + col] = acc[r];
+  }
+}
+
+// out[v] = sum_g in[g][v], g = 0..G-1 in order
+__global__ void k_sum_planes(const cx<float>* __restrict__ in, long long plane, int G, cx<float>* __restrict__ out,
+                             long long n) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+    cx<float> a = in[v];
+    for (int g = 1; g < G; ++g) a = a + in[(long long)g * plane + v];
+    out[v] = a;
+  }
 }
 
 // Rows: kFxRows rows per workgroup, thread (row, b) = (t / NL, t % NL), each row in its
@@ -295,9 +357,9 @@ __global__ void __launch_bounds__(F::N2 * kFxRows) k_fx_rows(const cx<float>* __
   const cx<float>* src = in + (long long)blockIdx.y * planeIn + (long long)(act ? row : 0) * ldIn;
   cx<float>* dst = out + (long long)blockIdx.y * planeOut + (long long)(act ? row : 0) * ldOut;
   fx_transform<F, DIR, 1>(
-      X + rl * F::P, tw, b,
+      X + rl * F::P, tw, b, true,
       [&](int j) { return act && j < nvalid ? src[j] : mk(0.f, 0.f); },
-      [&](int i, cx<float> v) {
+      [&](int, int i, cx<float> v) {
         if (act && i < nstore) dst[i] = v;
       });
 }
@@ -358,6 +420,69 @@ constexpr int term_index(int l, int mp, int m) {
   return t;
 }
 
+// Per-voxel state of the Wigner-D values of the voxel's rotation (float64): powers of
+// cos(beta/2) and sin(beta/2), e^{-i m alpha} and e^{-i m gamma} for m = 0..K.
+template <int K>
+struct WignerVoxel {
+  double cpw[2 * K + 1], spw[2 * K + 1];
+  double ear[K + 1], eai[K + 1], egr[K + 1], egi[K + 1];
+  __device__ __forceinline__ void init(float alpha, float beta, float gamma) {
+    double sb, cb, sa, ca, sg, cg;
+    sincos(0.5 * (double)beta, &sb, &cb);
+    sincos((double)alpha, &sa, &ca);
+    sincos((double)gamma, &sg, &cg);
+    cpw[0] = spw[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= 2 * K; ++j) {
+      cpw[j] = cpw[j - 1] * cb;
+      spw[j] = spw[j - 1] * sb;
+    }
+    ear[0] = egr[0] = 1.0;
+    eai[0] = egi[0] = 0.0;
+#pragma unroll
+    for (int j = 1; j <= K; ++j) {
+      ear[j] = ear[j - 1] * ca + eai[j - 1] * sa;
+      eai[j] = eai[j - 1] * ca - ear[j - 1] * sa;
+      egr[j] = egr[j - 1] * cg + egi[j - 1] * sg;
+      egi[j] = egi[j - 1] * cg - egr[j - 1] * sg;
+    }
+  }
+  // D^l_{m'm} = d (pr + i pi): d = d^l_{m'm}(beta) by Wigner's sum (coefficients in the
+  // order of term_index), pr + i pi = e^{-i m' alpha} e^{-i m gamma}
+  template <int l, int mp, int m>
+  __device__ __forceinline__ void entry(const double* __restrict__ coef, double& d, double& pr, double& pi) const {
+    constexpr int t0 = term_index(l, mp, m), k0 = cmax(0, m - mp), nk = wig_terms(l, mp, m);
+    d = 0.0;
+    static_for<0, nk>([&](auto J_) {
+      constexpr int k = k0 + decltype(J_)::value;
+      d = fma(coef[t0 + decltype(J_)::value], cpw[2 * l + m - mp - 2 * k] * spw[mp - m + 2 * k], d);
+    });
+    // for m < 0, e^{-i m gamma} = conj(e^{-i |m| gamma})
+    constexpr int am = m < 0 ? -m : m;
+    const double gr = egr[am], gi = m < 0 ? -egi[am] : egi[am];
+    pr = ear[mp] * gr - eai[mp] * gi;
+    pi = ear[mp] * gi + eai[mp] * gr;
+  }
+};
+
+// Calls fn(integral_constant<c>, integral_constant<l>, <m'>, <m>) for every half-set
+// component c of band limit K, in order.
+template <int K, class Fn>
+__device__ __forceinline__ void for_half_set(Fn&& fn) {
+  static_for<0, K + 1>([&](auto L_) {
+    constexpr int l = decltype(L_)::value;
+    static_for<0, l + 1>([&](auto MP_) {
+      constexpr int mp = decltype(MP_)::value;
+      static_for<hs_first_m(mp, l), l + 1>([&](auto M_) {
+        constexpr int m = decltype(M_)::value;
+        fn(std::integral_constant<int, hs_index(l, mp, m)>{}, L_, MP_, M_);
+      });
+    });
+  });
+}
+
+constexpr int half_set_size(int K) { return (K + 1) * (2 * K * K + 4 * K + 3) / 3; }
+
 // MODE 0 (correlation): y[v] = scale sum_c w_c Re(D_c G_c[v]); MODE 1 (convolution):
 // M[c][v] = H[v] D_c. coef: Wigner's coefficients in the order of term_index.
 template <int K, int MODE>
@@ -369,58 +494,79 @@ __global__ void __launch_bounds__(256) k_wigner_voxels(const float* __restrict__
                                                       float scale) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvox) return;
-  double sb, cb, sa, ca, sg, cg;
-  sincos(0.5 * (double)beta[v], &sb, &cb);
-  sincos((double)alpha[v], &sa, &ca);
-  sincos((double)gamma[v], &sg, &cg);
-  double cpw[2 * K + 1], spw[2 * K + 1];
-  cpw[0] = spw[0] = 1.0;
-#pragma unroll
-  for (int j = 1; j <= 2 * K; ++j) {
-    cpw[j] = cpw[j - 1] * cb;
-    spw[j] = spw[j - 1] * sb;
-  }
-  // e^{-i m alpha}, e^{-i m gamma} for m = 0..K
-  double ear[K + 1], eai[K + 1], egr[K + 1], egi[K + 1];
-  ear[0] = egr[0] = 1.0;
-  eai[0] = egi[0] = 0.0;
-#pragma unroll
-  for (int j = 1; j <= K; ++j) {
-    ear[j] = ear[j - 1] * ca + eai[j - 1] * sa;
-    eai[j] = eai[j - 1] * ca - ear[j - 1] * sa;
-    egr[j] = egr[j - 1] * cg + egi[j - 1] * sg;
-    egi[j] = egi[j - 1] * cg - egr[j - 1] * sg;
-  }
+  WignerVoxel<K> wv;
+  wv.init(alpha[v], beta[v], gamma[v]);
   const float h = MODE == 1 ? H[v] : 0.f;
   float acc = 0.f;
-  static_for<0, K + 1>([&](auto L_) {
-    constexpr int l = decltype(L_)::value;
-    static_for<0, l + 1>([&](auto MP_) {
-      constexpr int mp = decltype(MP_)::value;
-      static_for<hs_first_m(mp, l), l + 1>([&](auto M_) {
-        constexpr int m = decltype(M_)::value;
-        constexpr int t0 = term_index(l, mp, m), k0 = cmax(0, m - mp), nk = wig_terms(l, mp, m);
-        double d = 0.0;
-        static_for<0, nk>([&](auto J_) {
-          constexpr int k = k0 + decltype(J_)::value;
-          d = fma(coef[t0 + decltype(J_)::value], cpw[2 * l + m - mp - 2 * k] * spw[mp - m + 2 * k], d);
-        });
-        // D = e^{-i m' alpha} d e^{-i m gamma}; for m < 0, e^{-i m gamma} = conj(e^{-i |m| gamma})
-        constexpr int am = m < 0 ? -m : m;
-        const double gr = egr[am], gi = m < 0 ? -egi[am] : egi[am];
-        const double pr = ear[mp] * gr - eai[mp] * gi, pi = ear[mp] * gi + eai[mp] * gr;
-        constexpr int c = hs_index(l, mp, m);
-        if constexpr (MODE == 0) {
-          const cx<float> g = G[(long long)c * nvox + v];
-          // Re(D G) = d (pr g.re - pi g.im)
-          acc = fmaf(w[c] * (float)d, (float)pr * g.re - (float)pi * g.im, acc);
-        } else {
-          Mout[(long long)c * nvox + v] = mk((float)(d * pr) * h, (float)(d * pi) * h);
-        }
-      });
-    });
+  for_half_set<K>([&](auto C_, auto L_, auto MP_, auto M_) {
+    constexpr int c = decltype(C_)::value;
+    double d, pr, pi;
+    wv.template entry<decltype(L_)::value, decltype(MP_)::value, decltype(M_)::value>(coef, d, pr, pi);
+    if constexpr (MODE == 0) {
+      const cx<float> g = G[(long long)c * nvox + v];
+      // Re(D G) = d (pr g.re - pi g.im)
+      acc = fmaf(w[c] * (float)d, (float)pr * g.re - (float)pi * g.im, acc);
+    } else {
+      Mout[(long long)c * nvox + v] = mk((float)(d * pr) * h, (float)(d * pi) * h);
+    }
   });
   if constexpr (MODE == 0) y[v] = acc * scale;
+}
+
+// The correlation's last inverse pass (along x) fused with the Wigner-D combination, for a
+// compiled transform length: one workgroup per output row (z, y). Its components' rows are
+// transformed kFxCh at a time (kFxCh groups of NL threads, one row each) into LDS, then
+// thread x (one output voxel) adds w_c Re(D_c(x) G_c(x)) for those components; the
+// component loop is unrolled, so every D entry has constant indices. in: component planes
+// (planeIn apart) of nrows rows with pitch ldIn, nvalid valid elements per row; y: rows of
+// nx voxels; alpha, beta, gamma: the same layout as y.
+constexpr int kFxCh = 8;
+
+template <class F, int K>
+__global__ void __launch_bounds__(192) k_fx_rows_wigner(const cx<float>* __restrict__ in, long long planeIn, int ldIn,
+                                                       int nvalid, int nx, const float* __restrict__ alpha,
+                                                       const float* __restrict__ beta, const float* __restrict__ gamma,
+                                                       const double* __restrict__ coef, const float* __restrict__ w,
+                                                       float* __restrict__ y, float scale,
+                                                       const cx<float>* __restrict__ twg) {
+  constexpr int NL = F::N2, U = half_set_size(K), NCH = (U + kFxCh - 1) / kFxCh;
+  static_assert(kFxCh * NL <= 192, "one row transform per thread group");
+  __shared__ cx<float> tw[(F::TW + 1) & ~1];
+  __shared__ cx<float> X[kFxCh * F::P];
+  __shared__ cx<float> Gs[kFxCh * F::P];
+  for (int i = threadIdx.x; i < F::TW; i += blockDim.x) tw[i] = twg[i];
+  const int t = threadIdx.x;
+  const int kk = t / NL, b = t - kk * NL;   // transform role: component slot kk of a chunk
+  const long long row = blockIdx.x;
+  const bool vox = t < nx;                  // voxel role: x = t
+  const long long p = row * nx + t;
+  WignerVoxel<K> wv;
+  if (vox) wv.init(alpha[p], beta[p], gamma[p]);
+  float acc = 0.f;
+  static_for<0, NCH>([&](auto CH_) {
+    constexpr int c0 = decltype(CH_)::value * kFxCh;
+    const int c = c0 + kk;
+    const bool act = kk < kFxCh && c < U;
+    const cx<float>* src = in + (long long)(act ? c : 0) * planeIn + row * ldIn;
+    fx_transform<F, +1, 1>(
+        X + (kk < kFxCh ? kk : 0) * F::P, tw, b, act,
+        [&](int j) { return j < nvalid ? src[j] : mk(0.f, 0.f); },
+        [&](int, int i, cx<float> v) { Gs[kk * F::P + i] = v; });
+    __syncthreads();   // the chunk's rows are in Gs
+    if (vox) {
+      for_half_set<K>([&](auto C_, auto L_, auto MP_, auto M_) {
+        constexpr int cc = decltype(C_)::value;
+        if constexpr (cc >= c0 && cc < c0 + kFxCh) {
+          double d, pr, pi;
+          wv.template entry<decltype(L_)::value, decltype(MP_)::value, decltype(M_)::value>(coef, d, pr, pi);
+          const cx<float> g = Gs[(cc - c0) * F::P + t];
+          acc = fmaf(w[cc] * (float)d, (float)pr * g.re - (float)pi * g.im, acc);
+        }
+      });
+    }
+    __syncthreads();   // Gs and X are rewritten by the next chunk
+  });
+  if (vox) y[p] = acc * scale;
 }
 
 }  // namespace
@@ -505,6 +651,60 @@ hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<f
   }
   ECC_FX3_SIZES(ECC_FXR)
 #undef ECC_FXR
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fx_cols_accum(hipStream_t s, int P, int nplanes, const cx<float>* in, long long planeIn, int ldIn,
+                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, const float* w,
+                                int groups, cx<float>* part, long long planePart, cx<float>* out, int ldOut,
+                                const cx<float>* tw) {
+#define ECC_FXA(a, b_, c_)                                                                          \
+  if (P == (a) * (b_) * (c_)) {                                                                     \
+    using F = Fixed3<a, b_, c_>;                                                                    \
+    if (nvalid > P || nplanes < 1 || groups < 1) return hipErrorInvalidValue;                       \
+    const int per = (nplanes + groups - 1) / groups, G = (nplanes + per - 1) / per;                 \
+    cx<float>* dst = G > 1 ? part : out;                                                            \
+    hipLaunchKernelGGL((k_fx_cols_accum<F>), dim3((ncols + kFxB - 1) / kFxB, G), dim3(F::N2 * kFxB), 0, s, \
+                       in, planeIn, ldIn, ncols, nvalid, nplanes, Sp, planeSp, w, per, dst, planePart, ldOut, tw); \
+    if (G > 1) {                                                                                    \
+      hipError_t e = last();                                                                        \
+      if (e != hipSuccess) return e;                                                                \
+      const long long n = (long long)P * ldOut;                                                     \
+      hipLaunchKernelGGL(k_sum_planes, dim3(grid_for(n)), dim3(256), 0, s, part, planePart, G, out, n); \
+    }                                                                                               \
+    return last();                                                                                  \
+  }
+  ECC_FX3_SIZES(ECC_FXA)
+#undef ECC_FXA
+  return hipErrorInvalidValue;
+}
+
+bool fx_rows_wigner_supported(int P, int K, int nx) {
+  return fx3_supported(P) && K >= 0 && K <= kFusedWignerK && nx >= 1 && nx <= 192;
+}
+
+hipError_t launch_fx_rows_wigner(hipStream_t s, int P, int K, const cx<float>* in, long long planeIn, int ldIn,
+                                 int nrows, int nvalid, int nx, const float* alpha, const float* beta,
+                                 const float* gamma, const double* coef, const float* w, float* y, float scale,
+                                 const cx<float>* tw) {
+  if (!fx_rows_wigner_supported(P, K, nx) || nvalid > P || nrows < 1) return hipErrorInvalidValue;
+  const unsigned nthr = (unsigned)((std::max(kFxCh * 15, nx) + 63) / 64 * 64);
+#define ECC_FXW(a, b_, c_)                                                                               \
+  if (P == (a) * (b_) * (c_)) {                                                                          \
+    using F = Fixed3<a, b_, c_>;                                                                         \
+    static_assert(F::N2 == 15, "thread count above assumes 15 threads per row transform");              \
+    switch (K) {                                                                                         \
+      case 0: hipLaunchKernelGGL((k_fx_rows_wigner<F, 0>), dim3(nrows), dim3(nthr), 0, s, in, planeIn, ldIn, nvalid, nx, alpha, beta, gamma, coef, w, y, scale, tw); break; \
+      case 1: hipLaunchKernelGGL((k_fx_rows_wigner<F, 1>), dim3(nrows), dim3(nthr), 0, s, in, planeIn, ldIn, nvalid, nx, alpha, beta, gamma, coef, w, y, scale, tw); break; \
+      case 2: hipLaunchKernelGGL((k_fx_rows_wigner<F, 2>), dim3(nrows), dim3(nthr), 0, s, in, planeIn, ldIn, nvalid, nx, alpha, beta, gamma, coef, w, y, scale, tw); break; \
+      case 3: hipLaunchKernelGGL((k_fx_rows_wigner<F, 3>), dim3(nrows), dim3(nthr), 0, s, in, planeIn, ldIn, nvalid, nx, alpha, beta, gamma, coef, w, y, scale, tw); break; \
+      case 4: hipLaunchKernelGGL((k_fx_rows_wigner<F, 4>), dim3(nrows), dim3(nthr), 0, s, in, planeIn, ldIn, nvalid, nx, alpha, beta, gamma, coef, w, y, scale, tw); break; \
+      default: return hipErrorInvalidValue;                                                              \
+    }                                                                                                    \
+    return last();                                                                                       \
+  }
+  ECC_FX3_SIZES(ECC_FXW)
+#undef ECC_FXW
   return hipErrorInvalidValue;
 }
 

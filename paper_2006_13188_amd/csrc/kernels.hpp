@@ -295,6 +295,24 @@ hipError_t launch_fx_cols(hipStream_t s, int P, int dir, int nplanes, const cx<f
 hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<float>* in, long long planeIn,
                           int ldIn, int nrows, int nvalid, cx<float>* out, long long planeOut, int ldOut,
                           int nstore, const cx<float>* tw);
+// Forward column transforms of nplanes planes summed with weights against as many
+// spectra: out[i][v] = sum_u w_u Sp_u[i][v] DFT(in_u)[i][v], i < P (row pitch ldOut for
+// Sp and out). The components are split into at most `groups` consecutive groups, summed
+// in order within each group into planes of `part` (planePart apart; unused with one
+// group), then the groups are added in order.
+hipError_t launch_fx_cols_accum(hipStream_t s, int P, int nplanes, const cx<float>* in, long long planeIn, int ldIn,
+                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, const float* w,
+                                int groups, cx<float>* part, long long planePart, cx<float>* out, int ldOut,
+                                const cx<float>* tw);
+// The correlation's last inverse pass (along x, compiled length P) fused with the Wigner-D
+// combination: y[row][x] = scale sum_c w_c Re(D_c(x) IDFT(in_c[row])[x]) for K <= kFusedWignerK
+// and nx <= 192; alpha, beta, gamma and y are nrows x nx.
+constexpr int kFusedWignerK = 4;
+bool fx_rows_wigner_supported(int P, int K, int nx);
+hipError_t launch_fx_rows_wigner(hipStream_t s, int P, int K, const cx<float>* in, long long planeIn, int ldIn,
+                                 int nrows, int nvalid, int nx, const float* alpha, const float* beta,
+                                 const float* gamma, const double* coef, const float* w, float* y, float scale,
+                                 const cx<float>* tw);
 hipError_t prepare_fx_kernels();
 // A[v] = sum_c w_c X[c][v] Sp[c][v]
 hipError_t launch_spec_accumulate(hipStream_t s, const cx<float>* X, const cx<float>* Sp, const float* w, long long V,

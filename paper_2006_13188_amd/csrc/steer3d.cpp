@@ -411,18 +411,32 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
     ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyLx, PyLx, g.Pz, 0, W, (long long)nz * PyLx, PyLx, nz,
                               A)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, +1, W, plane, Lx, g.Px, g.Py, 0, Z, (long long)ny * Lx, Lx, ny)));
-    ECC_TRY((rows_pass<float>(st, *g.Tx, U, +1, Z, (long long)nz * ny * Lx, Lx, nz * ny, g.Px, 0, W, nv, nx, nx)));
-    // Wigner-D combination per voxel
-    ECC_HIP(launch_wigner_voxels(st, plan->K, 0, alpha, beta, gamma, nv, plan->coef.as<double>(),
-                                 plan->d_w.as<float>(), W, nullptr, out, nullptr, scale));
+    if (g.Tx->fR0 && fx_rows_wigner_supported(g.Px, plan->K, nx)) {
+      // last pass and the Wigner-D combination in one kernel (no component volumes stored)
+      ECC_HIP(launch_fx_rows_wigner(st, g.Px, plan->K, Z, (long long)nz * ny * Lx, Lx, nz * ny, g.Px, nx, alpha,
+                                    beta, gamma, plan->coef.as<double>(), plan->d_w.as<float>(), out, scale,
+                                    g.Tx->fx()));
+    } else {
+      ECC_TRY((rows_pass<float>(st, *g.Tx, U, +1, Z, (long long)nz * ny * Lx, Lx, nz * ny, g.Px, 0, W, nv, nx, nx)));
+      // Wigner-D combination per voxel
+      ECC_HIP(launch_wigner_voxels(st, plan->K, 0, alpha, beta, gamma, nv, plan->coef.as<double>(),
+                                   plan->d_w.as<float>(), W, nullptr, out, nullptr, scale));
+    }
   } else {
     // modulated signals H D_c, their spectra, the weighted sum of products, one inverse
     ECC_HIP(launch_wigner_voxels(st, plan->K, 1, alpha, beta, gamma, nv, plan->coef.as<double>(),
                                  plan->d_w.as<float>(), nullptr, signal, nullptr, Z, 1.0f));
     ECC_TRY((rows_pass<float>(st, *g.Tx, U * nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, Lx, g.Px)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, -1, W, plane, Lx, g.Px, ny, 0, Z, plane, Lx, g.Py)));
-    ECC_TRY((cols_pass<float>(st, *g.Tz, U, -1, Z, (long long)nz * PyLx, PyLx, PyLx, nz, 0, W, g.V, PyLx, g.Pz)));
-    ECC_HIP(launch_spec_accumulate(st, W, Sp, plan->d_w.as<float>(), g.V, U, A));
+    if (g.Tz->fR0 && fx3_supported(g.Pz)) {
+      // z pass and the weighted product sum in one kernel (components summed in registers,
+      // in four groups whose partial sums W holds, then added in order)
+      ECC_HIP(launch_fx_cols_accum(st, g.Pz, U, Z, (long long)nz * PyLx, PyLx, PyLx, nz, Sp, g.V,
+                                   plan->d_w.as<float>(), 4, W, g.V, A, PyLx, g.Tz->fx()));
+    } else {
+      ECC_TRY((cols_pass<float>(st, *g.Tz, U, -1, Z, (long long)nz * PyLx, PyLx, PyLx, nz, 0, W, g.V, PyLx, g.Pz)));
+      ECC_HIP(launch_spec_accumulate(st, W, Sp, plan->d_w.as<float>(), g.V, U, A));
+    }
     ECC_TRY((cols_pass<float>(st, *g.Tz, 1, +1, A, 0, PyLx, PyLx, g.Pz, 0, Z, 0, PyLx, nz)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, nz, +1, Z, plane, Lx, g.Px, g.Py, 0, W, (long long)ny * Lx, Lx, ny)));
     ECC_TRY((rows_pass<float>(st, *g.Tx, 1, +1, W, 0, Lx, nz * ny, g.Px, 0, Z, 0, nx, nx)));

@@ -118,7 +118,9 @@ def test_linear_filter_closed_form(E, ctx, op):
 
 
 CASES = [((20, 22, 24), 7, 3), ((17, 13, 29), 9, 4), ((24, 24, 24), 5, 2), ((1, 6, 9), 5, 2), ((11, 1, 1), 3, 1),
-         ((12, 14, 10), 7, 0), ((2, 3, 4), 15, 2), ((9, 11, 10), 9, 6), ((8, 7, 9), 7, 8), ((16, 12, 14), 11, 5)]
+         ((12, 14, 10), 7, 0), ((2, 3, 4), 15, 2), ((9, 11, 10), 9, 6), ((8, 7, 9), 7, 8), ((16, 12, 14), 11, 5),
+         # transform lengths of 135 (compiled schedule) along z, then along y and x
+         ((128, 6, 7), 15, 4), ((5, 128, 128), 15, 3)]
 
 
 @pytest.mark.parametrize("shape,S,K", CASES)
