@@ -186,32 +186,43 @@ template <int N, int T>
 constexpr int fx_per_thread() { return (N + T - 1) / T; }
 
 // The three passes on one transform held in LDS at X[pos * ES] (ES = element stride; the
-// caller offsets X), driven by thread b < NL. The first pass's inputs come from `load(j)`;
-// the outputs X[b + r NL], r < R2, are handed to `store(r, i = b + r NL, value)`.
-// Threads with act == false take part in the barriers only (the caller's other threads).
-template <class F, int DIR, int ES, class Load, class Store>
-__device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, int b, bool act, Load load,
-                                             Store store) {
-  static_assert(F::R2 > 1, "three-pass schedules");
-  constexpr int NL = F::N2;
-  constexpr int K0 = fx_per_thread<F::N0, NL>(), K1 = fx_per_thread<F::N1, NL>();
-  // pass 0: X[b0 R0 + r] = DFT_R0(in[b0 + r N0])
-  cx<float> v0[K0][F::R0];
+// caller offsets X), driven by thread b < NL. fx_load fetches the first pass's inputs
+// from `load(j)` into registers (so that a caller can issue the next transform's loads
+// before it runs the current one); fx_passes runs the passes and hands the outputs
+// X[b + r NL], r < R2, to `store(r, i = b + r NL, value)`. Threads with act == false take
+// part in the barriers only (the caller's other threads).
+template <class F>
+struct FxIn {
+  static constexpr int K0 = fx_per_thread<F::N0, F::N2>();
+  cx<float> v[K0][F::R0];
+};
+
+template <class F, class Load>
+__device__ __forceinline__ void fx_load(FxIn<F>& in, int b, bool act, Load load) {
 #pragma unroll
-  for (int k = 0; k < K0; ++k) {
-    const int b0 = b + k * NL;
+  for (int k = 0; k < FxIn<F>::K0; ++k) {
+    const int b0 = b + k * F::N2;
     if (act && b0 < F::N0) {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) v0[k][r] = load(b0 + r * F::N0);
+      for (int r = 0; r < F::R0; ++r) in.v[k][r] = load(b0 + r * F::N0);
     }
   }
+}
+
+template <class F, int DIR, int ES, class Store>
+__device__ __forceinline__ void fx_passes(cx<float>* X, const cx<float>* tw, int b, bool act, FxIn<F>& in,
+                                          Store store) {
+  static_assert(F::R2 > 1, "three-pass schedules");
+  constexpr int NL = F::N2;
+  constexpr int K0 = FxIn<F>::K0, K1 = fx_per_thread<F::N1, NL>();
+  // pass 0: X[b0 R0 + r] = DFT_R0(in[b0 + r N0])
 #pragma unroll
   for (int k = 0; k < K0; ++k) {
     const int b0 = b + k * NL;
     if (act && b0 < F::N0) {
-      dft<F::R0, DIR, float>(v0[k]);
+      dft<F::R0, DIR, float>(in.v[k]);
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) X[(b0 * F::R0 + r) * ES] = v0[k][r];
+      for (int r = 0; r < F::R0; ++r) X[(b0 * F::R0 + r) * ES] = in.v[k][r];
     }
   }
   __syncthreads();
@@ -249,6 +260,14 @@ __device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, 
 #pragma unroll
     for (int r = 0; r < F::R2; ++r) store(r, b + r * NL, v2[r]);
   }
+}
+
+template <class F, int DIR, int ES, class Load, class Store>
+__device__ __forceinline__ void fx_transform(cx<float>* X, const cx<float>* tw, int b, bool act, Load load,
+                                             Store store) {
+  FxIn<F> in;
+  fx_load<F>(in, b, act, load);
+  fx_passes<F, DIR, ES>(X, tw, b, act, in, store);
 }
 
 template <class F, int DIR>
@@ -305,21 +324,29 @@ __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols_accum(const cx<float>*
 #pragma unroll
   for (int r = 0; r < F::R2; ++r) acc[r] = mk(0.f, 0.f);
   const int u0 = blockIdx.y * per, u1 = min(U, u0 + per);
-  for (int u = u0; u < u1; ++u) {
+  auto loader = [&](int u) {
     const cx<float>* src = in + (long long)u * planeIn;
+    return [=](int j) { return cin && j < nvalid ? src[(long long)j * ldIn + col] : mk(0.f, 0.f); };
+  };
+  // software pipeline: the next component's inputs and this component's spectrum values
+  // are requested before this component is transformed
+  FxIn<F> cur, nxt;
+  if (u0 < u1) fx_load<F>(cur, b, true, loader(u0));
+  for (int u = u0; u < u1; ++u) {
+    if (u + 1 < u1) fx_load<F>(nxt, b, true, loader(u + 1));
     const cx<float>* sp = Sp + (long long)u * planeSp;
+    cx<float> spv[F::R2];
+#pragma unroll
+    for (int r = 0; r < F::R2; ++r)
+      spv[r] = cin ? sp[(long long)(b + r * F::N2) * ldOut + col] : mk(0.f, 0.f);
     const float wu = w[u];
-    fx_transform<F, -1, kFxB>(
-        X + c, tw, b, true,
-        [&](int j) { return cin && j < nvalid ? src[(long long)j * ldIn + col] : mk(0.f, 0.f); },
-        [&](int r, int i, cx<float> v) {
-          if (cin) {
-            const cx<float> p = cmul(v, sp[(long long)i * ldOut + col]);
-            acc[r].re = fmaf(wu, p.re, acc[r].re);
-            acc[r].im = fmaf(wu, p.im, acc[r].im);
-          }
-        });
+    fx_passes<F, -1, kFxB>(X + c, tw, b, true, cur, [&](int r, int, cx<float> v) {
+      const cx<float> p = cmul(v, spv[r]);
+      acc[r].re = fmaf(wu, p.re, acc[r].re);
+      acc[r].im = fmaf(wu, p.im, acc[r].im);
+    });
     __syncthreads();   // the next component rewrites X
+    cur = nxt;
   }
   if (cin) {
     cx<float>* dst = out + (long long)blockIdx.y * planeOut;
@@ -543,15 +570,19 @@ __global__ void __launch_bounds__(192) k_fx_rows_wigner(const cx<float>* __restr
   WignerVoxel<K> wv;
   if (vox) wv.init(alpha[p], beta[p], gamma[p]);
   float acc = 0.f;
+  auto active = [&](int c0) { return kk < kFxCh && c0 + kk < U; };
+  auto loader = [&](int c0) {
+    const cx<float>* src = in + (long long)(active(c0) ? c0 + kk : 0) * planeIn + row * ldIn;
+    return [=](int j) { return j < nvalid ? src[j] : mk(0.f, 0.f); };
+  };
+  // software pipeline: the next chunk's rows are requested before this chunk is transformed
+  FxIn<F> cur, nxt;
+  fx_load<F>(cur, b, active(0), loader(0));
   static_for<0, NCH>([&](auto CH_) {
     constexpr int c0 = decltype(CH_)::value * kFxCh;
-    const int c = c0 + kk;
-    const bool act = kk < kFxCh && c < U;
-    const cx<float>* src = in + (long long)(act ? c : 0) * planeIn + row * ldIn;
-    fx_transform<F, +1, 1>(
-        X + (kk < kFxCh ? kk : 0) * F::P, tw, b, act,
-        [&](int j) { return j < nvalid ? src[j] : mk(0.f, 0.f); },
-        [&](int, int i, cx<float> v) { Gs[kk * F::P + i] = v; });
+    if constexpr (c0 + kFxCh < U) fx_load<F>(nxt, b, active(c0 + kFxCh), loader(c0 + kFxCh));
+    fx_passes<F, +1, 1>(X + (kk < kFxCh ? kk : 0) * F::P, tw, b, active(c0), cur,
+                        [&](int, int i, cx<float> v) { Gs[kk * F::P + i] = v; });
     __syncthreads();   // the chunk's rows are in Gs
     if (vox) {
       for_half_set<K>([&](auto C_, auto L_, auto MP_, auto M_) {
@@ -565,6 +596,7 @@ __global__ void __launch_bounds__(192) k_fx_rows_wigner(const cx<float>* __restr
       });
     }
     __syncthreads();   // Gs and X are rewritten by the next chunk
+    cur = nxt;
   });
   if (vox) y[p] = acc * scale;
 }
