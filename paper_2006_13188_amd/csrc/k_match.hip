@@ -5,9 +5,9 @@
 //   D[m][2c] = w_c cos(2 pi c m / A),  D[m][2c+1] = -w_c sin(2 pi c m / A),
 // a dense [A x 2U] by [2U x pixels] product, then the maximum over m and the first m
 // attaining it. Three forms:
-//   * float32, one thread per pixel: for A = 64 (the usual angle count) as a length-64
-//     inverse DFT of the U nonzero inputs w_c G_c (four 16-point DFTs, below), else as
-//     fused multiply-adds with the table;
+//   * float32, one thread per pixel: for A = 64 (the usual angle count) as the real-output
+//     length-64 transform of the U nonzero inputs w_c G_c (one 32-point DFT, below), else
+//     as fused multiply-adds with the table;
 //   * matrix cores (16x16x16 MFMA) with float16 operands split into hi + lo parts:
 //     D g = D_hi g_hi + D_hi g_lo + D_lo g_hi (the lo*lo term, ~2^-22 relative, dropped),
 //     accumulated in float32; g is scaled per group of 16 pixels by a power of two so
@@ -59,44 +59,51 @@ __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restri
   index[y * ldOut + x] = bi;
 }
 
-// A = 64, U <= UMAX <= 32: C(m) = Re sum_c X_c e^{2 pi i c m / 64}, X_c = w_c G_c. With
-// m = 4 a + b (a < 16, b < 4) and c = 16 q + r (r < 16),
-//   C(4 a + b) = Re sum_r [sum_q X_{16 q + r} e^{2 pi i (16 q + r) b / 64}] e^{2 pi i r a / 16},
-// so each b is one 16-point DFT of the twiddled inputs folded modulo 16: about a quarter of
-// the arithmetic of the 64 x 2U product. The weights w_c are row m = 0 of the table.
+// A = 64, U <= UMAX <= 32: C(m) = Re sum_c X_c e^{2 pi i c m / 64}, X_c = w_c G_c (the
+// weights w_c are row m = 0 of the table). C is the length-64 transform of the Hermitian
+// sequence H_0 = Re X_0, H_c = X_c / 2 and H_{64-c} = conj(X_c) / 2 (0 < c < U), whose
+// output is real; as for any real-output transform, its even and odd samples are the real
+// and imaginary parts of one 32-point transform:
+//   C(2n) + i C(2n+1) = sum_{k<32} Z_k e^{2 pi i k n / 32},  Z_k = E_k + i O_k,
+//   E_k = H_k + conj(H_{32-k}),  O_k = (H_k - conj(H_{32-k})) e^{2 pi i k / 64}  (H_32 = 0),
+// about half the arithmetic of transforming the complex inputs at all 64 angles.
 template <int UMAX>
 __global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __restrict__ stack, int U,
                                                                 long long npix, const float* __restrict__ dtab,
                                                                 float* __restrict__ score, int* __restrict__ index,
                                                                 int ldOut, int nx) {
-  static_assert(UMAX <= 32, "inputs fold at most twice onto 16 bins");
+  static_assert(UMAX <= 32, "inputs below the 32nd frequency");
   const long long p = blockIdx.x * 256LL + threadIdx.x;
   if (p >= npix) return;
-  cx<float> X[UMAX];
+  cx<float> H[UMAX];
 #pragma unroll
   for (int c = 0; c < UMAX; ++c) {
     const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
     const float w = (c < U) ? dtab[2 * c] : 0.f;
-    X[c] = mk(w * v.x, w * v.y);
+    H[c] = c == 0 ? mk(w * v.x, 0.f) : mk(0.5f * w * v.x, 0.5f * w * v.y);
   }
+  cx<float> Z[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const cx<float> a = k < UMAX ? H[k] : mk(0.f, 0.f);
+    const cx<float> b = (k > 0 && 32 - k < UMAX) ? conj(H[32 - k]) : mk(0.f, 0.f);
+    const cx<float> e = a + b;
+    const cx<float> o = twiddle_const<64, +1, float>(a - b, k);
+    Z[k] = mk(e.re - o.im, e.im + o.re);
+  }
+  dft<32, +1, float>(Z);
   float best = -INFINITY;
   int bi = 0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    cx<float> y[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) y[r] = mk(0.f, 0.f);
-#pragma unroll
-    for (int c = 0; c < UMAX; ++c) y[c % 16] = y[c % 16] + twiddle_const<64, +1, float>(X[c], c * b);
-    dft<16, +1, float>(y);
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-      const int m = 4 * a + b;
-      const float v = y[a].re;
-      if (v > best || (v == best && m < bi)) {
-        best = v;
-        bi = m;
-      }
+  for (int n = 0; n < 32; ++n) {
+    // m = 2n then 2n + 1, in increasing m: the first maximum wins
+    if (Z[n].re > best) {
+      best = Z[n].re;
+      bi = 2 * n;
+    }
+    if (Z[n].im > best) {
+      best = Z[n].im;
+      bi = 2 * n + 1;
     }
   }
   const long long yy = p / nx, xx = p - yy * nx;
