@@ -1,6 +1,7 @@
 // Pattern detection by extended convolution (section "Application to Pattern Detection"):
 // the gradient signal and angle field of an image (eq. signal, eq. theta), the consensus
 // filter of a pattern by voting (eq. opt_filt), and peak picking on the response.
+#include <algorithm>
 #include <hipcub/hipcub.hpp>
 
 #include "kcommon.hpp"
@@ -92,13 +93,21 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict
 }
 
 // largest response (ordered encoding; max is independent of the order of the updates)
+// (each workgroup reduces a stripe of rows in registers, then through LDS, and adds one
+// atomic maximum: a few hundred atomics on the one word instead of one per wave)
 __global__ void __launch_bounds__(256) k_max_response(const float* __restrict__ D, int ld, int ny, int nx,
                                                       unsigned int* __restrict__ mx) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  __shared__ unsigned int wmax[4];
   unsigned int v = 0u;
-  if (x < nx) v = ordered(D[(long long)y * ld + x]);
+  for (int y = blockIdx.x; y < ny; y += gridDim.x)
+    for (int x = threadIdx.x; x < nx; x += 256) v = max(v, ordered(D[(long long)y * ld + x]));
   for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o));
-  if ((threadIdx.x & 63) == 0 && v) atomicMax(mx, v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (v) atomicMax(mx, v);
+  }
 }
 
 // A pixel is a peak if its response is >= the threshold (thr, or rel times the largest
@@ -121,6 +130,59 @@ __global__ void __launch_bounds__(256) k_mark_peaks(const float* __restrict__ D,
       const float w = D[(long long)yy * ld + xx];
       if (w > v || (w == v && (yy < y || (yy == y && xx < x)))) return;
     }
+  const unsigned int slot = atomicAdd(counter, 1u);
+  if (slot < cap) {
+    const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
+    keys[slot] = ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx);
+  }
+}
+
+// The same test with the window read from LDS: a workgroup covers a tile of kPkTx x kPkTy
+// pixels and stages its (kPkTx + 2 rad) x (kPkTy + 2 rad) neighbourhood once (positions
+// outside the image hold NaN, which no comparison selects, as the image border clips the
+// window in the form above). The window maximum comes from two one-dimensional passes
+// (rows, then columns; fmaxf skips NaN), so every thread does the same 2 (2 rad + 1)
+// steps; only a pixel equal to its window maximum then scans the window for an earlier
+// equal value. Launched for rad <= kPkMaxRad.
+constexpr int kPkTx = 64, kPkTy = 4, kPkMaxRad = 32;
+
+__global__ void __launch_bounds__(256) k_mark_peaks_tile(const float* __restrict__ D, int ld, int ny, int nx, int rad,
+                                                         float thr, float rel, const unsigned int* __restrict__ mx,
+                                                         unsigned long long* __restrict__ keys, unsigned int cap,
+                                                         unsigned int* __restrict__ counter) {
+  extern __shared__ float win[];
+  const int W = kPkTx + 2 * rad, Hh = kPkTy + 2 * rad;
+  float* rmax = win + W * Hh;   // Hh rows x kPkTx: maximum over each row's 2 rad + 1 window
+  const int tx0 = blockIdx.x * kPkTx - rad, ty0 = blockIdx.y * kPkTy - rad;
+  for (int e = threadIdx.x; e < W * Hh; e += 256) {
+    const int yy = ty0 + e / W, xx = tx0 + e % W;
+    win[e] = (yy >= 0 && yy < ny && xx >= 0 && xx < nx) ? D[(long long)yy * ld + xx] : __builtin_nanf("");
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < Hh * kPkTx; e += 256) {
+    const int ry = e / kPkTx, cx_ = e % kPkTx;
+    const float* wr = win + ry * W + cx_;
+    float m = wr[0];
+    for (int d = 1; d <= 2 * rad; ++d) m = fmaxf(m, wr[d]);
+    rmax[e] = m;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kPkTx, ly = threadIdx.x / kPkTx;
+  const int x = blockIdx.x * kPkTx + lx, y = blockIdx.y * kPkTy + ly;
+  if (x >= nx || y >= ny) return;
+  const float v = win[(ly + rad) * W + lx + rad];
+  const float t = rel > 0.f ? rel * unordered(*mx) : thr;
+  if (!(v >= t)) return;
+  float wm = rmax[ly * kPkTx + lx];
+  for (int d = 1; d <= 2 * rad; ++d) wm = fmaxf(wm, rmax[(ly + d) * kPkTx + lx]);
+  if (wm > v) return;
+  // v is the window maximum: it is the peak unless an equal value comes earlier in raster order
+  for (int dy = -rad; dy <= 0; ++dy) {
+    const float* wr = win + (ly + rad + dy) * W + lx + rad;
+    const int dx1 = dy < 0 ? rad : -1;
+    for (int dx = -rad; dx <= dx1; ++dx)
+      if (wr[dx] == v) return;
+  }
   const unsigned int slot = atomicAdd(counter, 1u);
   if (slot < cap) {
     const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
@@ -195,13 +257,20 @@ hipError_t launch_find_peaks(hipStream_t s, const float* D, int ld, int ny, int 
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, cap, counter, mx);
   hipError_t e = last();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny);
   if (rel > 0.f) {
-    hipLaunchKernelGGL(k_max_response, grid, dim3(256), 0, s, D, ld, ny, nx, mx);
+    hipLaunchKernelGGL(k_max_response, dim3((unsigned)std::min(ny, 1024)), dim3(256), 0, s, D, ld, ny, nx, mx);
     if ((e = last()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_mark_peaks, grid, dim3(256), 0, s, D, ld, ny, nx, rad, thr, rel, mx, keys,
-                     (unsigned int)cap, counter);
+  if (rad <= kPkMaxRad) {
+    const dim3 grid((unsigned)((nx + kPkTx - 1) / kPkTx), (unsigned)((ny + kPkTy - 1) / kPkTy));
+    const size_t lds = sizeof(float) * (size_t)(kPkTy + 2 * rad) * (kPkTx + 2 * rad + kPkTx);
+    hipLaunchKernelGGL(k_mark_peaks_tile, grid, dim3(256), lds, s, D, ld, ny, nx, rad, thr, rel, mx, keys,
+                       (unsigned int)cap, counter);
+  } else {
+    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny);
+    hipLaunchKernelGGL(k_mark_peaks, grid, dim3(256), 0, s, D, ld, ny, nx, rad, thr, rel, mx, keys,
+                       (unsigned int)cap, counter);
+  }
   if ((e = last()) != hipSuccess) return e;
   e = hipcub::DeviceRadixSort::SortKeysDescending(tmp, tmp_bytes, keys, sorted, (int)cap, 0, 64, s);
   if (e != hipSuccess) return e;

@@ -93,7 +93,8 @@ def peaks_equal(E, ctx, D, radius, thr, relative, max_peaks):
 
 
 @pytest.mark.parametrize("radius,thr,relative,max_peaks", [(3, 0.5, False, 1000), (8, 0.3, True, 10),
-                                                           (0, 0.55, False, 50), (1, 0.95, True, 3)])
+                                                           (0, 0.55, False, 50), (1, 0.95, True, 3),
+                                                           (32, 0.2, True, 100), (40, 0.2, True, 100)])
 def test_find_peaks_matches_the_oracle(E, ctx, radius, thr, relative, max_peaks):
     D = blurred_noise((150, 173), 21, sigma=1.5)
     peaks_equal(E, ctx, D, radius, thr, relative, max_peaks)
