@@ -55,11 +55,24 @@ size_t ws_corr_stack(int batch, int ny, int Py, int Px, int U) {
   const size_t ldW = (size_t)pitch16(Px / 2 + 1);
   return (size_t)batch * ((size_t)ny * ldW + (size_t)Py * ldW + 2 * (size_t)ny * ldW * U) * sizeof(cx<float>);
 }
-// two-pass convolution: modulated row spectra (unless saved by the caller) and the
-// column-summed plane, per signal
-size_t ws_conv_two_pass(int batch, int ny, int Px, int U, int nsig, bool saved) {
+// component groups of the two-pass convolution's column kernel: with fewer column
+// blocks than two per CU (a small batch of narrow images) the components are split so
+// that about 2048 workgroups run; the groups' partial sums are then added by a second
+// kernel. (With two or more blocks per CU the column transforms' LDS already limits the
+// workgroups per CU, and the split only adds the partial planes' traffic.)
+int conv_col_groups(int batch, int Px, int U) {
+  const long long blocks = (long long)((Px + 3) / 4) * batch;
+  if (blocks >= 512) return 1;
+  const long long g = (2048 + blocks - 1) / blocks;
+  return (int)std::max(1LL, std::min<long long>(g, std::min(U, 16)));
+}
+// two-pass convolution: modulated row spectra (unless saved by the caller), the
+// column-summed plane per signal, and the component groups' partial Py x Px planes
+size_t ws_conv_two_pass(int batch, int ny, int Py, int Px, int U, int nsig, bool saved) {
   const size_t plane = (size_t)ny * Px;
-  return ((saved ? 0 : (size_t)batch * nsig * U * plane) + (size_t)batch * nsig * plane) * sizeof(cx<float>);
+  const int G = conv_col_groups(batch, Px, U);
+  const size_t part = G > 1 ? (size_t)G * batch * nsig * Py * Px : 0;
+  return ((saved ? 0 : (size_t)batch * nsig * U * plane) + (size_t)batch * nsig * plane + part) * sizeof(cx<float>);
 }
 // tiled matching: the component stack, U planes of ny x nx
 size_t ws_match_tiled(int ny, int nx, int U) { return (size_t)ny * nx * U * sizeof(cx<float>); }
@@ -673,10 +686,13 @@ ecc_status conv_finish(ecc_context ctx, ecc_filter_plan plan, const Geometry& g,
   ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", true));
   ECC_TRY(check_cfg_row(r3, *g.Tx, sizeof(cx<float>), "row"));
   const float* par = plan->symmetric ? plan->d_parity.as<float>() : nullptr;
+  // the partial planes of the component groups follow C in the workspace
+  const int G = conv_col_groups(batch, Px, U);
+  cx<float>* part = C + (long long)batch * nsig * ny * Px;
   ECC_HIP(launch_conv_cols(st, c2, batch, Bk, pBk, pBs, pBi, Px, g.sp->buf.as<cx<float>>(),
                            (long long)Py * g.sp->ld, g.sp->ld, g.sp->full, par,
                            plan->d_weights.as<float>(), C, pCs, pCi, Px, ny, Py, Px, g.W, U, nsig,
-                           g.Ty->desc, g.Ty->f()));
+                           g.Ty->desc, g.Ty->f(), G, part));
   mark(ctx, 2, st);
   ECC_HIP(launch_conv_rows_inv(st, r3, batch, C, pCs, pCi, Px, y, planeY, ldY, ny, nx, nsig,
                                1.0f / ((float)Py * (float)Px), g.Tx->desc, g.Tx->f()));
@@ -807,7 +823,7 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
     return ECC_OK;
   }
   const long long pB = (long long)batch * plan->U * ny * g.Px;
-  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, plan->U, 1, saved != nullptr)));
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Py, g.Px, plan->U, 1, saved != nullptr)));
   cx<float>* Bk = saved ? static_cast<cx<float>*>(saved) : ctx->ws.as<cx<float>>();
   cx<float>* C = saved ? ctx->ws.as<cx<float>>() : ctx->ws.as<cx<float>>() + pB;
   Field fl = make_field(plan, field, pF, ld_field, 1.0);
@@ -958,7 +974,7 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   const long long pB = (long long)batch * 2 * plan->U * ny * g.Px;
-  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, plan->U, 2, false)));
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Py, g.Px, plan->U, 2, false)));
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + pB;
   Field fl = make_field(plan, field, pF, ld_field, 1.0);
@@ -988,7 +1004,7 @@ ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batc
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
   const int nsig = normalized ? 2 : 1, U = plan->U;
   const long long pS = (long long)ny * ld_signal, pO = (long long)ny * ld_out;
-  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Px, U, nsig, false)));
+  ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Py, g.Px, U, nsig, false)));
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + (long long)batch * nsig * U * ny * g.Px;
   JointField jf{};
@@ -1363,7 +1379,7 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       return ECC_OK;
     case ECC_WS_EXTENDED_CONVOLUTION:
       ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
-      *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 1, false);
+      *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 1, false);
       return ECC_OK;
     case ECC_WS_SCALE_SMOOTH:
     case ECC_WS_NORMALIZED_CONVOLUTION: {
@@ -1375,11 +1391,11 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       TileChoice rc;
       if (tiled && tc.N == 128 && pick_tile_ratio(plan, rc))
         *bytes = tratio_scratch_bytes(rc.N, rc.T, batch, ny, nx);
-      else *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 2, false);
+      else *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 2, false);
       return ECC_OK;
     }
     case ECC_WS_JOINT_CONVOLUTION:
-      *bytes = ws_conv_two_pass(batch, ny, Px, U, 2, false);
+      *bytes = ws_conv_two_pass(batch, ny, Py, Px, U, 2, false);
       return ECC_OK;
     case ECC_WS_MATCH_ROTATIONS:
       ECC_REQ(batch == 1, "matching takes one image");
@@ -1394,7 +1410,7 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
     case ECC_WS_BACKWARD_CORRELATION:
       ECC_TRY(corr_y2(&a));
       ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
-      b = tiled ? 0 : ws_conv_two_pass(batch, ny, Px, U, 1, false);
+      b = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 1, false);
       ECC_TRY(gradf(&c));
       *bytes = std::max(a, std::max(b, c));
       return ECC_OK;

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(512) k_conv_cols(
     int ldB, const cx<float>* __restrict__ Fh, long long planeFk, int ldF, int fullplane,
     const float* __restrict__ parity, const float* __restrict__ w, cx<float>* __restrict__ C,
     long long planeCsig, long long planeCimg, int ldC, int ny, int Px, int W, int U, int nsig,
-    FftDesc d, const cx<float>* __restrict__ tw, int lgB) {
+    FftDesc d, const cx<float>* __restrict__ tw, int lgB, int per, cx<float>* __restrict__ part) {
   extern __shared__ cx<float> smem_f[];
   cx<float>* twl = smem_f;
   cx<float>* buf = smem_f + lds_tw_pad(d.twsize);
@@ -99,7 +99,9 @@ __global__ void __launch_bounds__(512) k_conv_cols(
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int j = 0; j < EPT; ++j) Z[s][j] = mk(0.f, 0.f);
-  for (int k = 0; k < U; ++k) {
+  // component group blockIdx.z: components [k0, k1)
+  const int k0 = blockIdx.z * per, k1 = min(U, k0 + per);
+  for (int k = k0; k < k1; ++k) {
     const cx<float>* Fk = Fh + (long long)k * planeFk;
     const float wk = w[k];
     const float par = fullplane ? 1.f : parity[k];
@@ -138,6 +140,23 @@ __global__ void __launch_bounds__(512) k_conv_cols(
       }
     }
   }
+  if (part) {
+    // partial sums of this group: plane ((group * batch + img) * nsig + s) of Py x Px
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= nsig) break;
+      cx<float>* dst = part + (((long long)blockIdx.z * gridDim.y + img) * nsig + s) * ((long long)Py * Px);
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = threadIdx.x + j * nthr;
+        if (e < Py * B) {
+          const int u = e >> lgB, v = v0 + (e & (B - 1));
+          if (v < Px) dst[(long long)u * Px + v] = Z[s][j];
+        }
+      }
+    }
+    return;
+  }
   for (int s = 0; s < nsig; ++s) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -155,6 +174,50 @@ __global__ void __launch_bounds__(512) k_conv_cols(
         if (v < Px) dst[(long long)i * ldC + v] = buf[e];
       }
     }
+  }
+}
+
+// The groups' partial sums added in group order, then the inverse column transform and
+// the store of the ny output rows (the tail of k_conv_cols for split component loops).
+template <int NB, int EPT>
+__global__ void __launch_bounds__(512) k_conv_cols_sum(const cx<float>* __restrict__ part, int groups,
+                                                      cx<float>* __restrict__ C, long long planeCsig,
+                                                      long long planeCimg, int ldC, int ny, int Px, int nsig,
+                                                      FftDesc d, const cx<float>* __restrict__ tw, int lgB) {
+  extern __shared__ cx<float> smem_f[];
+  cx<float>* twl = smem_f;
+  cx<float>* buf = smem_f + lds_tw_pad(d.twsize);
+  stage_twiddles(twl, tw, d.twsize);
+  const int B = 1 << lgB, Py = d.P, nthr = blockDim.x, TF = nthr >> lgB;
+  const int c = threadIdx.x & (B - 1), f = threadIdx.x >> lgB;
+  const int v0 = blockIdx.x * B;
+  const int img = blockIdx.y, batch = gridDim.y;
+  Layout L{B, lgB, 0};
+  for (int s = 0; s < nsig; ++s) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      if (e < Py * B) {
+        const int u = e >> lgB, v = v0 + (e & (B - 1));
+        cx<float> a = mk(0.f, 0.f);
+        if (v < Px)
+          for (int g = 0; g < groups; ++g)
+            a = a + part[(((long long)g * batch + img) * nsig + s) * ((long long)Py * Px) + (long long)u * Px + v];
+        buf[e] = a;
+      }
+    }
+    __syncthreads();
+    run_fft<NB, +1, true, float>(buf, L, d, twl, c, f, TF, true);
+    cx<float>* dst = C + (long long)img * planeCimg + (long long)s * planeCsig;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      if (e < ny * B) {
+        const int i = e >> lgB, v = v0 + (e & (B - 1));
+        if (v < Px) dst[(long long)i * ldC + v] = buf[e];
+      }
+    }
+    __syncthreads();   // buf is refilled for the next signal
   }
 }
 
@@ -296,15 +359,26 @@ hipError_t launch_conv_cols(hipStream_t s, const ColCfg& c, int batch, const cx<
                             const cx<float>* Fh, long long planeFk, int ldF, int fullplane,
                             const float* parity, const float* w, cx<float>* C, long long planeCsig,
                             long long planeCimg, int ldC, int ny, int Py, int Px, int W, int U,
-                            int nsig, const FftDesc& d, const cx<float>* tw) {
+                            int nsig, const FftDesc& d, const cx<float>* tw, int groups, cx<float>* part) {
   (void)Py;
   const int B = 1 << c.lgB;
-  dim3 grid((Px + B - 1) / B, batch), block(c.nthr);
+  if (groups < 1 || (groups > 1 && !part)) return hipErrorInvalidValue;
+  const int per = (U + groups - 1) / groups, G = (U + per - 1) / per;
+  dim3 grid((Px + B - 1) / B, batch, G), block(c.nthr);
   const size_t lds = lds_cols(c, d, sizeof(cx<float>));
+  cx<float>* pp = G > 1 ? part : nullptr;
   ECC_NB_SWITCH(c.NB, ECC_EPT_SWITCH(c.EPT, hipLaunchKernelGGL((k_conv_cols<NB, EPT>), grid, block, lds, s,
                                          Bk, planeBk, planeBsig, planeBimg, ldB, Fh, planeFk, ldF,
                                          fullplane, parity, w, C, planeCsig, planeCimg, ldC, ny, Px,
-                                         W, U, nsig, d, tw, c.lgB)));
+                                         W, U, nsig, d, tw, c.lgB, per, pp)));
+  if (G > 1) {
+    hipError_t e = last();
+    if (e != hipSuccess) return e;
+    const dim3 g2((Px + B - 1) / B, batch);
+    ECC_NB_SWITCH(c.NB, ECC_EPT_SWITCH(c.EPT, hipLaunchKernelGGL((k_conv_cols_sum<NB, EPT>), g2, block, lds, s,
+                                           part, G, C, planeCsig, planeCimg, ldC, ny, Px, nsig, d, tw,
+                                           c.lgB)));
+  }
   return last();
 }
 
@@ -361,6 +435,8 @@ hipError_t prepare_conv_kernels() {
   ECC_ALLOW_EPX(k_conv_rows_inv);
   ECC_ALLOW_NB_E(k_conv_cols, 4); ECC_ALLOW_NB_E(k_conv_cols, 8); ECC_ALLOW_NB_E(k_conv_cols, 12);
   ECC_ALLOW_NB_E(k_conv_cols, 16); ECC_ALLOW_NB_E(k_conv_cols, 24); ECC_ALLOW_NB_E(k_conv_cols, 32);
+  ECC_ALLOW_NB_E(k_conv_cols_sum, 4); ECC_ALLOW_NB_E(k_conv_cols_sum, 8); ECC_ALLOW_NB_E(k_conv_cols_sum, 12);
+  ECC_ALLOW_NB_E(k_conv_cols_sum, 16); ECC_ALLOW_NB_E(k_conv_cols_sum, 24); ECC_ALLOW_NB_E(k_conv_cols_sum, 32);
   return e;
 }
 

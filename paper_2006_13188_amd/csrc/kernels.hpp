@@ -73,12 +73,17 @@ hipError_t launch_conv_rows_fwd_joint(hipStream_t s, const RowCfg& c, int batch,
 // joint plan components (float64): f_tmp (n + 2) x (2K + 1), c_tmp (2K + 1) x n, comps U x S x S
 hipError_t launch_joint_components(hipStream_t s, const float* F, int S, int K, int M, int n, double u_lo,
                                    double u_hi, double L, cx<double>* f_tmp, cx<double>* c_tmp, cx<double>* comps);
+// groups > 1: the components are split into that many consecutive groups (more
+// workgroups for small batches), each summed in order into a Py x Px partial plane per
+// image and signal in `part` (groups x batch x nsig planes), then the partial planes are
+// added in group order before the inverse transform.
 hipError_t launch_conv_cols(hipStream_t s, const ColCfg& c, int batch, const cx<float>* Bk,
                             long long planeBk, long long planeBsig, long long planeBimg, int ldB,
                             const cx<float>* Fh, long long planeFk, int ldF, int fullplane,
                             const float* parity, const float* w, cx<float>* C, long long planeCsig,
                             long long planeCimg, int ldC, int ny, int Py, int Px, int W, int U,
-                            int nsig, const FftDesc& d, const cx<float>* tw);
+                            int nsig, const FftDesc& d, const cx<float>* tw, int groups = 1,
+                            cx<float>* part = nullptr);
 hipError_t launch_conv_rows_inv(hipStream_t s, const RowCfg& c, int batch, const cx<float>* C,
                                 long long planeCsig, long long planeCimg, int ldC, float* y,
                                 long long planeY, int ldY, int ny, int nx, int nsig, float scale,
