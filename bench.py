@@ -414,7 +414,8 @@ def joint_workload(E, timeit):
     """Joint rotation and scale fields: 1024^2 block image, 31 x 31 anisotropic Gaussian
     (sigma 1.8 along, 0.7 across), K = 8 and 9 log-radial modes (77 components of the real
     half set), vortex angle field, scale field in [1, 2]; normalised smoothing and the plain
-    extended convolution (two-pass form)."""
+    extended convolution, by blocks (default) and in the two-pass form, with the sampled
+    difference of the two forms."""
     import torch
 
     from synthetic import joint_config
@@ -432,10 +433,26 @@ def joint_workload(E, timeit):
     res = {"workload": "joint rotation + scale normalised smoothing, 1024x1024, 31x31 anisotropic Gaussian, "
                        "K=8, 9 log-radial modes", "components": int(U),
            "plan_ms": round((time.perf_counter() - t0) * 1e3, 3)}
-    ms = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, True, out=out), reps=10)
-    ms1 = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, False, out=out), reps=10)
+    ms = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, True, out=out), reps=20)
+    ms1 = timeit(lambda: E.ecc_joint_convolution(c, plan, Hd, Td, Sd, False, out=out), reps=20)
+    strat, tn, tblk = c.describe(E.CONVOLUTION, plan, 1024, 1024)
     res.update(normalised_ms=round(ms, 4), plain_ms=round(ms1, 4),
-               plain_Mpix_comp_s=round(1024 * 1024 * (2 * U - 1) / (ms1 * 1e-3) / 1e6, 1))
+               plain_Mpix_comp_s=round(1024 * 1024 * (2 * U - 1) / (ms1 * 1e-3) / 1e6, 1),
+               block={"transform": tn, "side": tblk})
+    # the two-pass form of the same calls
+    c2 = E.Context(0)
+    c2.set_strategy(E.STRATEGY_TWO_PASS)
+    plan2 = E.FilterPlan.joint(c2, torch.from_numpy(filt).cuda(), 8, n_log=9, scale_min=1.0, scale_max=2.0)
+    out2 = torch.empty_like(Hd)
+    ms2 = timeit(lambda: E.ecc_joint_convolution(c2, plan2, Hd, Td, Sd, True, out=out2), reps=5)
+    ms3 = timeit(lambda: E.ecc_joint_convolution(c2, plan2, Hd, Td, Sd, False, out=out2), reps=5)
+    E.ecc_joint_convolution(c, plan, Hd, Td, Sd, False, out=out)
+    torch.cuda.synchronize()
+    res.update(two_pass_normalised_ms=round(ms2, 4), two_pass_plain_ms=round(ms3, 4),
+               blocks_vs_two_pass_max_abs_diff_over_max=float((out - out2).abs().max().item() /
+                                                              out2.abs().max().item()))
+    plan2.close()
+    c2.close()
     plan.close()
     c.close()
     return res

@@ -124,10 +124,12 @@ ecc_status ecc_set_autotune(ecc_context ctx, int enable);
 /* Sets the evaluation strategy of later ecc_extended correlations on this context.
  * TILED with a filter radius that has no block shape fails with UNSUPPORTED at the call. */
 ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy);
-/* Reports how ecc_extended(op, plan, ny x nx) would run on this context: the strategy,
- * the transform length (TILED: N; TWO_PASS: the column-direction size P_y) and the block
- * side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is enqueued, except
- * the autotuner's one-time calibration when it is enabled and has not run yet. */
+/* Reports how ecc_extended(op, plan, ny x nx) would run on this context (for a
+ * rotation-and-scale plan, op = ECC_CONVOLUTION only: how ecc_joint_convolution would run):
+ * the strategy, the transform length (TILED: N; TWO_PASS: the column-direction size P_y)
+ * and the block side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is
+ * enqueued, except the autotuner's one-time calibration when it is enabled and has not
+ * run yet. */
 ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx,
                         ecc_strategy* strategy, int* fft_size, int* block);
 
@@ -282,10 +284,15 @@ ecc_status ecc_normalized_convolution(ecc_context ctx, ecc_filter_plan plan, int
  * `normalized` is 0. With `normalized` nonzero the output is the normalised smoothing of
  * Sec. 8 for this group: Hn = H / s^2, divided by the same convolution of 1 / s^2.
  * signal, angle (radians), scale (> 0), out: device float32, batch x ny x nx with row
- * strides ld_* and image stride ny * ld_*; out must not alias an input. Runs the two-pass
- * form (one zero-padded transform per component and signal; context workspace as
- * ECC_WS_JOINT_CONVOLUTION reports). Errors: INVALID_ARGUMENT (sizes, strides, NULL,
- * aliasing, a plan of another group), OUT_OF_MEMORY, HIP. */
+ * strides ld_* and image stride ny * ld_*; out must not alias an input. Strategy as for
+ * ecc_extended's convolution (ecc_set_strategy, ecc_describe): by blocks, the block
+ * convolution with the components taken scale mode by scale mode (the phase of a pixel is
+ * seeded once per mode and advanced by e^{-i theta} within it; no workspace); else the
+ * two-pass form (one zero-padded transform per component and signal; context workspace as
+ * ECC_WS_JOINT_CONVOLUTION reports). The normalised form runs the numerator and the
+ * denominator as two launches. Errors: INVALID_ARGUMENT (sizes, strides, NULL, aliasing,
+ * a plan of another group), UNSUPPORTED (TILED strategy without a block shape),
+ * OUT_OF_MEMORY, HIP. */
 ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batch, int ny, int nx,
                                  const float* signal, int ld_signal, const float* angle, int ld_angle,
                                  const float* scale, int ld_scale, float* out, int ld_out,

@@ -863,7 +863,9 @@ ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny
                         ecc_strategy* strategy, int* fft_size, int* block) {
   ECC_REQ(ctx && plan, "NULL context or plan");
   ECC_REQ(op == ECC_CORRELATION || op == ECC_CONVOLUTION, "unknown op");
-  ECC_TRY(validate_images(plan, 1, ny, nx));
+  const bool joint = plan->group == ECC_GROUP_ROTATION_SCALE;
+  ECC_REQ(!joint || op == ECC_CONVOLUTION, "rotation-and-scale plans have the convolution only");
+  ECC_TRY(validate_images(plan, 1, ny, nx, joint));
   ecc_strategy used;
   TileChoice tc;
   if (ctx->autotune) {
@@ -999,11 +1001,53 @@ ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batc
           "out aliases an input");
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
+  const int nsig = normalized ? 2 : 1, U = plan->U;
+  const long long pS = (long long)ny * ld_signal, pO = (long long)ny * ld_out;
+  if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
+  ecc_strategy strat;
+  TileChoice tc;
+  ECC_TRY(resolve_strategy(ctx, ECC_CONVOLUTION, plan, ny, nx, batch, &strat, &tc));
+  if (strat == ECC_STRATEGY_TILED) {
+    // block convolution, components taken by scale mode (no workspace)
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
+    TileConvArgs ca{};
+    ca.H = signal;
+    ca.planeH = pS;
+    ca.ldH = ld_signal;
+    ca.fld.ptr = angle;
+    ca.fld.plane = (long long)ny * ld_angle;
+    ca.fld.ld = ld_angle;
+    ca.fld.log_mode = 0;
+    ca.fld.mul = 1.0;
+    ca.fld.add = 0.0;
+    ca.sig_norm = normalized ? 1 : 0;
+    ca.nsig = nsig;
+    ca.y = out;
+    ca.planeY = pO;
+    ca.ldY = ld_out;
+    ca.ny = ny;
+    ca.nx = nx;
+    ca.R = plan->R;
+    ca.T = tc.T;
+    ca.U = U;
+    ca.w = plan->d_weights.as<float>();
+    ca.scale = normalized ? 1.0f : 1.0f / ((float)tc.N * (float)tc.N);
+    ca.Fs = sp->buf.as<cx<float>>();
+    ca.joint_n = plan->joint_n;
+    ca.joint_K = plan->K;
+    ca.joint_om1 = (float)plan->joint_om1;
+    ca.jscale = scale_;
+    ca.plane_s = (long long)ny * ld_scale;
+    ca.ld_s = ld_scale;
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_conv(st, tc.N, tc.TV, batch, ca));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   WsUse wu(ctx, st);
   Geometry g{};
   ECC_TRY(geometry(ctx, plan, ny, nx, st, g));
-  const int nsig = normalized ? 2 : 1, U = plan->U;
-  const long long pS = (long long)ny * ld_signal, pO = (long long)ny * ld_out;
   ECC_HIP(ctx->ws.ensure(ws_conv_two_pass(batch, ny, g.Py, g.Px, U, nsig, false)));
   cx<float>* Bk = ctx->ws.as<cx<float>>();
   cx<float>* C = Bk + (long long)batch * nsig * U * ny * g.Px;
@@ -1395,7 +1439,8 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       return ECC_OK;
     }
     case ECC_WS_JOINT_CONVOLUTION:
-      *bytes = ws_conv_two_pass(batch, ny, Py, Px, U, 2, false);
+      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+      *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 2, false);
       return ECC_OK;
     case ECC_WS_MATCH_ROTATIONS:
       ECC_REQ(batch == 1, "matching takes one image");

@@ -42,8 +42,48 @@ __device__ __forceinline__ void stream_spectrum(const cx<float>* src) {
                                      16, 0, 0);
 }
 
+// Seed of scale mode l (joint plans): z = sig(q) e^{-i (k0 alpha(q) + omega_l ln s(q))} for
+// this thread's window pixels, k0 = 1 for l < 0 (the half set has no (0, l < 0)), else 0;
+// e1 = e^{-i alpha} is already in registers. The thread index comes in through an empty asm
+// so that the addresses are formed here rather than kept live across the component loop.
+template <int N, int NT, int NQ0>
+__device__ __forceinline__ void joint_seed(const TileConvArgs& a, int img, int y0, int x0, int l,
+                                           const cx<float> (&e1)[NQ0][8], cx<float> (&z)[NQ0][8]) {
+  constexpr int M = N / 8;
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  const float* Hb = a.H + (long long)img * a.planeH;
+  const float* Sb = a.jscale + (long long)img * a.plane_s;
+  const float om = a.joint_om1 * (float)l;
+  const bool den = a.step == 2;
+#pragma unroll
+  for (int s = 0; s < NQ0; ++s) {
+    const int q = t + s * NT;
+    const int v = q % N, b = q / N;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int gy = y0 - a.R + b + M * r, gx = x0 - a.R + v;
+      z[s][r] = mk(0.f, 0.f);
+      if (b < M && gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) {
+        const float sv = Sb[(long long)gy * a.ld_s + gx];
+        float sn, cs;
+        sincosf(om * logf(sv), &sn, &cs);
+        cx<float> p = mk(cs, -sn);
+        if (l < 0) p = cmul(p, e1[s][r]);
+        const float wn = a.sig_norm ? 1.f / (sv * sv) : 1.f;
+        const float sig = den ? wn : Hb[(long long)gy * a.ldH + gx] * wn;
+        z[s][r] = mk(sig * p.re, sig * p.im);
+      }
+    }
+  }
+}
+
 // NT threads (512 or 768); LS = NT / 8 threads share each pass-1 butterfly index.
-template <int N, int TV, int NT>
+// JOINT: the components of a joint rotation and scale plan, taken by scale mode l
+// (l = -h .. h, then k = k0 .. K within a mode, so that the phase of one mode advances by
+// e^{-i alpha} as for a rotation plan); component (k, l) is entry k = 0 ? l :
+// h + 1 + (k - 1) n + (l + h) of the plan's half set.
+template <int N, int TV, int NT, bool JOINT = false>
 __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, int tile, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr bool DMA = tconv_dma(N);
@@ -91,8 +131,10 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
             sincosf((float)a.fld.mul * fv + (float)a.fld.add, &sn, &cs);
           }
           e1[s][r] = mk(cs, -sn);
-          const float wn = a.sig_norm ? 1.f / (fv * fv) : 1.f;
-          z[s][r] = mk(den ? wn : Hb[(long long)gy * a.ldH + gx] * wn, 0.f);
+          if constexpr (!JOINT) {
+            const float wn = a.sig_norm ? 1.f / (fv * fv) : 1.f;
+            z[s][r] = mk(den ? wn : Hb[(long long)gy * a.ldH + gx] * wn, 0.f);
+          }
         }
       }
     }
@@ -102,10 +144,24 @@ __device__ __forceinline__ void conv_block_one(const TileConvArgs& a, int img, i
 #pragma unroll
       for (int r = 0; r < M; ++r) Z[i][r] = mk(0.f, 0.f);
 
+    // joint plans: scale mode index li = l + h and angular frequency kk of the next component
+    // (with K = 0 the modes l < 0 have no components: the walk starts at l = 0)
+    const int jh = JOINT ? (a.joint_n - 1) / 2 : 0;
+    int li = (JOINT && a.joint_K == 0) ? jh : 0, kk = li < jh ? 1 : 0;
     for (int c = 0; c < a.U; ++c) {
-      const cx<float>* Fc = a.Fs + (long long)c * FPL;
+      int ci = c;
+      if constexpr (JOINT) {
+        const int l = li - jh;
+        if (kk == (l < 0 ? 1 : 0)) joint_seed<N, NT, NQ0>(a, img, y0, x0, l, e1, z);
+        ci = kk == 0 ? l : jh + 1 + (kk - 1) * a.joint_n + li;
+        if (++kk > a.joint_K) {
+          ++li;
+          kk = li - jh < 0 ? 1 : 0;
+        }
+      }
+      const cx<float>* Fc = a.Fs + (long long)ci * FPL;
       if constexpr (DMA) stream_spectrum<N, NT>(Fc);
-      const float wc = a.w[c];
+      const float wc = a.w[ci];
       // ---- forward transform of m_c: column pass 0 from registers
 #pragma unroll
       for (int s = 0; s < NQ0; ++s) {
@@ -391,11 +447,11 @@ __global__ void k_gradf_final(const cx<double>* __restrict__ tmp, int n, int S, 
   out[idx] = mk((float)(re * f), (float)(im * f));
 }
 
-template <int N, int TV>
+template <int N, int TV, bool JOINT = false>
 __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  conv_block_one<N, TV, tconv_threads<N>()>(a, lb / ntile, lb % ntile, conv_img_lds<N>);
+  conv_block_one<N, TV, tconv_threads<N>(), JOINT>(a, lb / ntile, lb % ntile, conv_img_lds<N>);
 }
 
 
@@ -417,13 +473,21 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   a.ty = (a.ny + a.T - 1) / a.T;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  const bool joint = a.joint_n > 0;
+  if (joint && (a.joint_n % 2 == 0 || a.joint_K < 0 || !a.jscale ||
+                a.U != (a.joint_K + 1) * a.joint_n - (a.joint_n - 1) / 2))
+    return hipErrorInvalidValue;
   // nsig = 2: the numerator pass, then the denominator pass dividing into it
 #define ECC_CL(n, tv)                                                                              \
   if (N == n && TV == tv) {                                                                       \
     for (int step = (a.nsig == 1 ? 0 : 1); step <= (a.nsig == 1 ? 0 : 2); ++step) {              \
       a.step = step;                                                                              \
-      hipLaunchKernelGGL((k_tile_conv<n, tv>), dim3((unsigned)nblk), dim3(tconv_threads<n>()), 0, \
-                         s, a);                                                                   \
+      if (joint)                                                                                  \
+        hipLaunchKernelGGL((k_tile_conv<n, tv, true>), dim3((unsigned)nblk),                      \
+                           dim3(tconv_threads<n>()), 0, s, a);                                    \
+      else                                                                                        \
+        hipLaunchKernelGGL((k_tile_conv<n, tv>), dim3((unsigned)nblk), dim3(tconv_threads<n>()),  \
+                           0, s, a);                                                              \
       const hipError_t e = last();                                                                \
       if (e != hipSuccess) return e;                                                              \
     }                                                                                             \

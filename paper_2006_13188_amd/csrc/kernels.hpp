@@ -216,6 +216,14 @@ struct TileConvArgs {
   float scale;
   const cx<float>* Fs;     // U block spectra (tconv_plane(N) values apart, pitch N + 1),
                            // F_c at (x - R) mod N
+  // joint rotation and scale plans (joint_n > 0: n log-radial modes, angular frequencies
+  // 0..joint_K): the phase is e^{-i (k alpha + omega_l ln s)} with alpha from fld (radians)
+  // and s from jscale, omega_l = l joint_om1; the signal is divided by s^2 when sig_norm
+  int joint_n, joint_K;
+  float joint_om1;
+  const float* jscale;
+  long long plane_s;
+  int ld_s;
 };
 // Filter part of the convolution adjoint on chip (section 4 adjoint of the extended
 // convolution): per block of outputs and component k, the lags x in [-R, R]^2 of

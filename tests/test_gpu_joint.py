@@ -1,6 +1,7 @@
 """Joint rotation and scale fields on the GPU against the float64 oracle: the plan's
 components (k, l), the extended convolution with both fields and the normalised smoothing
-on ragged shapes, batches and the 1024 x 1024 workload. Tolerance rel-L2 and rel-inf 1e-5."""
+on ragged shapes, batches and the 1024 x 1024 workload, through the block convolution
+(default) and the two-pass form. Tolerance rel-L2 and rel-inf 1e-5."""
 import numpy as np
 import pytest
 
@@ -35,6 +36,14 @@ def ctx(E):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx2(E):
+    c = E.Context(0)
+    c.set_strategy(E.STRATEGY_TWO_PASS)
+    yield c
+    c.close()
+
+
 def dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -63,32 +72,43 @@ def test_components_match_the_oracle(E, ctx, S, K, n):
     plan.close()
 
 
+@pytest.mark.parametrize("strategy", ["blocks", "two_pass"])
 @pytest.mark.parametrize("normalized", [False, True])
-@pytest.mark.parametrize("shape,S,K,n", [((97, 130), 15, 4, 7), ((64, 64), 9, 3, 5), ((130, 111), 21, 6, 9)])
-def test_joint_convolution_parity(E, ctx, shape, S, K, n, normalized):
+@pytest.mark.parametrize("shape,S,K,n", [((97, 130), 15, 4, 7), ((64, 64), 9, 3, 5), ((130, 111), 21, 6, 9),
+                                         ((40, 300), 11, 2, 1), ((150, 37), 25, 6, 5), ((7, 9), 7, 1, 3),
+                                         ((33, 41), 9, 0, 5)])
+def test_joint_convolution_parity(E, ctx, ctx2, shape, S, K, n, normalized, strategy):
+    c = ctx if strategy == "blocks" else ctx2
     p = JointParams(K=K, n_log=n, s_min=1.0, s_max=2.0)
     F = anisotropic_gaussian(S, S / 8.0, S / 20.0)
     img = blurred_noise(shape, 70 + S)
     th = vortex_field(shape, 71 + S, sigma=6.0)
     s = scale_field(shape, 72 + S, 1.0, 2.0, sigma=5.0)
-    print(f"joint shape={shape} S={S} K={K} n={n} normalized={normalized}", flush=True)
-    plan = plan_for(E, ctx, F, p)
-    got = host(E.ecc_joint_convolution(ctx, plan, dev(img), dev(th), dev(s), normalized)).astype(np.float64)
+    print(f"joint shape={shape} S={S} K={K} n={n} normalized={normalized} {strategy}", flush=True)
+    plan = plan_for(E, c, F, p)
+    # the block form needs no workspace; the two-pass form does
+    ws = c.workspace_size(E.WS_JOINT_CONVOLUTION, plan, *shape)
+    assert (ws > 0) if strategy == "two_pass" else (ws == 0)
+    got = host(E.ecc_joint_convolution(c, plan, dev(img), dev(th), dev(s), normalized)).astype(np.float64)
     args = (img.astype(np.float64), th.astype(np.float64), s.astype(np.float64), F.astype(np.float64), p)
     ref = joint_smooth(*args)[0] if normalized else joint_conv_fft(*args)
     assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    again = host(E.ecc_joint_convolution(c, plan, dev(img), dev(th), dev(s), normalized)).astype(np.float64)
+    assert np.array_equal(got, again)
     plan.close()
 
 
-def test_joint_batch(E, ctx):
+@pytest.mark.parametrize("strategy", ["blocks", "two_pass"])
+def test_joint_batch(E, ctx, ctx2, strategy):
+    c = ctx if strategy == "blocks" else ctx2
     p = JointParams(K=3, n_log=5, s_min=1.0, s_max=2.0)
     F = anisotropic_gaussian(11, 1.5, 0.7)
     B, shape = 3, (70, 90)
     imgs = np.stack([blurred_noise(shape, 80 + b) for b in range(B)])
     ths = np.stack([vortex_field(shape, 85 + b, sigma=5.0) for b in range(B)])
     ss = np.stack([scale_field(shape, 90 + b, 1.0, 2.0, sigma=5.0) for b in range(B)])
-    plan = plan_for(E, ctx, F, p)
-    got = host(E.ecc_joint_convolution(ctx, plan, dev(imgs), dev(ths), dev(ss), True)).astype(np.float64)
+    plan = plan_for(E, c, F, p)
+    got = host(E.ecc_joint_convolution(c, plan, dev(imgs), dev(ths), dev(ss), True)).astype(np.float64)
     for b in range(B):
         ref = joint_smooth(imgs[b].astype(np.float64), ths[b].astype(np.float64), ss[b].astype(np.float64),
                            F.astype(np.float64), p)[0]
