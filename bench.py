@@ -508,19 +508,23 @@ def steer3d_workload(E, timeit):
     U, Lx, nv = plan.U, (P + 15) // 16 * 16, n ** 3
     V = P * P * Lx
     zy, yy = U * n * P * Lx * 8, U * n * n * Lx * 8      # U volumes of n x P / n x n rows of Lx
-    # correlation: z pass (spectra in, products formed on load), y pass, then (P = 135, a
+    # filter spectra read by the z pass: with the compiled length (P = 135) the plan keeps
+    # them transformed along x and y only (S planes per component; the z pass transforms
+    # each column on chip), else the full P x P x Lx volumes
+    spec = U * S * P * Lx * 8 if P == 135 else U * V * 8
+    # correlation: z pass (spectra in, products formed on chip), y pass, then (P = 135, a
     # compiled schedule, K <= 4) the x pass fused with the combination, else the x pass and
     # the combination
     if P == 135 and K <= 4:
-        corr = (U * V * 8 + zy) + (zy + yy) + (yy + 16 * nv)
+        corr = (spec + zy) + (zy + yy) + (yy + 16 * nv)
     else:
-        corr = (U * V * 8 + zy) + (zy + yy) + (yy + U * nv * 8) + (U * nv * 8 + 16 * nv)
+        corr = (spec + zy) + (zy + yy) + (yy + U * nv * 8) + (U * nv * 8 + 16 * nv)
     # convolution: modulation, x and y passes, then (P = 135, a compiled schedule) the z pass
     # fused with the product sum over four component groups and the sum of the groups, else
     # the z pass and a separate product sum (the single-volume inverse transforms are left
     # out: 6 V x 8 B)
     if P == 135:
-        conv = (16 * nv + U * nv * 8) + (U * nv * 8 + yy) + (yy + zy) + (zy + U * V * 8 + 4 * V * 8) + 5 * V * 8
+        conv = (16 * nv + U * nv * 8) + (U * nv * 8 + yy) + (yy + zy) + (zy + spec + 4 * V * 8) + 5 * V * 8
     else:
         conv = (16 * nv + U * nv * 8) + (U * nv * 8 + yy) + (yy + zy) + (zy + U * V * 8) + (2 * U * V * 8 + V * 8)
     for name, nbytes in (("correlation", corr), ("convolution", conv)):

@@ -300,18 +300,71 @@ __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols(const cx<float>* __res
       });
 }
 
+// Filter spectra kept transformed along x and y only ("partial": the S planes of a
+// component's z offsets, offset q_z = j - R in plane j, rows of pitch ld): the column of
+// the full spectrum is the transform along z of these planes placed at q_z mod P, so the
+// transform's input j is plane (j + R) mod P when that is < S, else zero.
+template <class F>
+__device__ __forceinline__ cx<float> fx_partial_at(const cx<float>* sp, int ld, int col, bool cin, int S, int R,
+                                                   int j) {
+  int d = j + R;
+  if (d >= F::P) d -= F::P;
+  return (cin && d < S) ? sp[(long long)d * ld + col] : mk(0.f, 0.f);
+}
+
+// The correlation's inverse z pass with the product formed on chip: per column, the
+// filter spectrum column (the transform along z, direction +1, of the component's partial
+// planes) times the signal spectrum A, transformed back along z; rows i < nstore of out.
+// Component blockIdx.y (partial spectra planeSp apart, outputs planeOut apart); every
+// array has row pitch ld.
+template <class F>
+__global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols_corr(const cx<float>* __restrict__ sp, long long planeSp,
+                                                             int ld, int ncols, int S, int R,
+                                                             const cx<float>* __restrict__ A,
+                                                             cx<float>* __restrict__ out, long long planeOut,
+                                                             int nstore, const cx<float>* __restrict__ twg) {
+  __shared__ cx<float> tw[(F::TW + 1) & ~1];
+  __shared__ cx<float> X[F::P * kFxB];
+  for (int i = threadIdx.x; i < F::TW; i += blockDim.x) tw[i] = twg[i];
+  const int c = threadIdx.x % kFxB, b = threadIdx.x / kFxB;
+  const int col = blockIdx.x * kFxB + c;
+  const bool cin = col < ncols;
+  const cx<float>* spc = sp + (long long)blockIdx.y * planeSp;
+  cx<float>* dst = out + (long long)blockIdx.y * planeOut;
+  // signal spectrum values of this thread's outputs of the first transform (rows b + r NL)
+  cx<float> av[F::R2];
+#pragma unroll
+  for (int r = 0; r < F::R2; ++r) av[r] = cin ? A[(long long)(b + r * F::N2) * ld + col] : mk(0.f, 0.f);
+  cx<float> pv[F::R2];
+  fx_transform<F, +1, kFxB>(
+      X + c, tw, b, true, [&](int j) { return fx_partial_at<F>(spc, ld, col, cin, S, R, j); },
+      [&](int r, int, cx<float> v) { pv[r] = cmul(v, av[r]); });
+  __syncthreads();   // the last pass's reads of X are done
+#pragma unroll
+  for (int r = 0; r < F::R2; ++r) X[(b + r * F::N2) * kFxB + c] = pv[r];
+  __syncthreads();
+  FxIn<F> in;
+  fx_load<F>(in, b, true, [&](int j) { return X[j * kFxB + c]; });
+  __syncthreads();   // the first pass below rewrites X
+  fx_passes<F, +1, kFxB>(X + c, tw, b, true, in, [&](int, int i, cx<float> v) {
+    if (cin && i < nstore) dst[(long long)i * ld + col] = v;
+  });
+}
+
 // Forward column transforms of U planes with the weighted sum of their products with U
 // spectra (the convolution's last forward pass and its sum over the components):
 // out_g[i][v] = sum_{u in group g} w_u Sp_u[i][v] (DFT of in_u along the rows)[i][v] for
 // every i < P, Sp_u and out with row pitch ldOut, in_u rows j >= nvalid zero. Group g =
 // blockIdx.y takes components [g per, (g + 1) per) and writes plane g of out (planeOut
 // apart); the groups are added by k_sum_planes. Within a group the components are summed
-// in order, in registers, so the result does not depend on the launch.
-template <class F>
+// in order, in registers, so the result does not depend on the launch. PARTIAL: Sp holds
+// the partial spectra (S planes of each component, planeSp apart, pitch ldOut), whose
+// column is transformed along z (direction -1) on chip before the product.
+template <class F, bool PARTIAL = false>
 __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols_accum(const cx<float>* __restrict__ in, long long planeIn,
                                                               int ldIn, int ncols, int nvalid, int U,
                                                               const cx<float>* __restrict__ Sp, long long planeSp,
-                                                              const float* __restrict__ w, int per,
+                                                              int S, int R, const float* __restrict__ w, int per,
                                                               cx<float>* __restrict__ out, long long planeOut,
                                                               int ldOut, const cx<float>* __restrict__ twg) {
   __shared__ cx<float> tw[(F::TW + 1) & ~1];
@@ -336,9 +389,16 @@ __global__ void __launch_bounds__(F::N2 * kFxB) k_fx_cols_accum(const cx<float>*
     if (u + 1 < u1) fx_load<F>(nxt, b, true, loader(u + 1));
     const cx<float>* sp = Sp + (long long)u * planeSp;
     cx<float> spv[F::R2];
+    if constexpr (PARTIAL) {
+      fx_transform<F, -1, kFxB>(
+          X + c, tw, b, true, [&](int j) { return fx_partial_at<F>(sp, ldOut, col, cin, S, R, j); },
+          [&](int r, int, cx<float> v) { spv[r] = v; });
+      __syncthreads();   // the signal's transform rewrites X
+    } else {
 #pragma unroll
-    for (int r = 0; r < F::R2; ++r)
-      spv[r] = cin ? sp[(long long)(b + r * F::N2) * ldOut + col] : mk(0.f, 0.f);
+      for (int r = 0; r < F::R2; ++r)
+        spv[r] = cin ? sp[(long long)(b + r * F::N2) * ldOut + col] : mk(0.f, 0.f);
+    }
     const float wu = w[u];
     fx_passes<F, -1, kFxB>(X + c, tw, b, true, cur, [&](int r, int, cx<float> v) {
       const cx<float> p = cmul(v, spv[r]);
@@ -686,18 +746,40 @@ hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<f
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_fx_cols_corr(hipStream_t s, int P, int nplanes, const cx<float>* sp, long long planeSp, int ld,
+                               int ncols, int S, int R, const cx<float>* A, cx<float>* out, long long planeOut,
+                               int nstore, const cx<float>* tw) {
+#define ECC_FXK(a, b_, c_)                                                                            \
+  if (P == (a) * (b_) * (c_)) {                                                                       \
+    using F = Fixed3<a, b_, c_>;                                                                      \
+    if (S != 2 * R + 1 || S > P || nstore > P || nplanes < 1 || nplanes > 65535) return hipErrorInvalidValue; \
+    hipLaunchKernelGGL((k_fx_cols_corr<F>), dim3((ncols + kFxB - 1) / kFxB, nplanes), dim3(F::N2 * kFxB), 0, \
+                       s, sp, planeSp, ld, ncols, S, R, A, out, planeOut, nstore, tw);                \
+    return last();                                                                                    \
+  }
+  ECC_FX3_SIZES(ECC_FXK)
+#undef ECC_FXK
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_fx_cols_accum(hipStream_t s, int P, int nplanes, const cx<float>* in, long long planeIn, int ldIn,
-                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, const float* w,
-                                int groups, cx<float>* part, long long planePart, cx<float>* out, int ldOut,
-                                const cx<float>* tw) {
+                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, int S, int R,
+                                const float* w, int groups, cx<float>* part, long long planePart, cx<float>* out,
+                                int ldOut, const cx<float>* tw) {
 #define ECC_FXA(a, b_, c_)                                                                          \
   if (P == (a) * (b_) * (c_)) {                                                                     \
     using F = Fixed3<a, b_, c_>;                                                                    \
-    if (nvalid > P || nplanes < 1 || groups < 1) return hipErrorInvalidValue;                       \
+    if (nvalid > P || nplanes < 1 || groups < 1 || (S > 0 && (S != 2 * R + 1 || S > P)))            \
+      return hipErrorInvalidValue;                                                                  \
     const int per = (nplanes + groups - 1) / groups, G = (nplanes + per - 1) / per;                 \
     cx<float>* dst = G > 1 ? part : out;                                                            \
-    hipLaunchKernelGGL((k_fx_cols_accum<F>), dim3((ncols + kFxB - 1) / kFxB, G), dim3(F::N2 * kFxB), 0, s, \
-                       in, planeIn, ldIn, ncols, nvalid, nplanes, Sp, planeSp, w, per, dst, planePart, ldOut, tw); \
+    const dim3 g((ncols + kFxB - 1) / kFxB, G), blk(F::N2 * kFxB);                                  \
+    if (S > 0)                                                                                      \
+      hipLaunchKernelGGL((k_fx_cols_accum<F, true>), g, blk, 0, s, in, planeIn, ldIn, ncols, nvalid, nplanes, \
+                         Sp, planeSp, S, R, w, per, dst, planePart, ldOut, tw);                     \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_fx_cols_accum<F>), g, blk, 0, s, in, planeIn, ldIn, ncols, nvalid, nplanes, Sp, \
+                         planeSp, 0, 0, w, per, dst, planePart, ldOut, tw);                         \
     if (G > 1) {                                                                                    \
       hipError_t e = last();                                                                        \
       if (e != hipSuccess) return e;                                                                \

@@ -312,11 +312,20 @@ hipError_t launch_fx_rows(hipStream_t s, int P, int dir, int nplanes, const cx<f
 // spectra: out[i][v] = sum_u w_u Sp_u[i][v] DFT(in_u)[i][v], i < P (row pitch ldOut for
 // Sp and out). The components are split into at most `groups` consecutive groups, summed
 // in order within each group into planes of `part` (planePart apart; unused with one
-// group), then the groups are added in order.
+// group), then the groups are added in order. S > 0: Sp holds partial spectra (each
+// component transformed along the other two axes only: S = 2R + 1 planes, offset j - R in
+// plane j), whose full column is formed on chip by the forward transform along this axis.
 hipError_t launch_fx_cols_accum(hipStream_t s, int P, int nplanes, const cx<float>* in, long long planeIn, int ldIn,
-                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, const float* w,
-                                int groups, cx<float>* part, long long planePart, cx<float>* out, int ldOut,
-                                const cx<float>* tw);
+                                int ncols, int nvalid, const cx<float>* Sp, long long planeSp, int S, int R,
+                                const float* w, int groups, cx<float>* part, long long planePart, cx<float>* out,
+                                int ldOut, const cx<float>* tw);
+// The correlation's inverse pass along z with the product formed on chip: for component
+// c < nplanes, out_c rows i < nstore = IDFT(DFT+(partial column of sp_c) * A) along the
+// rows (partial spectra as above, transformed with direction +1; planeSp, planeOut apart;
+// row pitch ld for sp, A and out).
+hipError_t launch_fx_cols_corr(hipStream_t s, int P, int nplanes, const cx<float>* sp, long long planeSp, int ld,
+                               int ncols, int S, int R, const cx<float>* A, cx<float>* out, long long planeOut,
+                               int nstore, const cx<float>* tw);
 // The correlation's last inverse pass (along x, compiled length P) fused with the Wigner-D
 // combination: y[row][x] = scale sum_c w_c Re(D_c(x) IDFT(in_c[row])[x]) for K <= kFusedWignerK
 // and nx <= 192; alpha, beta, gamma and y are nrows x nx.

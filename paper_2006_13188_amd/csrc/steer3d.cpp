@@ -182,10 +182,14 @@ ecc_status geometry3(ecc_context ctx, int R, int nz, int ny, int nx, Geo3& g) {
 
 // Spectra of the components on the Pz x Py x Px grid (float64, rounded once): component
 // c placed with offset q at q mod P; correlation: sum_q C(q) e^{+i w q} (the transform of
-// C(-q)), convolution: sum_q C(q) e^{-i w q}. Built in chunks of components.
-ecc_status volume_spectra(ecc_volume_plan plan, int op, const Geo3& g, hipStream_t st, const cx<float>** out) {
+// C(-q)), convolution: sum_q C(q) e^{-i w q}. Built in chunks of components. partial:
+// only the x and y transforms, the S planes of z offsets j - R kept as they are
+// ([c][S][Py][Lx]; the z pass forms each column's transform on chip), 1/9 of the bytes
+// at 128^3 with a 15^3 filter.
+ecc_status volume_spectra(ecc_volume_plan plan, int op, const Geo3& g, bool partial, hipStream_t st,
+                          const cx<float>** out) {
   std::lock_guard<std::mutex> lk(plan->mu);
-  const auto key = std::make_tuple(op, g.Pz, g.Py, g.Px);
+  const auto key = std::make_tuple(op * 2 + (partial ? 1 : 0), g.Pz, g.Py, g.Px);
   auto it = plan->spectra.find(key);
   if (it != plan->spectra.end()) {
     *out = it->second->as<cx<float>>();
@@ -193,14 +197,15 @@ ecc_status volume_spectra(ecc_volume_plan plan, int op, const Geo3& g, hipStream
   }
   const int S = plan->S, R = plan->R, U = plan->U;
   const int dir = op == ECC_CORRELATION ? +1 : -1;
+  const long long per = partial ? (long long)S * g.Py * g.Lx : g.V;   // stored values per component
   auto buf = std::make_unique<DevBuf>();
-  ECC_HIP(buf->ensure((size_t)U * g.V * sizeof(cx<float>)));
+  ECC_HIP(buf->ensure((size_t)U * per * sizeof(cx<float>)));
   const int chunk = (int)std::max<long long>(1, std::min<long long>(U, (512LL << 20) / (g.V * 16)));
   DevBuf t1, t2, s64;
   ECC_HIP(t1.ensure((size_t)chunk * S * S * g.Lx * sizeof(cx<double>)));
   ECC_HIP(t2.ensure((size_t)chunk * S * g.Py * g.Lx * sizeof(cx<double>)));
   const int PyLx = g.Py * g.Lx;
-  ECC_HIP(s64.ensure((size_t)chunk * g.V * sizeof(cx<double>)));
+  if (!partial) ECC_HIP(s64.ensure((size_t)chunk * g.V * sizeof(cx<double>)));
   const long long S3 = (long long)S * S * S;
   for (int c0 = 0; c0 < U; c0 += chunk) {
     const int nc = std::min(chunk, U - c0);
@@ -209,6 +214,10 @@ ecc_status volume_spectra(ecc_volume_plan plan, int op, const Geo3& g, hipStream
                                (long long)S * g.Lx, g.Lx, g.Px)));
     ECC_TRY((cols_pass<double>(st, *g.Ty, nc * S, dir, t1.as<cx<double>>(), (long long)S * g.Lx, g.Lx, g.Px, S, -R,
                                t2.as<cx<double>>(), (long long)PyLx, g.Lx, g.Py)));
+    if (partial) {
+      ECC_HIP(launch_d2f(st, t2.as<cx<double>>(), buf->as<cx<float>>() + (long long)c0 * per, (long long)nc * per));
+      continue;
+    }
     ECC_TRY((cols_pass<double>(st, *g.Tz, nc, dir, t2.as<cx<double>>(), (long long)S * PyLx, PyLx, PyLx, S, -R,
                                s64.as<cx<double>>(), g.V, PyLx, g.Pz)));
     ECC_HIP(launch_d2f(st, s64.as<cx<double>>(), buf->as<cx<float>>() + (long long)c0 * g.V, (long long)nc * g.V));
@@ -389,8 +398,12 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
   Geo3 g{};
   ECC_TRY(geometry3(ctx, plan->R, nz, ny, nx, g));
   ECC_REQ((long long)g.Pz * g.Py * g.Lx <= (1LL << 31) - 1, "volume too large");
+  // with the compiled z transform the spectra stay partial (the z pass forms them)
+  const bool partial = g.Tz->fR0 && fx3_supported(g.Pz);
   const cx<float>* Sp = nullptr;
-  ECC_TRY(volume_spectra(plan, op, g, st, &Sp));
+  ECC_TRY(volume_spectra(plan, op, g, partial, st, &Sp));
+  const int S = plan->S;
+  const long long planeSp = partial ? (long long)S * g.Py * g.Lx : g.V;
   WsUse wu(ctx, st);
   const int U = plan->U;
   ECC_HIP(ctx->ws.ensure(ws_volume(U, g)));
@@ -408,8 +421,12 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
     ECC_TRY((cols_pass<float>(st, *g.Tz, 1, -1, Z, 0, PyLx, PyLx, nz, 0, A, 0, PyLx, g.Pz)));
     // inverse transforms of the products A Sp_c (formed as the first pass loads them), only
     // the output voxels kept
-    ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyLx, PyLx, g.Pz, 0, W, (long long)nz * PyLx, PyLx, nz,
-                              A)));
+    if (partial)
+      ECC_HIP(launch_fx_cols_corr(st, g.Pz, U, Sp, planeSp, PyLx, PyLx, S, plan->R, A, W, (long long)nz * PyLx, nz,
+                                  g.Tz->fx()));
+    else
+      ECC_TRY((cols_pass<float>(st, *g.Tz, U, +1, Sp, g.V, PyLx, PyLx, g.Pz, 0, W, (long long)nz * PyLx, PyLx, nz,
+                                A)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, +1, W, plane, Lx, g.Px, g.Py, 0, Z, (long long)ny * Lx, Lx, ny)));
     if (g.Tx->fR0 && fx_rows_wigner_supported(g.Px, plan->K, nx)) {
       // last pass and the Wigner-D combination in one kernel (no component volumes stored)
@@ -428,10 +445,11 @@ ecc_status ecc_extended_3d(ecc_context ctx, ecc_op op, ecc_volume_plan plan, int
                                  plan->d_w.as<float>(), nullptr, signal, nullptr, Z, 1.0f));
     ECC_TRY((rows_pass<float>(st, *g.Tx, U * nz, -1, Z, (long long)ny * nx, nx, ny, nx, 0, W, plane, Lx, g.Px)));
     ECC_TRY((cols_pass<float>(st, *g.Ty, U * nz, -1, W, plane, Lx, g.Px, ny, 0, Z, plane, Lx, g.Py)));
-    if (g.Tz->fR0 && fx3_supported(g.Pz)) {
-      // z pass and the weighted product sum in one kernel (components summed in registers,
-      // in four groups whose partial sums W holds, then added in order)
-      ECC_HIP(launch_fx_cols_accum(st, g.Pz, U, Z, (long long)nz * PyLx, PyLx, PyLx, nz, Sp, g.V,
+    if (partial) {
+      // z pass and the weighted product sum in one kernel (each spectrum column formed on
+      // chip; components summed in registers, in four groups whose partial sums W holds,
+      // then added in order)
+      ECC_HIP(launch_fx_cols_accum(st, g.Pz, U, Z, (long long)nz * PyLx, PyLx, PyLx, nz, Sp, planeSp, S, plan->R,
                                    plan->d_w.as<float>(), 4, W, g.V, A, PyLx, g.Tz->fx()));
     } else {
       ECC_TRY((cols_pass<float>(st, *g.Tz, U, -1, Z, (long long)nz * PyLx, PyLx, PyLx, nz, 0, W, g.V, PyLx, g.Pz)));
