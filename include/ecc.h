@@ -442,12 +442,13 @@ typedef struct {
                                     per block; executions of one such plan must not
                                     overlap (they share the counter) */
 
-/* Builds a batch plan: every correlation instance that has a block shape (tiled path,
- * the filter's radius R <= 56) is split into blocks; blocks of the same shape and form go
- * into one kernel launch, ordered longest first, and the launches are captured once
- * into a HIP graph as parallel branches. Instances without a block shape, and convolutions,
- * are kept for the per-call path. Plans must outlive the batch plan. Errors:
- * INVALID_ARGUMENT (as ecc_extended for any instance), HIP. */
+/* Builds a batch plan: every instance that has a block shape (tiled path, the filter's
+ * radius R <= 56; correlations and convolutions) is split into blocks; blocks of the same
+ * op, shape and form go into one kernel launch, ordered longest first, and the launches
+ * are captured once into a HIP graph as parallel branches. Instances without a block shape
+ * are kept for the per-call path. Convolution launches always take the item table (one
+ * workgroup per block), also under ECC_BATCH_PERSISTENT. Plans must outlive the batch
+ * plan. Errors: INVALID_ARGUMENT (as ecc_extended for any instance), HIP. */
 ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,
                                  ecc_batch_plan* out);
 /* Replaces the instances' pointers and strides (same count, ops, plans and sizes as at

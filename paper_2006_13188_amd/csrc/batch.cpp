@@ -190,6 +190,7 @@ struct ecc_batch_plan_s {
   struct Shape {
     int N = 0, TV = 0, nwg = 0, nitems = 0;
     bool sym = false;                // symmetric form (centred spectra)
+    bool conv = false;               // convolutions (block convolution, item table)
     std::vector<int> members;        // instance indices, in descriptor order
     std::vector<int> T;              // block side per member
     DevBuf descs, items, ctr;        // ctr: the persistent form's counter pair
@@ -255,8 +256,45 @@ TileArgs make_desc(const ecc_instance& in, int N, int T, const Spectrum* sp) {
   return a;
 }
 
+TileConvArgs make_conv_desc(const ecc_instance& in, int N, int T, const Spectrum* sp) {
+  TileConvArgs a{};
+  a.H = in.signal;
+  a.planeH = 0;
+  a.ldH = in.ld_signal;
+  a.fld = make_field(in.plan, in.field, 0, in.ld_field, 1.0);
+  a.sig_norm = 0;
+  a.nsig = 1;
+  a.step = 0;
+  a.y = in.out;
+  a.planeY = 0;
+  a.ldY = in.ld_out;
+  a.ny = in.ny;
+  a.nx = in.nx;
+  a.R = in.plan->R;
+  a.T = T;
+  a.tx = (in.nx + T - 1) / T;
+  a.ty = (in.ny + T - 1) / T;
+  a.U = in.plan->U;
+  a.w = in.plan->d_weights.as<float>();
+  a.scale = 1.0f / ((float)N * (float)N);
+  a.Fs = sp->buf.as<cx<float>>();
+  return a;
+}
+
 ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
   for (auto& sh : bp->shapes) {
+    if (sh.conv) {
+      std::vector<TileConvArgs> d;
+      for (size_t m = 0; m < sh.members.size(); ++m) {
+        const ecc_instance& in = bp->inst[sh.members[m]];
+        const Spectrum* sp = nullptr;
+        ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp, SPEC_CONV));
+        d.push_back(make_conv_desc(in, sh.N, sh.T[m], sp));
+      }
+      ECC_HIP(sh.descs.ensure(d.size() * sizeof(TileConvArgs)));
+      ECC_HIP(hipMemcpy(sh.descs.p, d.data(), d.size() * sizeof(TileConvArgs), hipMemcpyHostToDevice));
+      continue;
+    }
     std::vector<TileArgs> d;
     for (size_t m = 0; m < sh.members.size(); ++m) {
       const ecc_instance& in = bp->inst[sh.members[m]];
@@ -291,21 +329,23 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
   ECC_HIP(hipEventCreateWithFlags(&bp->done, hipEventDisableTiming));
   if (flags & ECC_BATCH_AUTOTUNE) ECC_TRY(calibrate_tiles(ctx, bp->cs));
 
-  // ---- block shape and form per instance
-  std::map<std::tuple<int, int, bool>, int> shape_of;
+  // ---- block shape and form per instance (the shapes the per-call path would take)
+  std::map<std::tuple<int, int, bool, bool>, int> shape_of;
   for (int i = 0; i < n; ++i) {
     const ecc_instance& in = inst[i];
     TileChoice tc;
     const int R = in.plan->R;
     const int min_T = ctx->strategy == ECC_STRATEGY_AUTO ? 2 * R : 16;
-    const bool tiled = in.op == ECC_CORRELATION && ctx->strategy != ECC_STRATEGY_TWO_PASS &&
-                       pick_tile(ctx, R, in.plan->U, in.ny, in.nx, 1, true, min_T, tc);
+    const bool conv = in.op == ECC_CONVOLUTION;
+    const bool tiled = ctx->strategy != ECC_STRATEGY_TWO_PASS &&
+                       (conv ? pick_tile_conv(ctx, R, in.plan->U, in.ny, in.nx, 1, min_T, tc)
+                             : pick_tile(ctx, R, in.plan->U, in.ny, in.nx, 1, true, min_T, tc));
     if (!tiled) {
       bp->rest.push_back(i);
       continue;
     }
-    const bool sym = tile_symmetric(tc.N, tc.TV) && rotation_parity(in.plan);
-    auto key = std::make_tuple(tc.N, tc.TV, sym);
+    const bool sym = !conv && tile_symmetric(tc.N, tc.TV) && rotation_parity(in.plan);
+    auto key = std::make_tuple(tc.N, tc.TV, sym, conv);
     auto it = shape_of.find(key);
     if (it == shape_of.end()) {
       it = shape_of.emplace(key, (int)bp->shapes.size()).first;
@@ -313,6 +353,7 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       bp->shapes.back().N = tc.N;
       bp->shapes.back().TV = tc.TV;
       bp->shapes.back().sym = sym;
+      bp->shapes.back().conv = conv;
     }
     bp->shapes[it->second].members.push_back(i);
     bp->shapes[it->second].T.push_back(tc.T);
@@ -338,7 +379,7 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
     std::vector<int2> list;
     for (const Item& it : items) list.push_back(make_int2(it.desc, it.block));
     sh.nwg = sh.nitems;
-    if (flags & ECC_BATCH_PERSISTENT) {
+    if ((flags & ECC_BATCH_PERSISTENT) && !sh.conv) {
       // as many workgroups as fit at once; they draw the items, longest first, from the
       // counter pair (zero now, and zero again after every launch)
       sh.nwg = std::max(1, std::min<int>(sh.nitems, cus * blocks_per_cu(ctx, sh.N, sh.TV)));
@@ -369,8 +410,11 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       hipStream_t st = bp->branch[b];
       e = hipStreamWaitEvent(st, bp->fork, 0);
       if (e == hipSuccess)
-        e = launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(), sh.items.as<int2>(),
-                              sh.nitems, (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);
+        e = sh.conv ? launch_tile_conv_items(st, sh.N, sh.TV, sh.descs.as<TileConvArgs>(), sh.items.as<int2>(),
+                                             sh.nitems)
+                    : launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(),
+                                        sh.items.as<int2>(), sh.nitems,
+                                        (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);
       if (e == hipSuccess) e = hipEventRecord(bp->joined[b], st);
       if (e == hipSuccess) e = hipStreamWaitEvent(bp->cs, bp->joined[b], 0);
       ++b;

@@ -455,6 +455,15 @@ __global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv(TileConvArgs a
 }
 
 
+// Batches: one workgroup per item (descriptor, block) of a list ordered by decreasing
+// cost (the dispatcher starts workgroups in order, so the longest go first).
+template <int N, int TV>
+__global__ void __launch_bounds__(tconv_threads<N>()) k_tile_conv_items(const TileConvArgs* __restrict__ descs,
+                                                                      const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  conv_block_one<N, TV, tconv_threads<N>()>(descs[it.x], 0, it.y, conv_img_lds<N>);
+}
+
 }  // namespace
 
 #define ECC_TCONV_CONFIGS(X) X(64, 64) X(96, 64) X(128, 64) X(128, 96)
@@ -495,6 +504,20 @@ hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileC
   }
   ECC_TCONV_CONFIGS(ECC_CL)
 #undef ECC_CL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_conv_items(hipStream_t s, int N, int TV, const TileConvArgs* descs, const int2* items,
+                                  int nitems) {
+  if (nitems < 1) return hipErrorInvalidValue;
+#define ECC_CI(n, tv)                                                                                 \
+  if (N == n && TV == tv) {                                                                          \
+    hipLaunchKernelGGL((k_tile_conv_items<n, tv>), dim3((unsigned)nitems), dim3(tconv_threads<n>()), 0, s, \
+                       descs, items);                                                                \
+    return last();                                                                                   \
+  }
+  ECC_TCONV_CONFIGS(ECC_CI)
+#undef ECC_CI
   return hipErrorInvalidValue;
 }
 

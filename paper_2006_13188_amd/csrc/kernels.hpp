@@ -279,6 +279,10 @@ hipError_t launch_ratio_spectra(hipStream_t s, const cx<double>* spec, int U, in
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);
 hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);
+// Batches of convolutions: one workgroup per item (descriptor index, block index) of
+// device descriptors (plain form: nsig = 1, step = 0, tx and ty set) and items.
+hipError_t launch_tile_conv_items(hipStream_t s, int N, int TV, const TileConvArgs* descs, const int2* items,
+                                  int nitems);
 
 // LDS needed for a launch, in bytes (twiddles + transform buffers).
 size_t lds_rows(const RowCfg& c, const FftDesc& d, size_t elem);

@@ -1,11 +1,12 @@
-"""Batched execution (many uneven correlations in one captured graph) against the float64
-oracle and against one call per instance.
+"""Batched execution (many uneven correlations and convolutions in one captured graph)
+against the float64 oracle and against one call per instance.
 
 Instances have different image shapes (square and rectangular, ragged against every
-block size), filter sizes 7..63 and band limits; one convolution and one filter too large
-for a block shape exercise the per-call remainder. The graph is replayed several times
-with unrelated eager GPU work in between, and every replay is checked. Tolerance:
-rel-L2 and rel-inf <= 1e-5 against the oracle."""
+block size), filter sizes 7..63 and band limits; three convolutions of different block
+shapes go into the graph too, and one filter too large for a block shape exercises the
+per-call remainder. The graph is replayed several times with unrelated eager GPU work in
+between, and every replay is checked. Tolerance: rel-L2 and rel-inf <= 1e-5 against the
+oracle."""
 import numpy as np
 import pytest
 
@@ -17,6 +18,7 @@ TOL = 1e-5
 
 SHAPES = [(64, 64, 7, 4), (97, 130, 15, 6), (200, 173, 21, 10), (130, 90, 63, 12), (75, 75, 9, 3),
           (160, 230, 31, 16), (66, 201, 35, 8), (128, 128, 13, 24), (99, 64, 41, 5), (181, 77, 11, 7)]
+CONV_SHAPES = [(90, 100, 15, 5), (150, 131, 9, 3), (140, 170, 41, 6)]
 
 
 def rel2(a, b):
@@ -50,19 +52,21 @@ def setup(E):
         refs.append(O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
         insts.append((E.CORRELATION, plan, H, T, out))
         data.append((img, filt, th, K))
-    # per-call remainder: a convolution and a filter with no block shape (R = 60)
+    # convolutions (in the graph; block shapes 64, 96 and 128)
+    for i, (ny, nx, S, K) in enumerate(CONV_SHAPES):
+        img, filt, th = batch_instance(51 + i, ny, nx, S)
+        plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), K)
+        comps, _ = O.angular_components(filt, K)
+        out = torch.full((ny, nx), float("nan"), device="cuda")
+        insts.append((E.CONVOLUTION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
+        refs.append(O.ext_conv_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
+    # per-call remainder: a filter with no block shape (R = 60)
     img, filt, th = batch_instance(50, 130, 140, 121)
     plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), 3)
     comps, _ = O.angular_components(filt, 3)
     out = torch.full((130, 140), float("nan"), device="cuda")
     insts.append((E.CORRELATION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
     refs.append(O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
-    img, filt, th = batch_instance(51, 90, 100, 15)
-    plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), 5)
-    comps, _ = O.angular_components(filt, 5)
-    out = torch.full((90, 100), float("nan"), device="cuda")
-    insts.append((E.CONVOLUTION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
-    refs.append(O.ext_conv_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
     yield ctx, insts, refs
     ctx.close()
 
@@ -85,7 +89,7 @@ def test_batch_matches_oracle_over_replays(E, setup, flags):
         out.fill_(float("nan"))
     bp = E.BatchPlan(ctx, insts, flags)
     info = bp.info()
-    assert info["graph_instances"] == len(SHAPES) and 1 <= info["launches"] <= 6
+    assert info["graph_instances"] == len(SHAPES) + len(CONV_SHAPES) and 2 <= info["launches"] <= 9
     for rep in range(3):
         for *_, out in insts:
             out.fill_(float("nan"))
