@@ -68,11 +68,18 @@ typedef enum {
  * pixel (block shapes exist for R <= 56). AUTO takes TILED when a block shape with side
  * T >= 2R exists, choosing among those by a cost model (measured when the autotuner is
  * on). Correlation, convolution, scale smoothing, matching and the adjoint have both
- * forms (ecc_extended_save writes the two-pass stack and so always runs TWO_PASS). */
+ * forms (ecc_extended_save writes the two-pass stack and so always runs TWO_PASS).
+ * DIRECT: the forward correlation (ecc_extended with ECC_CORRELATION, and batch
+ * instances) evaluated as spatial sums, G_c(p) = sum_x H(p + x) conj(F_c(x)), without
+ * transforms: 2 U S^2 multiply-adds per pixel, for filter sides S = 3..15 (UNSUPPORTED
+ * for larger filters); every other call treats DIRECT as AUTO. AUTO takes DIRECT for a
+ * correlation when its estimated time is below the block path's (the smallest filters
+ * and band limits). */
 typedef enum {
   ECC_STRATEGY_AUTO = 0,
   ECC_STRATEGY_TWO_PASS = 1,
-  ECC_STRATEGY_TILED = 2
+  ECC_STRATEGY_TILED = 2,
+  ECC_STRATEGY_DIRECT = 3
 } ecc_strategy;
 
 typedef struct ecc_context_s* ecc_context;
@@ -126,8 +133,8 @@ ecc_status ecc_set_autotune(ecc_context ctx, int enable);
 ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy);
 /* Reports how ecc_extended(op, plan, ny x nx) would run on this context (for a
  * rotation-and-scale plan, op = ECC_CONVOLUTION only: how ecc_joint_convolution would run):
- * the strategy, the transform length (TILED: N; TWO_PASS: the column-direction size P_y)
- * and the block side T (0 for TWO_PASS). Any output pointer may be NULL. Nothing is
+ * the strategy, the transform length (TILED: N; TWO_PASS: the column-direction size P_y;
+ * DIRECT: 0) and the block side T (0 for TWO_PASS and DIRECT). Any output pointer may be NULL. Nothing is
  * enqueued, except the autotuner's one-time calibration when it is enabled and has not
  * run yet. */
 ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx,
@@ -446,8 +453,11 @@ typedef struct {
  * radius R <= 56; correlations and convolutions) is split into blocks; blocks of the same
  * op, shape and form go into one kernel launch, ordered longest first, and the launches
  * are captured once into a HIP graph as parallel branches. Instances without a block shape
- * are kept for the per-call path. Convolution launches always take the item table (one
- * workgroup per block), also under ECC_BATCH_PERSISTENT. Plans must outlive the batch
+ * are kept for the per-call path. Correlations take the direct sums (ECC_STRATEGY_DIRECT)
+ * as a single call would: forced under DIRECT for every filter side that has a kernel
+ * (larger filters then keep their block shapes), chosen by the time model under AUTO.
+ * Convolution and direct launches always take the item table (one workgroup per block),
+ * also under ECC_BATCH_PERSISTENT. Plans must outlive the batch
  * plan. Errors: INVALID_ARGUMENT (as ecc_extended for any instance), HIP. */
 ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int n, int flags,
                                  ecc_batch_plan* out);

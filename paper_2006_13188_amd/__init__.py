@@ -7,13 +7,16 @@ of `lib()` raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from typing import Optional
 
 from . import _lib
 from ._lib import (BATCH_AUTOTUNE, BATCH_PERSISTENT, CONVOLUTION, CORRELATION, GROUP_ROTATION,
                    GROUP_SCALE, PREC_FP32, PREC_MFMA_BF16_HILO, PREC_MFMA_FP16_HILO, STRATEGY_AUTO,
-                   STRATEGY_TILED, STRATEGY_TWO_PASS, WS_BACKWARD_CONVOLUTION,
+                   STRATEGY_TILED, STRATEGY_TWO_PASS, STRATEGY_DIRECT, WS_BACKWARD_CONVOLUTION,
                    WS_BACKWARD_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_EXTENDED_CORRELATION,
                    WS_MATCH_ROTATIONS, WS_NORMALIZED_CONVOLUTION, WS_SCALE_SMOOTH, WS_JOINT_CONVOLUTION,
                    GROUP_ROTATION_SCALE, EccError,
@@ -27,7 +30,7 @@ __all__ = [
     "ecc_match_rotations_noalloc", "VolumePlan", "ecc_extended_3d",
     "ecc_extended_backward", "ecc_extended_save", "ecc_backward_saved_size", "ExtConv", "ExtCorr",
     "CORRELATION", "CONVOLUTION", "GROUP_ROTATION", "GROUP_SCALE", "PREC_FP32", "EccError",
-    "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "BatchPlan", "BATCH_AUTOTUNE",
+    "STRATEGY_AUTO", "STRATEGY_TWO_PASS", "STRATEGY_TILED", "STRATEGY_DIRECT", "BatchPlan", "BATCH_AUTOTUNE",
     "PREC_MFMA_FP16_HILO", "PREC_MFMA_BF16_HILO",
     "BATCH_PERSISTENT",
     "GroupParams",
@@ -73,16 +76,46 @@ def _ld(t):
     return t.stride(-2) if t.dim() >= 2 else t.shape[-1]
 
 
+# Contexts and batch plans still open when the interpreter exits are destroyed by an exit
+# hook, while the HIP runtime is fully alive; finalizers that run later, during interpreter
+# teardown, do not call into the library (a runtime call at that point can block forever).
+_open_contexts = weakref.WeakSet()
+_open_batches = weakref.WeakSet()
+_exit_hook = []
+
+
+def _close_all_at_exit():
+    for b in list(_open_batches):
+        try:
+            b.close()
+        except Exception:
+            pass
+    for c in list(_open_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+def _track(registry, obj):
+    # registered on first use, i.e. after torch (imported by the caller to make device
+    # tensors) has registered its own exit handlers, so that this one runs before them
+    if not _exit_hook:
+        atexit.register(_close_all_at_exit)
+        _exit_hook.append(True)
+    registry.add(obj)
+
+
 class Context:
     """Owns a libecc context on one HIP device."""
 
     def __init__(self, device: int = 0):
-        import weakref
         h = C.c_void_p()
         _check(lib().ecc_create(device, C.byref(h)))
         self.h = h
         self.device = device
         self._plans = weakref.WeakSet()
+        _track(_open_contexts, self)
 
     def close(self):
         """Destroys the context; plans made from it are closed first."""
@@ -93,6 +126,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -204,6 +239,8 @@ class FilterPlan:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -246,6 +283,8 @@ class VolumePlan:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -583,6 +622,7 @@ class BatchPlan:
         h = C.c_void_p()
         _check(lib().ecc_batch_plan_create(ctx.h, arr, len(instances), flags, C.byref(h)))
         self.h = h
+        _track(_open_batches, self)
 
     @staticmethod
     def _array(instances):
@@ -615,6 +655,8 @@ class BatchPlan:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -13,7 +13,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory", 
 GROUP_ROTATION, GROUP_SCALE, GROUP_ROTATION_SCALE = 0, 1, 2
 CORRELATION, CONVOLUTION = 0, 1
 PREC_FP32, PREC_MFMA_FP16_HILO, PREC_MFMA_BF16_HILO = 0, 1, 2
-STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_TWO_PASS, STRATEGY_TILED, STRATEGY_DIRECT = 0, 1, 2, 3
 # ecc_ws_call: the calls whose workspace ecc_workspace_size reports
 (WS_EXTENDED_CORRELATION, WS_EXTENDED_CONVOLUTION, WS_SCALE_SMOOTH, WS_MATCH_ROTATIONS,
  WS_BACKWARD_CONVOLUTION, WS_BACKWARD_CORRELATION, WS_NORMALIZED_CONVOLUTION, WS_JOINT_CONVOLUTION) = range(8)

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libecc.so")
 
-SOURCES = ["k_corr.hip", "k_conv.hip", "k_generic.hip", "k_fixed.hip", "k_tile.hip", "k_match.hip", "k_tconv.hip", "k_tratio.hip", "k_detect.hip", "k_joint.hip", "k_steer3d.hip", "noalloc.hip", "api.cpp", "batch.cpp", "detect.cpp", "steer3d.cpp", "fft_plan.cpp"]
+SOURCES = ["k_corr.hip", "k_conv.hip", "k_generic.hip", "k_fixed.hip", "k_tile.hip", "k_match.hip", "k_tconv.hip", "k_tratio.hip", "k_detect.hip", "k_joint.hip", "k_steer3d.hip", "k_direct.hip", "noalloc.hip", "api.cpp", "batch.cpp", "detect.cpp", "steer3d.cpp", "fft_plan.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -356,7 +356,8 @@ ecc_status ecc_set_autotune(ecc_context ctx, int enable) {
 
 ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy) {
   ECC_REQ(ctx, "NULL context");
-  ECC_REQ(strategy == ECC_STRATEGY_AUTO || strategy == ECC_STRATEGY_TWO_PASS || strategy == ECC_STRATEGY_TILED,
+  ECC_REQ(strategy == ECC_STRATEGY_AUTO || strategy == ECC_STRATEGY_TWO_PASS || strategy == ECC_STRATEGY_TILED ||
+              strategy == ECC_STRATEGY_DIRECT,
           "unknown strategy");
   ctx->strategy = strategy;
   return ECC_OK;
@@ -742,20 +743,32 @@ namespace {
 
 // Strategy of a forward call: TILED needs a block shape; AUTO takes the tiled path when
 // a block shape with side >= the filter diameter exists (the halo then costs at most ~4x
-// the block in transform work); everything else runs TWO_PASS.
+// the block in transform work); everything else runs TWO_PASS. With allow_direct (the
+// forward correlation), DIRECT runs the spatial sums when the filter side has a kernel,
+// and AUTO takes them when direct_preferred says they are faster than the block path.
+// Calls without allow_direct treat DIRECT as AUTO.
 ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx, int batch,
-                            ecc_strategy* used, TileChoice* tc) {
+                            ecc_strategy* used, TileChoice* tc, bool allow_direct = false) {
   *used = ECC_STRATEGY_TWO_PASS;
+  const bool direct_ok = allow_direct && op == ECC_CORRELATION && direct_supported(plan->S);
+  if (ctx->strategy == ECC_STRATEGY_DIRECT && allow_direct && op == ECC_CORRELATION) {
+    if (!direct_ok) return fail(ECC_ERR_UNSUPPORTED, "the direct kernel takes filter sides 3..15");
+    *used = ECC_STRATEGY_DIRECT;
+    return ECC_OK;
+  }
+  const ecc_strategy want = ctx->strategy == ECC_STRATEGY_DIRECT ? ECC_STRATEGY_AUTO : ctx->strategy;
   auto pick = [&](int min_T) {
     return op == ECC_CORRELATION ? pick_tile(ctx, plan->R, plan->U, ny, nx, batch, false, min_T, *tc)
                                  : pick_tile_conv(ctx, plan->R, plan->U, ny, nx, batch, min_T, *tc);
   };
-  if (ctx->strategy == ECC_STRATEGY_TILED) {
+  if (want == ECC_STRATEGY_TILED) {
     if (!pick(16)) return fail(ECC_ERR_UNSUPPORTED, "no block shape for this filter radius (tiled strategy)");
     *used = ECC_STRATEGY_TILED;
-  } else if (ctx->strategy == ECC_STRATEGY_AUTO && pick(2 * plan->R)) {
+  } else if (want == ECC_STRATEGY_AUTO && pick(2 * plan->R)) {
     *used = ECC_STRATEGY_TILED;
   }
+  if (want == ECC_STRATEGY_AUTO && direct_ok && direct_preferred(ctx, plan->S, plan->U, ny, nx, batch))
+    *used = ECC_STRATEGY_DIRECT;
   return ECC_OK;
 }
 
@@ -768,8 +781,30 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
   if (ctx->autotune) ECC_TRY(calibrate_tiles(ctx, st));
   ecc_strategy strat;
   TileChoice tc;
-  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc));
+  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, batch, &strat, &tc, saved == nullptr));
   if (saved) strat = ECC_STRATEGY_TWO_PASS;   // the saved stack is the two-pass form's row stack
+  if (strat == ECC_STRATEGY_DIRECT) {
+    TileArgs a{};
+    a.H = signal;
+    a.planeH = pS;
+    a.ldH = ld_signal;
+    a.fld = make_field(plan, field, pF, ld_field, 1.0);
+    a.y = out;
+    a.planeY = pO;
+    a.ldY = ld_out;
+    a.ny = ny;
+    a.nx = nx;
+    a.R = plan->R;
+    a.U = plan->U;
+    a.kofs = 0;
+    a.w = plan->d_weights.as<float>();
+    a.scale = 1.0f;
+    a.Fs = plan->comps32.as<cx<float>>();
+    mark(ctx, 0, st);
+    ECC_HIP(launch_direct_corr(st, plan->S, batch, a));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
@@ -872,9 +907,10 @@ ecc_status ecc_describe(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny
     DeviceGuard dg(ctx->device);
     ECC_TRY(calibrate_tiles(ctx, nullptr));
   }
-  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, 1, &used, &tc));
+  ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, 1, &used, &tc, true));
   if (strategy) *strategy = used;
-  if (fft_size) *fft_size = used == ECC_STRATEGY_TILED ? tc.N : fft_size_for(ctx, ny, plan->R);
+  if (fft_size)
+    *fft_size = used == ECC_STRATEGY_TILED ? tc.N : used == ECC_STRATEGY_DIRECT ? 0 : fft_size_for(ctx, ny, plan->R);
   if (block) *block = used == ECC_STRATEGY_TILED ? tc.T : 0;
   return ECC_OK;
 }
@@ -1386,10 +1422,10 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
                           size_t* bytes) {
   const int R = plan->R, U = plan->U, Sz = plan->S;
   const int Py = fft_size_for(ctx, ny, R), Px = fft_size_for(ctx, nx, R);
-  auto strat = [&](ecc_op op, int b, TileChoice& tc, bool* tiled) -> ecc_status {
+  auto strat = [&](ecc_op op, int b, TileChoice& tc, bool* tiled, bool allow_direct = false) -> ecc_status {
     ecc_strategy used = ECC_STRATEGY_TWO_PASS;
-    ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, b, &used, &tc));
-    *tiled = used == ECC_STRATEGY_TILED;
+    ECC_TRY(resolve_strategy(ctx, op, plan, ny, nx, b, &used, &tc, allow_direct));
+    *tiled = used == ECC_STRATEGY_TILED || used == ECC_STRATEGY_DIRECT;   // neither takes workspace
     return ECC_OK;
   };
   // the signal/field part of the convolution adjoint, and the field part of the
@@ -1418,7 +1454,7 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
   size_t a = 0, b = 0, c = 0;
   switch (call) {
     case ECC_WS_EXTENDED_CORRELATION:
-      ECC_TRY(strat(ECC_CORRELATION, batch, tc, &tiled));
+      ECC_TRY(strat(ECC_CORRELATION, batch, tc, &tiled, true));
       *bytes = tiled ? 0 : ws_corr_stack(batch, ny, Py, Px, U);
       return ECC_OK;
     case ECC_WS_EXTENDED_CONVOLUTION:

@@ -77,6 +77,22 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
   return found;
 }
 
+// Time per output pixel of the two forms, fitted to one MI355X (2048^2 images, S = 3..15,
+// K = 1..16): the direct sums about 4.2 ps + 0.0545 ps per component and tap (two FMAs at
+// ~93% of the non-packed FP32 rate), the block path with the 64-point blocks that small
+// filters take about 6.6 ps + 1.6 ps per component. Smaller images favour the direct
+// form further (the block path's last wave of blocks is partly empty), so the comparison
+// is made at the per-pixel rates alone.
+bool direct_preferred(ecc_context ctx, int S, int U, int ny, int nx, int batch) {
+  (void)ctx;
+  (void)ny;
+  (void)nx;
+  (void)batch;
+  const double direct_ps = 4.2 + 0.0545 * U * (double)S * S;
+  const double blocks_ps = 6.6 + 1.6 * U;
+  return direct_ps < blocks_ps;
+}
+
 bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best) {
   bool found = false;
   const int cus = cu_count(ctx);
@@ -191,6 +207,7 @@ struct ecc_batch_plan_s {
     int N = 0, TV = 0, nwg = 0, nitems = 0;
     bool sym = false;                // symmetric form (centred spectra)
     bool conv = false;               // convolutions (block convolution, item table)
+    bool direct = false;             // direct correlations (N holds the filter side)
     std::vector<int> members;        // instance indices, in descriptor order
     std::vector<int> T;              // block side per member
     DevBuf descs, items, ctr;        // ctr: the persistent form's counter pair
@@ -298,6 +315,24 @@ ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
     std::vector<TileArgs> d;
     for (size_t m = 0; m < sh.members.size(); ++m) {
       const ecc_instance& in = bp->inst[sh.members[m]];
+      if (sh.direct) {
+        TileArgs a{};
+        a.H = in.signal;
+        a.ldH = in.ld_signal;
+        a.fld = make_field(in.plan, in.field, 0, in.ld_field, 1.0);
+        a.y = in.out;
+        a.ldY = in.ld_out;
+        a.ny = in.ny;
+        a.nx = in.nx;
+        a.R = in.plan->R;
+        direct_blocks(in.ny, in.nx, &a.tx, &a.ty);
+        a.U = in.plan->U;
+        a.w = in.plan->d_weights.as<float>();
+        a.scale = 1.0f;
+        a.Fs = in.plan->comps32.as<cx<float>>();
+        d.push_back(a);
+        continue;
+      }
       const Spectrum* sp = nullptr;
       ECC_TRY(get_tile_spectrum(in.plan, sh.N, st, &sp, sh.sym ? SPEC_CENTRED : SPEC_CORR));
       d.push_back(make_desc(in, sh.N, sh.T[m], sp));
@@ -330,22 +365,33 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
   if (flags & ECC_BATCH_AUTOTUNE) ECC_TRY(calibrate_tiles(ctx, bp->cs));
 
   // ---- block shape and form per instance (the shapes the per-call path would take)
-  std::map<std::tuple<int, int, bool, bool>, int> shape_of;
+  std::map<std::tuple<int, int, bool, bool, bool>, int> shape_of;
   for (int i = 0; i < n; ++i) {
     const ecc_instance& in = inst[i];
     TileChoice tc;
-    const int R = in.plan->R;
-    const int min_T = ctx->strategy == ECC_STRATEGY_AUTO ? 2 * R : 16;
+    const int R = in.plan->R, S = in.plan->S, U = in.plan->U;
     const bool conv = in.op == ECC_CONVOLUTION;
-    const bool tiled = ctx->strategy != ECC_STRATEGY_TWO_PASS &&
-                       (conv ? pick_tile_conv(ctx, R, in.plan->U, in.ny, in.nx, 1, min_T, tc)
-                             : pick_tile(ctx, R, in.plan->U, in.ny, in.nx, 1, true, min_T, tc));
+    // direct sums: forced (DIRECT strategy, any correlation with a kernel for its side)
+    // or chosen by the same time model as a single call (AUTO)
+    const bool direct = !conv && direct_supported(S) &&
+                        (ctx->strategy == ECC_STRATEGY_DIRECT ||
+                         (ctx->strategy == ECC_STRATEGY_AUTO && direct_preferred(ctx, S, U, in.ny, in.nx, 1)));
+    const ecc_strategy want = ctx->strategy == ECC_STRATEGY_DIRECT ? ECC_STRATEGY_AUTO : ctx->strategy;
+    const int min_T = want == ECC_STRATEGY_AUTO ? 2 * R : 16;
+    const bool tiled = direct || (want != ECC_STRATEGY_TWO_PASS &&
+                                  (conv ? pick_tile_conv(ctx, R, U, in.ny, in.nx, 1, min_T, tc)
+                                        : pick_tile(ctx, R, U, in.ny, in.nx, 1, true, min_T, tc)));
     if (!tiled) {
       bp->rest.push_back(i);
       continue;
     }
-    const bool sym = !conv && tile_symmetric(tc.N, tc.TV) && rotation_parity(in.plan);
-    auto key = std::make_tuple(tc.N, tc.TV, sym, conv);
+    if (direct) {
+      tc.N = S;
+      tc.TV = 0;
+      tc.T = 0;
+    }
+    const bool sym = !conv && !direct && tile_symmetric(tc.N, tc.TV) && rotation_parity(in.plan);
+    auto key = std::make_tuple(tc.N, tc.TV, sym, conv, direct);
     auto it = shape_of.find(key);
     if (it == shape_of.end()) {
       it = shape_of.emplace(key, (int)bp->shapes.size()).first;
@@ -354,6 +400,7 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       bp->shapes.back().TV = tc.TV;
       bp->shapes.back().sym = sym;
       bp->shapes.back().conv = conv;
+      bp->shapes.back().direct = direct;
     }
     bp->shapes[it->second].members.push_back(i);
     bp->shapes[it->second].T.push_back(tc.T);
@@ -369,8 +416,15 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
     std::vector<Item> items;
     for (size_t m = 0; m < sh.members.size(); ++m) {
       const ecc_instance& in = inst[sh.members[m]];
-      const int T = sh.T[m];
-      const int nb = ((in.ny + T - 1) / T) * ((in.nx + T - 1) / T);
+      int nb;
+      if (sh.direct) {
+        int tx, ty;
+        direct_blocks(in.ny, in.nx, &tx, &ty);
+        nb = tx * ty;
+      } else {
+        const int T = sh.T[m];
+        nb = ((in.ny + T - 1) / T) * ((in.nx + T - 1) / T);
+      }
       for (int b = 0; b < nb; ++b) items.push_back({(int)m, b, in.plan->U});
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
@@ -379,7 +433,7 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
     std::vector<int2> list;
     for (const Item& it : items) list.push_back(make_int2(it.desc, it.block));
     sh.nwg = sh.nitems;
-    if ((flags & ECC_BATCH_PERSISTENT) && !sh.conv) {
+    if ((flags & ECC_BATCH_PERSISTENT) && !sh.conv && !sh.direct) {
       // as many workgroups as fit at once; they draw the items, longest first, from the
       // counter pair (zero now, and zero again after every launch)
       sh.nwg = std::max(1, std::min<int>(sh.nitems, cus * blocks_per_cu(ctx, sh.N, sh.TV)));
@@ -410,11 +464,12 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       hipStream_t st = bp->branch[b];
       e = hipStreamWaitEvent(st, bp->fork, 0);
       if (e == hipSuccess)
-        e = sh.conv ? launch_tile_conv_items(st, sh.N, sh.TV, sh.descs.as<TileConvArgs>(), sh.items.as<int2>(),
-                                             sh.nitems)
-                    : launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(),
-                                        sh.items.as<int2>(), sh.nitems,
-                                        (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);
+        e = sh.conv     ? launch_tile_conv_items(st, sh.N, sh.TV, sh.descs.as<TileConvArgs>(),
+                                                 sh.items.as<int2>(), sh.nitems)
+            : sh.direct ? launch_direct_items(st, sh.N, sh.descs.as<TileArgs>(), sh.items.as<int2>(), sh.nitems)
+                        : launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(),
+                                            sh.items.as<int2>(), sh.nitems,
+                                            (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);
       if (e == hipSuccess) e = hipEventRecord(bp->joined[b], st);
       if (e == hipSuccess) e = hipStreamWaitEvent(bp->cs, bp->joined[b], 0);
       ++b;
