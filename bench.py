@@ -550,6 +550,55 @@ def steer3d_workload(E, timeit):
     return res
 
 
+def direct_workload(E, timeit):
+    """Direct (spatial) correlation of a small filter: 2048^2 image, 5 x 5 filter, K = 8
+    (9 components); the direct sums (the form AUTO takes for this filter) against the block
+    path on the same call, the sums' FMA rate against the FP32 peak, and sampled pixels
+    summed by the definition in float64."""
+    import numpy as np
+    import torch
+
+    from synthetic import blurred_noise, random_filter, theta_field
+
+    n, S, Kd = 2048, 5, 8
+    img, th = blurred_noise((n, n), 81), theta_field((n, n), 82)
+    filt = random_filter(S, 83, 4.0 * S / 15)
+    Hd, Td, Fd = (torch.from_numpy(a).cuda() for a in (img, th, filt))
+    res = {"workload": f"direct correlation, {n}x{n}, {S}x{S} filter, K={Kd}"}
+    outs = {}
+    for name, strat in (("direct", E.STRATEGY_DIRECT), ("blocks", E.STRATEGY_TILED)):
+        c = E.Context(0)
+        c.set_strategy(strat)
+        plan = E.FilterPlan.rotation(c, Fd, Kd)
+        out = torch.empty_like(Hd)
+        res[name + "_ms"] = round(timeit(lambda: E.ecc_extended(c, E.CORRELATION, plan, Hd, Td, out=out), reps=20), 4)
+        outs[name] = out.cpu().numpy().astype(np.float64)
+        if name == "direct":
+            comps = plan.components().cpu().numpy()
+            U = comps.shape[0]
+        plan.close()
+        c.close()
+    ca = E.Context(0)
+    plan = E.FilterPlan.rotation(ca, Fd, Kd)
+    res["auto_strategy"] = {E.STRATEGY_DIRECT: "direct", E.STRATEGY_TILED: "blocks"}.get(
+        ca.describe(E.CORRELATION, plan, n, n)[0], "two_pass")
+    plan.close()
+    ca.close()
+    fmas = n * n * 2 * U * S * S
+    tf = 2 * fmas / (res["direct_ms"] * 1e-3) / 1e12
+    res["direct_roofline"] = {"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                              "frac_of_nonpacked_fp32": round(tf / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                              "alg_flops": 2 * fmas, "flops_formula": "2 FLOP x 2 U S^2 per pixel"}
+    rng = np.random.default_rng(84)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1)] + [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(13)]
+    ref = sampled_values(img, th, comps, pts)
+    scale_ = float(np.max(np.abs(outs["blocks"])))
+    res["sampled_max_abs_err_over_max"] = float(max(abs(outs["direct"][p] - r) for p, r in zip(pts, ref)) / scale_)
+    res["direct_vs_blocks_max_abs_diff_over_max"] = float(np.max(np.abs(outs["direct"] - outs["blocks"])) / scale_)
+    return res
+
+
 def batch_workload(E, timeit):
     """256 uneven correlation instances (sides 64..1024, odd filter sides 7..63, K 4..24,
     per-instance seeds): one graph-captured batch execution against one call per
@@ -659,7 +708,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma list of side workloads: "
-                         "two_pass,conv,matching,scale,lic,detection,joint,steer3d,adjoint,batch")
+                         "two_pass,conv,matching,scale,lic,detection,joint,steer3d,adjoint,batch,direct")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device copies (reference for counter runs)")
     args = ap.parse_args()
@@ -711,7 +760,7 @@ def main():
 
     side = {}
     want = set() if args.no_extras else (
-        {"two_pass", "conv", "matching", "scale", "lic", "detection", "joint", "steer3d", "adjoint", "batch"}
+        {"two_pass", "conv", "matching", "scale", "lic", "detection", "joint", "steer3d", "adjoint", "batch", "direct"}
         if args.extras == "all"
         else set(args.extras.split(",")))
     if "two_pass" in want:
@@ -753,6 +802,8 @@ def main():
         side["adjoint_16x512"] = adjoint_workload(E, ctx, timeit)
     if "batch" in want:
         side["batch_256"] = batch_workload(E, timeit)
+    if "direct" in want:
+        side["direct_2048"] = direct_workload(E, timeit)
 
     # a step is one call of the C ABI with its arguments marshalled once (the Python
     # binding's per-call checks cost tens of microseconds of host time, comparable to the
