@@ -128,6 +128,18 @@ ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
  * (once per context, a few milliseconds); block shapes are then chosen from the measured
  * per-block costs instead of an operation count. */
 ecc_status ecc_set_autotune(ecc_context ctx, int enable);
+/* The autotuner's measurements as JSON text, to be kept between processes:
+ *   {"device": "<architecture name>", "tile_cost": [[N, TV, a, b], ...]}
+ * with the time of one full wave of blocks of shape (N, TV) modelled as a + b U ms.
+ * ecc_autotune_export writes the text and its terminating NUL to buf (cap bytes) and the
+ * text's length to *len; buf may be NULL to ask for the length. INVALID_ARGUMENT if the
+ * context has not calibrated yet (enable the autotuner and make one call, or
+ * ecc_describe) or buf is too small. ecc_autotune_import takes such text, checks that it
+ * was measured on the same architecture and covers every compiled block shape, and marks
+ * the context calibrated, so no measurement runs (INVALID_ARGUMENT otherwise; the
+ * context is then unchanged). Neither call enqueues GPU work. */
+ecc_status ecc_autotune_export(ecc_context ctx, char* buf, size_t cap, size_t* len);
+ecc_status ecc_autotune_import(ecc_context ctx, const char* json);
 /* Sets the evaluation strategy of later ecc_extended correlations on this context.
  * TILED with a filter radius that has no block shape fails with UNSUPPORTED at the call. */
 ecc_status ecc_set_strategy(ecc_context ctx, ecc_strategy strategy);

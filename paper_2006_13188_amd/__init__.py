@@ -141,6 +141,23 @@ class Context:
     def set_strategy(self, strategy: int):
         _check(lib().ecc_set_strategy(self.h, strategy))
 
+    def set_autotune(self, enable: bool = True):
+        """Block shapes chosen from on-device measurements (taken once per context, at the
+        next forward call or describe) instead of an operation count."""
+        _check(lib().ecc_set_autotune(self.h, 1 if enable else 0))
+
+    def autotune_export(self) -> str:
+        """The autotuner's measurements as JSON text (see ecc_autotune_export)."""
+        n = C.c_size_t()
+        _check(lib().ecc_autotune_export(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value + 1)
+        _check(lib().ecc_autotune_export(self.h, buf, n.value + 1, C.byref(n)))
+        return buf.value.decode()
+
+    def autotune_import(self, text: str):
+        """Takes measurements exported on the same kind of device; no calibration runs."""
+        _check(lib().ecc_autotune_import(self.h, text.encode()))
+
     def workspace_size(self, call: int, plan: "FilterPlan", ny: int, nx: int, batch: int = 1) -> int:
         """Bytes of context workspace that `call` (an ecc_ws_call value, WS_*) needs."""
         n = C.c_size_t()

@@ -65,6 +65,8 @@ PROTOS = {
     "ecc_destroy": [_P],
     "ecc_fft_size": [_P, _I, _I, C.POINTER(_I)],
     "ecc_set_autotune": [_P, _I],
+    "ecc_autotune_export": [_P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
+    "ecc_autotune_import": [_P, C.c_char_p],
     "ecc_set_stage_events": [_P, C.POINTER(_P), _I],
     "ecc_set_strategy": [_P, _I],
     "ecc_describe": [_P, _I, _P, _I, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)],

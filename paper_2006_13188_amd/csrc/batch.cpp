@@ -3,8 +3,11 @@
 // the tiled path with its on-device calibration.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <deque>
 #include <numeric>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -538,6 +541,77 @@ ecc_status ecc_batch_plan_destroy(ecc_batch_plan bp) {
   if (bp->cs) (void)hipStreamSynchronize(bp->cs);
   (void)hipDeviceSynchronize();
   delete bp;
+  return ECC_OK;
+}
+
+
+namespace {
+// the device's architecture name ("gfx950:sramecc+:xnack-"), which the costs belong to
+std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName);
+}
+}  // namespace
+
+ecc_status ecc_autotune_export(ecc_context ctx, char* buf, size_t cap, size_t* len) {
+  ECC_REQ(ctx && len, "NULL argument");
+  ECC_REQ(ctx->tile_calibrated, "the context has not calibrated its block shapes yet");
+  std::string j = "{\"device\": \"" + arch_name(ctx->device) + "\", \"tile_cost\": [";
+  bool first = true;
+  for (const auto& kv : ctx->tile_cost) {
+    char item[128];
+    std::snprintf(item, sizeof(item), "%s[%d, %d, %.9g, %.9g]", first ? "" : ", ", kv.first.first, kv.first.second,
+                  kv.second.a, kv.second.b);
+    j += item;
+    first = false;
+  }
+  j += "]}";
+  *len = j.size();
+  if (buf) {
+    ECC_REQ(cap > j.size(), "buffer too small (see *len)");
+    std::memcpy(buf, j.c_str(), j.size() + 1);
+  }
+  return ECC_OK;
+}
+
+ecc_status ecc_autotune_import(ecc_context ctx, const char* json) {
+  ECC_REQ(ctx && json, "NULL argument");
+  const std::string j(json);
+  const std::string dkey = "\"device\": \"";
+  const size_t d0 = j.find(dkey);
+  ECC_REQ(d0 != std::string::npos, "no device name in the autotuner text");
+  const size_t d1 = j.find('"', d0 + dkey.size());
+  ECC_REQ(d1 != std::string::npos, "unterminated device name");
+  ECC_REQ(j.substr(d0 + dkey.size(), d1 - d0 - dkey.size()) == arch_name(ctx->device),
+          "the autotuner text was measured on another kind of device");
+  const size_t t0 = j.find("\"tile_cost\"", d1);
+  ECC_REQ(t0 != std::string::npos, "no tile_cost in the autotuner text");
+  size_t pos = j.find('[', t0);
+  ECC_REQ(pos != std::string::npos, "malformed tile_cost");
+  std::map<std::pair<int, int>, ecc_context_s::TileCost> costs;
+  ++pos;
+  while (true) {
+    const size_t open = j.find('[', pos), close = j.find(']', pos);
+    ECC_REQ(close != std::string::npos, "malformed tile_cost");
+    if (open == std::string::npos || open > close) break;   // the list's closing bracket
+    int N = 0, TV = 0;
+    double a = 0, b = 0;
+    ECC_REQ(std::sscanf(j.c_str() + open, "[%d , %d , %lf , %lf ]", &N, &TV, &a, &b) == 4,
+            "malformed tile_cost entry");
+    ECC_REQ(tile_supported(N, TV) && std::isfinite(a) && std::isfinite(b) && a >= 0 && b >= 0,
+            "tile_cost entry for an unknown block shape or with a negative cost");
+    ecc_context_s::TileCost tc;
+    tc.a = a;
+    tc.b = b;
+    costs[{N, TV}] = tc;
+    pos = j.find(']', open) + 1;
+  }
+  for (const auto& c : kShapes)
+    if (tile_supported(c[0], c[1]))
+      ECC_REQ(costs.count({c[0], c[1]}), "the autotuner text lacks a block shape this library has");
+  ctx->tile_cost = costs;
+  ctx->tile_calibrated = true;
   return ECC_OK;
 }
 

@@ -208,3 +208,39 @@ def test_batch_with_direct_instances(E, direct):
         check_all(insts, refs)
     bp.close()
     ctx.close()
+
+
+def test_autotune_measurements_move_between_contexts(E):
+    """The autotuner's block-shape costs exported as JSON from one context and imported
+    into another give the same choices without measuring again; text from another kind of
+    device, or missing a shape, is refused and leaves the context as it was."""
+    import json
+    import torch
+    a = E.Context(0)
+    with pytest.raises(E.EccError):
+        a.autotune_export()                      # nothing measured yet
+    a.set_autotune(True)
+    _, filt, _ = batch_instance(300, 64, 64, 31)
+    plan_a = E.FilterPlan.rotation(a, torch.from_numpy(filt).cuda(), 16)
+    a.describe(E.CORRELATION, plan_a, 1024, 1024)   # measures
+    text = a.autotune_export()
+    d = json.loads(text)
+    assert d["device"].startswith("gfx") and len(d["tile_cost"]) >= 3
+    b = E.Context(0)
+    b.set_autotune(True)
+    bad = dict(d, device="gfx000")
+    with pytest.raises(E.EccError):
+        b.autotune_import(json.dumps(bad))
+    with pytest.raises(E.EccError):
+        b.autotune_import(json.dumps(dict(d, tile_cost=d["tile_cost"][:-1])))
+    with pytest.raises(E.EccError):
+        b.autotune_export()                      # still unmeasured after the refusals
+    b.autotune_import(text)
+    assert b.autotune_export() == text
+    plan_b = E.FilterPlan.rotation(b, torch.from_numpy(filt).cuda(), 16)
+    for ny, nx, K in ((1024, 1024, 16), (300, 500, 4), (2048, 700, 24)):
+        assert a.describe(E.CORRELATION, plan_a, ny, nx) == b.describe(E.CORRELATION, plan_b, ny, nx)
+    plan_a.close()
+    plan_b.close()
+    a.close()
+    b.close()
