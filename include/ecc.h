@@ -69,12 +69,12 @@ typedef enum {
  * T >= 2R exists, choosing among those by a cost model (measured when the autotuner is
  * on). Correlation, convolution, scale smoothing, matching and the adjoint have both
  * forms (ecc_extended_save writes the two-pass stack and so always runs TWO_PASS).
- * DIRECT: the forward correlation (ecc_extended with ECC_CORRELATION, and batch
- * instances) evaluated as spatial sums, G_c(p) = sum_x H(p + x) conj(F_c(x)), without
- * transforms: 2 U S^2 multiply-adds per pixel, for filter sides S = 3..15 (UNSUPPORTED
- * for larger filters); every other call treats DIRECT as AUTO. AUTO takes DIRECT for a
- * correlation when its estimated time is below the block path's (the smallest filters
- * and band limits). */
+ * DIRECT: ecc_extended (both ops, and batch instances) evaluated as spatial sums without
+ * transforms, G_c(p) = sum_x H(p + x) conj(F_c(x)) for the correlation and
+ * sum_x (H e^{-i c alpha})(p - x) F_c(x) for the convolution: 2 U S^2 multiply-adds per
+ * pixel, for filter sides S = 3..15 (UNSUPPORTED for larger filters); every other call
+ * treats DIRECT as AUTO. AUTO takes DIRECT when its estimated time is below the block
+ * path's (the smallest filters and band limits). */
 typedef enum {
   ECC_STRATEGY_AUTO = 0,
   ECC_STRATEGY_TWO_PASS = 1,

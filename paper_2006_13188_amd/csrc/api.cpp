@@ -744,15 +744,15 @@ namespace {
 // Strategy of a forward call: TILED needs a block shape; AUTO takes the tiled path when
 // a block shape with side >= the filter diameter exists (the halo then costs at most ~4x
 // the block in transform work); everything else runs TWO_PASS. With allow_direct (the
-// forward correlation), DIRECT runs the spatial sums when the filter side has a kernel,
-// and AUTO takes them when direct_preferred says they are faster than the block path.
-// Calls without allow_direct treat DIRECT as AUTO.
+// forward correlation and convolution of ecc_extended), DIRECT runs the spatial sums when
+// the filter side has a kernel, and AUTO takes them when direct_preferred says they are
+// faster than the block path. Calls without allow_direct treat DIRECT as AUTO.
 ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ny, int nx, int batch,
                             ecc_strategy* used, TileChoice* tc, bool allow_direct = false) {
   *used = ECC_STRATEGY_TWO_PASS;
-  const bool direct_ok = allow_direct && op == ECC_CORRELATION && direct_supported(plan->S);
-  if (ctx->strategy == ECC_STRATEGY_DIRECT && allow_direct && op == ECC_CORRELATION) {
-    if (!direct_ok) return fail(ECC_ERR_UNSUPPORTED, "the direct kernel takes filter sides 3..15");
+  const bool direct_ok = allow_direct && direct_supported(plan->S);
+  if (ctx->strategy == ECC_STRATEGY_DIRECT && allow_direct) {
+    if (!direct_ok) return fail(ECC_ERR_UNSUPPORTED, "the direct kernels take filter sides 3..15");
     *used = ECC_STRATEGY_DIRECT;
     return ECC_OK;
   }
@@ -767,7 +767,8 @@ ecc_status resolve_strategy(ecc_context ctx, ecc_op op, ecc_filter_plan plan, in
   } else if (want == ECC_STRATEGY_AUTO && pick(2 * plan->R)) {
     *used = ECC_STRATEGY_TILED;
   }
-  if (want == ECC_STRATEGY_AUTO && direct_ok && direct_preferred(ctx, plan->S, plan->U, ny, nx, batch))
+  if (want == ECC_STRATEGY_AUTO && direct_ok &&
+      direct_preferred(ctx, op == ECC_CONVOLUTION, plan->S, plan->U, ny, nx, batch))
     *used = ECC_STRATEGY_DIRECT;
   return ECC_OK;
 }
@@ -801,7 +802,7 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
     a.scale = 1.0f;
     a.Fs = plan->comps32.as<cx<float>>();
     mark(ctx, 0, st);
-    ECC_HIP(launch_direct_corr(st, plan->S, batch, a));
+    ECC_HIP(launch_direct(st, op == ECC_CONVOLUTION, plan->S, batch, a));
     mark(ctx, 1, st);
     return ECC_OK;
   }
@@ -1458,7 +1459,7 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       *bytes = tiled ? 0 : ws_corr_stack(batch, ny, Py, Px, U);
       return ECC_OK;
     case ECC_WS_EXTENDED_CONVOLUTION:
-      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled));
+      ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled, true));
       *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 1, false);
       return ECC_OK;
     case ECC_WS_SCALE_SMOOTH:

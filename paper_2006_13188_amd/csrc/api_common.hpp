@@ -87,9 +87,9 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
 ecc_status calibrate_tiles(ecc_context ctx, hipStream_t st);
 // Same choice for the tiled convolution (static operation count).
 bool pick_tile_conv(ecc_context ctx, int R, int U, int ny, int nx, int batch, int min_T, TileChoice& best);
-// Whether the direct (spatial) correlation is expected to beat the block path for a
-// filter side S with U components on batch x ny x nx images.
-bool direct_preferred(ecc_context ctx, int S, int U, int ny, int nx, int batch);
+// Whether the direct (spatial) correlation (conv: convolution) is expected to beat the
+// block path for a filter side S with U components on batch x ny x nx images.
+bool direct_preferred(ecc_context ctx, bool conv, int S, int U, int ny, int nx, int batch);
 // Block shape of the overlap-add ratio kernel for the plan's filter radius R (plans with
 // component parity only): among the compiled shapes, the smallest transform work per
 // output pixel, N^2 log2 N / T^2 with T = min(TV, N - 2R) >= 16. The normalised

@@ -81,18 +81,20 @@ bool pick_tile(ecc_context ctx, int R, int U, int ny, int nx, int batch, bool th
 }
 
 // Time per output pixel of the two forms, fitted to one MI355X (2048^2 images, S = 3..15,
-// K = 1..16): the direct sums about 4.2 ps + 0.0545 ps per component and tap (two FMAs at
-// ~93% of the non-packed FP32 rate), the block path with the 64-point blocks that small
-// filters take about 6.6 ps + 1.6 ps per component. Smaller images favour the direct
-// form further (the block path's last wave of blocks is partly empty), so the comparison
-// is made at the per-pixel rates alone.
-bool direct_preferred(ecc_context ctx, int S, int U, int ny, int nx, int batch) {
+// K = 1..16). Correlation: the direct sums about 4.2 ps + 0.0545 ps per component and tap
+// (two FMAs at ~93% of the non-packed FP32 rate), the block path with the 64-point blocks
+// that small filters take about 6.6 ps + 1.6 ps per component. Convolution: 4.8 + 0.0553
+// per component and tap against 7.85 + 1.84 per component. Smaller images favour the
+// direct form further (the block path's last wave of blocks is partly empty), so the
+// comparison is made at the per-pixel rates alone.
+bool direct_preferred(ecc_context ctx, bool conv, int S, int U, int ny, int nx, int batch) {
   (void)ctx;
   (void)ny;
   (void)nx;
   (void)batch;
-  const double direct_ps = 4.2 + 0.0545 * U * (double)S * S;
-  const double blocks_ps = 6.6 + 1.6 * U;
+  const double taps = (double)U * S * S;
+  const double direct_ps = conv ? 4.8 + 0.0553 * taps : 4.2 + 0.0545 * taps;
+  const double blocks_ps = conv ? 7.85 + 1.84 * U : 6.6 + 1.6 * U;
   return direct_ps < blocks_ps;
 }
 
@@ -303,7 +305,7 @@ TileConvArgs make_conv_desc(const ecc_instance& in, int N, int T, const Spectrum
 
 ecc_status upload_descs(ecc_batch_plan bp, hipStream_t st) {
   for (auto& sh : bp->shapes) {
-    if (sh.conv) {
+    if (sh.conv && !sh.direct) {
       std::vector<TileConvArgs> d;
       for (size_t m = 0; m < sh.members.size(); ++m) {
         const ecc_instance& in = bp->inst[sh.members[m]];
@@ -374,11 +376,11 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
     TileChoice tc;
     const int R = in.plan->R, S = in.plan->S, U = in.plan->U;
     const bool conv = in.op == ECC_CONVOLUTION;
-    // direct sums: forced (DIRECT strategy, any correlation with a kernel for its side)
-    // or chosen by the same time model as a single call (AUTO)
-    const bool direct = !conv && direct_supported(S) &&
+    // direct sums: forced (DIRECT strategy, any instance with a kernel for its side) or
+    // chosen by the same time model as a single call (AUTO)
+    const bool direct = direct_supported(S) &&
                         (ctx->strategy == ECC_STRATEGY_DIRECT ||
-                         (ctx->strategy == ECC_STRATEGY_AUTO && direct_preferred(ctx, S, U, in.ny, in.nx, 1)));
+                         (ctx->strategy == ECC_STRATEGY_AUTO && direct_preferred(ctx, conv, S, U, in.ny, in.nx, 1)));
     const ecc_strategy want = ctx->strategy == ECC_STRATEGY_DIRECT ? ECC_STRATEGY_AUTO : ctx->strategy;
     const int min_T = want == ECC_STRATEGY_AUTO ? 2 * R : 16;
     const bool tiled = direct || (want != ECC_STRATEGY_TWO_PASS &&
@@ -467,9 +469,10 @@ ecc_status ecc_batch_plan_create(ecc_context ctx, const ecc_instance* inst, int 
       hipStream_t st = bp->branch[b];
       e = hipStreamWaitEvent(st, bp->fork, 0);
       if (e == hipSuccess)
-        e = sh.conv     ? launch_tile_conv_items(st, sh.N, sh.TV, sh.descs.as<TileConvArgs>(),
-                                                 sh.items.as<int2>(), sh.nitems)
-            : sh.direct ? launch_direct_items(st, sh.N, sh.descs.as<TileArgs>(), sh.items.as<int2>(), sh.nitems)
+        e = sh.direct ? launch_direct_items(st, sh.conv, sh.N, sh.descs.as<TileArgs>(), sh.items.as<int2>(),
+                                            sh.nitems)
+            : sh.conv ? launch_tile_conv_items(st, sh.N, sh.TV, sh.descs.as<TileConvArgs>(), sh.items.as<int2>(),
+                                               sh.nitems)
                         : launch_tile_batch(st, sh.N, sh.TV, sh.sym, sh.nwg, sh.descs.as<TileArgs>(),
                                             sh.items.as<int2>(), sh.nitems,
                                             (flags & ECC_BATCH_PERSISTENT) ? sh.ctr.as<int>() : nullptr);

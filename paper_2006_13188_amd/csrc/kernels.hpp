@@ -279,15 +279,16 @@ hipError_t launch_ratio_spectra(hipStream_t s, const cx<double>* spec, int U, in
 bool tconv_supported(int N, int TV);
 size_t tconv_lds_bytes(int N);
 hipError_t launch_tile_conv(hipStream_t s, int N, int TV, int batch, const TileConvArgs& a);
-// Direct (spatial) extended correlation for filter sides S in {3, 5, ..., 15}: the fields
-// of TileArgs as for launch_tile_corr's single form (H, planeH, ldH, fld, y, planeY, ldY,
-// ny, nx, R = (S - 1) / 2, U, kofs, w, scale), Fs = the U components as U x S x S complex64
-// values; blocks of 16 x 64 outputs (tx, ty set by the launcher, or by direct_blocks for
-// batch descriptors).
+// Direct (spatial) extended correlation or convolution (conv) for filter sides S in
+// {3, 5, ..., 15}: the fields of TileArgs as for launch_tile_corr's single form (H, planeH,
+// ldH, fld, y, planeY, ldY, ny, nx, R = (S - 1) / 2, U, kofs (0 for the convolution), w,
+// scale), Fs = the U components as U x S x S complex64 values; blocks of 16 x 64 outputs
+// (tx, ty set by the launcher, or by direct_blocks for batch descriptors).
 bool direct_supported(int S);
 void direct_blocks(int ny, int nx, int* tx, int* ty);
-hipError_t launch_direct_corr(hipStream_t s, int S, int batch, const TileArgs& a);
-hipError_t launch_direct_items(hipStream_t s, int S, const TileArgs* descs, const int2* items, int nitems);
+hipError_t launch_direct(hipStream_t s, bool conv, int S, int batch, const TileArgs& a);
+hipError_t launch_direct_items(hipStream_t s, bool conv, int S, const TileArgs* descs, const int2* items,
+                               int nitems);
 // Batches of convolutions: one workgroup per item (descriptor index, block index) of
 // device descriptors (plain form: nsig = 1, step = 0, tx and ty set) and items.
 hipError_t launch_tile_conv_items(hipStream_t s, int N, int TV, const TileConvArgs* descs, const int2* items,

@@ -175,29 +175,31 @@ def test_empty_and_invalid_batches(E, setup):
 
 @pytest.mark.parametrize("direct", [False, True], ids=["auto", "direct"])
 def test_batch_with_direct_instances(E, direct):
-    """Small filters take the direct sums inside the graph: S = 3 and 5 under AUTO (the
-    time model prefers them there), every side up to 15 under DIRECT; the larger filter
-    keeps its block shape in both (a single call of it under DIRECT is refused).
-    Replayed twice, each replay against the oracle."""
+    """Small filters take the direct sums inside the graph, correlations and convolutions:
+    S = 3 and 5 under AUTO (the time model prefers them there), every side up to 15 under
+    DIRECT; the larger filter keeps its block shape in both (a single call of it under
+    DIRECT is refused). Replayed twice, each replay against the oracle."""
     import torch
     ctx = E.Context(0)
     if direct:
         ctx.set_strategy(E.STRATEGY_DIRECT)
-    specs = [(70, 90, 3, 2), (130, 64, 5, 6), (48, 200, 11, 4), (100, 100, 21, 5)]
+    specs = [(0, 70, 90, 3, 2), (0, 130, 64, 5, 6), (0, 48, 200, 11, 4), (0, 100, 100, 21, 5),
+             (1, 60, 80, 5, 3), (1, 75, 66, 11, 2)]
     insts, refs = [], []
-    for i, (ny, nx, S, K) in enumerate(specs):
+    for i, (op, ny, nx, S, K) in enumerate(specs):
         img, filt, th = batch_instance(200 + i, ny, nx, S)
         plan = E.FilterPlan.rotation(ctx, torch.from_numpy(filt).cuda(), K)
         comps, _ = O.angular_components(filt, K)
-        refs.append(O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
+        f = O.ext_corr_half if op == 0 else O.ext_conv_half
+        refs.append(f(img.astype(np.float64), th.astype(np.float64), O.half_components(comps)))
         out = torch.full((ny, nx), float("nan"), device="cuda")
-        insts.append((E.CORRELATION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
+        insts.append((op, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda(), out))
         if direct and S > 15:
             with pytest.raises(E.EccError):
-                ctx.describe(E.CORRELATION, plan, ny, nx)
+                ctx.describe(op, plan, ny, nx)
         else:
             want = E.STRATEGY_DIRECT if (S <= 5 or direct) else E.STRATEGY_TILED
-            assert ctx.describe(E.CORRELATION, plan, ny, nx)[0] == want
+            assert ctx.describe(op, plan, ny, nx)[0] == want
     bp = E.BatchPlan(ctx, insts, 0)
     info = bp.info()
     assert info["graph_instances"] == len(specs) and info["launches"] >= 3
