@@ -121,7 +121,10 @@ const char* ecc_last_error(ecc_context ctx);
 /* FFT size of the two-pass path for an image side n and filter radius R: the smallest
  * 7-smooth integer >= max(n + R, 2R + 1, 16) (zero-boundary linear correlation needs
  * >= n + R; the filter window of 2R + 1 taps is placed without wrapping onto itself; the
- * floor of 16 keeps every transform at two passes or more). */
+ * floor of 16 keeps every transform at two passes or more). With the autotuner on
+ * (ecc_set_autotune), the fastest of the 7-smooth sizes from that one up to 1/8 above it
+ * (at most four), timed once per context and (n, R) as the two-pass form's forward
+ * transform of an n x n signal; the first call for a pair may enqueue that timing. */
 ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
 /* Enables (1) or disables (0) the autotuner. When enabled, the next forward call (or
  * ecc_describe) first times every compiled block shape of the tiled path on this device
@@ -129,8 +132,10 @@ ecc_status ecc_fft_size(ecc_context ctx, int n, int R, int* P);
  * per-block costs instead of an operation count. */
 ecc_status ecc_set_autotune(ecc_context ctx, int enable);
 /* The autotuner's measurements as JSON text, to be kept between processes:
- *   {"device": "<architecture name>", "tile_cost": [[N, TV, a, b], ...]}
- * with the time of one full wave of blocks of shape (N, TV) modelled as a + b U ms.
+ *   {"device": "<architecture name>", "tile_cost": [[N, TV, a, b], ...],
+ *    "fft_size": [[n, R, P], ...]}
+ * with the time of one full wave of blocks of shape (N, TV) modelled as a + b U ms, and the
+ * two-pass FFT sizes chosen so far (see ecc_fft_size; the list is optional on import).
  * ecc_autotune_export writes the text and its terminating NUL to buf (cap bytes) and the
  * text's length to *len; buf may be NULL to ask for the length. INVALID_ARGUMENT if the
  * context has not calibrated yet (enable the autotuner and make one call, or

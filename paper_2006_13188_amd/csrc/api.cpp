@@ -22,15 +22,27 @@ ecc_status fail(ecc_status s, const std::string& msg) {
 
 namespace {
 
+int tune_fft_size(ecc_context ctx, int n, int Pmin);
+
+// FFT size of the two-pass form for an image side n and filter radius R: the smallest
+// 7-smooth size >= max(n + R, 2R + 1, 16) (at least 16: every transform then has two or
+// more passes, and zero padding beyond n + R changes nothing in the result; at least
+// 2R + 1: the filter window is placed without wrapping onto itself). With the autotuner
+// on, the fastest of the 7-smooth sizes up to 1/8 above it (tune_fft_size), chosen once
+// per context and side.
 int fft_size_for(ecc_context ctx, int n, int R) {
-  std::lock_guard<std::mutex> g(ctx->mu);
+  const int Pmin = next_smooth7(std::max(std::max(n + R, 2 * R + 1), 16));
   const std::string key = std::to_string(n) + ":" + std::to_string(R);
-  auto it = ctx->tuned.find(key);
-  if (it != ctx->tuned.end()) return it->second;
-  // at least 16: every transform then has two or more passes (zero padding beyond n + R
-  // changes nothing in the result); at least 2R + 1: the filter window is placed without
-  // wrapping onto itself
-  return next_smooth7(std::max(std::max(n + R, 2 * R + 1), 16));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+  }
+  if (!ctx->autotune) return Pmin;
+  const int P = tune_fft_size(ctx, n, Pmin);   // (launches kernels: outside the lock)
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->tuned.emplace(key, P);
+  return ctx->tuned[key];
 }
 
 }  // namespace
@@ -101,6 +113,76 @@ ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const
   return ECC_OK;
 }
 
+
+// The candidates of fft_size_for are timed as the two-pass form's forward transform of
+// an n x n signal (its own row and column kernels: the compiled-schedule or generic
+// engine that length takes), best of three after one warm-up run, on a private stream;
+// any failure keeps the smallest size.
+int tune_fft_size(ecc_context ctx, int n, int Pmin) {
+  std::vector<int> cand{Pmin};
+  for (int P = next_smooth7(Pmin + 1); (long long)P * 8 <= (long long)Pmin * 9 && cand.size() < 4;
+       P = next_smooth7(P + 1))
+    cand.push_back(P);
+  if (cand.size() == 1) return Pmin;
+  DeviceGuard dg(ctx->device);
+  const int Pmax = cand.back(), ldW = (Pmax / 2 + 1 + 15) & ~15;
+  DevBuf h, a, hh;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = h.ensure((size_t)n * n * sizeof(float));
+  if (e == hipSuccess) e = a.ensure((size_t)n * ldW * sizeof(cx<float>));
+  if (e == hipSuccess) e = hh.ensure((size_t)Pmax * ldW * sizeof(cx<float>));
+  if (e == hipSuccess) e = hipMemsetAsync(h.p, 0, (size_t)n * n * sizeof(float), st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = Pmin;
+  double best_ms = 1e30;
+  for (int P : cand) {
+    if (e != hipSuccess) break;
+    const Transform* T = nullptr;
+    if (get_transform(ctx, P, &T) != hipSuccess) continue;
+    const int W = P / 2 + 1;
+    const RowCfg r1 = row_config(*T, P, sizeof(cx<float>));
+    const ColCfg c2 = col_config(*T, 2, sizeof(cx<float>), 512);
+    ColCfg c3 = col_config(*T, 2, sizeof(cx<float>), 1024);
+    {
+      // the limits the two-pass calls check for this length (the component kernel: NB <= 2,
+      // at most 16 rows per thread): a size they would refuse is not a candidate
+      const int TF = c3.nthr >> c3.lgB;
+      if (c3.NB > 2 || (P + TF - 1) / TF > 16) c3.NB = -1;
+    }
+    if (check_cfg_row(r1, *T, sizeof(cx<float>), "row") != ECC_OK ||
+        check_cfg_col(c2, *T, sizeof(cx<float>), "column", true) != ECC_OK ||
+        check_cfg_col(c3, *T, sizeof(cx<float>), "column", true) != ECC_OK)
+      continue;
+    double ms_min = 1e30;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess)
+        e = launch_rows_r2c(st, r1, 1, h.as<float>(), 0, n, a.as<cx<float>>(), 0, ldW, n, n, W, T->desc, T->f());
+      if (e == hipSuccess)
+        e = launch_cols_fwd(st, c2, 1, a.as<cx<float>>(), 0, ldW, n, W, hh.as<cx<float>>(), 0, ldW, T->desc,
+                            T->f());
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && rep > 0) ms_min = std::min(ms_min, (double)ms);
+    }
+    if (e == hipSuccess && ms_min < best_ms) {
+      best_ms = ms_min;
+      best = P;
+    }
+  }
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e == hipSuccess ? best : Pmin;
+}
 
 // records stage event i of the measurement hook, if set
 inline hipError_t mark_event(ecc_context ctx, int i, hipStream_t st) {

@@ -569,6 +569,19 @@ ecc_status ecc_autotune_export(ecc_context ctx, char* buf, size_t cap, size_t* l
     j += item;
     first = false;
   }
+  j += "], \"fft_size\": [";
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    first = true;
+    for (const auto& kv : ctx->tuned) {
+      int n = 0, R = 0;
+      if (std::sscanf(kv.first.c_str(), "%d:%d", &n, &R) != 2) continue;
+      char item[64];
+      std::snprintf(item, sizeof(item), "%s[%d, %d, %d]", first ? "" : ", ", n, R, kv.second);
+      j += item;
+      first = false;
+    }
+  }
   j += "]}";
   *len = j.size();
   if (buf) {
@@ -613,8 +626,32 @@ ecc_status ecc_autotune_import(ecc_context ctx, const char* json) {
   for (const auto& c : kShapes)
     if (tile_supported(c[0], c[1]))
       ECC_REQ(costs.count({c[0], c[1]}), "the autotuner text lacks a block shape this library has");
+  // two-pass FFT sizes chosen by the autotuner (optional): [n, R, P] with P a 7-smooth size
+  // at least the smallest admissible one
+  std::map<std::string, int> sizes;
+  const size_t f0 = j.find("\"fft_size\"");
+  if (f0 != std::string::npos) {
+    size_t fp = j.find('[', f0);
+    ECC_REQ(fp != std::string::npos, "malformed fft_size");
+    ++fp;
+    while (true) {
+      const size_t open = j.find('[', fp), close = j.find(']', fp);
+      ECC_REQ(close != std::string::npos, "malformed fft_size");
+      if (open == std::string::npos || open > close) break;
+      int n = 0, R = 0, P = 0;
+      ECC_REQ(std::sscanf(j.c_str() + open, "[%d , %d , %d ]", &n, &R, &P) == 3, "malformed fft_size entry");
+      ECC_REQ(n >= 1 && R >= 0 && P >= n + R && P >= 2 * R + 1 && P >= 16 && next_smooth7(P) == P && P <= 16384,
+              "fft_size entry out of range");
+      sizes[std::to_string(n) + ":" + std::to_string(R)] = P;
+      fp = j.find(']', open) + 1;
+    }
+  }
   ctx->tile_cost = costs;
   ctx->tile_calibrated = true;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (const auto& kv : sizes) ctx->tuned[kv.first] = kv.second;
+  }
   return ECC_OK;
 }
 

@@ -246,3 +246,47 @@ def test_autotune_measurements_move_between_contexts(E):
     plan_b.close()
     a.close()
     b.close()
+
+
+def test_autotuned_fft_size(E):
+    """With the autotuner on, the two-pass FFT size of (n, R) is one of the 7-smooth sizes
+    from the smallest admissible one up to 1/8 above it, chosen once (cached); a two-pass
+    correlation at the chosen sizes matches the oracle; the choices travel in the JSON."""
+    import json
+    import torch
+
+    def smooth7(m):
+        for f in (2, 3, 5, 7):
+            while m % f == 0:
+                m //= f
+        return m == 1
+
+    plain = E.Context(0)
+    c = E.Context(0)
+    c.set_autotune(True)
+    c.set_strategy(E.STRATEGY_TWO_PASS)
+    for n, R in ((1000, 15), (700, 15), (1500, 31), (100, 3)):
+        Pmin = plain.fft_size(n, R)
+        P = c.fft_size(n, R)
+        assert smooth7(P) and Pmin <= P and 8 * P <= 9 * Pmin, (n, R, Pmin, P)
+        assert c.fft_size(n, R) == P
+    ny, nx, S, K = 700, 1000, 31, 6
+    img, filt, th = batch_instance(400, ny, nx, S)
+    plan = E.FilterPlan.rotation(c, torch.from_numpy(filt).cuda(), K)
+    y = E.ecc_extended(c, E.CORRELATION, plan, torch.from_numpy(img).cuda(), torch.from_numpy(th).cuda())
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    comps, _ = O.angular_components(filt, K)
+    ref = O.ext_corr_half(img.astype(np.float64), th.astype(np.float64), O.half_components(comps))
+    assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    text = c.autotune_export()
+    sizes = {(a, b): p for a, b, p in json.loads(text)["fft_size"]}
+    assert sizes[(1000, 15)] == c.fft_size(1000, 15) and sizes[(700, 15)] == c.fft_size(700, 15)
+    d = E.Context(0)
+    d.set_autotune(True)
+    d.autotune_import(text)
+    for (a, b), p in sizes.items():
+        assert d.fft_size(a, b) == p
+    plan.close()
+    for x in (plain, c, d):
+        x.close()
