@@ -125,8 +125,9 @@ class Context:
             lib().ecc_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals are gone when the interpreter tears down)
+        if _finalizing():
             return
         try:
             self.close()
@@ -255,8 +256,9 @@ class FilterPlan:
             lib().ecc_filter_plan_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals are gone when the interpreter tears down)
+        if _finalizing():
             return
         try:
             self.close()
@@ -299,8 +301,9 @@ class VolumePlan:
             lib().ecc_volume_plan_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals are gone when the interpreter tears down)
+        if _finalizing():
             return
         try:
             self.close()
@@ -671,8 +674,9 @@ class BatchPlan:
             lib().ecc_batch_plan_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals are gone when the interpreter tears down)
+        if _finalizing():
             return
         try:
             self.close()

@@ -114,9 +114,28 @@ ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const
 }
 
 
-// The candidates of fft_size_for are timed as the two-pass form's forward transform of
-// an n x n signal (its own row and column kernels: the compiled-schedule or generic
-// engine that length takes), best of three after one warm-up run, on a private stream;
+// Launch shape of the two-pass correlation's component column kernel (1024 threads): it
+// takes at most two butterflies and 16 rows per thread, so narrower column blocks are
+// tried when 4-column blocks exceed that (long transforms of small radices); NB = -1 if
+// no block width fits.
+ColCfg corr_col_config(const Transform& t) {
+  ColCfg c{};
+  for (int lgB = 2; lgB >= 0; --lgB) {
+    c = col_config(t, lgB, sizeof(cx<float>), 1024);
+    const int TF = c.nthr >> c.lgB;
+    if (c.NB > 0 && c.NB <= 2 && (t.desc.P + TF - 1) / TF <= 16 &&
+        check_cfg_col(c, t, sizeof(cx<float>), "column", true) == ECC_OK)
+      return c;
+  }
+  c.NB = -1;
+  return c;
+}
+
+// The candidates of fft_size_for are timed as the two-pass correlation's own kernels on up
+// to 512 rows of an n-wide signal: the forward row and column transforms of the signal and
+// the inverse row pass of four components with the per-pixel combination (the dominant
+// stage, which runs on a compiled schedule for some lengths), best of three after one
+// warm-up run, on a private stream. A size the two-pass calls would refuse is skipped;
 // any failure keeps the smallest size.
 int tune_fft_size(ecc_context ctx, int n, int Pmin) {
   std::vector<int> cand{Pmin};
@@ -125,17 +144,26 @@ int tune_fft_size(ecc_context ctx, int n, int Pmin) {
     cand.push_back(P);
   if (cand.size() == 1) return Pmin;
   DeviceGuard dg(ctx->device);
+  constexpr int Ucal = 4;
+  const int rows = std::min(n, 512);
   const int Pmax = cand.back(), ldW = (Pmax / 2 + 1 + 15) & ~15;
-  DevBuf h, a, hh;
+  const long long pTk = 2LL * rows * ldW;
+  DevBuf h, a, hh, tk, yb, wb;
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = h.ensure((size_t)n * n * sizeof(float));
-  if (e == hipSuccess) e = a.ensure((size_t)n * ldW * sizeof(cx<float>));
+  if (e == hipSuccess) e = h.ensure((size_t)rows * n * sizeof(float));
+  if (e == hipSuccess) e = a.ensure((size_t)rows * ldW * sizeof(cx<float>));
   if (e == hipSuccess) e = hh.ensure((size_t)Pmax * ldW * sizeof(cx<float>));
-  if (e == hipSuccess) e = hipMemsetAsync(h.p, 0, (size_t)n * n * sizeof(float), st);
+  if (e == hipSuccess) e = tk.ensure((size_t)Ucal * pTk * sizeof(cx<float>));
+  if (e == hipSuccess) e = yb.ensure((size_t)rows * n * sizeof(float));
+  if (e == hipSuccess) e = wb.ensure(Ucal * sizeof(float));
+  if (e == hipSuccess) e = hipMemsetAsync(h.p, 0, (size_t)rows * n * sizeof(float), st);
+  if (e == hipSuccess) e = hipMemsetAsync(tk.p, 0, (size_t)Ucal * pTk * sizeof(cx<float>), st);
+  if (e == hipSuccess) e = hipMemsetAsync(wb.p, 0, Ucal * sizeof(float), st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  Field fl{h.as<float>(), 0, n, 0, 1.0, 0.0};   // the zero signal doubles as the angle field
   int best = Pmin;
   double best_ms = 1e30;
   for (int P : cand) {
@@ -145,25 +173,32 @@ int tune_fft_size(ecc_context ctx, int n, int Pmin) {
     const int W = P / 2 + 1;
     const RowCfg r1 = row_config(*T, P, sizeof(cx<float>));
     const ColCfg c2 = col_config(*T, 2, sizeof(cx<float>), 512);
-    ColCfg c3 = col_config(*T, 2, sizeof(cx<float>), 1024);
-    {
-      // the limits the two-pass calls check for this length (the component kernel: NB <= 2,
-      // at most 16 rows per thread): a size they would refuse is not a candidate
-      const int TF = c3.nthr >> c3.lgB;
-      if (c3.NB > 2 || (P + TF - 1) / TF > 16) c3.NB = -1;
-    }
+    const ColCfg c3 = corr_col_config(*T);   // a size the two-pass calls would refuse is no candidate
+    RowCfg r4 = row_config(*T, n, sizeof(cx<float>));
+    r4.B = 2;
     if (check_cfg_row(r1, *T, sizeof(cx<float>), "row") != ECC_OK ||
         check_cfg_col(c2, *T, sizeof(cx<float>), "column", true) != ECC_OK ||
-        check_cfg_col(c3, *T, sizeof(cx<float>), "column", true) != ECC_OK)
+        check_cfg_col(c3, *T, sizeof(cx<float>), "column", true) != ECC_OK ||
+        (T->fR0 <= 0 && check_cfg_row(r4, *T, sizeof(cx<float>), "row") != ECC_OK))
       continue;
     double ms_min = 1e30;
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, st);
       if (e == hipSuccess)
-        e = launch_rows_r2c(st, r1, 1, h.as<float>(), 0, n, a.as<cx<float>>(), 0, ldW, n, n, W, T->desc, T->f());
-      if (e == hipSuccess)
-        e = launch_cols_fwd(st, c2, 1, a.as<cx<float>>(), 0, ldW, n, W, hh.as<cx<float>>(), 0, ldW, T->desc,
+        e = launch_rows_r2c(st, r1, 1, h.as<float>(), 0, n, a.as<cx<float>>(), 0, ldW, rows, n, W, T->desc,
                             T->f());
+      if (e == hipSuccess)
+        e = launch_cols_fwd(st, c2, 1, a.as<cx<float>>(), 0, ldW, rows, W, hh.as<cx<float>>(), 0, ldW, T->desc,
+                            T->f());
+      if (e == hipSuccess) {
+        if (T->fR0 > 0)
+          e = launch_corr_rows_fixed(st, 4, 1, tk.as<cx<float>>(), pTk, Ucal * pTk, ldW, fl, yb.as<float>(), 0, n,
+                                     rows, n, Ucal, wb.as<float>(), 1.0f, nullptr, nullptr, 0, 0, 1.0f, 0, 0, P,
+                                     T->fx());
+        else
+          e = launch_corr_rows(st, r4, 1, tk.as<cx<float>>(), pTk, Ucal * pTk, ldW, fl, yb.as<float>(), 0, n, rows,
+                               n, Ucal, wb.as<float>(), 1.0f, nullptr, nullptr, 0, 0, 1.0f, 0, 0, T->desc, T->f());
+      }
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -713,12 +748,7 @@ ecc_status corr_stack(ecc_context ctx, ecc_filter_plan plan, const Geometry& g, 
   cx<float>* T = Hh + batch * pH;
   RowCfg r1 = row_config(*g.Tx, Px, sizeof(cx<float>));
   ColCfg c2 = col_config(*g.Ty, 2, sizeof(cx<float>), 512);
-  ColCfg c3 = col_config(*g.Ty, 2, sizeof(cx<float>), 1024);
-  {
-    // the component kernel supports NB <= 2 and at most 16 rows per thread
-    const int TF = c3.nthr >> c3.lgB;
-    if (c3.NB > 2 || (g.Py + TF - 1) / TF > 16) c3.NB = -1;
-  }
+  ColCfg c3 = corr_col_config(*g.Ty);
   ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
   ECC_TRY(check_cfg_col(c2, *g.Ty, sizeof(cx<float>), "column", false));
   ECC_TRY(check_cfg_col(c3, *g.Ty, sizeof(cx<float>), "column", true));

@@ -299,3 +299,23 @@ def test_tiled_symmetric_pair_form_few_components(E, K):
         plan.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("op", [0, 1], ids=["corr", "conv"])
+def test_two_pass_long_radix3_columns(E, op):
+    """Column transforms of length 2025 = 3^4 5^2 (2005 rows, R = 20): more butterflies per
+    pass than the component kernel takes with 4-column blocks, so it runs narrower blocks
+    (a size the two-pass form refused before)."""
+    c = E.Context(0)
+    c.set_strategy(TWO_PASS)
+    shape, S, K = (2005, 100), 41, 6
+    assert c.fft_size(shape[0], (S - 1) // 2) == 2025
+    img = blurred_noise(shape, 90)
+    filt = random_filter(S, 91, 4.0 * S / 15)
+    theta = theta_field(shape, 92)
+    plan = E.FilterPlan.rotation(c, dev(filt), K)
+    got = host(E.ecc_extended(c, op, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K, op)
+    assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    plan.close()
+    c.close()
