@@ -121,7 +121,9 @@ const char* ecc_last_error(ecc_context ctx);
 /* FFT size of the two-pass path for an image side n and filter radius R: the smallest
  * 7-smooth integer >= max(n + R, 2R + 1, 16) (zero-boundary linear correlation needs
  * >= n + R; the filter window of 2R + 1 taps is placed without wrapping onto itself; the
- * floor of 16 keeps every transform at two passes or more). With the autotuner on
+ * floor of 16 keeps every transform at two passes or more) whose transforms every
+ * two-pass kernel takes (a length with more butterflies per pass than they handle is
+ * passed over for the next, up to 4096; beyond that the smallest). With the autotuner on
  * (ecc_set_autotune), the fastest of the 7-smooth sizes from that one up to 1/8 above it
  * (at most four), timed once per context and (n, R) as the two-pass form's forward
  * transform of an n x n signal; the first call for a pair may enqueue that timing. */

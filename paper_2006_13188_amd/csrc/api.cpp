@@ -23,15 +23,23 @@ ecc_status fail(ecc_status s, const std::string& msg) {
 namespace {
 
 int tune_fft_size(ecc_context ctx, int n, int Pmin);
+bool two_pass_size_ok(ecc_context ctx, int P);
+ColCfg corr_col_config(const Transform& t);
 
 // FFT size of the two-pass form for an image side n and filter radius R: the smallest
 // 7-smooth size >= max(n + R, 2R + 1, 16) (at least 16: every transform then has two or
 // more passes, and zero padding beyond n + R changes nothing in the result; at least
-// 2R + 1: the filter window is placed without wrapping onto itself). With the autotuner
-// on, the fastest of the 7-smooth sizes up to 1/8 above it (tune_fft_size), chosen once
-// per context and side.
+// 2R + 1: the filter window is placed without wrapping onto itself) that every two-pass
+// kernel takes (two_pass_size_ok; a size with too many butterflies per pass is passed
+// over for the next one, up to 4096). With the autotuner on, the fastest of the 7-smooth
+// sizes up to 1/8 above it (tune_fft_size), chosen once per context and side.
 int fft_size_for(ecc_context ctx, int n, int R) {
-  const int Pmin = next_smooth7(std::max(std::max(n + R, 2 * R + 1), 16));
+  int Pmin = next_smooth7(std::max(std::max(n + R, 2 * R + 1), 16));
+  for (int P = Pmin; P <= 4096; P = next_smooth7(P + 1))
+    if (two_pass_size_ok(ctx, P)) {
+      Pmin = P;
+      break;
+    }
   const std::string key = std::to_string(n) + ":" + std::to_string(R);
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -114,6 +122,19 @@ ecc_status check_cfg_col(const ColCfg& c, const Transform& t, size_t elem, const
 }
 
 
+// Whether every two-pass kernel takes transforms of length P: rows with at most 256
+// threads per line (the correlation's combined inverse row kernel runs two per
+// workgroup), the column kernels' configurations.
+bool two_pass_size_ok(ecc_context ctx, int P) {
+  const Transform* T = nullptr;
+  if (get_transform(ctx, P, &T) != hipSuccess) return false;
+  const RowCfg r = row_config(*T, P, sizeof(cx<float>));
+  const ColCfg c2 = col_config(*T, 2, sizeof(cx<float>), 512);
+  return r.TF <= 256 && r.NB > 0 && r.EPX > 0 && lds_rows(r, T->desc, sizeof(cx<float>)) <= kMaxLds &&
+         c2.NB > 0 && c2.EPT > 0 && lds_cols(c2, T->desc, sizeof(cx<float>)) <= kMaxLds &&
+         corr_col_config(*T).NB > 0;
+}
+
 // Launch shape of the two-pass correlation's component column kernel (1024 threads): it
 // takes at most two butterflies and 16 rows per thread, so narrower column blocks are
 // tried when 4-column blocks exceed that (long transforms of small radices); NB = -1 if
@@ -176,7 +197,7 @@ int tune_fft_size(ecc_context ctx, int n, int Pmin) {
     const ColCfg c3 = corr_col_config(*T);   // a size the two-pass calls would refuse is no candidate
     RowCfg r4 = row_config(*T, n, sizeof(cx<float>));
     r4.B = 2;
-    if (check_cfg_row(r1, *T, sizeof(cx<float>), "row") != ECC_OK ||
+    if (r4.TF > 256 || check_cfg_row(r1, *T, sizeof(cx<float>), "row") != ECC_OK ||
         check_cfg_col(c2, *T, sizeof(cx<float>), "column", true) != ECC_OK ||
         check_cfg_col(c3, *T, sizeof(cx<float>), "column", true) != ECC_OK ||
         (T->fR0 <= 0 && check_cfg_row(r4, *T, sizeof(cx<float>), "row") != ECC_OK))
@@ -253,8 +274,12 @@ ecc_status get_spectrum(ecc_filter_plan plan, int Py, int Px, hipStream_t st, co
   ECC_HIP(spec64.ensure((size_t)U * Py * ld * sizeof(cx<double>)));
   ECC_HIP(sp->buf.ensure((size_t)U * Py * ld * sizeof(cx<float>)));
   ECC_HIP(hipMemsetAsync(spec64.p, 0, (size_t)U * Py * ld * sizeof(cx<double>), st));
+  // float64 transforms: 256 threads per line, or 512 for lengths whose passes have more
+  // butterflies than 256 threads take (about 3000 and above)
   RowCfg rc = row_config(*Tx, Px, sizeof(cx<double>));
+  if (rc.NB < 0 || rc.EPX < 0) rc = row_config(*Tx, Px, sizeof(cx<double>), 512);
   ColCfg cc = col_config(*Ty, 2, sizeof(cx<double>), 256);
+  if (cc.NB < 0) cc = col_config(*Ty, 2, sizeof(cx<double>), 512);
   ECC_TRY(check_cfg_row(rc, *Tx, sizeof(cx<double>), "filter row"));
   ECC_TRY(check_cfg_col(cc, *Ty, sizeof(cx<double>), "filter column", false));
   ECC_HIP((launch_fft_rows<double>(st, rc, U, -1, plan->comps64.as<cx<double>>(), (long long)Sz * Sz, Sz,
@@ -829,7 +854,11 @@ ecc_status corr_rows(ecc_filter_plan plan, const Geometry& g, int batch, const c
     return ECC_OK;
   }
   RowCfg r4 = row_config(*g.Tx, g.nx, sizeof(cx<float>));
-  r4.B = 2;   // two component transforms per workgroup
+  // two component transforms of up to 256 threads per workgroup: rows that need 512
+  // threads (above 4096 points, or more than 1024 butterflies per pass) are refused
+  if (r4.TF > 256)
+    return fail(ECC_ERR_UNSUPPORTED, "row transform too long for the two-pass correlation's row kernel");
+  r4.B = 2;
   ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "row"));
   ECC_HIP(launch_corr_rows(st, r4, batch, T, pTk, pTi, pitch16(g.W), fl, y, planeY, ldY, g.ny, g.nx, U,
                            wts, scl, y2, mulsig, planeMul, ldMul, 1.0f, kb, accum, g.Tx->desc,
@@ -1211,6 +1240,8 @@ ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batc
   const long long pBk = (long long)ny * g.Px, pBs = pBk * U, pBi = pBs * nsig;
   RowCfg r1 = row_config(*g.Tx, nx, sizeof(cx<float>));
   ECC_TRY(check_cfg_row(r1, *g.Tx, sizeof(cx<float>), "row"));
+  // (the joint row kernel keeps 256 threads: its per-pixel state fills the registers)
+  if (r1.B * r1.TF > 256) return fail(ECC_ERR_UNSUPPORTED, "image too wide for the two-pass joint row kernel");
   mark(ctx, 0, st);
   ECC_HIP(launch_conv_rows_fwd_joint(st, r1, batch, signal, pS, ld_signal, jf, normalized ? 1 : 0, nsig, Bk, pBk,
                                      pBs, pBi, g.Px, ny, nx, U, plan->joint_n, g.Tx->desc, g.Tx->f()));
@@ -1290,17 +1321,18 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
   long long pTk, pTi;
   ECC_TRY(corr_stack(ctx, plan, g, 1, signal, 0, ld, 0, st, &T, &pTk, &pTi));
   // one row per workgroup, up to 512 threads, at most 2 pixels per thread (each pixel
-  // keeps n_angles accumulators in registers)
+  // keeps n_angles accumulators in registers); wider rows are split into segments of
+  // 1024 pixels, each a workgroup that transforms the whole row
   RowCfg r4 = row_config(*g.Tx, nx, sizeof(cx<float>), 512);
   r4.B = 1;
   if ((nx + r4.TF - 1) / r4.TF > 2) {
     r4.TF = 512;
     const int nb = max_butterflies(*g.Tx);
     r4.NB = nb <= 512 ? 1 : (nb <= 1024 ? 2 : (nb <= 2048 ? 4 : -1));
-    const int need = (nx + 511) / 512;
-    r4.EPX = need <= 1 ? 1 : (need <= 2 ? 2 : -1);
+    r4.EPX = 2;
   }
-  if (r4.EPX < 0 || r4.EPX > 2) return fail(ECC_ERR_UNSUPPORTED, "image too wide for the matching kernel");
+  if (r4.NB < 0 || r4.EPX < 1 || r4.EPX > 2)
+    return fail(ECC_ERR_UNSUPPORTED, "transform too long for the matching kernel");
   if (lds_rows(r4, g.Tx->desc, sizeof(cx<float>)) + 64 * sizeof(cx<float>) > kMaxLds) return fail(ECC_ERR_UNSUPPORTED, "matching row transform too long");
   ECC_TRY(check_cfg_row(r4, *g.Tx, sizeof(cx<float>), "matching row"));
   ECC_HIP(launch_match_rows(st, r4, T, pTk, pitch16(g.W), best_score, best_index, ld_out, ny, nx, plan->U,

@@ -180,6 +180,10 @@ RowCfg row_config(const Transform& t, int span, size_t elem, int max_threads) {
   while (c.B > 1 && lds_rows(c, t.desc, elem) > 64 * 1024) c.B >>= 1;
   const int need = (span + TF - 1) / TF;
   c.EPX = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : -1;
+  // lines longer than max_threads can take (more than four butterflies or sixteen elements
+  // per thread: lengths above 4096, or small radices above ~3000) get 512 threads, which
+  // every row kernel accepts
+  if ((c.NB < 0 || c.EPX < 0) && max_threads < 512) return row_config(t, span, elem, 512);
   return c;
 }
 

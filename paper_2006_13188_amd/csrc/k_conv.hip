@@ -13,7 +13,7 @@ namespace ecc {
 // conv_rows_fwd: B_{k,s} = FFT_x(sig_s e^{-i k alpha}); sig_0 = H (or H / s^2 when
 // sig_norm), sig_1 = 1 / s^2 (the constant signal of the normalising denominator).
 template <int NB, int EPX>
-__global__ void __launch_bounds__(256) k_conv_rows_fwd(
+__global__ void __launch_bounds__(512) k_conv_rows_fwd(
     const float* __restrict__ H, long long planeH, int ldH, Field fld, int sig_norm, int nsig,
     cx<float>* __restrict__ Bk, long long planeBk, long long planeBsig, long long planeBimg, int ldB,
     int ny, int nx, int U, FftDesc d, const cx<float>* __restrict__ tw, int B, int TF) {
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(512) k_conv_cols_sum(const cx<float>* __restri
 
 // conv_rows_inv: y = scale * Re IFFT_x(C_0), or Re IFFT_x(C_0) / Re IFFT_x(C_1).
 template <int NB, int EPX>
-__global__ void __launch_bounds__(256) k_conv_rows_inv(
+__global__ void __launch_bounds__(512) k_conv_rows_inv(
     const cx<float>* __restrict__ C, long long planeCsig, long long planeCimg, int ldC,
     float* __restrict__ y, long long planeY, int ldY, int ny, int nx, int nsig, float scl,
     FftDesc d, const cx<float>* __restrict__ tw, int B, int TF) {
@@ -346,6 +346,7 @@ hipError_t launch_conv_rows_fwd(hipStream_t s, const RowCfg& c, int batch, const
                                 int nsig, cx<float>* Bk, long long planeBk, long long planeBsig,
                                 long long planeBimg, int ldB, int ny, int nx, int U,
                                 const FftDesc& d, const cx<float>* tw) {
+  if (c.B * c.TF > 512) return hipErrorInvalidValue;   // the kernel's launch bound
   dim3 grid((ny + c.B - 1) / c.B, batch), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<float>));
   ECC_NB_SWITCH(c.NB, ECC_EPX_SWITCH(c.EPX, hipLaunchKernelGGL((k_conv_rows_fwd<NB, EPX>), grid, block, lds, s,
@@ -386,6 +387,7 @@ hipError_t launch_conv_rows_inv(hipStream_t s, const RowCfg& c, int batch, const
                                 long long planeCsig, long long planeCimg, int ldC, float* y,
                                 long long planeY, int ldY, int ny, int nx, int nsig, float scale_,
                                 const FftDesc& d, const cx<float>* tw) {
+  if (c.B * c.TF > 512) return hipErrorInvalidValue;   // the kernel's launch bound
   dim3 grid((ny + c.B - 1) / c.B, batch), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<float>));
   ECC_NB_SWITCH(c.NB, ECC_EPX_SWITCH(c.EPX, hipLaunchKernelGGL((k_conv_rows_inv<NB, EPX>), grid, block, lds, s,

@@ -15,7 +15,7 @@ namespace ecc {
 // ---------------------------------------------------------------------------------
 // rows_r2c: two real rows packed as one complex transform, split after the FFT.
 template <int NB>
-__global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ H, long long planeH,
+__global__ void __launch_bounds__(512) k_rows_r2c(const float* __restrict__ H, long long planeH,
                                                  int ldH, cx<float>* __restrict__ A,
                                                  long long planeA, int ldA, int ny, int nx, int W,
                                                  FftDesc d, const cx<float>* __restrict__ tw,
@@ -314,7 +314,9 @@ __global__ void __launch_bounds__(512) k_corr_rows(
 
 // ---------------------------------------------------------------------------------
 // match_rows: response at n_angles equispaced angles, C(m) = sum_k w_k Re(e^{2 pi i k m / A} G_k),
-// kept per pixel in registers; best score and the smallest maximising index.
+// kept per pixel in registers; best score and the smallest maximising index. A row wider
+// than the EPX TF pixels one workgroup keeps is split into segments (blockIdx.y), each
+// transforming the whole row and keeping its own pixels.
 template <int NB, int EPX>
 __global__ void __launch_bounds__(512) k_match_rows(
     const cx<float>* __restrict__ T, long long planeTk, int ldT, float* __restrict__ score,
@@ -336,6 +338,7 @@ __global__ void __launch_bounds__(512) k_match_rows(
   const int c = threadIdx.x / TF, f = threadIdx.x - c * TF;
   const int row = blockIdx.x * B + c;
   const bool active = (c < B) && (row < ny);
+  const int xs = blockIdx.y * EPX * TF;   // first pixel of this segment
   Layout L{B, 0, Px};
   float acc[EPX][AMAX];
 #pragma unroll
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(512) k_match_rows(
     const float wk = w[k];
 #pragma unroll
     for (int j = 0; j < EPX; ++j) {
-      const int x = f + j * TF;
+      const int x = xs + f + j * TF;
       if (active && x < nx) {
         const cx<float> g = buf[c * Px + x];
         const float gr = wk * g.re, gi = wk * g.im;
@@ -372,7 +375,7 @@ __global__ void __launch_bounds__(512) k_match_rows(
   if (active) {
 #pragma unroll
     for (int j = 0; j < EPX; ++j) {
-      const int x = f + j * TF;
+      const int x = xs + f + j * TF;
       if (x < nx) {
         float best = acc[j][0];
         int bi = 0;
@@ -395,6 +398,7 @@ __global__ void __launch_bounds__(512) k_match_rows(
 hipError_t launch_rows_r2c(hipStream_t s, const RowCfg& c, int batch, const float* H, long long planeH,
                            int ldH, cx<float>* A, long long planeA, int ldA, int ny, int nx, int W,
                            const FftDesc& d, const cx<float>* tw) {
+  if (c.B * c.TF > 512) return hipErrorInvalidValue;   // the kernel's launch bound
   const int pairs = (ny + 1) / 2;
   dim3 grid((pairs + c.B - 1) / c.B, batch), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<float>));
@@ -462,7 +466,10 @@ hipError_t launch_match_rows(hipStream_t s, const RowCfg& c, const cx<float>* T,
                              int ldT, float* score, int* index, int ldOut, int ny, int nx, int U,
                              const float* w, float scale_, int n_angles, const float* angle_tab,
                              const FftDesc& d, const cx<float>* tw) {
-  dim3 grid((ny + c.B - 1) / c.B), block(c.B * c.TF);
+  if (c.EPX < 1 || c.TF < 1) return hipErrorInvalidValue;
+  const int nseg = (nx + c.EPX * c.TF - 1) / (c.EPX * c.TF);   // row segments (wide images)
+  if (nseg > 65535) return hipErrorInvalidValue;
+  dim3 grid((ny + c.B - 1) / c.B, nseg), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<float>)) + 64 * sizeof(cx<float>);
   ECC_NB_SWITCH(c.NB, ECC_EPX_SWITCH(c.EPX, hipLaunchKernelGGL((k_match_rows<NB, EPX>), grid, block, lds, s,
                                          T, planeTk, ldT, score, index, ldOut, ny, nx, U, w, scale_,

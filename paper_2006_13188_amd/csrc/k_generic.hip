@@ -15,7 +15,7 @@ namespace ecc {
 constexpr int kLoadGroup = 8;
 
 template <typename T, int NB, int DIR>
-__global__ void __launch_bounds__(256) k_fft_rows(const cx<T>* __restrict__ in, long long planeIn,
+__global__ void __launch_bounds__(512) k_fft_rows(const cx<T>* __restrict__ in, long long planeIn,
                                                  int ldIn, int nrows, int nvalid, int shift_in,
                                                  cx<T>* __restrict__ out, long long planeOut,
                                                  int ldOut, int nstore, int shift_out, FftDesc d,
@@ -296,6 +296,7 @@ hipError_t launch_fft_rows(hipStream_t s, const RowCfg& c, int nplanes, int dir,
   if (nstore > d.P || nvalid > d.P) return hipErrorInvalidValue;
   shift_in = ((shift_in % d.P) + d.P) % d.P;
   shift_out = ((shift_out % d.P) + d.P) % d.P;
+  if (c.B * c.TF > 512) return hipErrorInvalidValue;   // the kernel's launch bound
   dim3 grid((nrows + c.B - 1) / c.B, nplanes), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<T>));
   if (dir < 0) {

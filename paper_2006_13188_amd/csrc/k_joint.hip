@@ -252,6 +252,7 @@ hipError_t launch_conv_rows_fwd_joint(hipStream_t s, const RowCfg& c, int batch,
                                       int ldH, const JointField& jf, int sig_norm, int nsig, cx<float>* Bk,
                                       long long planeBk, long long planeBsig, long long planeBimg, int ldB, int ny,
                                       int nx, int U, int n, const FftDesc& d, const cx<float>* tw) {
+  if (c.B * c.TF > 256) return hipErrorInvalidValue;   // the kernel's launch bound
   dim3 grid((ny + c.B - 1) / c.B, batch), block(c.B * c.TF);
   const size_t lds = lds_rows(c, d, sizeof(cx<float>));
   ECC_NB_SWITCH(c.NB, ECC_EPX_SWITCH(c.EPX, hipLaunchKernelGGL((k_conv_rows_fwd_joint<NB, EPX>), grid, block, lds,

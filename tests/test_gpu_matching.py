@@ -107,3 +107,21 @@ def test_full_size_planted_patterns(E, prec):
         m = int(round(hit[0][2] / (2 * np.pi) * 64)) % 64
         assert min(abs(int(index[i, j]) - m), 64 - abs(int(index[i, j]) - m)) <= 1
         s[max(0, i - 40):i + 40, max(0, j - 40):j + 40] = -np.inf
+
+
+@pytest.mark.parametrize("shape,A", [((40, 2600), 16), ((30, 1025), 64)])
+def test_two_pass_matching_wide_rows(E, shape, A):
+    """Two-pass matching of rows wider than one workgroup's 1024 pixels: the rows are split
+    into segments, each transforming the whole row (was refused)."""
+    c = E.Context(0)
+    c.set_strategy(TWO_PASS)
+    img = blurred_noise(shape, 5)
+    S, K = 21, 6
+    filt = random_filter(S, 6, 4.0 * S / 15)
+    plan = E.FilterPlan.rotation(c, dev(filt), K)
+    score, index = E.ecc_match_rotations(c, plan, dev(img), A)
+    comps, _ = O.angular_components(filt, K)
+    ref, _, C = O.match_rotations(img.astype(np.float64), comps, A)
+    check(host(score).astype(np.float64), host(index), ref, C, TOLS[FP32])
+    plan.close()
+    c.close()

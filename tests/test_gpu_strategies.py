@@ -319,3 +319,28 @@ def test_two_pass_long_radix3_columns(E, op):
     assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
     plan.close()
     c.close()
+
+
+@pytest.mark.parametrize("shape", [(4096, 40), (40, 4096)], ids=["tall", "wide"])
+@pytest.mark.parametrize("op", [0, 1], ids=["corr", "conv"])
+def test_two_pass_transforms_above_4096(E, op, shape):
+    """Two-pass transforms of 4116 points (4096 + R, 7-smooth): the plan's float64 filter
+    spectra and the row kernels take 512-thread transforms there (refused before), except
+    the correlation's combined inverse row kernel, which refuses rows that long."""
+    c = E.Context(0)
+    c.set_strategy(TWO_PASS)
+    S, K = 21, 4
+    assert c.fft_size(4096, (S - 1) // 2) == 4116
+    img = blurred_noise(shape, 93)
+    filt = random_filter(S, 94, 4.0 * S / 15)
+    theta = theta_field(shape, 95)
+    plan = E.FilterPlan.rotation(c, dev(filt), K)
+    if op == 0 and shape[1] == 4096:
+        with pytest.raises(E.EccError, match="too long"):
+            E.ecc_extended(c, op, plan, dev(img), dev(theta))
+        return
+    got = host(E.ecc_extended(c, op, plan, dev(img), dev(theta))).astype(np.float64)
+    ref = oracle_corr(img, filt, theta, K, op)
+    assert rel2(got, ref) <= TOL and relinf(got, ref) <= TOL, (rel2(got, ref), relinf(got, ref))
+    plan.close()
+    c.close()
