@@ -331,7 +331,8 @@ ecc_status ecc_joint_convolution(ecc_context ctx, ecc_filter_plan plan, int batc
  * signal: device float32 ny x nx (stride ld); best_score (float32) and best_index
  * (int32): device ny x nx with stride ld_out.
  * With a block shape (TILED / AUTO strategy) the components are computed block by block
- * into a stack in the context's workspace (K+1 planes of ny nx complex64) and the
+ * into a stack in the context's workspace (K+1 planes of ny nx complex64 values, each
+ * padded by less than 1.5 KiB) and the
  * angle search runs in the precision `prec`: ECC_PREC_FP32 (float32; for n_angles = 64
  * and K <= 31 a length-64 inverse DFT over k per pixel, else the dense product of the
  * angle table with the components), ECC_PREC_MFMA_FP16_HILO (the dense product on matrix
@@ -356,8 +357,9 @@ ecc_status ecc_match_rotations(ecc_context ctx, ecc_filter_plan plan, int ny, in
  * the filter radius under the context's strategy; the plan's block spectra and angle
  * table for this image size and n_angles exist, i.e. ecc_match_rotations has run once
  * with the same plan, size and n_angles; if the autotuner is on, it has calibrated.
- * One block row of the stack, (K+1) * T * nx complex64 values (T = the block side, 64
- * for the 63 x 63 pattern), must fit in 64 MiB, else ECC_ERR_INVALID_ARGUMENT. */
+ * One block row of the stack, K+1 planes of T * nx complex64 values (T = the block side,
+ * 64 for the 63 x 63 pattern) each padded by less than 1.5 KiB, must fit in 64 MiB, else
+ * ECC_ERR_INVALID_ARGUMENT. */
 ecc_status ecc_match_rotations_noalloc(ecc_context ctx, ecc_filter_plan plan, int ny, int nx,
                                        const float* signal, int ld, int n_angles, float* best_score,
                                        int* best_index, int ld_out, ecc_precision prec,

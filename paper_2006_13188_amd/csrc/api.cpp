@@ -95,7 +95,7 @@ size_t ws_conv_two_pass(int batch, int ny, int Py, int Px, int U, int nsig, bool
   return ((saved ? 0 : (size_t)batch * nsig * U * plane) + (size_t)batch * nsig * plane + part) * sizeof(cx<float>);
 }
 // tiled matching: the component stack, U planes of ny x nx
-size_t ws_match_tiled(int ny, int nx, int U) { return (size_t)ny * nx * U * sizeof(cx<float>); }
+size_t ws_match_tiled(int ny, int nx, int U) { return (size_t)stack_pitch((long long)ny * nx) * U * sizeof(cx<float>); }
 // on-chip filter gradient: per-block lag sums (256-byte aligned) + the reduction's scratch
 size_t ws_gradf_parts(long long nblk, int U, int Sz) {
   return ((size_t)nblk * U * Sz * Sz * sizeof(cx<float>) + 255) / 256 * 256;

@@ -20,12 +20,13 @@ namespace ecc {
 
 namespace {
 
-// The stack holds U planes of npix complex values (component-major). UMAX >= U (the
-// components beyond U are zero and their products are not formed past UMAX); the table
-// rows of the A angles are staged in LDS (read as broadcasts).
+// The stack holds U planes of npix complex values (component-major), `pitch` apart.
+// UMAX >= U (the components beyond U are zero and their products are not formed past
+// UMAX); the table rows of the A angles are staged in LDS (read as broadcasts).
 template <int UMAX>
 __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restrict__ stack, int U,
-                                                          long long npix, int A, const float* __restrict__ dtab,
+                                                          long long npix, long long pitch, int A,
+                                                          const float* __restrict__ dtab,
                                                           float* __restrict__ score, int* __restrict__ index,
                                                           int ldOut, int nx) {
   constexpr int K2 = 2 * UMAX;
@@ -37,7 +38,7 @@ __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restri
   float g[K2];
 #pragma unroll
   for (int c = 0; c < UMAX; ++c) {
-    const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
+    const float2 v = (c < U) ? stack[c * pitch + p] : make_float2(0.f, 0.f);
     g[2 * c] = v.x;
     g[2 * c + 1] = v.y;
   }
@@ -69,7 +70,8 @@ __global__ void __launch_bounds__(256) k_match_angles_f32(const float2* __restri
 // about half the arithmetic of transforming the complex inputs at all 64 angles.
 template <int UMAX>
 __global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __restrict__ stack, int U,
-                                                                long long npix, const float* __restrict__ dtab,
+                                                                long long npix, long long pitch,
+                                                                const float* __restrict__ dtab,
                                                                 float* __restrict__ score, int* __restrict__ index,
                                                                 int ldOut, int nx) {
   static_assert(UMAX <= 32, "inputs below the 32nd frequency");
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __
   cx<float> H[UMAX];
 #pragma unroll
   for (int c = 0; c < UMAX; ++c) {
-    const float2 v = (c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
+    const float2 v = (c < U) ? stack[c * pitch + p] : make_float2(0.f, 0.f);
     const float w = (c < U) ? dtab[2 * c] : 0.f;
     H[c] = c == 0 ? mk(w * v.x, 0.f) : mk(0.5f * w * v.x, 0.5f * w * v.y);
   }
@@ -117,7 +119,8 @@ __global__ void __launch_bounds__(256) k_match_angles_f32_dft64(const float2* __
 // 4 (l/16) + j][l%16] comes back in lane l.
 template <bool BF16, int MT, int KS>
 __global__ void __launch_bounds__(256) k_match_angles_mfma(const float2* __restrict__ stack, int U,
-                                                           long long npix, int A, const float* __restrict__ dtab,
+                                                           long long npix, long long pitch, int A,
+                                                          const float* __restrict__ dtab,
                                                            float* __restrict__ score, int* __restrict__ index,
                                                            int ldOut, int nx) {
   using SP = Split<BF16>;
@@ -144,8 +147,8 @@ __global__ void __launch_bounds__(256) k_match_angles_mfma(const float2* __restr
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int c = 8 * s + 2 * lq;   // entries 2c .. 2c + 3 = components c and c + 1
-      const float2 q0 = (p < npix && c < U) ? stack[c * npix + p] : make_float2(0.f, 0.f);
-      const float2 q1 = (p < npix && c + 1 < U) ? stack[(c + 1) * npix + p] : make_float2(0.f, 0.f);
+      const float2 q0 = (p < npix && c < U) ? stack[c * pitch + p] : make_float2(0.f, 0.f);
+      const float2 q1 = (p < npix && c + 1 < U) ? stack[(c + 1) * pitch + p] : make_float2(0.f, 0.f);
       v[s][0] = q0.x;
       v[s][1] = q0.y;
       v[s][2] = q1.x;
@@ -211,11 +214,12 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int
                                const float* dtab, float* score, int* index, int ldOut, int nx) {
   if (U < 1 || 2 * U > 64 || A < 1 || A > 64 || npix < 1) return hipErrorInvalidValue;
   const float2* stack = reinterpret_cast<const float2*>(stackf);
+  const long long pitch = stack_pitch(npix);
   if (prec == 0) {
     const unsigned grid = (unsigned)((npix + 255) / 256);
     if (A == 64) {
 #define ECC_MD(UM)                                                                                         \
-  hipLaunchKernelGGL((k_match_angles_f32_dft64<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, dtab,    \
+  hipLaunchKernelGGL((k_match_angles_f32_dft64<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, pitch, dtab,    \
                      score, index, ldOut, nx)
       if (U <= 8) ECC_MD(8);
       else if (U <= 16) ECC_MD(16);
@@ -226,7 +230,7 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int
       return last();
     }
 #define ECC_MF(UM)                                                                                         \
-  hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, A, dtab,      \
+  hipLaunchKernelGGL((k_match_angles_f32<UM>), dim3(grid), dim3(256), 0, s, stack, U, npix, pitch, A, dtab,      \
                      score, index, ldOut, nx)
     if (U <= 4) ECC_MF(4);
     else if (U <= 8) ECC_MF(8);
@@ -244,7 +248,7 @@ hipError_t launch_match_angles(hipStream_t s, int prec, const float* stackf, int
   const unsigned grid = (unsigned)std::min<long long>((groups + 3) / 4, 256LL * 8);
 #define ECC_MM(BF, mt, ks)                                                                                    \
   if (MT == mt && KS == ks) {                                                                                 \
-    hipLaunchKernelGGL((k_match_angles_mfma<BF, mt, ks>), dim3(grid), dim3(256), 0, s, stack, U, npix, A,      \
+    hipLaunchKernelGGL((k_match_angles_mfma<BF, mt, ks>), dim3(grid), dim3(256), 0, s, stack, U, npix, pitch, A, \
                        dtab, score, index, ldOut, nx);                                                        \
     return last();                                                                                            \
   }

@@ -1016,7 +1016,7 @@ hipError_t launch_tile_stack(hipStream_t s, int N, int TV, const float* H, int l
   a.Fs = Fs;
   a.stack = stack;
   a.stack_y0 = by0 * T;
-  a.stack_plane = (long long)((ny < by1 * T ? ny : by1 * T) - a.stack_y0) * nx;
+  a.stack_plane = stack_pitch((long long)((ny < by1 * T ? ny : by1 * T) - a.stack_y0) * nx);
   a.tile0 = by0 * a.tx;
   const long long nblk = (long long)a.tx * (by1 - by0);
 #define ECC_TSK(n, tv, sb, hv) \

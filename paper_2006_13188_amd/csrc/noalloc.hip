@@ -69,18 +69,22 @@ ecc_status ecc_match_rotations_noalloc(ecc_context ctx, ecc_filter_plan plan, in
     return fail(ECC_ERR_UNSUPPORTED,
                 "the plan's block spectra or angle table for this image size and angle count do not exist yet: "
                 "run ecc_match_rotations once with the same plan, size and n_angles first");
-  const size_t row_bytes = (size_t)U * tc.T * nx * sizeof(float2);   // one block row of the stack
-  if (row_bytes > kScratchBytes)
+  // a band of b block rows takes U planes of stack_pitch(b T nx) complex values
+  const int nby = (ny + tc.T - 1) / tc.T;
+  auto band_bytes = [&](int b) {
+    return (size_t)U * (size_t)stack_pitch((long long)std::min(ny, b * tc.T) * nx) * sizeof(float2);
+  };
+  if (band_bytes(1) > kScratchBytes)
     return fail(ECC_ERR_INVALID_ARGUMENT,
-                "one block row of the component stack (" + std::to_string(row_bytes) + " bytes) exceeds the " +
+                "one block row of the component stack (" + std::to_string(band_bytes(1)) + " bytes) exceeds the " +
                     std::to_string(kScratchBytes) + "-byte scratch array: use ecc_match_rotations");
   DeviceGuard dg(ctx->device);
   hipStream_t st = S(stream);
   void* scr = nullptr;
   ECC_TRY(scratch_for(ctx->device, &scr));
   float* stack = static_cast<float*>(scr);
-  const int nby = (ny + tc.T - 1) / tc.T;
-  const int band = (int)std::min<size_t>((size_t)nby, kScratchBytes / row_bytes);   // block rows per band
+  int band = 1;   // block rows per band: the most that fit
+  while (band < nby && band_bytes(band + 1) <= kScratchBytes) ++band;
   const int pc = prec == ECC_PREC_FP32 ? 0 : (prec == ECC_PREC_MFMA_FP16_HILO ? 1 : 2);
   const float scale = 1.0f / ((float)tc.N * (float)tc.N);
   for (int by0 = 0; by0 < nby; by0 += band) {
