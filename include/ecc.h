@@ -398,8 +398,9 @@ ecc_status ecc_voting_filter(ecc_context ctx, int S, const float* pattern, float
  * window around them, ties going to the first pixel in raster order. The strongest
  * min(max_peaks, number of peaks) are written to rows, cols (device int32) and values
  * (device float32) by decreasing value (ties by raster index); `count` (device int32)
- * receives their number. Deterministic. Uses the context workspace (16 bytes per
- * (radius+1)^2 cell of the image plus the sort's temporary storage).
+ * receives their number. Deterministic. Uses the context workspace: 16 bytes per key
+ * slot (one per (radius+1)^2 cell of each 64 x 16 pixel block for radius <= 32, one per
+ * radius+1 pixels of each 256-pixel row segment above) plus the sort's temporary storage.
  * Errors: INVALID_ARGUMENT, OUT_OF_MEMORY, HIP. */
 ecc_status ecc_find_peaks(ecc_context ctx, int ny, int nx, const float* response, int ld,
                           int radius, float threshold, int relative, int max_peaks, int* rows,

@@ -82,120 +82,165 @@ __device__ __forceinline__ float unordered(unsigned int o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
 }
 
-__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict__ a, long long n,
-                                                  unsigned int* __restrict__ counter, unsigned int* __restrict__ mx) {
+// Adds `key`, for every lane with `take` set, to its workgroup's slots: one update of the
+// workgroup's LDS counter per wave, slots in lane order after it. Every active lane of the
+// wave must make the call. (A counter shared by the whole device would be one memory-side
+// atomic per peak, serialised on one address: thousands of them took ~50 us at 1024^2.)
+__device__ __forceinline__ void append_keys(bool take, unsigned long long key, unsigned long long* __restrict__ slots,
+                                            unsigned int nslot, unsigned int* wcnt) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = __lane_id();
+  const int first = __ffsll((unsigned long long)m) - 1;
+  unsigned int base = 0u;
+  if (lane == first) base = atomicAdd(wcnt, (unsigned int)__popcll(m));
+  base = (unsigned int)__shfl((int)base, first);
+  if (take) {
+    const unsigned int slot = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+    if (slot < nslot) slots[slot] = key;
+  }
+}
+
+// zero keys: below every peak's key
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict__ a, long long n) {
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k < n) a[k] = 0ull;
-  if (k == 0) {
-    *counter = 0u;
-    *mx = 0u;   // below every ordered value
-  }
 }
 
-// largest response (ordered encoding; max is independent of the order of the updates)
-// (each workgroup reduces a stripe of rows in registers, then through LDS, and adds one
-// atomic maximum: a few hundred atomics on the one word instead of one per wave)
-__global__ void __launch_bounds__(256) k_max_response(const float* __restrict__ D, int ld, int ny, int nx,
-                                                      unsigned int* __restrict__ mx) {
-  __shared__ unsigned int wmax[4];
-  unsigned int v = 0u;
-  for (int y = blockIdx.x; y < ny; y += gridDim.x)
-    for (int x = threadIdx.x; x < nx; x += 256) v = max(v, ordered(D[(long long)y * ld + x]));
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    v = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-    if (v) atomicMax(mx, v);
-  }
-}
-
-// A pixel is a peak if its response is >= the threshold (thr, or rel times the largest
-// response when rel > 0), no response in the (2r+1)^2 window is larger, and no earlier
-// pixel (raster order) in it is equal. Peaks go to a list as 64-bit keys: ordered value in
-// the high word, ~index in the low word (so a descending sort lists larger values first and
-// equal values by increasing index).
+// A pixel is a peak if its response is >= thr, no response in the (2r+1)^2 window is
+// larger, and no earlier pixel (raster order) in it is equal. Peaks go to a list as 64-bit
+// keys: ordered value in the high word, ~index in the low word (so a descending sort lists
+// larger values first and equal values by increasing index), each workgroup's in its own
+// slots (as many as peaks fit in its pixels: peaks are more than r apart in y or x), the
+// unused ones left zero so that they sort last. A relative threshold is
+// applied after the sort: the largest response of the image is the value of its first peak
+// (the first pixel holding the maximum is one), so the list is marked with thr = -inf and
+// cut where the values fall below rel times the first.
 __global__ void __launch_bounds__(256) k_mark_peaks(const float* __restrict__ D, int ld, int ny, int nx, int rad,
-                                                    float thr, float rel, const unsigned int* __restrict__ mx,
-                                                    unsigned long long* __restrict__ keys, unsigned int cap,
-                                                    unsigned int* __restrict__ counter) {
+                                                    float thr, unsigned long long* __restrict__ keys, unsigned int spw) {
+  __shared__ unsigned int wcnt;
+  if (threadIdx.x == 0) wcnt = 0u;
+  __syncthreads();
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= nx) return;
-  const float v = D[(long long)y * ld + x];
-  const float t = rel > 0.f ? rel * unordered(*mx) : thr;
-  if (!(v >= t)) return;
-  const int y0 = max(0, y - rad), y1 = min(ny - 1, y + rad), x0 = max(0, x - rad), x1 = min(nx - 1, x + rad);
-  for (int yy = y0; yy <= y1; ++yy)
-    for (int xx = x0; xx <= x1; ++xx) {
-      const float w = D[(long long)yy * ld + xx];
-      if (w > v || (w == v && (yy < y || (yy == y && xx < x)))) return;
-    }
-  const unsigned int slot = atomicAdd(counter, 1u);
-  if (slot < cap) {
-    const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
-    keys[slot] = ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx);
+  bool peak = false;
+  float v = 0.f;
+  if (x < nx) {
+    v = D[(long long)y * ld + x];
+    peak = v >= thr;
+    const int y0 = max(0, y - rad), y1 = min(ny - 1, y + rad), x0 = max(0, x - rad), x1 = min(nx - 1, x + rad);
+    for (int yy = y0; yy <= y1 && peak; ++yy)
+      for (int xx = x0; xx <= x1; ++xx) {
+        const float w = D[(long long)yy * ld + xx];
+        if (w > v || (w == v && (yy < y || (yy == y && xx < x)))) {
+          peak = false;
+          break;
+        }
+      }
   }
+  const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
+  append_keys(peak, ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx),
+              keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw, spw, &wcnt);
 }
 
-// The same test with the window read from LDS: a workgroup covers a tile of kPkTx x kPkTy
-// pixels and stages its (kPkTx + 2 rad) x (kPkTy + 2 rad) neighbourhood once (positions
-// outside the image hold NaN, which no comparison selects, as the image border clips the
-// window in the form above). The window maximum comes from two one-dimensional passes
-// (rows, then columns; fmaxf skips NaN), so every thread does the same 2 (2 rad + 1)
-// steps; only a pixel equal to its window maximum then scans the window for an earlier
-// equal value. Launched for rad <= kPkMaxRad.
-constexpr int kPkTx = 64, kPkTy = 4, kPkMaxRad = 32;
+// The same test with the window read from LDS: a workgroup of 256 threads covers a tile of
+// kPkTx x kPkTy pixels and stages its (kPkTx + 2 rad) x (kPkTy + 2 rad) neighbourhood once
+// (positions outside the image hold NaN, which no comparison selects, as the image border
+// clips the window in the form above). The window maxima come from two one-dimensional
+// passes (rows, then columns; fmaxf skips NaN), the column pass split so that the same
+// reads also give the maximum over the pixels before the centre in raster order (the rows
+// above and the left part of the centre's row): a pixel is a peak iff that maximum is not
+// equal to it and nothing in the window is larger, with no per-pixel scan (a scan that
+// stops at the first earlier equal value makes each wave holding a local maximum wait on
+// ~(rad + 1)(2 rad + 1) dependent LDS reads). A wave owns the 64 columns of a group of
+// four rows (no LDS bank conflicts along a row), and a thread the four pixels of one
+// column in it. Launched for rad <= kPkMaxRad.
+constexpr int kPkTx = 64, kPkTy = 16, kPkMaxRad = 32;
 
 __global__ void __launch_bounds__(256) k_mark_peaks_tile(const float* __restrict__ D, int ld, int ny, int nx, int rad,
-                                                         float thr, float rel, const unsigned int* __restrict__ mx,
-                                                         unsigned long long* __restrict__ keys, unsigned int cap,
-                                                         unsigned int* __restrict__ counter) {
+                                                         float thr, unsigned long long* __restrict__ keys,
+                                                         unsigned int spw) {
   extern __shared__ float win[];
+  __shared__ unsigned int wcnt;
+  if (threadIdx.x == 0) wcnt = 0u;
   const int W = kPkTx + 2 * rad, Hh = kPkTy + 2 * rad;
   float* rmax = win + W * Hh;   // Hh rows x kPkTx: maximum over each row's 2 rad + 1 window
   const int tx0 = blockIdx.x * kPkTx - rad, ty0 = blockIdx.y * kPkTy - rad;
-  for (int e = threadIdx.x; e < W * Hh; e += 256) {
-    const int yy = ty0 + e / W, xx = tx0 + e % W;
-    win[e] = (yy >= 0 && yy < ny && xx >= 0 && xx < nx) ? D[(long long)yy * ld + xx] : __builtin_nanf("");
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int r = g; r < Hh; r += 4) {
+    const int yy = ty0 + r;
+    const bool rin = yy >= 0 && yy < ny;
+    const float* src = D + (long long)(rin ? yy : 0) * ld;
+    for (int q = c; q < W; q += 64) {
+      const int xx = tx0 + q;
+      win[r * W + q] = (rin && xx >= 0 && xx < nx) ? src[xx] : __builtin_nanf("");
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < Hh * kPkTx; e += 256) {
-    const int ry = e / kPkTx, cx_ = e % kPkTx;
-    const float* wr = win + ry * W + cx_;
+  for (int r = g; r < Hh; r += 4) {
+    const float* wr = win + r * W + c;
     float m = wr[0];
+#pragma unroll 4
     for (int d = 1; d <= 2 * rad; ++d) m = fmaxf(m, wr[d]);
-    rmax[e] = m;
+    rmax[r * kPkTx + c] = m;
   }
   __syncthreads();
-  const int lx = threadIdx.x % kPkTx, ly = threadIdx.x / kPkTx;
-  const int x = blockIdx.x * kPkTx + lx, y = blockIdx.y * kPkTy + ly;
-  if (x >= nx || y >= ny) return;
-  const float v = win[(ly + rad) * W + lx + rad];
-  const float t = rel > 0.f ? rel * unordered(*mx) : thr;
-  if (!(v >= t)) return;
-  float wm = rmax[ly * kPkTx + lx];
-  for (int d = 1; d <= 2 * rad; ++d) wm = fmaxf(wm, rmax[(ly + d) * kPkTx + lx]);
-  if (wm > v) return;
-  // v is the window maximum: it is the peak unless an equal value comes earlier in raster order
-  for (int dy = -rad; dy <= 0; ++dy) {
-    const float* wr = win + (ly + rad + dy) * W + lx + rad;
-    const int dx1 = dy < 0 ? rad : -1;
-    for (int dx = -rad; dx <= dx1; ++dx)
-      if (wr[dx] == v) return;
-  }
-  const unsigned int slot = atomicAdd(counter, 1u);
-  if (slot < cap) {
+  const int x = blockIdx.x * kPkTx + c;
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    const int ly = 4 * g + j, y = blockIdx.y * kPkTy + ly;
+    bool peak = false;
+    float v = 0.f;
+    if (x < nx && y < ny) {
+      v = win[(ly + rad) * W + c + rad];
+      // maxima over the window rows above the pixel (`up`), over the part of its own row
+      // left of it (`left`): together the window's pixels before it in raster order, and
+      // over the rest (its whole row and the rows below). NaN is the empty maximum (fmaxf
+      // skips it and it equals nothing), so positions outside the image drop out.
+      float up = __builtin_nanf(""), left = __builtin_nanf(""), rest = rmax[(ly + rad) * kPkTx + c];
+#pragma unroll 4
+      for (int d = 0; d < rad; ++d) {
+        up = fmaxf(up, rmax[(ly + d) * kPkTx + c]);
+        rest = fmaxf(rest, rmax[(ly + rad + 1 + d) * kPkTx + c]);
+        left = fmaxf(left, win[(ly + rad) * W + c + d]);
+      }
+      // a peak: nothing in the window larger, nothing before it equal
+      peak = v >= thr && !(fmaxf(up, rest) > v) && !(fmaxf(up, left) == v);
+    }
     const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
-    keys[slot] = ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx);
+    append_keys(peak, ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx),
+                keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw, spw, &wcnt);
   }
 }
 
-__global__ void __launch_bounds__(256) k_emit_peaks(const unsigned long long* __restrict__ sorted, int nx, int max_peaks,
-                                                    const unsigned int* __restrict__ counter, int* __restrict__ rows,
+// Writes the first min(max_peaks, n) peaks of the sorted slots (n = the nonzero keys, a
+// prefix); with rel > 0 only those whose value is >= rel times the first one's (a shorter
+// prefix). Both lengths by binary search.
+__global__ void __launch_bounds__(256) k_emit_peaks(const unsigned long long* __restrict__ sorted, unsigned int nslots,
+                                                    int nx, int max_peaks, float rel, int* __restrict__ rows,
                                                     int* __restrict__ cols, float* __restrict__ vals,
                                                     int* __restrict__ count) {
   const int k = blockIdx.x * 256 + threadIdx.x;
-  const int n = (int)min((unsigned int)max_peaks, *counter);
+  unsigned int m = 0u;
+  {
+    unsigned int hi = nslots;   // keys at [0, m) nonzero, at [hi, nslots) zero
+    while (m < hi) {
+      const unsigned int mid = (m + hi) >> 1;
+      if (sorted[mid] != 0ull) m = mid + 1u;
+      else hi = mid;
+    }
+  }
+  if (rel > 0.f && m > 0u) {
+    const float t = rel * unordered((unsigned int)(sorted[0] >> 32));
+    unsigned int lo = 0u, hi = m;   // values at [0, lo) are >= t, at [hi, m) below t
+    while (lo < hi) {
+      const unsigned int mid = (lo + hi) >> 1;
+      if (unordered((unsigned int)(sorted[mid] >> 32)) >= t) lo = mid + 1u;
+      else hi = mid;
+    }
+    m = lo;
+  }
+  const int n = (int)min((unsigned int)max_peaks, m);
   if (k == 0) *count = n;
   if (k >= n) return;
   const unsigned long long key = sorted[k];
@@ -229,53 +274,59 @@ hipError_t launch_voting_filter(hipStream_t s, const float* P, int S, float* F, 
 }
 
 // peaks are more than `rad` apart in both directions: at most one per (rad+1)^2 cell
-long long peak_capacity(int ny, int nx, int rad) {
-  return (long long)((ny + rad) / (rad + 1)) * (long long)((nx + rad) / (rad + 1));
+// Workgroups of the marking kernel and the key slots of each (the most peaks its pixels
+// can hold: peaks are more than rad apart in y or x, one per (rad + 1)^2 cell at most).
+void peak_slots(int ny, int nx, int rad, long long* nwg, long long* spw) {
+  const long long c = rad + 1;
+  if (rad <= kPkMaxRad) {
+    *nwg = (long long)((nx + kPkTx - 1) / kPkTx) * ((ny + kPkTy - 1) / kPkTy);
+    *spw = ((kPkTx + c - 1) / c) * ((kPkTy + c - 1) / c);
+  } else {
+    *nwg = (long long)((nx + 255) / 256) * ny;
+    *spw = (256 + c - 1) / c;
+  }
 }
 
 size_t peak_scratch_bytes(int ny, int nx, int rad) {
-  const long long cap = peak_capacity(ny, nx, rad);
+  long long nwg = 0, spw = 0;
+  peak_slots(ny, nx, rad, &nwg, &spw);
+  const long long n = nwg * spw;
   size_t tmp = 0;
   (void)hipcub::DeviceRadixSort::SortKeysDescending(nullptr, tmp, (const unsigned long long*)nullptr,
-                                                    (unsigned long long*)nullptr, (int)cap);
-  return 256 + 2 * (size_t)cap * sizeof(unsigned long long) + ((tmp + 255) / 256) * 256;
+                                                    (unsigned long long*)nullptr, (int)n);
+  return 2 * (size_t)n * sizeof(unsigned long long) + ((tmp + 255) / 256) * 256;
 }
 
 hipError_t launch_find_peaks(hipStream_t s, const float* D, int ld, int ny, int nx, int rad, float thr, float rel,
                              int max_peaks, int* rows, int* cols, float* vals, int* count, void* scratch,
                              size_t scratch_bytes) {
   if (ny < 1 || nx < 1 || ny > 65535 || rad < 0 || max_peaks < 1) return hipErrorInvalidValue;
-  const long long cap = peak_capacity(ny, nx, rad);
-  if (cap > 0x7fffffffLL || scratch_bytes < peak_scratch_bytes(ny, nx, rad)) return hipErrorInvalidValue;
-  char* base = static_cast<char*>(scratch);
-  unsigned int* counter = reinterpret_cast<unsigned int*>(base);
-  unsigned int* mx = counter + 1;
-  unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + 256);
-  unsigned long long* sorted = keys + cap;
-  void* tmp = base + 256 + 2 * (size_t)cap * sizeof(unsigned long long);
-  size_t tmp_bytes = scratch_bytes - (256 + 2 * (size_t)cap * sizeof(unsigned long long));
-  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, cap, counter, mx);
+  long long nwg = 0, spw = 0;
+  peak_slots(ny, nx, rad, &nwg, &spw);
+  const long long n = nwg * spw;
+  if (n > 0x7fffffffLL || scratch_bytes < peak_scratch_bytes(ny, nx, rad)) return hipErrorInvalidValue;
+  unsigned long long* keys = static_cast<unsigned long long*>(scratch);
+  unsigned long long* sorted = keys + n;
+  void* tmp = sorted + n;
+  size_t tmp_bytes = scratch_bytes - 2 * (size_t)n * sizeof(unsigned long long);
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n);
   hipError_t e = last();
   if (e != hipSuccess) return e;
-  if (rel > 0.f) {
-    hipLaunchKernelGGL(k_max_response, dim3((unsigned)std::min(ny, 1024)), dim3(256), 0, s, D, ld, ny, nx, mx);
-    if ((e = last()) != hipSuccess) return e;
-  }
+  const float mark_thr = rel > 0.f ? -INFINITY : thr;
   if (rad <= kPkMaxRad) {
     const dim3 grid((unsigned)((nx + kPkTx - 1) / kPkTx), (unsigned)((ny + kPkTy - 1) / kPkTy));
     const size_t lds = sizeof(float) * (size_t)(kPkTy + 2 * rad) * (kPkTx + 2 * rad + kPkTx);
-    hipLaunchKernelGGL(k_mark_peaks_tile, grid, dim3(256), lds, s, D, ld, ny, nx, rad, thr, rel, mx, keys,
-                       (unsigned int)cap, counter);
+    hipLaunchKernelGGL(k_mark_peaks_tile, grid, dim3(256), lds, s, D, ld, ny, nx, rad, mark_thr, keys,
+                       (unsigned int)spw);
   } else {
     const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)ny);
-    hipLaunchKernelGGL(k_mark_peaks, grid, dim3(256), 0, s, D, ld, ny, nx, rad, thr, rel, mx, keys,
-                       (unsigned int)cap, counter);
+    hipLaunchKernelGGL(k_mark_peaks, grid, dim3(256), 0, s, D, ld, ny, nx, rad, mark_thr, keys, (unsigned int)spw);
   }
   if ((e = last()) != hipSuccess) return e;
-  e = hipcub::DeviceRadixSort::SortKeysDescending(tmp, tmp_bytes, keys, sorted, (int)cap, 0, 64, s);
+  e = hipcub::DeviceRadixSort::SortKeysDescending(tmp, tmp_bytes, keys, sorted, (int)n, 0, 64, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_peaks, dim3((unsigned)((max_peaks + 255) / 256)), dim3(256), 0, s, sorted, nx, max_peaks,
-                     counter, rows, cols, vals, count);
+  hipLaunchKernelGGL(k_emit_peaks, dim3((unsigned)((max_peaks + 255) / 256)), dim3(256), 0, s, sorted,
+                     (unsigned int)n, nx, max_peaks, rel, rows, cols, vals, count);
   return last();
 }
 

@@ -100,6 +100,16 @@ def test_find_peaks_matches_the_oracle(E, ctx, radius, thr, relative, max_peaks)
     peaks_equal(E, ctx, D, radius, thr, relative, max_peaks)
 
 
+@pytest.mark.parametrize("shape,radius,thr,relative,max_peaks", [
+    ((256, 256), 1, -10.0, False, 20000),   # every local maximum; 128^2 cells: the largest on-chip sort
+    ((150, 173), 0, 0.5, True, 30000),      # 25950 cells: the device-wide sort, relative threshold
+    ((300, 260), 2, 0.1, True, 5000)])
+def test_find_peaks_long_lists(E, ctx, shape, radius, thr, relative, max_peaks):
+    """Lists of thousands of peaks, in both sorts, with either threshold."""
+    D = blurred_noise(shape, 23, sigma=1.0)
+    peaks_equal(E, ctx, D, radius, thr, relative, max_peaks)
+
+
 def test_find_peaks_ties_and_plateaus(E, ctx):
     D = np.zeros((40, 50), np.float32)
     D[10:13, 10:13] = 2.0          # a plateau: only its first pixel is a peak
