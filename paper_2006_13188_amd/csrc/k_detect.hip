@@ -101,10 +101,12 @@ __device__ __forceinline__ void append_keys(bool take, unsigned long long key, u
   }
 }
 
-// zero keys: below every peak's key
-__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict__ a, long long n) {
-  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (k < n) a[k] = 0ull;
+// Zeroes the workgroup's slots past its last key (zero sorts below every peak's key). Every
+// thread of the workgroup must make the call, after its last append.
+__device__ __forceinline__ void zero_unused(unsigned long long* __restrict__ slots, unsigned int nslot,
+                                            const unsigned int* wcnt) {
+  __syncthreads();
+  for (unsigned int i = min(*wcnt, nslot) + threadIdx.x; i < nslot; i += blockDim.x) slots[i] = 0ull;
 }
 
 // A pixel is a peak if its response is >= thr, no response in the (2r+1)^2 window is
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* __restrict
 // keys: ordered value in the high word, ~index in the low word (so a descending sort lists
 // larger values first and equal values by increasing index), each workgroup's in its own
 // slots (as many as peaks fit in its pixels: peaks are more than r apart in y or x), the
-// unused ones left zero so that they sort last. A relative threshold is
+// unused ones set to zero so that they sort last. A relative threshold is
 // applied after the sort: the largest response of the image is the value of its first peak
 // (the first pixel holding the maximum is one), so the list is marked with thr = -inf and
 // cut where the values fall below rel times the first.
@@ -138,8 +140,9 @@ __global__ void __launch_bounds__(256) k_mark_peaks(const float* __restrict__ D,
       }
   }
   const unsigned int idx = (unsigned int)y * (unsigned int)nx + (unsigned int)x;
-  append_keys(peak, ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx),
-              keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw, spw, &wcnt);
+  unsigned long long* slots = keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw;
+  append_keys(peak, ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx), slots, spw, &wcnt);
+  zero_unused(slots, spw, &wcnt);
 }
 
 // The same test with the window read from LDS: a workgroup of 256 threads covers a tile of
@@ -211,6 +214,7 @@ __global__ void __launch_bounds__(256) k_mark_peaks_tile(const float* __restrict
     append_keys(peak, ((unsigned long long)ordered(v) << 32) | (unsigned long long)(~idx),
                 keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw, spw, &wcnt);
   }
+  zero_unused(keys + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * spw, spw, &wcnt);
 }
 
 // Writes the first min(max_peaks, n) peaks of the sorted slots (n = the nonzero keys, a
@@ -309,9 +313,7 @@ hipError_t launch_find_peaks(hipStream_t s, const float* D, int ld, int ny, int 
   unsigned long long* sorted = keys + n;
   void* tmp = sorted + n;
   size_t tmp_bytes = scratch_bytes - 2 * (size_t)n * sizeof(unsigned long long);
-  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n);
-  hipError_t e = last();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   const float mark_thr = rel > 0.f ? -INFINITY : thr;
   if (rad <= kPkMaxRad) {
     const dim3 grid((unsigned)((nx + kPkTx - 1) / kPkTx), (unsigned)((ny + kPkTy - 1) / kPkTy));
