@@ -190,8 +190,9 @@ typedef enum {
  * anything, the bytes that `call` (an ecc_ws_call; ECC_CORRELATION and ECC_CONVOLUTION
  * mean ecc_extended with that op) needs for `batch` images of ny x nx with `plan` under
  * the context's current strategy: 0 for the on-chip block paths of the correlation and
- * convolution; the overlap-add regions of the normalised convolution and the scale
- * smoothing; the component stack of matching; the two-pass stacks otherwise. (The adjoints also allocate a temporary image when grad_signal is NULL.)
+ * of the convolution with 64- and 96-point blocks; the overlap-add regions of the
+ * convolution with 128-point blocks, the normalised convolution and the scale smoothing;
+ * the component stack of matching; the two-pass stacks otherwise. (The adjoints also allocate a temporary image when grad_signal is NULL.)
  * When the autotuner is enabled and has not run, this call runs it first (the choice of
  * block shape depends on it). Errors: INVALID_ARGUMENT, HIP. */
 ecc_status ecc_workspace_size(ecc_context ctx, int call, ecc_filter_plan plan, int batch, int ny,

@@ -947,6 +947,37 @@ ecc_status forward_impl(ecc_context ctx, ecc_op op, ecc_filter_plan plan, int ba
     mark(ctx, 1, st);
     return ECC_OK;
   }
+  TileChoice rc;
+  if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION && tc.N == 128 && pick_tile_ratio(plan, rc)) {
+    // 128-point blocks: overlap-add (sources T x T per block, pruned forward transforms;
+    // the overlap-save form holds too many registers at this size), regions added by a
+    // second kernel
+    const Spectrum* sp = nullptr;
+    ECC_TRY(get_tile_spectrum(plan, rc.N, st, &sp, SPEC_RATIO));
+    WsUse wu(ctx, st);
+    ECC_HIP(ctx->ws.ensure(tratio_scratch_bytes(rc.N, rc.T, batch, ny, nx)));
+    TileRatioArgs ra{};
+    ra.H = signal;
+    ra.planeH = pS;
+    ra.ldH = ld_signal;
+    ra.fld = make_field(plan, field, pF, ld_field, 1.0);
+    ra.sig_norm = 0;
+    ra.y = out;
+    ra.planeY = pO;
+    ra.ldY = ld_out;
+    ra.ny = ny;
+    ra.nx = nx;
+    ra.R = plan->R;
+    ra.T = rc.T;
+    ra.U = plan->U;
+    ra.Fs = sp->buf.as<float2>();
+    ra.par = plan->d_parity.as<float>();
+    ra.part = ctx->ws.as<cx<float>>();
+    mark(ctx, 0, st);
+    ECC_HIP(launch_tile_ratio(st, rc.N, rc.TV, batch, ra, 0, true));
+    mark(ctx, 1, st);
+    return ECC_OK;
+  }
   if (strat == ECC_STRATEGY_TILED && op == ECC_CONVOLUTION) {
     const Spectrum* sp = nullptr;
     ECC_TRY(get_tile_spectrum(plan, tc.N, st, &sp, SPEC_CONV));
@@ -1602,10 +1633,14 @@ ecc_status workspace_need(ecc_context ctx, int call, ecc_filter_plan plan, int b
       ECC_TRY(strat(ECC_CORRELATION, batch, tc, &tiled, true));
       *bytes = tiled ? 0 : ws_corr_stack(batch, ny, Py, Px, U);
       return ECC_OK;
-    case ECC_WS_EXTENDED_CONVOLUTION:
+    case ECC_WS_EXTENDED_CONVOLUTION: {
       ECC_TRY(strat(ECC_CONVOLUTION, batch, tc, &tiled, true));
-      *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 1, false);
+      TileChoice rc;
+      if (tiled && tc.N == 128 && pick_tile_ratio(plan, rc))
+        *bytes = tratio_scratch_bytes(rc.N, rc.T, batch, ny, nx);
+      else *bytes = tiled ? 0 : ws_conv_two_pass(batch, ny, Py, Px, U, 1, false);
       return ECC_OK;
+    }
     case ECC_WS_SCALE_SMOOTH:
     case ECC_WS_NORMALIZED_CONVOLUTION: {
       if (call == ECC_WS_SCALE_SMOOTH) {

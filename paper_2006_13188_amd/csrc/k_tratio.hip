@@ -147,7 +147,7 @@ __shared__ float ratio_h_lds[NV * NT];
 template <int NT>
 __shared__ cx<float> ratio_e1_lds[NT];
 
-template <int N, int TV, int NT, int PREC>
+template <int N, int TV, int NT, int PREC, bool PLAIN>
 __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int tile, int blk, cx<float>* A) {
   constexpr int M = N / 8, P = N + 1, LS = NT / 8;
   constexpr int RMAX = (TV + M - 1) / M;        // pass-0 inputs that can lie below T
@@ -161,6 +161,11 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
   // float16 / bfloat16 hi + lo operands (tiles: 16 lines of one butterfly per wave)
   constexpr bool MF = PREC != 0;
   static_assert(!MF || (N == 128 && NT == 1024), "matrix-core passes: 128-point blocks, 16 waves");
+  // PLAIN: one signal, y = Re sum_c w_c (m_c * F_c) with m_c = s1 e^{-i c alpha}: one
+  // forward transform of the complex m_c per component, times the complex spectrum
+  // F_c = a_c + i b_c (rho_a + i rho_b, or i rho_a - rho_b for odd parity)
+  static_assert(!PLAIN || !MF, "the plain convolution runs on the vector units");
+  constexpr int NPART = PLAIN ? 1 : 2;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int mlr = lane & 15, mlq = lane >> 4;
   const int mbq = wv & 7;   // the pass-1 butterfly of every tile of this wave
@@ -235,7 +240,7 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
   for (int c = 0; c < a.U; ++c) {
     const bool odd = a.par[c] < 0.f;   // spectra imaginary
 #pragma unroll 1
-    for (int part = 0; part < 2; ++part) {   // P (cosine, with a_c), then Q (sine, with b_c)
+    for (int part = 0; part < NPART; ++part) {   // P (cosine, with a_c), then Q (sine, with b_c)
 
       // ---- column pass 0 (radix 8, inputs below T only), straight from the sources
 #pragma unroll
@@ -247,8 +252,13 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
             if (r < RMAX) {
-              const float f = part ? z[s][r].im : z[s][r].re;
-              x[r] = mk(hs[(s * RMAX + r) * NT + t] * f, f);
+              if constexpr (PLAIN) {
+                const float hv = hs[(s * RMAX + r) * NT + t];
+                x[r] = mk(hv * z[s][r].re, -hv * z[s][r].im);
+              } else {
+                const float f = part ? z[s][r].im : z[s][r].re;
+                x[r] = mk(hs[(s * RMAX + r) * NT + t] * f, f);
+              }
             } else {
               x[r] = mk(0.f, 0.f);
             }
@@ -356,6 +366,17 @@ __device__ __forceinline__ void ratio_block(const TileRatioArgs& a, int img, int
           dft<M, -1, float>(x);
 #pragma unroll
           for (int r = 0; r < M; ++r) {
+            if constexpr (PLAIN) {
+              const int so = ((c * N + bq + 8 * r) * N) * (int)sizeof(float2);
+              const float ra = __builtin_bit_cast(
+                  float, __builtin_amdgcn_raw_buffer_load_b32(fsrc, u * (int)sizeof(float2), so, 0));
+              const float rb = __builtin_bit_cast(
+                  float, __builtin_amdgcn_raw_buffer_load_b32(fsrc, u * (int)sizeof(float2), so + 4, 0));
+              const cx<float> F = odd ? mk(-rb, ra) : mk(ra, rb);
+              Z[i][r].re += x[r].re * F.re - x[r].im * F.im;
+              Z[i][r].im += x[r].re * F.im + x[r].im * F.re;
+              continue;
+            }
             // w_c rho_a (P) or w_c rho_b (Q): one word of the element's float2
             const float rho = __builtin_bit_cast(
                 float, __builtin_amdgcn_raw_buffer_load_b32(
@@ -434,11 +455,29 @@ constexpr int tratio_threads() {
   return 1024;
 }
 
-template <int N, int TV, int PREC>
+template <int N, int TV, int PREC, bool PLAIN = false>
 __global__ void __launch_bounds__(tratio_threads<N>()) k_tile_ratio(TileRatioArgs a) {
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int ntile = a.tx * a.ty;
-  ratio_block<N, TV, tratio_threads<N>(), PREC>(a, lb / ntile, lb % ntile, lb, ratio_img_lds<N>);
+  ratio_block<N, TV, tratio_threads<N>(), PREC, PLAIN>(a, lb / ntile, lb % ntile, lb, ratio_img_lds<N>);
+}
+
+// the plain convolution's gather: out(p) = scale * the sum of the real parts over the
+// regions that cover p, in the same fixed order
+__global__ void __launch_bounds__(256) k_conv_sum(TileRatioArgs a, int N, float scale) {
+  const int px = blockIdx.x * 256 + threadIdx.x, py = blockIdx.y, img = blockIdx.z;
+  if (px >= a.nx) return;
+  const int T = a.T, R = a.R;
+  const int ny0 = py + R - N + 1, nx0 = px + R - N + 1;
+  const int by0 = ny0 <= 0 ? 0 : (ny0 + T - 1) / T, by1 = min(a.ty - 1, (py + R) / T);
+  const int bx0 = nx0 <= 0 ? 0 : (nx0 + T - 1) / T, bx1 = min(a.tx - 1, (px + R) / T);
+  float acc = 0.f;
+  for (int by = by0; by <= by1; ++by)
+    for (int bx = bx0; bx <= bx1; ++bx) {
+      const long long blk = ((long long)img * a.ty + by) * a.tx + bx;
+      acc += a.part[(blk * N + (py - by * T + R)) * N + (px - bx * T + R)].re;
+    }
+  a.y[(long long)img * a.planeY + (long long)py * a.ldY + px] = acc * scale;
 }
 
 // out(p) = sum of the real parts over the regions that cover p / the same sum of the
@@ -507,15 +546,25 @@ size_t tratio_scratch_bytes(int N, int T, int batch, int ny, int nx) {
   return (size_t)nblk * N * N * sizeof(cx<float>);
 }
 
-hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a0, int prec) {
+hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a0, int prec, bool plain) {
   TileRatioArgs a = a0;
   if (a.T < 1 || a.T > TV || a.T + 2 * a.R > N || a.R < 0 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+  if (plain && prec != 0) return hipErrorInvalidValue;
   a.tx = (a.nx + a.T - 1) / a.T;
   a.ty = (a.ny + a.T - 1) / a.T;
   const long long nblk = (long long)a.tx * a.ty * batch;
   if (nblk > 0x7fffffffLL || a.ny > 65535 || batch > 65535) return hipErrorInvalidValue;
 #define ECC_RL(n, tv)                                                                                 \
   if (N == n && TV == tv) {                                                                          \
+    if (plain) {                                                                                     \
+      hipLaunchKernelGGL((k_tile_ratio<n, tv, 0, true>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, \
+                         a);                                                                         \
+      hipError_t e = last();                                                                         \
+      if (e != hipSuccess) return e;                                                                 \
+      hipLaunchKernelGGL(k_conv_sum, dim3((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)batch), \
+                         dim3(256), 0, s, a, n, 1.0f / ((float)n * (float)n));                       \
+      return last();                                                                                 \
+    }                                                                                                \
     if (prec == 0)                                                                                   \
       hipLaunchKernelGGL((k_tile_ratio<n, tv, 0>), dim3((unsigned)nblk), dim3(tratio_threads<n>()), 0, s, a); \
     else if (prec == 1)                                                                              \

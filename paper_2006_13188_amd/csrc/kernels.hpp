@@ -274,8 +274,11 @@ struct TileRatioArgs {
 bool tratio_supported(int N, int TV);
 size_t tratio_scratch_bytes(int N, int T, int batch, int ny, int nx);
 // prec 0: float32; 1 / 2: the radix-16 passes of the forward transforms on the matrix
-// cores with float16 / bfloat16 hi + lo operands (float32 accumulation)
-hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a, int prec = 0);
+// cores with float16 / bfloat16 hi + lo operands (float32 accumulation). plain (prec 0
+// only): the extended convolution of the one signal s1 instead of the ratio,
+// y = Re sum_c w_c (s1 e^{-i c alpha}) * F_c, one forward transform per component
+hipError_t launch_tile_ratio(hipStream_t s, int N, int TV, int batch, const TileRatioArgs& a, int prec = 0,
+                             bool plain = false);
 // spectra of the overlap-add ratio kernel from the centred float64 spectra of the
 // components (U planes of N x N, [row freq][column freq]): per component the real parts of
 // the spectra of Re F_c and Im F_c (parity +1) or their imaginary parts (parity -1), times
